@@ -1,0 +1,197 @@
+"""FP64 CPU oracle for the Schwarzschild model-build hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg.  The product path never imports it, and it
+imports nothing from the product package.
+
+The orbit integration, symmetrisation, projection and binning live in the
+plain C library ``schw_oracle.c`` (double precision, no FMA contraction);
+this module wraps it with ctypes.  The weight solve, chi^2, Gauss-Hermite
+moments, the MLP and the delayed-acceptance sampler are plain NumPy in the
+sibling modules.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6}
+G = 4.300917270e-6
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        src = os.path.join(_build.HERE, "schw_oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        _lib = C.CDLL(path)
+        _declare(_lib)
+    return _lib
+
+
+class _Comp(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 8)]
+
+
+class _Pot(C.Structure):
+    _fields_ = [("ncomp", C.c_int), ("comp", _Comp * 8), ("omega", C.c_double)]
+
+
+class _Obs(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("npx", C.c_int), ("npy", C.c_int),
+                ("plo", C.c_double * 2), ("phi", C.c_double * 2),
+                ("pix2ap", C.POINTER(C.c_int32)), ("n_ap", C.c_int),
+                ("nv", C.c_int), ("vlo", C.c_double), ("vhi", C.c_double),
+                ("R", C.c_double * 9), ("symmetrize", C.c_int), ("drift_every", C.c_int)]
+
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_i32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def _declare(L):
+    P, O = C.POINTER(_Pot), C.POINTER(_Obs)
+    L.orc_phi.argtypes = [P, _dp]; L.orc_phi.restype = C.c_double
+    L.orc_accel.argtypes = [P, _dp, _dp]; L.orc_accel.restype = None
+    L.orc_density.argtypes = [P, _dp]; L.orc_density.restype = C.c_double
+    L.orc_jacobi.argtypes = [P, _dp]; L.orc_jacobi.restype = C.c_double
+    L.orc_ferrers_lambda.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+    L.orc_ferrers_lambda.restype = C.c_double
+    L.orc_nfw_derived.argtypes = [C.c_double, C.c_double, C.c_double, _dp]; L.orc_nfw_derived.restype = None
+    L.orc_euler_matrix.argtypes = [C.c_double, C.c_double, C.c_double, _dp]; L.orc_euler_matrix.restype = None
+    L.orc_step.argtypes = [P, _dp, C.c_double]; L.orc_step.restype = None
+    L.orc_orbit.argtypes = [P, _dp, C.c_double, C.c_int, _dp]; L.orc_orbit.restype = None
+    L.orc_ncon.argtypes = [O]; L.orc_ncon.restype = C.c_int
+    L.orc_integrate_and_bin.argtypes = [P, O, C.c_long, _dp, _dp, C.c_int, _i32, _i64, _dp, _u8, C.c_int]
+    L.orc_integrate_and_bin.restype = None
+    L.orc_bin_points_f64.argtypes = [O, C.c_long, _dp, _i32, _i32]; L.orc_bin_points_f64.restype = None
+    L.orc_bin_points_f32.argtypes = [O, C.c_long, _fp, _i32, _i32]; L.orc_bin_points_f32.restype = None
+
+
+def make_pot(components, omega=0.0):
+    """components: list of (kind_name, params tuple) in the kind's slot order."""
+    p = _Pot()
+    p.ncomp = len(components)
+    for i, (kind, params) in enumerate(components):
+        p.comp[i].kind = KINDS[kind]
+        for j, v in enumerate(params):
+            p.comp[i].p[j] = float(v)
+    p.omega = float(omega)
+    return p
+
+
+def euler_matrix(alpha, beta, gamma):
+    R = np.zeros(9)
+    lib().orc_euler_matrix(alpha, beta, gamma, R)
+    return R.reshape(3, 3)
+
+
+def make_obs(spec, R):
+    """spec: dict with keys nx, ny, nz, lo, hi, npx, npy, plo, phi, pix2ap (array or None),
+    n_ap, nv, vlo, vhi, symmetrize, drift_every.  R: 3x3 projection matrix."""
+    o = _Obs()
+    o.nx, o.ny, o.nz = spec["nx"], spec["ny"], spec["nz"]
+    for i in range(3):
+        o.lo[i], o.hi[i] = spec["lo"][i], spec["hi"][i]
+    o.npx, o.npy = spec["npx"], spec["npy"]
+    for i in range(2):
+        o.plo[i], o.phi[i] = spec["plo"][i], spec["phi"][i]
+    m = spec.get("pix2ap")
+    if m is not None:
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        o.pix2ap = m.ctypes.data_as(C.POINTER(C.c_int32))
+        o._keep = m
+        o.n_ap = int(spec["n_ap"])
+    else:
+        o.pix2ap = C.POINTER(C.c_int32)()
+        o.n_ap = spec["npx"] * spec["npy"]
+    o.nv, o.vlo, o.vhi = spec["nv"], spec["vlo"], spec["vhi"]
+    R = np.asarray(R, dtype=np.float64).reshape(9)
+    for i in range(9):
+        o.R[i] = R[i]
+    o.symmetrize = int(spec.get("symmetrize", 1))
+    o.drift_every = int(spec.get("drift_every", 1))
+    return o
+
+
+def phi(pot, x):
+    return lib().orc_phi(C.byref(pot), np.ascontiguousarray(x, dtype=np.float64))
+
+
+def accel(pot, x):
+    g = np.zeros(3)
+    lib().orc_accel(C.byref(pot), np.ascontiguousarray(x, dtype=np.float64), g)
+    return g
+
+
+def density(pot, x):
+    return lib().orc_density(C.byref(pot), np.ascontiguousarray(x, dtype=np.float64))
+
+
+def jacobi(pot, s):
+    return lib().orc_jacobi(C.byref(pot), np.ascontiguousarray(s, dtype=np.float64))
+
+
+def ferrers_lambda(a, b, c, x):
+    return lib().orc_ferrers_lambda(a, b, c, np.ascontiguousarray(x, dtype=np.float64))
+
+
+def nfw_derived(M200, c, H0=70.0):
+    out = np.zeros(3)
+    lib().orc_nfw_derived(M200, c, H0, out)
+    return out  # R_s, M_DM, R200
+
+
+def orbit(pot, ic, dt, nsteps):
+    traj = np.zeros((nsteps + 1, 6))
+    lib().orc_orbit(C.byref(pot), np.ascontiguousarray(ic, dtype=np.float64), dt, nsteps, traj)
+    return traj
+
+
+def ncon(obs):
+    return lib().orc_ncon(C.byref(obs))
+
+
+def integrate_and_bin(pot, obs, ics, dt, nsteps, nthreads=0):
+    """ics: [6][n] float64; dt: [n].  Returns (counts [n][ncon] int32,
+    overflow [n][2] int64, drift [n], flags [n] uint8)."""
+    ics = np.ascontiguousarray(ics, dtype=np.float64)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    n = ics.shape[1]
+    nc = ncon(obs)
+    counts = np.zeros((n, nc), dtype=np.int32)
+    ov = np.zeros((n, 2), dtype=np.int64)
+    drift = np.zeros(n)
+    flags = np.zeros(n, dtype=np.uint8)
+    lib().orc_integrate_and_bin(C.byref(pot), C.byref(obs), n, ics, dt, nsteps, counts, ov, drift, flags,
+                                nthreads)
+    return counts, ov, drift, flags
+
+
+def bin_points(obs, pts, precision="f64"):
+    """pts: [6][n] phase-space points on the bar axes.  Returns (mass, kin) [n][4] int32."""
+    n = pts.shape[1]
+    mass = np.zeros((n, 4), dtype=np.int32)
+    kin = np.zeros((n, 4), dtype=np.int32)
+    if precision == "f64":
+        lib().orc_bin_points_f64(C.byref(obs), n, np.ascontiguousarray(pts, dtype=np.float64), mass, kin)
+    else:
+        lib().orc_bin_points_f32(C.byref(obs), n, np.ascontiguousarray(pts, dtype=np.float32), mass, kin)
+    return mass, kin
+
+
+def time_fractions(counts, nsteps, symmetrize=True):
+    """Sec. 2.2.4: each sample carries weight dt / t_total = 1 / nsteps, split
+    over the mirror copies."""
+    return counts / float((4 if symmetrize else 1) * nsteps)

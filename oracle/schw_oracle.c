@@ -1,0 +1,530 @@
+/*
+ * FP64 CPU oracle for the Schwarzschild model-build hot path.
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.
+ *
+ * Built with -ffp-contract=off so that every expression below is evaluated
+ * exactly in the order it is written.
+ *
+ * Passages followed (SchwarMAX paper, arXiv 2607.00117):
+ *   potentials ........ Sec. 2.1; NFW Eq. 8-9; Miyamoto-Nagai Eq. 10-11.
+ *                        Plummer, Kepler, isochrone and the Ferrers n=2 bar
+ *                        are textbook pairs (Binney & Tremaine 2008, Sec. 2.2,
+ *                        2.5); the Ferrers potential is the homoeoid-theorem
+ *                        integral for rho = rho_c (1 - m^2)^2.
+ *   integration ........ Sec. 2.2.2: fixed number of steps, corotating bar
+ *                        frame, velocities kept inertial, Jacobi-energy cut.
+ *   symmetrisation ..... Sec. 2.2.2, Table 1 (four mirror copies).
+ *   projection ......... Sec. 2.2.3, Eq. 1 (z-x-z Euler rotation), line of
+ *                        sight along z'.
+ *   binning ............ Sec. 2.2.4 (time-weighted samples into 3D cells and
+ *                        sky apertures x LOS-velocity bins).
+ */
+#include "schw_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* NFW halo (Eq. 8-9): M_DM from M200 and c; R_s = R200 / c, where      */
+/* R200 encloses 200 rho_crit, rho_crit = 3 H0^2 / (8 pi G).            */
+/* ------------------------------------------------------------------ */
+void orc_nfw_derived(double M200, double c, double H0, double out[3]) {
+  if (H0 <= 0.0) H0 = 70.0;
+  double H = H0 / 1000.0; /* km/s/kpc */
+  double rho_crit = 3.0 * H * H / (8.0 * M_PI * ORC_G);
+  double R200 = cbrt(3.0 * M200 / (4.0 * M_PI * 200.0 * rho_crit));
+  double Rs = R200 / c;
+  double Mdm = M200 / (log(1.0 + c) - c / (1.0 + c));
+  out[0] = Rs;
+  out[1] = Mdm;
+  out[2] = R200;
+}
+
+/* ------------------------------------------------------------------ */
+/* Ferrers n = 2 ellipsoid: rho = rho_c (1 - m^2)^2 inside m < 1.        */
+/*   Phi(x)   = -(pi G a b c rho_c / 3) Int_lam^inf (1 - m^2(u))^3 du / Delta(u)
+ *   dPhi/dx_i = 2 pi G a b c rho_c x_i Int_lam^inf (1 - m^2(u))^2 du / ((a_i^2+u) Delta(u))
+ * m^2(u) = sum_j x_j^2 / (a_j^2 + u), Delta = sqrt(prod_j (a_j^2 + u)),
+ * lam = 0 inside, else the root of m^2(lam) = 1.                          */
+/* ------------------------------------------------------------------ */
+static double m2_of(const double A2[3], const double x[3], double u) {
+  return x[0] * x[0] / (A2[0] + u) + x[1] * x[1] / (A2[1] + u) + x[2] * x[2] / (A2[2] + u);
+}
+
+double orc_ferrers_lambda(double a, double b, double c, const double x[3]) {
+  double A2[3] = {a * a, b * b, c * c};
+  if (m2_of(A2, x, 0.0) <= 1.0) return 0.0;
+  /* m^2 decreases in u and m^2(r^2) < 1, so [0, r^2] brackets the root */
+  double lo = 0.0, hi = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  for (int it = 0; it < 400; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (m2_of(A2, x, mid) > 1.0) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* Gauss-Kronrod 7/15 abscissae and weights (QUADPACK qk15). */
+static const double XGK[8] = {
+    0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+    0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+    0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+    0.207784955007898467600689403773245, 0.000000000000000000000000000000000};
+static const double WGK[8] = {
+    0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+    0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+    0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+    0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+static const double WG[4] = {
+    0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+    0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+typedef struct {
+  double A2[3];
+  double x[3];
+  double lam, K;
+} fer_ctx;
+
+/* integrand vector at t in (0,1]: u = lam + K (1/t^2 - 1), du = 2 K t^-3 dt
+ * f[0] = (1-m^2)^3 / Delta, f[1+i] = (1-m^2)^2 / ((a_i^2+u) Delta)          */
+static void fer_integrand(const fer_ctx* C, double t, double f[4]) {
+  double q = 1.0 / (t * t) - 1.0;
+  double u = C->lam + C->K * q;
+  double d0 = C->A2[0] + u, d1 = C->A2[1] + u, d2 = C->A2[2] + u;
+  double Delta = sqrt(d0 * d1 * d2);
+  double m2 = C->x[0] * C->x[0] / d0 + C->x[1] * C->x[1] / d1 + C->x[2] * C->x[2] / d2;
+  double w = 1.0 - m2;
+  if (w < 0.0) w = 0.0; /* only at round-off distance from t = 1 */
+  double jac = 2.0 * C->K / (t * t * t);
+  f[0] = w * w * w / Delta * jac;
+  f[1] = w * w / (d0 * Delta) * jac;
+  f[2] = w * w / (d1 * Delta) * jac;
+  f[3] = w * w / (d2 * Delta) * jac;
+}
+
+static void gk15(const fer_ctx* C, double lo, double hi, double res[4], double err[4]) {
+  double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+  double k[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0}, f1[4], f2[4];
+  fer_integrand(C, mid, f1);
+  for (int j = 0; j < 4; ++j) { k[j] = WGK[7] * f1[j]; g[j] = WG[3] * f1[j]; }
+  for (int i = 0; i < 7; ++i) {
+    fer_integrand(C, mid - half * XGK[i], f1);
+    fer_integrand(C, mid + half * XGK[i], f2);
+    for (int j = 0; j < 4; ++j) {
+      k[j] += WGK[i] * (f1[j] + f2[j]);
+      if (i & 1) g[j] += WG[i / 2] * (f1[j] + f2[j]);
+    }
+  }
+  for (int j = 0; j < 4; ++j) {
+    res[j] = k[j] * half;
+    err[j] = fabs((k[j] - g[j]) * half);
+  }
+}
+
+static void adapt(const fer_ctx* C, double lo, double hi, double tol, int depth, double out[4]) {
+  double r[4], e[4];
+  gk15(C, lo, hi, r, e);
+  int ok = 1;
+  for (int j = 0; j < 4; ++j)
+    if (e[j] > tol * fabs(r[j]) && e[j] > 1e-300) ok = 0;
+  if (ok || depth >= 40) {
+    for (int j = 0; j < 4; ++j) out[j] += r[j];
+    return;
+  }
+  double mid = 0.5 * (lo + hi);
+  adapt(C, lo, mid, tol, depth + 1, out);
+  adapt(C, mid, hi, tol, depth + 1, out);
+}
+
+/* I[0] = potential integral, I[1..3] = force integrals */
+static void ferrers_integrals(double a, double b, double c, const double x[3], double I[4]) {
+  fer_ctx C;
+  C.A2[0] = a * a; C.A2[1] = b * b; C.A2[2] = c * c;
+  C.x[0] = x[0]; C.x[1] = x[1]; C.x[2] = x[2];
+  C.lam = orc_ferrers_lambda(a, b, c, x);
+  double amin2 = C.A2[0];
+  if (C.A2[1] < amin2) amin2 = C.A2[1];
+  if (C.A2[2] < amin2) amin2 = C.A2[2];
+  C.K = amin2 + C.lam;
+  I[0] = I[1] = I[2] = I[3] = 0.0;
+  adapt(&C, 0.0, 1.0, 1e-13, 0, I);
+}
+
+static double ferrers_rho_c(const double* p) { return 105.0 * p[0] / (32.0 * M_PI * p[1] * p[2] * p[3]); }
+
+/* ------------------------------------------------------------------ */
+/* Components.                                                          */
+/* ------------------------------------------------------------------ */
+static double comp_phi(const orc_comp* C, const double x[3]) {
+  const double* p = C->p;
+  double GM = ORC_G * p[0];
+  switch (C->kind) {
+    case ORC_KEPLER: {
+      double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      return -GM / r;
+    }
+    case ORC_ISOCHRONE: {
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      return -GM / (p[1] + sqrt(p[1] * p[1] + r2));
+    }
+    case ORC_PLUMMER: {
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      return -GM / sqrt(r2 + p[1] * p[1]);
+    }
+    case ORC_MN: {
+      double R2 = x[0] * x[0] + x[1] * x[1];
+      double zeta = sqrt(x[2] * x[2] + p[2] * p[2]);
+      double s = p[1] + zeta;
+      return -GM / sqrt(R2 + s * s);
+    }
+    case ORC_NFW_Q: {
+      double d[3];
+      orc_nfw_derived(p[0], p[1], p[3], d);
+      double q = p[2];
+      double m = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] / (q * q));
+      double GMd = ORC_G * d[1];
+      if (m == 0.0) return -GMd / d[0];
+      return -GMd * log1p(m / d[0]) / m;
+    }
+    case ORC_FERRERS2: {
+      double I[4];
+      ferrers_integrals(p[1], p[2], p[3], x, I);
+      return -(M_PI * ORC_G * p[1] * p[2] * p[3] * ferrers_rho_c(p) / 3.0) * I[0];
+    }
+  }
+  return NAN;
+}
+
+/* acceleration g = -grad Phi, added into g[] */
+static void comp_accel_add(const orc_comp* C, const double x[3], double g[3]) {
+  const double* p = C->p;
+  double GM = ORC_G * p[0];
+  switch (C->kind) {
+    case ORC_KEPLER: {
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      double r = sqrt(r2);
+      double f = GM / (r2 * r);
+      g[0] = g[0] - f * x[0];
+      g[1] = g[1] - f * x[1];
+      g[2] = g[2] - f * x[2];
+      return;
+    }
+    case ORC_ISOCHRONE: {
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      double s = sqrt(p[1] * p[1] + r2);
+      double den = p[1] + s;
+      double f = GM / (den * den * s); /* dPhi/dr / r */
+      g[0] = g[0] - f * x[0];
+      g[1] = g[1] - f * x[1];
+      g[2] = g[2] - f * x[2];
+      return;
+    }
+    case ORC_PLUMMER: {
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      double d2 = r2 + p[1] * p[1];
+      double d = sqrt(d2);
+      double f = GM / (d2 * d);
+      g[0] = g[0] - f * x[0];
+      g[1] = g[1] - f * x[1];
+      g[2] = g[2] - f * x[2];
+      return;
+    }
+    case ORC_MN: {
+      double R2 = x[0] * x[0] + x[1] * x[1];
+      double zeta = sqrt(x[2] * x[2] + p[2] * p[2]);
+      double s = p[1] + zeta;
+      double D2 = R2 + s * s;
+      double D = sqrt(D2);
+      double f = GM / (D2 * D);
+      g[0] = g[0] - f * x[0];
+      g[1] = g[1] - f * x[1];
+      g[2] = g[2] - f * x[2] * s / zeta;
+      return;
+    }
+    case ORC_NFW_Q: {
+      double d[3];
+      orc_nfw_derived(p[0], p[1], p[3], d);
+      double q = p[2], Rs = d[0], GMd = ORC_G * d[1];
+      double m = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] / (q * q));
+      if (m == 0.0) return;
+      /* dPhi/dm = G M_DM [ ln(1+m/Rs)/m^2 - 1/(m (Rs+m)) ] */
+      double dphidm = GMd * (log1p(m / Rs) / (m * m) - 1.0 / (m * (Rs + m)));
+      double f = dphidm / m;
+      g[0] = g[0] - f * x[0];
+      g[1] = g[1] - f * x[1];
+      g[2] = g[2] - f * x[2] / (q * q);
+      return;
+    }
+    case ORC_FERRERS2: {
+      double I[4];
+      ferrers_integrals(p[1], p[2], p[3], x, I);
+      double k = 2.0 * M_PI * ORC_G * p[1] * p[2] * p[3] * ferrers_rho_c(p);
+      g[0] = g[0] - k * x[0] * I[1];
+      g[1] = g[1] - k * x[1] * I[2];
+      g[2] = g[2] - k * x[2] * I[3];
+      return;
+    }
+  }
+}
+
+static double comp_density(const orc_comp* C, const double x[3]) {
+  const double* p = C->p;
+  double M = p[0];
+  switch (C->kind) {
+    case ORC_KEPLER:
+      return 0.0;
+    case ORC_ISOCHRONE: {
+      double b = p[1];
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      double a = sqrt(b * b + r2);
+      return M * (3.0 * (b + a) * a * a - r2 * (b + 3.0 * a)) / (4.0 * M_PI * pow(b + a, 3) * a * a * a);
+    }
+    case ORC_PLUMMER: {
+      double b = p[1];
+      double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      return 3.0 * M / (4.0 * M_PI * b * b * b) * pow(1.0 + r2 / (b * b), -2.5);
+    }
+    case ORC_MN: { /* Eq. 11 */
+      double a = p[1], b = p[2];
+      double R2 = x[0] * x[0] + x[1] * x[1];
+      double zeta = sqrt(x[2] * x[2] + b * b);
+      double calR2 = R2 + (a + zeta) * (a + zeta);
+      double calR = sqrt(calR2);
+      return (b * b * M / (4.0 * M_PI)) * (a * calR2 + 3.0 * zeta * (zeta + a) * (zeta + a)) /
+             (pow(calR, 5) * zeta * zeta * zeta);
+    }
+    case ORC_NFW_Q: { /* Eq. 8, spherical case only */
+      if (p[2] != 1.0) return NAN;
+      double d[3];
+      orc_nfw_derived(p[0], p[1], p[3], d);
+      double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) / d[0];
+      return d[1] / (4.0 * M_PI * d[0] * d[0] * d[0]) / (r * (1.0 + r) * (1.0 + r));
+    }
+    case ORC_FERRERS2: {
+      double m2 = x[0] * x[0] / (p[1] * p[1]) + x[1] * x[1] / (p[2] * p[2]) + x[2] * x[2] / (p[3] * p[3]);
+      if (m2 >= 1.0) return 0.0;
+      return ferrers_rho_c(p) * (1.0 - m2) * (1.0 - m2);
+    }
+  }
+  return NAN;
+}
+
+double orc_phi(const orc_pot* P, const double x[3]) {
+  double s = 0.0;
+  for (int i = 0; i < P->ncomp; ++i) s = s + comp_phi(&P->comp[i], x);
+  return s;
+}
+
+void orc_accel(const orc_pot* P, const double x[3], double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  for (int i = 0; i < P->ncomp; ++i) comp_accel_add(&P->comp[i], x, g);
+}
+
+double orc_density(const orc_pot* P, const double x[3]) {
+  double s = 0.0;
+  for (int i = 0; i < P->ncomp; ++i) s = s + comp_density(&P->comp[i], x);
+  return s;
+}
+
+/* Jacobi energy E_J = |p|^2/2 + Phi(x) - Omega (x p_y - y p_x), with p the
+ * inertial velocity expressed on the rotating axes. */
+double orc_jacobi(const orc_pot* P, const double s[6]) {
+  double kin = 0.5 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+  double Lz = s[0] * s[4] - s[1] * s[3];
+  return kin + orc_phi(P, s) - P->omega * Lz;
+}
+
+/* Eq. 1: R = R_z(gamma) R_x(beta) R_z(alpha), active right-handed rotations */
+static void matmul3(const double A[9], const double B[9], double C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s = s + A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+void orc_euler_matrix(double alpha, double beta, double gamma, double R[9]) {
+  double ca = cos(alpha), sa = sin(alpha), cb = cos(beta), sb = sin(beta), cg = cos(gamma), sg = sin(gamma);
+  double Rza[9] = {ca, -sa, 0, sa, ca, 0, 0, 0, 1};
+  double Rxb[9] = {1, 0, 0, 0, cb, -sb, 0, sb, cb};
+  double Rzg[9] = {cg, -sg, 0, sg, cg, 0, 0, 0, 1};
+  double T[9];
+  matmul3(Rxb, Rza, T);
+  matmul3(Rzg, T, R);
+}
+
+/* Kick-drift-kick step of H = |p|^2/2 + Phi(x) - Omega L_z.
+ * The drift is the exact flow of |p|^2/2 - Omega L_z: a straight-line move
+ * by dt p followed by a rotation of both x and p by -Omega dt about z. */
+void orc_step(const orc_pot* P, double s[6], double dt) {
+  double g[3];
+  double h = 0.5 * dt;
+  orc_accel(P, s, g);
+  s[3] = s[3] + h * g[0];
+  s[4] = s[4] + h * g[1];
+  s[5] = s[5] + h * g[2];
+  s[0] = s[0] + dt * s[3];
+  s[1] = s[1] + dt * s[4];
+  s[2] = s[2] + dt * s[5];
+  double c = cos(P->omega * dt), sn = sin(P->omega * dt);
+  double x = c * s[0] + sn * s[1];
+  double y = c * s[1] - sn * s[0];
+  double px = c * s[3] + sn * s[4];
+  double py = c * s[4] - sn * s[3];
+  s[0] = x; s[1] = y; s[3] = px; s[4] = py;
+  orc_accel(P, s, g);
+  s[3] = s[3] + h * g[0];
+  s[4] = s[4] + h * g[1];
+  s[5] = s[5] + h * g[2];
+}
+
+void orc_orbit(const orc_pot* P, const double ic[6], double dt, int nsteps, double* traj) {
+  double s[6];
+  memcpy(s, ic, sizeof s);
+  memcpy(traj, s, sizeof s);
+  for (int k = 1; k <= nsteps; ++k) {
+    orc_step(P, s, dt);
+    memcpy(traj + 6 * (long)k, s, sizeof s);
+  }
+}
+
+int orc_ncon(const orc_obs* O) { return O->nx * O->ny * O->nz + O->n_ap * O->nv; }
+
+/* ------------------------------------------------------------------ */
+/* Binning (Sec. 2.2.4).  A coordinate v falls in bin floor(t) with      */
+/* t = (v - lo) * (n / (hi - lo)), the scale taken in double precision;  */
+/* the sample is inside iff 0 <= t < n.                                  */
+/* ------------------------------------------------------------------ */
+static int bin_d(double v, double lo, double inv, int n) {
+  double t = (v - lo) * inv;
+  if (!(t >= 0.0 && t < (double)n)) return -1;
+  return (int)t;
+}
+static int bin_f(float v, float lo, float inv, int n) {
+  float t = (v - lo) * inv;
+  if (!(t >= 0.0f && t < (float)n)) return -1;
+  return (int)t;
+}
+
+static const double MIRROR[4][3] = {{1, 1, 1}, {1, 1, -1}, {-1, -1, 1}, {-1, -1, -1}};
+
+static void cells_d(const orc_obs* O, const double s6[6], int copy, int* mcell, int* kcell) {
+  double x = MIRROR[copy][0] * s6[0], y = MIRROR[copy][1] * s6[1], z = MIRROR[copy][2] * s6[2];
+  double px = MIRROR[copy][0] * s6[3], py = MIRROR[copy][1] * s6[4], pz = MIRROR[copy][2] * s6[5];
+  int ix = bin_d(x, O->lo[0], O->nx / (O->hi[0] - O->lo[0]), O->nx);
+  int iy = bin_d(y, O->lo[1], O->ny / (O->hi[1] - O->lo[1]), O->ny);
+  int iz = bin_d(z, O->lo[2], O->nz / (O->hi[2] - O->lo[2]), O->nz);
+  *mcell = (ix < 0 || iy < 0 || iz < 0) ? -1 : (ix * O->ny + iy) * O->nz + iz;
+  const double* R = O->R;
+  double X = R[0] * x + R[1] * y + R[2] * z;
+  double Y = R[3] * x + R[4] * y + R[5] * z;
+  double V = R[6] * px + R[7] * py + R[8] * pz;
+  int jx = bin_d(X, O->plo[0], O->npx / (O->phi[0] - O->plo[0]), O->npx);
+  int jy = bin_d(Y, O->plo[1], O->npy / (O->phi[1] - O->plo[1]), O->npy);
+  int kv = bin_d(V, O->vlo, O->nv / (O->vhi - O->vlo), O->nv);
+  int ap = -1;
+  if (jx >= 0 && jy >= 0) {
+    int pix = jx * O->npy + jy;
+    ap = O->pix2ap ? O->pix2ap[pix] : pix;
+  }
+  *kcell = (ap < 0 || kv < 0) ? -1 : ap * O->nv + kv;
+}
+
+static void cells_f(const orc_obs* O, const float s6[6], int copy, int* mcell, int* kcell) {
+  float sx = (float)MIRROR[copy][0], sy = (float)MIRROR[copy][1], sz = (float)MIRROR[copy][2];
+  float x = sx * s6[0], y = sy * s6[1], z = sz * s6[2];
+  float px = sx * s6[3], py = sy * s6[4], pz = sz * s6[5];
+  int ix = bin_f(x, (float)O->lo[0], (float)(O->nx / (O->hi[0] - O->lo[0])), O->nx);
+  int iy = bin_f(y, (float)O->lo[1], (float)(O->ny / (O->hi[1] - O->lo[1])), O->ny);
+  int iz = bin_f(z, (float)O->lo[2], (float)(O->nz / (O->hi[2] - O->lo[2])), O->nz);
+  *mcell = (ix < 0 || iy < 0 || iz < 0) ? -1 : (ix * O->ny + iy) * O->nz + iz;
+  float R[9];
+  for (int i = 0; i < 9; ++i) R[i] = (float)O->R[i];
+  float X = R[0] * x + R[1] * y + R[2] * z;
+  float Y = R[3] * x + R[4] * y + R[5] * z;
+  float V = R[6] * px + R[7] * py + R[8] * pz;
+  int jx = bin_f(X, (float)O->plo[0], (float)(O->npx / (O->phi[0] - O->plo[0])), O->npx);
+  int jy = bin_f(Y, (float)O->plo[1], (float)(O->npy / (O->phi[1] - O->plo[1])), O->npy);
+  int kv = bin_f(V, (float)O->vlo, (float)(O->nv / (O->vhi - O->vlo)), O->nv);
+  int ap = -1;
+  if (jx >= 0 && jy >= 0) {
+    int pix = jx * O->npy + jy;
+    ap = O->pix2ap ? O->pix2ap[pix] : pix;
+  }
+  *kcell = (ap < 0 || kv < 0) ? -1 : ap * O->nv + kv;
+}
+
+void orc_bin_points_f64(const orc_obs* O, long n, const double* pts, int32_t* mass, int32_t* kin) {
+  for (long i = 0; i < n; ++i) {
+    double s6[6];
+    for (int j = 0; j < 6; ++j) s6[j] = pts[j * n + i];
+    for (int c = 0; c < 4; ++c) {
+      int m, k;
+      cells_d(O, s6, c, &m, &k);
+      mass[4 * i + c] = m;
+      kin[4 * i + c] = k;
+    }
+  }
+}
+
+void orc_bin_points_f32(const orc_obs* O, long n, const float* pts, int32_t* mass, int32_t* kin) {
+  for (long i = 0; i < n; ++i) {
+    float s6[6];
+    for (int j = 0; j < 6; ++j) s6[j] = pts[j * n + i];
+    for (int c = 0; c < 4; ++c) {
+      int m, k;
+      cells_f(O, s6, c, &m, &k);
+      mass[4 * i + c] = m;
+      kin[4 * i + c] = k;
+    }
+  }
+}
+
+void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics,
+                           const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
+                           double* drift, uint8_t* flags, int nthreads) {
+  int ncon = orc_ncon(O);
+  int nmass = O->nx * O->ny * O->nz;
+  int ncopy = O->symmetrize ? 4 : 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (long i = 0; i < n; ++i) {
+    double s[6];
+    for (int j = 0; j < 6; ++j) s[j] = ics[j * n + i];
+    int32_t* row = counts + i * (long)ncon;
+    memset(row, 0, sizeof(int32_t) * (size_t)ncon);
+    int64_t ovm = 0, ovk = 0;
+    double E0 = orc_jacobi(P, s), dmax = 0.0;
+    int nonfinite = 0;
+    for (int k = 1; k <= nsteps; ++k) {
+      orc_step(P, s, dt[i]);
+      for (int j = 0; j < 6; ++j)
+        if (!isfinite(s[j])) nonfinite = 1;
+      for (int c = 0; c < ncopy; ++c) {
+        int m, kc;
+        cells_d(O, s, c, &m, &kc);
+        if (m >= 0) row[m] += 1; else ovm += 1;
+        if (kc >= 0) row[nmass + kc] += 1; else ovk += 1;
+      }
+      if (O->drift_every > 0 && k % O->drift_every == 0) {
+        double e = fabs(orc_jacobi(P, s) / E0 - 1.0);
+        if (!(e <= dmax)) dmax = e; /* NaN propagates */
+      }
+    }
+    overflow[2 * i] = ovm;
+    overflow[2 * i + 1] = ovk;
+    drift[i] = dmax;
+    uint8_t f = 0;
+    if (!(dmax <= 0.1)) f |= 1;
+    if (nonfinite) f |= 2;
+    flags[i] = f;
+  }
+}
