@@ -1,0 +1,288 @@
+/*
+ * schw.h - C ABI of the MI355X Schwarzschild model-build library (libschw.so).
+ *
+ * The library implements, for one or many trial potentials, the hot path of
+ * Schwarzschild orbit-superposition model construction described in the
+ * SchwarMAX paper (arXiv 2607.00117, Sec. 2):
+ *
+ *   build_potential    Sec. 2.1: analytic density-potential pairs -> derived constants.
+ *   integrate_and_bin  Sec. 2.2.2-2.2.4 and Table 1: integrate the orbit library in
+ *                      the bar's corotating frame, co-add the four mirror copies,
+ *                      project with the Euler rotation of Eq. 1 and bin every step
+ *                      into the orbit matrix (3D mass grid | apertures x LOS-velocity
+ *                      bins), plus the relative Jacobi-energy drift used for the
+ *                      quality cut.
+ *   solve_weights      Sec. 2.3, Eq. 3-4: regularised non-negative least squares for
+ *                      the orbit weights by ADMM (linear solve + clip + dual update).
+ *   chi2               Sec. 2.4, Eq. 5: chi^2 over a constraint range.
+ *
+ * Conventions shared by every entry point
+ *  - Units: kpc, km/s, Msun; G = 4.300917270e-6 kpc (km/s)^2 / Msun; time in
+ *    kpc/(km/s); pattern speed in km/s/kpc; angles in radians.
+ *  - Ownership: the caller owns every buffer.  No entry point allocates or
+ *    frees device memory; scratch space is the caller's `workspace`, whose
+ *    size is given by the matching *_workspace_bytes query.
+ *  - Pointers marked "device" are HIP device pointers on the current device;
+ *    "host" pointers are ordinary host memory.
+ *  - Asynchrony: device work is enqueued on `stream` (a hipStream_t; NULL is
+ *    the default stream).  Entry points that return host results (solve_weights'
+ *    report, chi2's value) synchronise that stream before returning.
+ *  - Errors: every argument is validated on the host before any launch.  A
+ *    negative status is returned on failure and sw_last_error() gives a
+ *    thread-local message.  Non-finite orbit states are not errors: they are
+ *    reported in the per-orbit flags.
+ */
+#ifndef SCHW_H
+#define SCHW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define SW_OK 0
+#define SW_EINVAL (-1)   /* bad argument, shape, or non-finite parameter           */
+#define SW_ENOMEM (-2)   /* workspace smaller than the size query demands          */
+#define SW_EHIP (-3)     /* HIP runtime error; message in sw_last_error()          */
+#define SW_ENOTCONV (-4) /* solve reached its iteration cap; outputs still written */
+
+/* ---- element types ---- */
+#define SW_F32 1
+#define SW_F64 2
+
+/* ---- potential component kinds; parameters p[] in this slot order ---- */
+#define SW_KEPLER 1    /* p0 = M                                                  */
+#define SW_ISOCHRONE 2 /* p0 = M, p1 = b                                          */
+#define SW_PLUMMER 3   /* p0 = M, p1 = b                                          */
+#define SW_MN 4        /* Miyamoto-Nagai (Eq. 10): p0 = M, p1 = a (R_d), p2 = b (H_d) */
+#define SW_NFW_Q 5     /* NFW (Eq. 8-9) with potential flattening q:
+                          p0 = M200, p1 = c, p2 = q, p3 = H0 [km/s/Mpc] (<= 0: 70);
+                          Phi = -G M_DM ln(1 + m/R_s) / m,  m^2 = x^2 + y^2 + z^2/q^2 */
+#define SW_FERRERS2 6  /* Ferrers n = 2 bar, rho = rho_c (1 - m^2)^2:
+                          p0 = M, p1 = a (along bar-frame x), p2 = b (y), p3 = c (z) */
+
+#define SW_MAX_COMP 8
+
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double p[8];
+} sw_component;
+
+/* Sec. 2.1 and Sec. 2.2.2-2.2.3: the trial potential, the bar pattern speed
+ * (rotation about +z, bar major axis on x) and the viewing angles of Eq. 1. */
+typedef struct {
+  int32_t n_comp;
+  int32_t reserved;
+  sw_component comp[SW_MAX_COMP];
+  double omega_b;  /* km/s/kpc */
+  double euler[3]; /* alpha, beta, gamma [rad]; R = R_z(gamma) R_x(beta) R_z(alpha) */
+} sw_potential_desc;
+
+/* Derived constants, plain data copied by value into kernels. */
+typedef struct {
+  uint8_t opaque[2048];
+} sw_potential;
+
+/* Observables (Sec. 2.2.4).  Column order of the orbit matrix:
+ *   [ mass cells (ix*ny + iy)*nz + iz | kinematic cells aperture*nv + v_bin ].
+ * A coordinate v falls in bin floor(t), t = (v - lo) * (n / (hi - lo)) taken in
+ * the integration precision with n / (hi - lo) rounded from double; it is
+ * inside iff 0 <= t < n.  Mass cells use bar-frame (x, y, z); apertures use
+ * sky pixels on (X, Y) = (x', y'); velocity bins use v_los = v_z'. */
+typedef struct {
+  int32_t nx, ny, nz, reserved0;
+  double lo[3], hi[3];
+  int32_t npx, npy;
+  double plo[2], phi[2];
+  const int32_t* pix2ap; /* device [npx*npy]: aperture of each pixel, -1 = unused; NULL = identity */
+  int32_t n_ap;          /* number of apertures (npx*npy when pix2ap is NULL) */
+  int32_t nv;
+  double vlo, vhi;
+  int32_t symmetrize;  /* 1: co-add the four mirror copies of Table 1; 0: orbit alone */
+  int32_t drift_every; /* Jacobi energy sampled every this many steps (0: never) */
+} sw_obs_spec;
+
+/* flags per orbit */
+#define SW_FLAG_DRIFT 1     /* max relative Jacobi drift above the cut (0.1, Sec. 2.2.2) */
+#define SW_FLAG_NONFINITE 2 /* a non-finite state was met                                */
+
+/* ---------------------------------------------------------------------------
+ * build_potential (Sec. 2.1; NFW Eq. 8-9; Miyamoto-Nagai Eq. 10; Eq. 1).
+ * Host only, pure.  Validates the description (kinds, finite positive masses
+ * and scales, q > 0, finite angles and pattern speed) and derives the
+ * constants the kernels use: G M of each component, NFW R_s and M_DM from
+ * (M200, c) with rho_crit = 3 H0^2 / (8 pi G), Ferrers rho_c = 105 M / (32 pi a b c),
+ * the projection matrix of Eq. 1 and the quadrature nodes of the bar.
+ * Returns SW_OK or SW_EINVAL.                                                */
+int build_potential(const sw_potential_desc* in, sw_potential* out);
+
+/* ---------------------------------------------------------------------------
+ * integrate_and_bin (Sec. 2.2.2-2.2.4, Table 1, Eq. 1).
+ * Integrates every orbit for n_steps fixed steps of a kick-drift-kick
+ * leapfrog for H = |p|^2/2 + Phi(x) - Omega L_z in the bar frame (p is the
+ * inertial velocity on the rotating axes), bins the synchronised state after
+ * each step (its four mirror copies when obs->symmetrize) and writes time
+ * fractions: each event weighs 1 / (ncopy * n_steps), ncopy = 4 or 1.
+ *   pots          host [n_pot] built potentials; orbits [offsets[k], offsets[k+1])
+ *                 use pots[k] (n_pot = 1, offsets = {0, n_orb} for one model)
+ *   orbit_offsets host [n_pot + 1], non-decreasing, offsets[0] = 0, offsets[n_pot] = n_orb
+ *   ics           device [6][n_orb] of `dtype`: x, y, z, px, py, pz (bar frame at t = 0)
+ *   dt            device [n_orb] of `dtype`, > 0
+ *   A             device [n_orb][n_con] of `dtype`, n_con = nx*ny*nz + n_ap*nv;
+ *                 row i sums, with overflow[i], to 1 per block
+ *   overflow      device [n_orb][2] double: fraction of events outside the mass
+ *                 grid / outside the apertures or velocity range
+ *   drift         device [n_orb] double: max_k |E_J(t_k)/E_J(0) - 1| over the
+ *                 sampled steps, evaluated in double precision
+ *   flags         device [n_orb] uint8 (SW_FLAG_*)
+ *   workspace     device scratch holding the event stream of the orbits in flight:
+ *                 integrate_workspace_bytes(obs, n_pot, n_orb, n_steps, dtype) bytes
+ *                 process all orbits at once; less (but at least 64 orbits' worth)
+ *                 processes them in chunks
+ * Limits: n_con block sizes < 65535, n_steps >= 1, dtype SW_F32 or SW_F64.   */
+int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const int64_t* orbit_offsets,
+                      const void* ics, const void* dt, int64_t n_orb, int32_t n_steps, int32_t dtype,
+                      const sw_obs_spec* obs, void* A, double* overflow, double* drift, uint8_t* flags,
+                      void* workspace, size_t ws_bytes, void* stream);
+size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t n_orb, int32_t n_steps,
+                                 int32_t dtype);
+
+/* ---------------------------------------------------------------------------
+ * solve_weights (Sec. 2.3, Eq. 3-4).
+ * Minimises  1/2 sum_n ((sum_i w_i A[i][n] - d_n) / sigma_n)^2 + (lambda/N) sum_i (w_i / w_tilde)^2
+ * over w >= 0 (N = number of orbits not masked).  In the scaled variables
+ * U[n][i] = w_tilde A[i][n] / sigma_n, y_n = d_n / sigma_n, w' = w / w_tilde this is
+ * Eq. 4, 1/2 ||U w' - y||^2 + (lambda/N) ||w'||^2.  ADMM splits it into an
+ * unconstrained ridge solve (done in constraint space through the Gram
+ * matrix U U^T, factorised once) and a clip to w >= 0, with the scaled dual
+ * vector carried between iterations (over-relaxed, alpha = 1.6).  A final double-precision stage refines
+ * the ADMM iterates with residuals accumulated in FP64 and reports the KKT
+ * natural residual  ||min(w', g)||_inf / ||U^T y||_inf,  g = U^T (U w' - y) + (2 lambda / N) w'.
+ *   A         device [n_orb][n_con], dtype SW_F32 or SW_F64 (e.g. integrate_and_bin's output)
+ *   d, sigma  device [n_con] double; sigma > 0
+ *   w_tilde   > 0; lambda >= 0 absolute, or < 0 to take 2 lambda / N = opt->nu * mean_i ||U[:, i]||^2
+ *   w         device [n_orb] double, physical weights (masked orbits get 0)
+ *   rep       host, may be NULL
+ * Returns SW_OK, SW_ENOTCONV (cap reached, w still written), SW_EINVAL,
+ * SW_ENOMEM or SW_EHIP.                                                       */
+#define SW_GRAM_BF16 0   /* U rounded to bf16, one MFMA pass, fp32 accumulate         */
+#define SW_GRAM_BF16X3 1 /* U split hi+lo bf16, three MFMA passes, fp32 accumulate    */
+#define SW_GRAM_F32 2    /* fp32 MFMA, fp32 accumulate                                */
+
+typedef struct {
+  int32_t gram;        /* SW_GRAM_* */
+  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 500) */
+  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 300) */
+  int32_t check_every; /* convergence checked every this many iterations (<= 0: 10) */
+  double rho;          /* ADMM penalty for the scaled problem (<= 0: trace(U U^T) / N) */
+  double tol;          /* relative primal/dual tolerance of the FP32 stage (<= 0: 1e-4) */
+  double tol_kkt;      /* target relative KKT residual of the FP64 stage (<= 0: 1e-7) */
+  double nu;           /* relative regularisation used when lambda < 0 */
+  const uint8_t* mask; /* device [n_orb], nonzero = orbit excluded (e.g. flags); may be NULL */
+} sw_solve_opts;
+
+typedef struct {
+  int32_t iters, refine_iters, converged, n_active;
+  double mu;       /* 2 lambda / N in the scaled problem */
+  double rho;      /* ADMM penalty used */
+  double kkt;      /* relative KKT natural residual at return */
+  double objective;/* Eq. 4 in the scaled variables */
+  double primal_res, dual_res;
+  /* GPU time between stage boundaries, HIP events on the solve's stream:
+     prep = scaling + transposed operand, gram = the Gram kernel alone,
+     factor = rho' I + blocked Cholesky, admm = q, Ky and the fp32 iterations,
+     refine = fp64 refinement, KKT evaluations and output */
+  double t_prep_ms, t_gram_ms, t_factor_ms, t_admm_ms, t_refine_ms;
+} sw_solve_report;
+
+int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,
+                  const double* sigma, double w_tilde, double lambda, const sw_solve_opts* opt, double* w,
+                  sw_solve_report* rep, void* workspace, size_t ws_bytes, void* stream);
+size_t solve_workspace_bytes(int64_t n_orb, int64_t n_con, const sw_solve_opts* opt);
+
+/* ---------------------------------------------------------------------------
+ * solve_weights_batched: n_prob independent weight problems of Eq. 4 solved
+ * together (one launch per ADMM operation for all of them), e.g. the trial
+ * potentials of many MCMC walkers.  Problem b owns orbit rows
+ * [orbit_offsets[b], orbit_offsets[b+1]) of A, its data d + b*n_con and
+ * sigma + b*n_con (device [n_prob][n_con] double), equal weight w_tilde[b]
+ * (host), and writes w rows of its orbits.  opt and lambda are shared; a
+ * problem stops iterating when it meets the tolerances.  rep: host [n_prob] or
+ * NULL.  Same status codes as solve_weights (SW_ENOTCONV if any problem did
+ * not converge).  orbit_offsets: host [n_prob + 1], increasing, offsets[0] = 0. */
+int solve_weights_batched(const void* A, int32_t dtype, int32_t n_prob, const int64_t* orbit_offsets,
+                          int64_t n_con, const double* d, const double* sigma, const double* w_tilde, double lambda,
+                          const sw_solve_opts* opt, double* w, sw_solve_report* rep, void* workspace,
+                          size_t ws_bytes, void* stream);
+size_t solve_batched_workspace_bytes(int32_t n_prob, const int64_t* orbit_offsets, int64_t n_con,
+                                     const sw_solve_opts* opt);
+
+/* ---------------------------------------------------------------------------
+ * chi2 (Sec. 2.4, Eq. 5): sum over n in [col_begin, col_end) of
+ * ((sum_i w_i A[i][n] - d_n) / sigma_n)^2, accumulated in double precision.
+ * With the column range of the kinematic block this is chi^2_lum + chi^2_kine
+ * of Eq. 5 (the density block excluded).
+ *   A device [n_orb][n_con] (dtype); w device [n_orb] double; d, sigma device
+ *   [n_con] double; out host double.  workspace >= chi2_workspace_bytes(n_con). */
+int chi2(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, const double* d,
+         const double* sigma, int64_t col_begin, int64_t col_end, double* out, void* workspace,
+         size_t ws_bytes, void* stream);
+size_t chi2_workspace_bytes(int64_t n_con);
+
+/* ---------------------------------------------------------------------------
+ * model_observables: out[n] = sum_i w_i A[i][n] in double precision (the
+ * superposition of Sec. 2.3 for given weights; used to form mock data).
+ *   A device [n_orb][n_con] (dtype), w device [n_orb] double, out device [n_con] double. */
+int model_observables(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, double* out,
+                      void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Test and inspection entry points.
+ * bin_points: bins the four mirror copies of n phase-space points exactly as
+ *   integrate_and_bin does.  pts device [6][n] (dtype); mass, kin device [n][4]
+ *   int32, -1 = outside.  The projection comes from pot (Eq. 1).
+ * integrate_orbits: integrates n orbits for n_steps steps and returns the
+ *   final states only.  ics device [6][n], dt device [n], out device [6][n] (dtype). */
+int bin_points(const sw_potential* pot, const sw_obs_spec* obs, const void* pts, int64_t n, int32_t dtype,
+               int32_t* mass, int32_t* kin, void* stream);
+int integrate_orbits(const sw_potential* pot, const void* ics, const void* dt, int64_t n, int32_t n_steps,
+                     int32_t dtype, void* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned chi^2 surrogate (a screen for delayed-acceptance MCMC; the paper
+ * motivates emulators in Sec. 4.3).  MLP 12 -> 256 -> 256 -> 256 -> 1 with
+ * SiLU hidden activations.  Parameters: device fp32 vector of
+ * mlp_param_count() values packed [W1 (256x12), b1, W2 (256x256), b2,
+ * W3 (256x256), b3, W4 (1x256), b4], weights row-major [out][in].
+ * mlp_forward:   y[B] = f(x[B][12]); keeps the activations in `workspace`
+ *                (>= mlp_workspace_bytes(B)) for mlp_backward.
+ * mlp_backward:  grad = d(sum_b dy[b] y[b]) / dparams for the same x/params
+ *                and workspace as the preceding mlp_forward (fp32).
+ * mlp_adam_step: one Adam update (Kingma & Ba 2015) at step t >= 1, in place on
+ *                params, first/second moments m, v (device fp32 [n]).
+ * mlp_mse_grad:  dy[b] = 2 (y[b] - t[b]) / B, the gradient of the mean squared error.
+ * mlp_pack_bf16: params -> bf16 copy (device, mlp_param_count() bf16 values).
+ * mlp_infer_bf16: fused inference with the bf16 copy, fp32 accumulation.   */
+int64_t mlp_param_count(void);
+size_t mlp_workspace_bytes(int64_t batch);
+int mlp_forward(const float* params, const float* x, int64_t B, float* y, void* workspace, size_t ws_bytes,
+                void* stream);
+int mlp_backward(const float* params, const float* x, int64_t B, const float* dy, float* grad, void* workspace,
+                 size_t ws_bytes, void* stream);
+int mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, int32_t t, float lr, float beta1,
+                  float beta2, float eps, void* stream);
+int mlp_mse_grad(const float* y, const float* t, int64_t B, float* dy, void* stream);
+int mlp_pack_bf16(const float* params, void* packed, void* stream);
+int mlp_infer_bf16(const void* packed, const float* x, int64_t B, float* y, void* stream);
+
+/* Thread-local message describing the last failure of this thread. */
+const char* sw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCHW_H */

@@ -1,0 +1,297 @@
+"""ctypes binding of libschw.so (see include/schw.h for every entry point's contract).
+
+Arguments that are device buffers are passed as torch tensors on the current
+HIP device (their data pointers are handed to the library); the stream is
+torch's current stream.  Nothing here computes: it validates dtypes/shapes
+only as far as needed to pass pointers, and raises SchwError on a non-zero
+status.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SW_F32, SW_F64 = 1, 2
+SW_GRAM_BF16, SW_GRAM_BF16X3, SW_GRAM_F32 = 0, 1, 2
+SW_FLAG_DRIFT, SW_FLAG_NONFINITE = 1, 2
+KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6}
+
+
+class SchwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class Component(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("p", C.c_double * 8)]
+
+
+class PotentialDesc(C.Structure):
+    _fields_ = [("n_comp", C.c_int32), ("reserved", C.c_int32), ("comp", Component * 8),
+                ("omega_b", C.c_double), ("euler", C.c_double * 3)]
+
+
+class Potential(C.Structure):
+    _fields_ = [("opaque", C.c_uint8 * 2048)]
+
+
+class ObsSpec(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved0", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("npx", C.c_int32), ("npy", C.c_int32), ("plo", C.c_double * 2), ("phi", C.c_double * 2),
+                ("pix2ap", C.c_void_p), ("n_ap", C.c_int32), ("nv", C.c_int32),
+                ("vlo", C.c_double), ("vhi", C.c_double),
+                ("symmetrize", C.c_int32), ("drift_every", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("gram", C.c_int32), ("max_iter", C.c_int32), ("refine_iter", C.c_int32),
+                ("check_every", C.c_int32), ("rho", C.c_double), ("tol", C.c_double),
+                ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("refine_iters", C.c_int32), ("converged", C.c_int32),
+                ("n_active", C.c_int32), ("mu", C.c_double), ("rho", C.c_double), ("kkt", C.c_double),
+                ("objective", C.c_double), ("primal_res", C.c_double), ("dual_res", C.c_double),
+                ("t_prep_ms", C.c_double), ("t_gram_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_admm_ms", C.c_double), ("t_refine_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_L = None
+
+
+def library_path():
+    return os.path.join(HERE, "libschw.so")
+
+
+def load():
+    """Loads libschw.so; raises if it has not been built (no fallback)."""
+    global _L
+    if _L is not None:
+        return _L
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2607_00117_amd/build.py "
+                          "(or __graft_entry__.build()); there is no non-HIP fallback")
+    L = C.CDLL(path)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    L.build_potential.argtypes = [C.POINTER(PotentialDesc), C.POINTER(Potential)]
+    L.integrate_and_bin.argtypes = [C.POINTER(Potential), i32, C.POINTER(C.c_int64), vp, vp, i64, i32, i32,
+                                    C.POINTER(ObsSpec), vp, vp, vp, vp, vp, sz, vp]
+    L.integrate_workspace_bytes.argtypes = [C.POINTER(ObsSpec), i32, i64, i32, i32]
+    L.integrate_workspace_bytes.restype = sz
+    L.solve_weights.argtypes = [vp, i32, i64, i64, vp, vp, C.c_double, C.c_double, C.POINTER(SolveOpts), vp,
+                                C.POINTER(SolveReport), vp, sz, vp]
+    L.solve_workspace_bytes.argtypes = [i64, i64, C.POINTER(SolveOpts)]
+    L.solve_workspace_bytes.restype = sz
+    L.solve_weights_batched.argtypes = [vp, i32, i32, C.POINTER(C.c_int64), i64, vp, vp, C.POINTER(C.c_double),
+                                        C.c_double, C.POINTER(SolveOpts), vp, C.POINTER(SolveReport), vp, sz, vp]
+    L.solve_batched_workspace_bytes.argtypes = [i32, C.POINTER(C.c_int64), i64, C.POINTER(SolveOpts)]
+    L.solve_batched_workspace_bytes.restype = sz
+    L.chi2.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp, sz, vp]
+    L.chi2_workspace_bytes.argtypes = [i64]
+    L.chi2_workspace_bytes.restype = sz
+    L.model_observables.argtypes = [vp, i32, i64, i64, vp, vp, vp]
+    L.bin_points.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), vp, i64, i32, vp, vp, vp]
+    L.integrate_orbits.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, i32, vp, vp]
+    L.mlp_param_count.restype = i64
+    L.mlp_workspace_bytes.argtypes = [i64]
+    L.mlp_workspace_bytes.restype = sz
+    L.mlp_forward.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+    L.mlp_backward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
+    L.mlp_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.mlp_pack_bf16.argtypes = [vp, vp, vp]
+    L.mlp_mse_grad.argtypes = [vp, vp, i64, vp, vp]
+    L.mlp_infer_bf16.argtypes = [vp, vp, i64, vp, vp]
+    L.sw_last_error.restype = C.c_char_p
+    _L = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise SchwError(status, load().sw_last_error().decode())
+    return status
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return SW_F32
+    if t.dtype == torch.float64:
+        return SW_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def build_potential(components, omega=0.0, euler=(0.0, 0.0, 0.0)):
+    """components: list of (kind name, params) in the slot order of include/schw.h."""
+    d = PotentialDesc()
+    d.n_comp = len(components)
+    for i, (kind, params) in enumerate(components):
+        d.comp[i].kind = KINDS[kind] if isinstance(kind, str) else int(kind)
+        for j, v in enumerate(params):
+            d.comp[i].p[j] = float(v)
+    d.omega_b = float(omega)
+    for i in range(3):
+        d.euler[i] = float(euler[i])
+    out = Potential()
+    _check(load().build_potential(C.byref(d), C.byref(out)))
+    return out
+
+
+def obs_spec(spec, pix2ap=None):
+    """spec: dict (nx, ny, nz, lo, hi, npx, npy, plo, phi, nv, vlo, vhi, symmetrize, drift_every,
+    n_ap); pix2ap: optional int32 device tensor."""
+    o = ObsSpec()
+    o.nx, o.ny, o.nz = spec["nx"], spec["ny"], spec["nz"]
+    for i in range(3):
+        o.lo[i], o.hi[i] = spec["lo"][i], spec["hi"][i]
+    o.npx, o.npy = spec["npx"], spec["npy"]
+    for i in range(2):
+        o.plo[i], o.phi[i] = spec["plo"][i], spec["phi"][i]
+    if pix2ap is not None:
+        o.pix2ap = pix2ap.data_ptr()
+        o.n_ap = int(spec["n_ap"])
+    else:
+        o.pix2ap = None
+        o.n_ap = spec["npx"] * spec["npy"]
+    o.nv, o.vlo, o.vhi = spec["nv"], spec["vlo"], spec["vhi"]
+    o.symmetrize = int(spec.get("symmetrize", 1))
+    o.drift_every = int(spec.get("drift_every", 1))
+    return o
+
+
+def ncon(obs):
+    return obs.nx * obs.ny * obs.nz + obs.n_ap * obs.nv
+
+
+def _pots_array(pots):
+    if isinstance(pots, Potential):
+        pots = [pots]
+    arr = (Potential * len(pots))(*pots)
+    return arr, len(pots)
+
+
+def integrate_workspace_bytes(obs, n_pot, n_orb, n_steps, dtype):
+    return load().integrate_workspace_bytes(C.byref(obs), n_pot, n_orb, n_steps, dtype)
+
+
+def integrate_and_bin(pots, offsets, ics, dt, n_steps, obs, A, overflow, drift, flags, workspace):
+    arr, n_pot = _pots_array(pots)
+    offs = (C.c_int64 * (n_pot + 1))(*[int(v) for v in offsets])
+    n_orb = ics.shape[1]
+    _check(load().integrate_and_bin(arr, n_pot, offs, _ptr(ics), _ptr(dt), n_orb, int(n_steps),
+                                    _dtype_code(ics), C.byref(obs), _ptr(A), _ptr(overflow), _ptr(drift),
+                                    _ptr(flags), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                    _stream()))
+
+
+def solve_workspace_bytes(n_orb, n_con, opts):
+    return load().solve_workspace_bytes(n_orb, n_con, C.byref(opts))
+
+
+def solve_weights(A, d, sigma, w_tilde, lam, opts, w, workspace):
+    rep = SolveReport()
+    n_orb, n_con = A.shape
+    st = load().solve_weights(_ptr(A), _dtype_code(A), n_orb, n_con, _ptr(d), _ptr(sigma), float(w_tilde),
+                              float(lam), C.byref(opts), _ptr(w), C.byref(rep), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream())
+    if st not in (0, -4):
+        _check(st)
+    return st, rep
+
+
+def solve_batched_workspace_bytes(offsets, n_con, opts):
+    offs = (C.c_int64 * len(offsets))(*[int(v) for v in offsets])
+    return load().solve_batched_workspace_bytes(len(offsets) - 1, offs, n_con, C.byref(opts))
+
+
+def solve_weights_batched(A, offsets, d, sigma, w_tilde, lam, opts, w, workspace):
+    """d, sigma: device [n_prob][n_con]; w_tilde: sequence of n_prob floats."""
+    n_prob = len(offsets) - 1
+    offs = (C.c_int64 * (n_prob + 1))(*[int(v) for v in offsets])
+    wt = (C.c_double * n_prob)(*[float(v) for v in w_tilde])
+    reps = (SolveReport * n_prob)()
+    st = load().solve_weights_batched(_ptr(A), _dtype_code(A), n_prob, offs, A.shape[1], _ptr(d), _ptr(sigma), wt,
+                                      float(lam), C.byref(opts), _ptr(w), reps, _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream())
+    if st not in (0, -4):
+        _check(st)
+    return st, list(reps)
+
+
+def chi2_workspace_bytes(n_con):
+    return load().chi2_workspace_bytes(n_con)
+
+
+def chi2(A, w, d, sigma, col_begin, col_end, workspace):
+    out = C.c_double(0.0)
+    n_orb, n_con = A.shape
+    _check(load().chi2(_ptr(A), _dtype_code(A), n_orb, n_con, _ptr(w), _ptr(d), _ptr(sigma), int(col_begin),
+                       int(col_end), C.byref(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                       _stream()))
+    return out.value
+
+
+def model_observables(A, w, out):
+    n_orb, n_con = A.shape
+    _check(load().model_observables(_ptr(A), _dtype_code(A), n_orb, n_con, _ptr(w), _ptr(out), _stream()))
+
+
+def bin_points(pot, obs, pts, mass, kin):
+    _check(load().bin_points(C.byref(pot), C.byref(obs), _ptr(pts), pts.shape[1], _dtype_code(pts), _ptr(mass),
+                             _ptr(kin), _stream()))
+
+
+def integrate_orbits(pot, ics, dt, n_steps, out):
+    _check(load().integrate_orbits(C.byref(pot), _ptr(ics), _ptr(dt), ics.shape[1], int(n_steps),
+                                   _dtype_code(ics), _ptr(out), _stream()))
+
+
+def mlp_param_count():
+    return load().mlp_param_count()
+
+
+def mlp_workspace_bytes(batch):
+    return load().mlp_workspace_bytes(batch)
+
+
+def mlp_forward(params, x, y, workspace):
+    _check(load().mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(y), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream()))
+
+
+def mlp_backward(params, x, dy, grad, workspace):
+    _check(load().mlp_backward(_ptr(params), _ptr(x), x.shape[0], _ptr(dy), _ptr(grad), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream()))
+
+
+def mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load().mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(t), lr, beta1, beta2,
+                                eps, _stream()))
+
+
+def mlp_pack_bf16(params, packed):
+    _check(load().mlp_pack_bf16(_ptr(params), _ptr(packed), _stream()))
+
+
+def mlp_infer_bf16(packed, x, y):
+    _check(load().mlp_infer_bf16(_ptr(packed), _ptr(x), x.shape[0], _ptr(y), _stream()))
+
+
+def mlp_mse_grad(y, t, dy):
+    _check(load().mlp_mse_grad(_ptr(y), _ptr(t), y.shape[0], _ptr(dy), _stream()))

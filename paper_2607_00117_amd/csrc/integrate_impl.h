@@ -1,0 +1,187 @@
+// Orbit integration kernel (Sec. 2.2.2-2.2.4), templated on the working
+// precision.  One orbit per lane.  Each lane integrates its orbit with a
+// kick-drift-kick leapfrog in the corotating bar frame, keeps the force of the
+// last kick for the next step's first kick, bins the four mirror copies of
+// every synchronised state and stages the packed cell indices of
+// kStage steps in LDS.  The wave then writes each orbit's staged steps as one
+// contiguous 128-byte segment of that orbit's event stream, so the stream is
+// written with full-line stores although each lane owns a different orbit.
+//
+// Event word (uint64, one per orbit per step per block): four 16-bit cell
+// indices, copy c in bits [16c, 16c+16), 0xFFFF = outside the block.
+#pragma once
+#include "potential.h"
+
+namespace sw {
+
+constexpr int kStage = 16;
+constexpr int kWave = 64;
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<float> {
+  __device__ static void accel(const PotK& P, const float* s, float* g) { accel_f32(P, s[0], s[1], s[2], g[0], g[1], g[2]); }
+};
+template <>
+struct Prec<double> {
+  __device__ static void accel(const PotK& P, const double* s, double* g) { accel_f64(P, s, g); }
+};
+
+__device__ __forceinline__ uint64_t pack4(const int* c) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v |= (uint64_t)(uint16_t)(c[i] < 0 ? 0xFFFF : c[i]) << (16 * i);
+  return v;
+}
+
+// Potential index of orbit o: the last k with offsets[k] <= o.
+__device__ __forceinline__ int pot_index(const int64_t* offsets, int n_pot, int64_t o) {
+  int lo = 0, hi = n_pot - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, bool BATCHED, bool BIN>
+__global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_potential* __restrict__ pots,
+                                                    const int64_t* __restrict__ offsets, int32_t n_pot, ObsK O,
+                                                    const T* __restrict__ ics, const T* __restrict__ dts,
+                                                    int64_t n_orb, int64_t orb0, int64_t n_chunk, int32_t n_steps,
+                                                    uint64_t* __restrict__ ev_m, uint64_t* __restrict__ ev_k,
+                                                    double* __restrict__ drift, uint8_t* __restrict__ flags,
+                                                    T* __restrict__ final_state) {
+  __shared__ uint64_t stm[kStage][kWave + 1];
+  __shared__ uint64_t stk[kStage][kWave + 1];
+  const int lane = threadIdx.x;
+  const int64_t jbase = (int64_t)blockIdx.x * kWave;  // chunk-local index of lane 0
+  const int64_t j = jbase + lane;
+  const bool valid = j < n_chunk;
+  const int64_t o = orb0 + (valid ? j : n_chunk - 1);
+  const int kpot = BATCHED ? pot_index(offsets, n_pot, o) : 0;
+  const PotK& P = BATCHED ? *reinterpret_cast<const PotK*>(pots + kpot) : p0;
+
+  T s[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s[i] = ics[(int64_t)i * n_orb + o];
+  const T dt = dts[o];
+  const T h = T(0.5) * dt;
+  const double th = P.omega * (double)dt;
+  const T c = (T)cos(th), sn = (T)sin(th);
+
+  double sd[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
+  const double E0 = jacobi_f64(P, sd);
+  double dmax = 0.0;
+  const int de = O.drift_every;
+
+  T g[3];
+  Prec<T>::accel(P, s, g);
+  int slot = 0;
+  for (int k = 1; k <= n_steps; ++k) {
+    s[3] = s[3] + h * g[0];
+    s[4] = s[4] + h * g[1];
+    s[5] = s[5] + h * g[2];
+    s[0] = s[0] + dt * s[3];
+    s[1] = s[1] + dt * s[4];
+    s[2] = s[2] + dt * s[5];
+    {
+      T x = c * s[0] + sn * s[1];
+      T y = c * s[1] - sn * s[0];
+      T px = c * s[3] + sn * s[4];
+      T py = c * s[4] - sn * s[3];
+      s[0] = x; s[1] = y; s[3] = px; s[4] = py;
+    }
+    Prec<T>::accel(P, s, g);
+    s[3] = s[3] + h * g[0];
+    s[4] = s[4] + h * g[1];
+    s[5] = s[5] + h * g[2];
+
+    if (de > 0 && k % de == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
+      double e = fabs(jacobi_f64(P, sd) / E0 - 1.0);
+      if (!(e <= dmax)) dmax = e;
+    }
+    if constexpr (BIN) {
+      int mc[4], kc[4];
+      cells4<T>(P, O, s, mc, kc);
+      stm[slot][lane] = pack4(mc);
+      stk[slot][lane] = pack4(kc);
+      ++slot;
+      if (slot == kStage || k == n_steps) {
+        __syncthreads();
+        const int64_t step0 = k - slot;
+        const int total = slot * kWave;
+        for (int idx = lane; idx < total; idx += kWave) {
+          const int jj = idx / slot, ss = idx - jj * slot;
+          const int64_t jo = jbase + jj;
+          if (jo < n_chunk) {
+            const int64_t at = jo * n_steps + step0 + ss;
+            ev_m[at] = stm[ss][jj];
+            ev_k[at] = stk[ss][jj];
+          }
+        }
+        __syncthreads();
+        slot = 0;
+      }
+    }
+  }
+  if (valid) {
+    bool nonfinite = false;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) nonfinite |= !isfinite(s[i]);
+    if (drift) drift[o] = dmax;
+    if (flags) flags[o] = (uint8_t)((!(dmax <= 0.1) ? SW_FLAG_DRIFT : 0) | (nonfinite ? SW_FLAG_NONFINITE : 0));
+    if constexpr (!BIN) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) final_state[(int64_t)i * n_orb + o] = s[i];
+    }
+  }
+}
+
+struct IntegrateLaunch {
+  PotK p0;                     // the potential when n_pot == 1
+  const sw_potential* pots_dev;  // device copies when n_pot > 1
+  const int64_t* offsets_dev;
+  int32_t n_pot;
+  ObsK obs;
+  const void* ics;
+  const void* dt;
+  int64_t n_orb, orb0, n_chunk;
+  int32_t n_steps;
+  uint64_t* ev_m;
+  uint64_t* ev_k;
+  double* drift;
+  uint8_t* flags;
+  void* final_state;
+  bool bin;
+};
+
+template <typename T>
+hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
+  dim3 grid((unsigned)((L.n_chunk + kWave - 1) / kWave)), block(kWave);
+  const T* ics = (const T*)L.ics;
+  const T* dt = (const T*)L.dt;
+  T* fs = (T*)L.final_state;
+  if (L.bin) {
+    if (L.n_pot > 1)
+      hipLaunchKernelGGL((k_integrate<T, true, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev, L.n_pot, L.obs,
+                         ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift, L.flags, fs);
+    else
+      hipLaunchKernelGGL((k_integrate<T, false, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev, L.n_pot, L.obs,
+                         ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift, L.flags, fs);
+  } else {
+    hipLaunchKernelGGL((k_integrate<T, false, false>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev, L.n_pot, L.obs,
+                       ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift, L.flags, fs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate_f32(const IntegrateLaunch& L, hipStream_t st);
+hipError_t launch_integrate_f64(const IntegrateLaunch& L, hipStream_t st);
+
+}  // namespace sw

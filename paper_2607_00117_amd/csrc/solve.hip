@@ -1,0 +1,929 @@
+// solve_weights(_batched), chi2 and model_observables (Sec. 2.3-2.4, Eq. 3-5).
+//
+// Scaled problem (Eq. 4): U[n][i] = w~ A[i][n] / sigma_n, y_n = d_n / sigma_n,
+// minimise 1/2 ||U w' - y||^2 + (mu/2) ||w'||^2, w' >= 0, mu = 2 lambda / N.
+//
+// ADMM with the splitting x = z (Sec. 2.3): the x-update is the ridge solve
+//   (U^T U + rho' I) x = q + rho (z - u),  q = U^T y,  rho' = rho + mu,
+// done in constraint space with the Woodbury identity
+//   x = (1/rho') (b - U^T (rho' I + U U^T)^{-1} U b),
+// where U U^T is formed once by the MFMA Gram kernel and factorised once by
+// the blocked Cholesky; the z-update clips to w >= 0 (over-relaxed) and u
+// carries the scaled dual.  Every pass over U streams A itself (orbit-major)
+// with the scaling folded into per-constraint multipliers:
+//   column sums   t_n = (w~/sigma_n) sum_i A[i][n] v_i       (U v)
+//   row dots      h_i = sum_n A[i][n] (w~ s_n / sigma_n)     (U^T s)
+// both accumulated in double precision.
+//
+// Stage 1 keeps the iterates in fp32 and uses the factor of the (bf16 or fp32)
+// Gram directly.  Stage 2 (refinement) keeps them in fp64 and makes each
+// x-update exact up to the preconditioner's contraction: the residual of the
+// ridge system is formed with fp64-accumulated passes over A and corrected
+// with one application of the Woodbury preconditioner.  The KKT natural
+// residual of the true problem is evaluated in fp64.
+//
+// A batch of independent problems (e.g. many walkers' trial potentials) is
+// solved together: the orbits of problem b are rows [off[b], off[b+1]) of A,
+// every kernel launch covers all problems, and a problem that has converged
+// is frozen by a per-problem flag while the others continue.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gemm.h"
+
+namespace sw {
+
+constexpr int kRowsBlock = 256;   // row-dot workgroup: 4 waves, one row per wave
+constexpr int kColThreads = 256;
+constexpr int kColsPerThread = 4;
+constexpr int kColTile = kColThreads * kColsPerThread;
+constexpr int kSlabs = 256;       // orbit slabs per problem in the column-sum reduction
+constexpr int kPar = 8;           // per-problem scalars: wt, rho, rho', mu, alpha, active
+constexpr int kAcc = 16;          // per-problem accumulators
+
+static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// last b with off[b] <= i
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ off, int n, int64_t i) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// X[n][xoff_b + j] = w~_b A[off_b + j][n] / sigma_b,n (zero-padded, masked
+// orbits zero): constraint-major operand of the Gram.  64 x 64 LDS tiles.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_t C, int64_t Npt,
+                                                const int64_t* __restrict__ off, const int64_t* __restrict__ xoff,
+                                                int nprob, const double* __restrict__ sigma,
+                                                const double* __restrict__ par, const uint8_t* __restrict__ mask,
+                                                int mode, __bf16* __restrict__ hi, __bf16* __restrict__ lo,
+                                                float* __restrict__ xf) {
+  __shared__ float tile[64][65];
+  const int64_t n0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int b = find_problem(xoff, nprob, c0);
+  const int64_t nb = off[b + 1] - off[b];
+  const double wt = par[b * kPar + 0];
+  const double* sg = sigma + (int64_t)b * C;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t j = c0 - xoff[b] + r, n = n0 + tx;
+    float v = 0.0f;
+    if (j < nb && n < C) {
+      const int64_t i = off[b] + j;
+      if (!(mask && mask[i])) v = (float)((double)A[i * C + n] * (wt / sg[n]));
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t n = n0 + r, col = c0 + tx;
+    const float v = tile[tx][r];
+    const int64_t at = n * Npt + col;
+    if (mode == SW_GRAM_F32) {
+      xf[at] = v;
+    } else {
+      const __bf16 h = (__bf16)v;
+      hi[at] = h;
+      if (mode == SW_GRAM_BF16X3) lo[at] = (__bf16)(v - (float)h);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column sums over orbit slabs: part[b][s][n] = sum_{i in slab s of b} A[i][n] v_i.
+// ---------------------------------------------------------------------------
+template <typename TA, typename TV>
+__global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A, int64_t C,
+                                                        const TV* __restrict__ v, const int64_t* __restrict__ off,
+                                                        const int64_t* __restrict__ rps, double* __restrict__ part) {
+  const int b = blockIdx.z;
+  const int64_t c0 = (int64_t)blockIdx.x * kColTile;
+  const int64_t s = blockIdx.y;
+  const int64_t i_beg = off[b] + s * rps[b];
+  int64_t i_end = i_beg + rps[b];
+  if (i_end > off[b + 1]) i_end = off[b + 1];
+  double acc[kColsPerThread] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = i_beg; i < i_end; ++i) {
+    const double vi = (double)v[i];
+    if (vi == 0.0) continue;
+    const TA* row = A + i * C;
+#pragma unroll
+    for (int k = 0; k < kColsPerThread; ++k) {
+      const int64_t c = c0 + threadIdx.x + k * kColThreads;
+      if (c < C) acc[k] += (double)row[c] * vi;
+    }
+  }
+  double* pb = part + ((int64_t)b * kSlabs + s) * C;
+#pragma unroll
+  for (int k = 0; k < kColsPerThread; ++k) {
+    const int64_t c = c0 + threadIdx.x + k * kColThreads;
+    if (c < C) pb[c] = acc[k];
+  }
+}
+
+enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
+
+// t_n = (w~/sigma_n) sum_s part[b][s][n] (COL_OBS: no scaling), per problem b = blockIdx.y:
+//  COL_PLAIN: outd = t, outf = (float) t
+//  COL_ADMM:  outf = (float)(kyf + rho t)
+//  COL_RESID: outd = t - y,  acc[b][9] += (t - y)^2
+//  COL_OBS:   outd = t
+// Vectors are [nprob][Cp]; entries in [C, Cp) are written as 0.
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int64_t C, int64_t Cp,
+                                                   const double* __restrict__ sigma, const double* __restrict__ par,
+                                                   int op, const float* __restrict__ kyf, const double* __restrict__ y,
+                                                   float* __restrict__ outf, double* __restrict__ outd,
+                                                   double* __restrict__ acc) {
+  const int b = blockIdx.y;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double wt = par[b * kPar + 0], rho = par[b * kPar + 1];
+  const int64_t vb = (int64_t)b * Cp;
+  double contrib = 0.0;
+  if (n < Cp) {
+    double t = 0.0;
+    if (n < C) {
+      const double* pb = part + (int64_t)b * kSlabs * C;
+      for (int64_t s = 0; s < kSlabs; ++s) t += pb[s * C + n];
+      if (op != COL_OBS) t *= wt / sigma[(int64_t)b * C + n];
+    }
+    switch (op) {
+      case COL_PLAIN:
+        if (outd) outd[vb + n] = t;
+        if (outf) outf[vb + n] = (float)t;
+        break;
+      case COL_ADMM:
+        outf[vb + n] = (n < C) ? (float)((double)kyf[vb + n] + rho * t) : 0.0f;
+        break;
+      case COL_RESID: {
+        const double e = (n < C) ? t - y[vb + n] : 0.0;
+        outd[vb + n] = e;
+        contrib = e * e;
+        break;
+      }
+      case COL_OBS:
+        if (n < C) outd[vb + n] = t;
+        break;
+    }
+  }
+  if (op == COL_RESID && acc) {
+    __shared__ double red[256];
+    red[threadIdx.x] = contrib;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(&acc[b * kAcc + 9], red[0]);
+  }
+}
+
+// sc[b][n] = w~_b s[b][n] / sigma[b][n]: the multiplier of column n in a row dot
+template <typename TS>
+__global__ void k_colscale(const TS* __restrict__ s, int64_t C, int64_t Cp, const double* __restrict__ sigma,
+                           const double* __restrict__ par, double* __restrict__ sc) {
+  const int b = blockIdx.y;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < C) sc[(int64_t)b * Cp + n] = par[b * kPar + 0] * (double)s[(int64_t)b * Cp + n] / sigma[(int64_t)b * C + n];
+}
+
+// y[b][n] = d[b][n] / sigma[b][n] (zero padded to Cp)
+__global__ void k_scaled_data(const double* __restrict__ d, const double* __restrict__ sigma, int64_t C, int64_t Cp,
+                              double* __restrict__ y) {
+  const int b = blockIdx.y;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < Cp) y[(int64_t)b * Cp + n] = n < C ? d[(int64_t)b * C + n] / sigma[(int64_t)b * C + n] : 0.0;
+}
+
+enum RowOp { ROW_Q = 0, ROW_ADMM = 1, ROW_H = 2, ROW_CORR = 3, ROW_KKT = 4 };
+
+struct RowArgs {
+  int op;
+  int nprob;
+  int64_t Cp;
+  const int64_t* off;
+  const double* par;
+  const uint8_t* mask;
+  // fp32 stage
+  float* qf; float* zf; float* uf; float* vf;
+  // fp64 stage
+  double* qd; double* xd; double* zd; double* ud; double* vd; double* rd;
+  double* acc;  // per problem [kAcc]: 0 |x-z|^2, 1 |z-zold|^2, 2 |x|^2, 3 |z|^2, 4 |u|^2, 5 max|q|, 6 kkt max, 7 |z|^2, 9 |e|^2
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void atomic_max_pos(double* a, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
+}
+
+// One wave per orbit row: dot = sum_n A[i][n] sc[b][n], then the row's update.
+template <typename TA>
+__global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A, int64_t N, int64_t C,
+                                                       const double* __restrict__ sc, RowArgs R) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * (kRowsBlock / 64) + w;
+  if (i >= N) return;
+  const int b = find_problem(R.off, R.nprob, i);
+  const double* P = R.par + b * kPar;
+  if (P[5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
+  const TA* row = A + i * C;
+  const double* scb = sc + (int64_t)b * R.Cp;
+  double dot = 0.0;
+  for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
+  dot = wave_sum(dot);
+  if (lane != 0) return;
+  const bool masked = R.mask && R.mask[i];
+  const double rho = P[1], rhop = P[2], mu = P[3], alpha = P[4];
+  double* acc = R.acc ? R.acc + b * kAcc : nullptr;
+  switch (R.op) {
+    case ROW_Q: {
+      const double q = masked ? 0.0 : dot;
+      R.qd[i] = q;
+      R.qf[i] = (float)q;
+      if (acc && q != 0.0) atomic_max_pos(&acc[5], fabs(q));
+      break;
+    }
+    case ROW_ADMM: {
+      const double z0 = R.zf[i], u0 = R.uf[i];
+      const double x = masked ? 0.0 : ((double)R.qf[i] + rho * (double)R.vf[i] - dot) / rhop;
+      const double xh = alpha * x + (1.0 - alpha) * z0;
+      const double z = masked ? 0.0 : fmax(0.0, xh + u0);
+      const double u = masked ? 0.0 : u0 + xh - z;
+      R.zf[i] = (float)z;
+      R.uf[i] = (float)u;
+      R.vf[i] = (float)(z - u);
+      if (acc) {
+        atomicAdd(&acc[0], (x - z) * (x - z));
+        atomicAdd(&acc[1], (z - z0) * (z - z0));
+        atomicAdd(&acc[2], x * x);
+        atomicAdd(&acc[3], z * z);
+        atomicAdd(&acc[4], u * u);
+      }
+      break;
+    }
+    case ROW_H: {
+      const double bb = R.qd[i] + rho * R.vd[i];
+      R.rd[i] = masked ? 0.0 : bb - dot - rhop * R.xd[i];
+      break;
+    }
+    case ROW_CORR: {
+      const double z0 = R.zd[i], u0 = R.ud[i];
+      const double x = masked ? 0.0 : R.xd[i] + (R.rd[i] - dot) / rhop;
+      const double xh = alpha * x + (1.0 - alpha) * z0;
+      const double z = masked ? 0.0 : fmax(0.0, xh + u0);
+      const double u = masked ? 0.0 : u0 + xh - z;
+      R.xd[i] = x;
+      R.zd[i] = z;
+      R.ud[i] = u;
+      R.vd[i] = z - u;
+      break;
+    }
+    case ROW_KKT: {
+      const double z = R.zd[i];
+      const double g = dot + mu * z;
+      const double k = masked ? 0.0 : fabs(fmin(z, g));
+      if (acc) {
+        if (k > 0.0) atomic_max_pos(&acc[6], k);
+        if (z != 0.0) atomicAdd(&acc[7], z * z);
+      }
+      break;
+    }
+  }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Sum of the first C diagonal entries of K_b, one block per problem, fixed order.
+__global__ void k_trace(const float* __restrict__ K, int64_t ld, int64_t sK, int64_t C, double* __restrict__ out) {
+  __shared__ double red[256];
+  const float* Kb = K + blockIdx.x * sK;
+  double s = 0.0;
+  for (int64_t n = threadIdx.x; n < C; n += 256) s += (double)Kb[n * ld + n];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void k_add_diag(float* __restrict__ K, int64_t ld, int64_t sK, int64_t n, const double* __restrict__ par) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) K[blockIdx.y * sK + i * ld + i] += (float)par[blockIdx.y * kPar + 2];
+}
+
+template <typename TS, typename TD>
+__global__ void k_cast(const TS* __restrict__ s, TD* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (TD)s[i];
+}
+
+__global__ void k_scale_out(const double* __restrict__ z, int64_t N, const int64_t* __restrict__ off, int nprob,
+                            const double* __restrict__ par, double* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) w[i] = par[find_problem(off, nprob, i) * kPar + 0] * z[i];
+}
+
+// chi^2 over [cb, ce): one block, fixed summation order.
+__global__ void k_chi2_final(const double* __restrict__ m, const double* __restrict__ d,
+                             const double* __restrict__ sigma, int64_t cb, int64_t ce, double* __restrict__ out) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int64_t n = cb + threadIdx.x; n < ce; n += 1024) {
+    const double r = (m[n] - d[n]) / sigma[n];
+    s += r * r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+static unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Workspace layout.
+// ---------------------------------------------------------------------------
+struct SolveLayout {
+  int P;
+  int64_t N, C, Cp, Npt;
+  std::vector<int64_t> off, xoff, xlen, rps;
+  size_t off_hi, off_lo, off_xf, off_K, off_dinv, off_part;
+  size_t off_qf, off_zf, off_uf, off_vf;
+  size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
+  size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
+  size_t off_par, off_acc, off_idx, off_bad, total;
+};
+
+static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
+  SolveLayout L;
+  L.P = P;
+  L.C = C;
+  L.Cp = (C + kNB - 1) / kNB * kNB;
+  L.off.assign(off, off + P + 1);
+  L.N = off[P];
+  L.Npt = 0;
+  for (int b = 0; b < P; ++b) {
+    const int64_t nb = off[b + 1] - off[b];
+    L.xoff.push_back(L.Npt);
+    L.xlen.push_back((nb + 63) / 64 * 64);
+    L.rps.push_back(nb > 0 ? (nb + kSlabs - 1) / kSlabs : 1);
+    L.Npt += L.xlen.back();
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += a256(bytes); return at; };
+  const size_t xe = (size_t)L.Cp * L.Npt;
+  const size_t N = (size_t)L.N, VP = (size_t)P * L.Cp;
+  L.off_hi = take(gram_mode == SW_GRAM_F32 ? 0 : xe * 2);
+  L.off_lo = take(gram_mode == SW_GRAM_BF16X3 ? xe * 2 : 0);
+  L.off_xf = take(gram_mode == SW_GRAM_F32 ? xe * 4 : 0);
+  L.off_K = take((size_t)P * L.Cp * L.Cp * 4);
+  L.off_dinv = take((size_t)P * L.Cp * kNB * 4);
+  L.off_part = take((size_t)P * kSlabs * L.C * 8);
+  L.off_qf = take(N * 4); L.off_zf = take(N * 4); L.off_uf = take(N * 4); L.off_vf = take(N * 4);
+  L.off_qd = take(N * 8); L.off_xd = take(N * 8); L.off_zd = take(N * 8); L.off_ud = take(N * 8);
+  L.off_vd = take(N * 8); L.off_rd = take(N * 8);
+  L.off_kyf = take(VP * 4); L.off_r = take(VP * 4); L.off_tmp = take(VP * 4); L.off_s = take(VP * 4);
+  L.off_sc = take(VP * 8); L.off_td = take(VP * 8); L.off_ys = take(VP * 8);
+  L.off_par = take((size_t)P * kPar * 8);
+  L.off_acc = take((size_t)P * kAcc * 8);
+  L.off_idx = take((size_t)(P + 1) * 8 * 4);
+  L.off_bad = take(64);
+  L.total = o;
+  return L;
+}
+
+struct Ctx {
+  SolveLayout L;
+  char* ws;
+  hipStream_t st;
+  const void* A;
+  int dtype;
+  const double* sigma;
+  const int64_t *off_d, *xoff_d, *xlen_d, *rps_d;
+  double* par;
+  template <typename T> T* p(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+};
+
+template <typename TV>
+static hipError_t colsum(const Ctx& X, const TV* v) {
+  dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
+  if (X.dtype == SW_F32)
+    hipLaunchKernelGGL((k_colsum<float, TV>), grid, dim3(kColThreads), 0, X.st, (const float*)X.A, X.L.C, v, X.off_d,
+                       X.rps_d, X.p<double>(X.L.off_part));
+  else
+    hipLaunchKernelGGL((k_colsum<double, TV>), grid, dim3(kColThreads), 0, X.st, (const double*)X.A, X.L.C, v,
+                       X.off_d, X.rps_d, X.p<double>(X.L.off_part));
+  return hipGetLastError();
+}
+
+static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
+  hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
+                     X.p<double>(X.L.off_part), X.L.C, X.L.Cp, X.sigma, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
+                     outd, acc);
+  return hipGetLastError();
+}
+
+static hipError_t rowdot(const Ctx& X, const RowArgs& R) {
+  dim3 grid((unsigned)((X.L.N + 3) / 4));
+  if (X.dtype == SW_F32)
+    hipLaunchKernelGGL(k_rowdot<float>, grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C,
+                       X.p<double>(X.L.off_sc), R);
+  else
+    hipLaunchKernelGGL(k_rowdot<double>, grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
+                       X.p<double>(X.L.off_sc), R);
+  return hipGetLastError();
+}
+
+template <typename TS>
+static hipError_t colscale(const Ctx& X, const TS* s) {
+  hipLaunchKernelGGL(k_colscale<TS>, dim3(blocks_for(X.L.C), (unsigned)X.L.P), dim3(256), 0, X.st, s, X.L.C, X.L.Cp,
+                     X.sigma, X.par, X.p<double>(X.L.off_sc));
+  return hipGetLastError();
+}
+
+static hipError_t zero_acc(const Ctx& X) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for((int64_t)X.L.P * kAcc)), dim3(256), 0, X.st,
+                     X.p<double>(X.L.off_acc), (int64_t)X.L.P * kAcc, 0.0);
+  return hipGetLastError();
+}
+
+}  // namespace sw
+
+using namespace sw;
+
+#define SW_TRY(expr)                                      \
+  do {                                                    \
+    hipError_t e__ = (expr);                              \
+    if (e__ != hipSuccess) return hip_fail(e__, #expr);   \
+  } while (0)
+
+extern "C" size_t solve_batched_workspace_bytes(int32_t n_prob, const int64_t* orbit_offsets, int64_t n_con,
+                                                const sw_solve_opts* opt) {
+  if (n_prob < 1 || !orbit_offsets || n_con <= 0) return 0;
+  const int mode = opt ? opt->gram : SW_GRAM_BF16X3;
+  return layout(n_prob, orbit_offsets, n_con, mode).total;
+}
+
+extern "C" size_t solve_workspace_bytes(int64_t n_orb, int64_t n_con, const sw_solve_opts* opt) {
+  if (n_orb <= 0 || n_con <= 0) return 0;
+  const int64_t off[2] = {0, n_orb};
+  return solve_batched_workspace_bytes(1, off, n_con, opt);
+}
+
+extern "C" size_t chi2_workspace_bytes(int64_t n_con) {
+  if (n_con <= 0) return 0;
+  return a256((size_t)kSlabs * n_con * 8) + a256((size_t)n_con * 8) + 256;
+}
+
+extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_prob, const int64_t* orbit_offsets,
+                                     int64_t n_con, const double* d, const double* sigma, const double* w_tilde,
+                                     double lambda, const sw_solve_opts* opt, double* w, sw_solve_report* rep,
+                                     void* workspace, size_t ws_bytes, void* stream) {
+  SW_CHECK(opt && orbit_offsets && w_tilde, "solve_weights: null argument");
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "solve_weights: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_prob >= 1 && n_con > 0, "solve_weights: need n_prob >= 1 and n_con > 0");
+  SW_CHECK(orbit_offsets[0] == 0, "solve_weights: orbit_offsets[0] must be 0");
+  for (int b = 0; b < n_prob; ++b) {
+    SW_CHECK(orbit_offsets[b + 1] > orbit_offsets[b], "solve_weights: every problem needs at least one orbit");
+    SW_CHECK(std::isfinite(w_tilde[b]) && w_tilde[b] > 0.0, "solve_weights: w_tilde must be finite and > 0");
+  }
+  SW_CHECK(std::isfinite(lambda), "solve_weights: lambda must be finite");
+  SW_CHECK(lambda >= 0.0 || (std::isfinite(opt->nu) && opt->nu > 0.0),
+           "solve_weights: lambda < 0 needs opt->nu > 0");
+  SW_CHECK(opt->gram == SW_GRAM_BF16 || opt->gram == SW_GRAM_BF16X3 || opt->gram == SW_GRAM_F32,
+           "solve_weights: unknown gram mode %d", opt->gram);
+  SW_CHECK(A && d && sigma && w, "solve_weights: null device buffer");
+  SW_CHECK(workspace, "solve_weights: null workspace");
+  const size_t need = solve_batched_workspace_bytes(n_prob, orbit_offsets, n_con, opt);
+  if (ws_bytes < need) {
+    set_error("solve_weights: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return SW_ENOMEM;
+  }
+  const int max_iter = opt->max_iter > 0 ? opt->max_iter : 500;
+  const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 300 : opt->refine_iter);
+  const int check_every = opt->check_every > 0 ? opt->check_every : 10;
+  const double tol = opt->tol > 0.0 ? opt->tol : 1e-4;
+  const double tol_kkt = opt->tol_kkt > 0.0 ? opt->tol_kkt : 1e-7;
+  const int P = n_prob;
+
+  Ctx X;
+  X.L = layout(P, orbit_offsets, n_con, opt->gram);
+  const SolveLayout& L = X.L;
+  X.ws = (char*)workspace;
+  X.st = (hipStream_t)stream;
+  X.A = A;
+  X.dtype = dtype;
+  X.sigma = sigma;
+  X.par = X.p<double>(L.off_par);
+  int64_t* idx = X.p<int64_t>(L.off_idx);
+  X.off_d = idx;
+  X.xoff_d = idx + (P + 1);
+  X.xlen_d = idx + 2 * (P + 1);
+  X.rps_d = idx + 3 * (P + 1);
+  const uint8_t* mask = opt->mask;
+
+  // stage boundaries are timed with HIP events on the solve's stream
+  hipEvent_t ev[7];
+  for (auto& e : ev) SW_TRY(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 7; ++i) (void)hipEventDestroy(e[i]); }
+  } ev_guard{ev};
+
+  // ---- index arrays and per-problem scalars ----
+  std::vector<int64_t> hidx(4 * (P + 1), 0);
+  for (int b = 0; b <= P; ++b) hidx[b] = L.off[b];
+  for (int b = 0; b < P; ++b) {
+    hidx[(P + 1) + b] = L.xoff[b];
+    hidx[2 * (P + 1) + b] = L.xlen[b];
+    hidx[3 * (P + 1) + b] = L.rps[b];
+  }
+  hidx[(P + 1) + P] = L.Npt;
+  std::vector<double> hpar((size_t)P * kPar, 0.0);
+  for (int b = 0; b < P; ++b) {
+    hpar[b * kPar + 0] = w_tilde[b];
+    hpar[b * kPar + 4] = 1.6;  // over-relaxation (Boyd et al. 2011, Sec. 3.4.3)
+    hpar[b * kPar + 5] = 1.0;  // active
+  }
+  SW_TRY(hipMemcpyAsync(idx, hidx.data(), hidx.size() * 8, hipMemcpyHostToDevice, X.st));
+  SW_TRY(hipMemcpyAsync(X.par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice, X.st));
+  SW_TRY(hipEventRecord(ev[0], X.st));
+
+  // ---- scaled data and the transposed operand of the Gram ----
+  hipLaunchKernelGGL(k_scaled_data, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, d, sigma, L.C, L.Cp,
+                     X.p<double>(L.off_ys));
+  {
+    dim3 grid((unsigned)(L.Cp / 64), (unsigned)(L.Npt / 64));
+    if (dtype == SW_F32)
+      hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.off_d, X.xoff_d, P,
+                         sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
+                         X.p<float>(L.off_xf));
+    else
+      hipLaunchKernelGGL(k_prep_x<double>, grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt, X.off_d, X.xoff_d,
+                         P, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
+                         X.p<float>(L.off_xf));
+    SW_TRY(hipGetLastError());
+  }
+  SW_TRY(hipEventRecord(ev[1], X.st));
+
+  // ---- Gram K_b = U_b U_b^T (lower tiles) ----
+  float* K = X.p<float>(L.off_K);
+  const int64_t sK = L.Cp * L.Cp, sD = L.Cp * kNB;
+  SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
+              L.xoff.data(), L.xlen.data(), P, K, L.Cp, sK, X.st));
+  SW_TRY(hipEventRecord(ev[2], X.st));
+  double* acc = X.p<double>(L.off_acc);
+  SW_TRY(zero_acc(X));
+  double* trace_d = X.p<double>(L.off_td);  // borrowed scratch
+  hipLaunchKernelGGL(k_trace, dim3((unsigned)P), dim3(256), 0, X.st, K, L.Cp, sK, L.C, trace_d);
+  std::vector<double> trace(P);
+  SW_TRY(hipMemcpyAsync(trace.data(), trace_d, P * 8, hipMemcpyDeviceToHost, X.st));
+  std::vector<uint8_t> hmask;
+  if (mask) {
+    hmask.resize(L.N);
+    SW_TRY(hipMemcpyAsync(hmask.data(), mask, L.N, hipMemcpyDeviceToHost, X.st));
+  }
+  SW_TRY(hipStreamSynchronize(X.st));
+
+  // ---- regularisation and penalty per problem ----
+  std::vector<double> mu(P), rho(P);
+  for (int b = 0; b < P; ++b) {
+    int64_t n_eff = L.off[b + 1] - L.off[b];
+    if (mask) {
+      n_eff = 0;
+      for (int64_t i = L.off[b]; i < L.off[b + 1]; ++i) n_eff += hmask[i] ? 0 : 1;
+    }
+    if (n_eff == 0) n_eff = 1;
+    const double mean_col = trace[b] / (double)n_eff;
+    mu[b] = lambda >= 0.0 ? 2.0 * lambda / (double)n_eff : opt->nu * mean_col;
+    rho[b] = opt->rho > 0.0 ? opt->rho : (mean_col > 0.0 ? mean_col : 1.0);
+    hpar[b * kPar + 1] = rho[b];
+    hpar[b * kPar + 2] = rho[b] + mu[b];
+    hpar[b * kPar + 3] = mu[b];
+  }
+  SW_TRY(hipMemcpyAsync(X.par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice, X.st));
+
+  // ---- factorise rho' I + K_b ----
+  SW_TRY(hipEventRecord(ev[3], X.st));
+  hipLaunchKernelGGL(k_add_diag, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, K, L.Cp, sK, L.Cp, X.par);
+  int* bad = X.p<int>(L.off_bad);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, X.st, bad, (int64_t)1, 0);
+  float* dinv = X.p<float>(L.off_dinv);
+  SW_TRY(cholesky(K, L.Cp, L.Cp, sK, dinv, sD, P, X.st, bad));
+  SW_TRY(hipEventRecord(ev[4], X.st));
+  int hbad = 0;
+  SW_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, X.st));
+  SW_TRY(hipStreamSynchronize(X.st));
+  if (hbad) {
+    set_error("solve_weights: Gram matrix not positive definite in working precision");
+    return SW_EHIP;
+  }
+
+  // ---- q = U^T y, Ky = U q ----
+  float *qf = X.p<float>(L.off_qf), *zf = X.p<float>(L.off_zf), *uf = X.p<float>(L.off_uf),
+        *vf = X.p<float>(L.off_vf);
+  double *qd = X.p<double>(L.off_qd), *xd = X.p<double>(L.off_xd), *zd = X.p<double>(L.off_zd),
+         *ud = X.p<double>(L.off_ud), *vd = X.p<double>(L.off_vd), *rd = X.p<double>(L.off_rd);
+  float *kyf = X.p<float>(L.off_kyf), *r = X.p<float>(L.off_r), *tmp = X.p<float>(L.off_tmp),
+        *s = X.p<float>(L.off_s);
+  double* td = X.p<double>(L.off_td);
+  RowArgs RA;
+  std::memset(&RA, 0, sizeof RA);
+  RA.nprob = P;
+  RA.Cp = L.Cp;
+  RA.off = X.off_d;
+  RA.par = X.par;
+  RA.mask = mask;
+  RA.qf = qf; RA.zf = zf; RA.uf = uf; RA.vf = vf;
+  RA.qd = qd; RA.xd = xd; RA.zd = zd; RA.ud = ud; RA.vd = vd; RA.rd = rd;
+  RA.acc = acc;
+  SW_TRY(colscale<double>(X, X.p<double>(L.off_ys)));
+  RA.op = ROW_Q;
+  SW_TRY(rowdot(X, RA));
+  SW_TRY(colsum<float>(X, qf));
+  SW_TRY(colreduce(X, COL_PLAIN, nullptr, kyf, nullptr, nullptr));
+  for (float* p : {zf, uf, vf}) hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(L.N)), dim3(256), 0, X.st, p, L.N, 0.0f);
+  std::vector<double> hacc((size_t)P * kAcc);
+  SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
+  SW_TRY(hipStreamSynchronize(X.st));
+  std::vector<double> qmax(P);
+  for (int b = 0; b < P; ++b) qmax[b] = hacc[b * kAcc + 5] > 0.0 ? hacc[b * kAcc + 5] : 1.0;
+
+  std::vector<sw_solve_report> R(P);
+  for (int b = 0; b < P; ++b) {
+    std::memset(&R[b], 0, sizeof R[b]);
+    R[b].mu = mu[b];
+    R[b].rho = rho[b];
+  }
+  auto set_active = [&](const std::vector<int>& act) -> hipError_t {
+    for (int b = 0; b < P; ++b) hpar[b * kPar + 5] = act[b] ? 1.0 : 0.0;
+    return hipMemcpyAsync(X.par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice, X.st);
+  };
+
+  // ---- stage 1: fp32 ADMM ----
+  std::vector<int> active(P, 1);
+  int n_active = P;
+  int it = 0;
+  for (it = 1; it <= max_iter && n_active > 0; ++it) {
+    const bool check = (it % check_every == 0) || it == max_iter;
+    SW_TRY(colsum<float>(X, vf));
+    SW_TRY(colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr));
+    SW_TRY(chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st));
+    SW_TRY(colscale<float>(X, s));
+    RowArgs Ri = RA;
+    Ri.op = ROW_ADMM;
+    if (check) {
+      SW_TRY(zero_acc(X));
+    } else {
+      Ri.acc = nullptr;
+    }
+    SW_TRY(rowdot(X, Ri));
+    if (check) {
+      // stopping rule of Boyd et al. (2011) on this iteration's residuals
+      SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
+      SW_TRY(hipStreamSynchronize(X.st));
+      for (int b = 0; b < P; ++b) {
+        if (!active[b]) continue;
+        const double* a = &hacc[b * kAcc];
+        const double rp = std::sqrt(a[0]), rdl = rho[b] * std::sqrt(a[1]);
+        const double scale_p = std::fmax(std::sqrt(a[2]), std::sqrt(a[3]));
+        R[b].primal_res = rp / (scale_p + 1e-300);
+        R[b].dual_res = rdl / (rho[b] * std::sqrt(a[4]) + 1e-300);
+        R[b].iters = it;
+        if (rp <= tol * scale_p + 1e-300 && rdl <= tol * rho[b] * std::sqrt(a[4]) + 1e-300) {
+          active[b] = 0;
+          --n_active;
+        }
+      }
+      SW_TRY(set_active(active));
+    }
+  }
+  for (int b = 0; b < P; ++b)
+    if (R[b].iters == 0) R[b].iters = it - 1;
+  SW_TRY(hipEventRecord(ev[5], X.st));
+
+  // ---- stage 2: fp64 refinement of the ADMM iterates + KKT ----
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, zf, zd, L.N);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, uf, ud, L.N);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, zf, xd, L.N);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, vf, vd, L.N);
+  SW_TRY(hipGetLastError());
+  std::vector<double> kkt(P, 0.0), obj(P, 0.0);
+  auto kkt_eval = [&]() -> int {
+    SW_TRY(zero_acc(X));
+    SW_TRY(colsum<double>(X, zd));
+    SW_TRY(colreduce(X, COL_RESID, nullptr, nullptr, td, acc));
+    SW_TRY(colscale<double>(X, td));
+    RowArgs K2 = RA;
+    K2.op = ROW_KKT;
+    SW_TRY(rowdot(X, K2));
+    SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
+    SW_TRY(hipStreamSynchronize(X.st));
+    for (int b = 0; b < P; ++b) {
+      kkt[b] = hacc[b * kAcc + 6] / qmax[b];
+      obj[b] = 0.5 * hacc[b * kAcc + 9] + 0.5 * mu[b] * hacc[b * kAcc + 7];
+    }
+    return SW_OK;
+  };
+  int rc = kkt_eval();
+  if (rc != SW_OK) return rc;
+  for (int b = 0; b < P; ++b) active[b] = kkt[b] > tol_kkt ? 1 : 0;
+  n_active = 0;
+  for (int b = 0; b < P; ++b) n_active += active[b];
+  SW_TRY(set_active(active));
+  std::vector<int> rit(P, 0);
+  for (int k = 1; k <= refine_iter && n_active > 0; ++k) {
+    // residual of the ridge system at x_old: r = q + rho v - (U^T U + rho' I) x_old
+    SW_TRY(colsum<double>(X, xd));
+    SW_TRY(colreduce(X, COL_PLAIN, nullptr, nullptr, td, nullptr));
+    SW_TRY(colscale<double>(X, td));
+    RowArgs Rh = RA;
+    Rh.op = ROW_H;
+    Rh.acc = nullptr;
+    SW_TRY(rowdot(X, Rh));
+    // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
+    SW_TRY(colsum<double>(X, rd));
+    SW_TRY(colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr));
+    SW_TRY(chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st));
+    SW_TRY(colscale<float>(X, s));
+    RowArgs Rc = RA;
+    Rc.op = ROW_CORR;
+    Rc.acc = nullptr;
+    SW_TRY(rowdot(X, Rc));
+    for (int b = 0; b < P; ++b)
+      if (active[b]) rit[b] = k;
+    if (k % check_every == 0 || k == refine_iter) {
+      rc = kkt_eval();
+      if (rc != SW_OK) return rc;
+      for (int b = 0; b < P; ++b)
+        if (active[b] && kkt[b] <= tol_kkt) {
+          active[b] = 0;
+          --n_active;
+        }
+      SW_TRY(set_active(active));
+    }
+  }
+  int all_conv = 1;
+  for (int b = 0; b < P; ++b) {
+    R[b].refine_iters = rit[b];
+    R[b].kkt = kkt[b];
+    R[b].objective = obj[b];
+    R[b].converged = kkt[b] <= tol_kkt ? 1 : 0;
+    all_conv &= R[b].converged;
+  }
+  hipLaunchKernelGGL(k_scale_out, dim3(blocks_for(L.N)), dim3(256), 0, X.st, zd, L.N, X.off_d, P, X.par, w);
+  SW_TRY(hipGetLastError());
+  SW_TRY(hipEventRecord(ev[6], X.st));
+  SW_TRY(hipStreamSynchronize(X.st));
+  float ms[6];
+  for (int k = 0; k < 6; ++k) SW_TRY(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+  for (int b = 0; b < P; ++b) {
+    R[b].t_prep_ms = ms[0];
+    R[b].t_gram_ms = ms[1];
+    R[b].t_factor_ms = ms[3];
+    R[b].t_admm_ms = ms[4];
+    R[b].t_refine_ms = ms[5];
+  }
+  if (rep)
+    for (int b = 0; b < P; ++b) rep[b] = R[b];
+  if (!all_conv) {
+    set_error("solve_weights: not every problem converged (kkt of problem 0: %.3e after %d + %d iterations)", kkt[0],
+              R[0].iters, R[0].refine_iters);
+    return SW_ENOTCONV;
+  }
+  return SW_OK;
+}
+
+extern "C" int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,
+                             const double* sigma, double w_tilde, double lambda, const sw_solve_opts* opt, double* w,
+                             sw_solve_report* rep, void* workspace, size_t ws_bytes, void* stream) {
+  SW_CHECK(n_orb > 0, "solve_weights: need n_orb > 0");
+  const int64_t off[2] = {0, n_orb};
+  return solve_weights_batched(A, dtype, 1, off, n_con, d, sigma, &w_tilde, lambda, opt, w, rep, workspace, ws_bytes,
+                               stream);
+}
+
+// ---------------------------------------------------------------------------
+// chi2 and model_observables
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(kColThreads) void k_colsum1(const TA* __restrict__ A, int64_t N, int64_t C,
+                                                         const double* __restrict__ v, int64_t rps,
+                                                         double* __restrict__ part, int atomic) {
+  const int64_t c0 = (int64_t)blockIdx.x * kColTile;
+  const int64_t i_beg = (int64_t)blockIdx.y * rps;
+  int64_t i_end = i_beg + rps;
+  if (i_end > N) i_end = N;
+  double acc[kColsPerThread] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = i_beg; i < i_end; ++i) {
+    const double vi = v[i];
+    if (vi == 0.0) continue;
+#pragma unroll
+    for (int k = 0; k < kColsPerThread; ++k) {
+      const int64_t c = c0 + threadIdx.x + k * kColThreads;
+      if (c < C) acc[k] += (double)A[i * C + c] * vi;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kColsPerThread; ++k) {
+    const int64_t c = c0 + threadIdx.x + k * kColThreads;
+    if (c >= C) continue;
+    if (atomic) {
+      if (acc[k] != 0.0) atomicAdd(&part[c], acc[k]);
+    } else {
+      part[(int64_t)blockIdx.y * C + c] = acc[k];
+    }
+  }
+}
+
+__global__ void k_sum_slabs(const double* __restrict__ part, int64_t C, double* __restrict__ m) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= C) return;
+  double t = 0.0;
+  for (int s = 0; s < kSlabs; ++s) t += part[(int64_t)s * C + n];
+  m[n] = t;
+}
+
+extern "C" int chi2(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, const double* d,
+                    const double* sigma, int64_t col_begin, int64_t col_end, double* out, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "chi2: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_orb > 0 && n_con > 0, "chi2: need n_orb > 0 and n_con > 0");
+  SW_CHECK(col_begin >= 0 && col_end <= n_con && col_begin <= col_end, "chi2: bad column range");
+  SW_CHECK(A && w && d && sigma && out && workspace, "chi2: null argument");
+  if (ws_bytes < chi2_workspace_bytes(n_con)) {
+    set_error("chi2: workspace too small");
+    return SW_ENOMEM;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  double* part = (double*)ws;
+  double* m = (double*)(ws + a256((size_t)kSlabs * n_con * 8));
+  double* res = (double*)(ws + a256((size_t)kSlabs * n_con * 8) + a256((size_t)n_con * 8));
+  const int64_t rps = (n_orb + kSlabs - 1) / kSlabs;
+  dim3 grid((unsigned)((n_con + kColTile - 1) / kColTile), (unsigned)kSlabs);
+  if (dtype == SW_F32)
+    hipLaunchKernelGGL(k_colsum1<float>, grid, dim3(kColThreads), 0, st, (const float*)A, n_orb, n_con, w, rps, part, 0);
+  else
+    hipLaunchKernelGGL(k_colsum1<double>, grid, dim3(kColThreads), 0, st, (const double*)A, n_orb, n_con, w, rps, part,
+                       0);
+  hipLaunchKernelGGL(k_sum_slabs, dim3(blocks_for(n_con)), dim3(256), 0, st, part, n_con, m);
+  hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st, m, d, sigma, col_begin, col_end, res);
+  SW_HIP(hipGetLastError());
+  SW_HIP(hipMemcpyAsync(out, res, 8, hipMemcpyDeviceToHost, st));
+  SW_HIP(hipStreamSynchronize(st));
+  return SW_OK;
+}
+
+extern "C" int model_observables(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w,
+                                 double* out, void* stream) {
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "model_observables: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_orb >= 0 && n_con >= 0, "model_observables: negative size");
+  if (n_con == 0) return SW_OK;
+  SW_CHECK(out, "model_observables: null output");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n_con)), dim3(256), 0, st, out, n_con, 0.0);
+  if (n_orb == 0) {
+    SW_HIP(hipGetLastError());
+    return SW_OK;
+  }
+  SW_CHECK(A && w, "model_observables: null input");
+  const int64_t rps = (n_orb + kSlabs - 1) / kSlabs;
+  dim3 grid((unsigned)((n_con + kColTile - 1) / kColTile), (unsigned)kSlabs);
+  if (dtype == SW_F32)
+    hipLaunchKernelGGL(k_colsum1<float>, grid, dim3(kColThreads), 0, st, (const float*)A, n_orb, n_con, w, rps, out, 1);
+  else
+    hipLaunchKernelGGL(k_colsum1<double>, grid, dim3(kColThreads), 0, st, (const double*)A, n_orb, n_con, w, rps, out,
+                       1);
+  SW_HIP(hipGetLastError());
+  return SW_OK;
+}

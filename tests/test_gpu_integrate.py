@@ -1,0 +1,137 @@
+"""GPU parity of integrate_and_bin / bin_points / integrate_orbits against the oracle.
+
+Bar: bin indices are bit-exact on identical inputs (both sides decide in the
+same precision); double-precision trajectories of the analytic potentials are
+bit-exact (both sides evaluate the same expression order with IEEE sqrt and
+division and no FMA contraction), hence counts, drifts and flags are equal;
+the single-precision barred path is compared statistically with the FP64
+oracle on a seeded subsample.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_common import counts_from_fractions, gpu_integrate, lib, oracle_integrate
+
+pytestmark = pytest.mark.gpu
+
+
+def edge_points(obs, R, rng, n, dtype):
+    """Random states plus states whose coordinates sit on, and one ulp either
+    side of, grid edges (in the given precision)."""
+    pts = np.stack([rng.uniform(-12, 12, n), rng.uniform(-12, 12, n), rng.uniform(-4, 4, n),
+                    rng.normal(0, 200, n), rng.normal(0, 200, n), rng.normal(0, 200, n)]).astype(dtype)
+    k = n // 4
+    for axis, (lo, hi, nb) in enumerate(zip(obs["lo"], obs["hi"], (obs["nx"], obs["ny"], obs["nz"]))):
+        edges = lo + (hi - lo) * rng.integers(0, nb + 1, k) / nb
+        e = edges.astype(dtype)
+        jitter = rng.integers(-1, 2, k)
+        e = np.where(jitter < 0, np.nextafter(e, dtype(-np.inf)), np.where(jitter > 0, np.nextafter(e, dtype(np.inf)), e))
+        pts[axis, axis * k:(axis + 1) * k] = e
+    return pts
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_bin_points_bit_exact(gpu, dtype):
+    import torch
+    P = lib()
+    cfg = W.BARRED
+    npd = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(11)
+    pts = edge_points(cfg["obs"], None, rng, 20000, npd)
+    pot = P.build_potential(cfg["components"], cfg["omega"], cfg["euler"])
+    o = P.obs_spec(cfg["obs"])
+    t = torch.from_numpy(pts).to(gpu)
+    mass = torch.empty((pts.shape[1], 4), dtype=torch.int32, device=gpu)
+    kin = torch.empty_like(mass)
+    P.bin_points(pot, o, t, mass, kin)
+    torch.cuda.synchronize()
+    om, ok = O.bin_points(O.make_obs(cfg["obs"], O.euler_matrix(*cfg["euler"])), pts, dtype)
+    assert np.array_equal(mass.cpu().numpy(), om)
+    assert np.array_equal(kin.cpu().numpy(), ok)
+    assert (om < 0).any() and (om >= 0).any()
+
+
+def test_integrate_orbits_fp64_bit_exact(gpu):
+    """Plummer + Miyamoto-Nagai, static and rotating frame: final states equal to the last bit."""
+    import torch
+    P = lib()
+    rng = np.random.default_rng(5)
+    n = 193
+    ics = np.stack([rng.uniform(-8, 8, n), rng.uniform(-8, 8, n), rng.uniform(-1, 1, n),
+                    rng.normal(0, 120, n), rng.normal(0, 120, n), rng.normal(0, 40, n)])
+    dt = rng.uniform(5e-4, 3e-3, n)
+    comps = [("plummer", (1e10, 0.5)), ("mn", (5e10, 3.0, 0.3)), ("kepler", (1e8,)), ("isochrone", (2e9, 1.0))]
+    pot = P.build_potential(comps, 0.0, (0.0, 0.0, 0.0))
+    out = torch.empty((6, n), dtype=torch.float64, device=gpu)
+    P.integrate_orbits(pot, torch.from_numpy(ics).to(gpu), torch.from_numpy(dt).to(gpu), 500, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    opot = O.make_pot(comps, 0.0)
+    for i in range(n):
+        ref = O.orbit(opot, ics[:, i], dt[i], 500)[-1]
+        assert np.array_equal(g[:, i], ref), (i, g[:, i] - ref)
+
+
+def test_small_workload_fp64_counts_identical(gpu):
+    """The full Plummer + MN workload (2,000 orbits x 1,000 FP64 steps): integer
+    counts, overflow, Jacobi drift and flags identical to the oracle."""
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, ov, dr, fl = gpu_integrate(cfg, ics, dt, cfg["n_steps"], "f64")
+    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ics, dt, cfg["n_steps"])
+    assert np.array_equal(counts_from_fractions(A, cfg["n_steps"]), c_o)
+    assert np.array_equal(A, O.time_fractions(c_o, cfg["n_steps"]))
+    assert np.array_equal(np.rint(ov * 4 * cfg["n_steps"]).astype(np.int64), ov_o)
+    assert np.max(np.abs(dr - dr_o)) <= 1e-5  # parity bar; expected bit-exact
+    assert np.array_equal(dr, dr_o)
+    assert np.array_equal(fl, fl_o)
+
+
+@pytest.mark.parametrize("n,n_steps,sym", [(1, 7, 1), (63, 33, 0), (130, 50, 1)])
+def test_ragged_shapes_fp64(gpu, n, n_steps, sym):
+    cfg = W.SMALL
+    rng = np.random.default_rng(n)
+    ics = np.stack([rng.uniform(-8, 8, n), rng.uniform(-8, 8, n), rng.uniform(-1, 1, n),
+                    rng.normal(0, 150, n), rng.normal(0, 150, n), rng.normal(0, 50, n)])
+    dt = rng.uniform(1e-3, 4e-3, n)
+    obs = dict(cfg["obs"], symmetrize=sym, drift_every=3)
+    A, ov, dr, fl = gpu_integrate(cfg, ics, dt, n_steps, "f64", obs=obs)
+    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ics, dt, n_steps, obs=obs)
+    ncopy = 4 if sym else 1
+    assert np.array_equal(counts_from_fractions(A, n_steps, ncopy), c_o)
+    assert np.array_equal(np.rint(ov * ncopy * n_steps).astype(np.int64), ov_o)
+    assert np.array_equal(dr, dr_o) and np.array_equal(fl, fl_o)
+
+
+def test_barred_fp32_subsample_vs_fp64_oracle(gpu):
+    """Barred model (MN + Ferrers + flattened NFW, 40 km/s/kpc) in FP32 against the
+    FP64 oracle on the seeded 1,000-orbit subsample of the 100,000-orbit library,
+    full 10,000 steps: exact per-block normalisation, Jacobi-drift parity and
+    per-orbit time-fraction agreement."""
+    cfg = W.BARRED
+    n_steps = cfg["n_steps"]
+    table = W.load_table(cfg["table"])
+    ics, dt = W.disc_ics(table, cfg["n_orb"], seed=cfg["ic_seed"], n_steps=n_steps)
+    sub = W.subsample_draw(cfg["n_orb"], cfg["subsample"]["n"], cfg["subsample"]["seed"])
+    ics32, dt32 = ics[:, sub].astype(np.float32), dt[sub].astype(np.float32)
+    A, ov, dr, fl = gpu_integrate(cfg, ics32, dt32, n_steps, "f32")
+    # the oracle integrates the same (fp32-rounded) initial conditions in fp64
+    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ics32.astype(np.float64), dt32.astype(np.float64), n_steps)
+    c_g = counts_from_fractions(A, n_steps)
+    nm = 30 * 30 * 20
+    ovc = np.rint(ov * 4 * n_steps).astype(np.int64)
+    assert np.all(c_g[:, :nm].sum(1) + ovc[:, 0] == 4 * n_steps)
+    assert np.all(c_g[:, nm:].sum(1) + ovc[:, 1] == 4 * n_steps)
+    A_o = O.time_fractions(c_o, n_steps)
+    l1 = np.abs(A.astype(np.float64) - A_o).sum(1) / 2  # per orbit, both blocks (max 2 -> 1)
+    ddr = np.abs(dr - dr_o)
+    print(f"row L1 median {np.median(l1):.3g} p90 {np.percentile(l1, 90):.3g}; "
+          f"|drift_f32 - drift_f64| median {np.median(ddr):.3g} p90 {np.percentile(ddr, 90):.3g}; "
+          f"drift median {np.median(dr_o):.3g}; flagged {np.mean(fl & 1):.4f} vs {np.mean(fl_o & 1):.4f}")
+    assert np.median(ddr) <= 1e-5
+    assert np.median(l1) < 0.02
+    assert abs(np.mean(fl & 1) - np.mean(fl_o & 1)) <= 0.01

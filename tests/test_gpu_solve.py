@@ -1,0 +1,175 @@
+"""GPU parity of solve_weights / chi2 / model_observables against the exact
+FP64 NNLS oracle (Eq. 4) and the FP64 chi^2 of Eq. 5.
+
+Bar (from the build's target): weights L1 relative error < 1e-2 and chi^2
+relative error < 1e-3 against the oracle, on the same matrix and data.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nnls as N
+from tests.gpu_common import counts_from_fractions, gpu_integrate, lib
+
+pytestmark = pytest.mark.gpu
+
+W_L1_TOL = 1e-2
+CHI2_TOL = 1e-3
+
+
+def mock_problem(A, blocks, mock_seed, noise, tol):
+    A64 = A.astype(np.float64)
+    n, c = A.shape
+    w_true = W.mock_draw(n, mock_seed)
+    d = A64.T @ w_true
+    if noise > 0:
+        d = d * (1 + noise * W.noise_draw(c, mock_seed))
+    sig = N.sigma_from_data(d, blocks, tol)
+    wt = N.w_tilde_from_data(d, blocks[0], n)
+    return d, sig, wt
+
+
+def oracle_solve(A, d, sig, wt, nu):
+    U, y = N.scale_problem(A.astype(np.float64), d, sig, wt)
+    mu = N.relative_mu(U, nu)
+    return N.nnls_oracle(U, y, mu) * wt, mu
+
+
+def gpu_solve(A, d, sig, wt, nu, gram, **kw):
+    import torch
+    P = lib()
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    dt = torch.from_numpy(d).to(dev)
+    st = torch.from_numpy(sig).to(dev)
+    opts = P._lib.SolveOpts()
+    opts.gram = gram
+    opts.nu = nu
+    opts.max_iter = kw.get("max_iter", 0)
+    opts.refine_iter = kw.get("refine_iter", 0)
+    opts.tol = kw.get("tol", 0.0)
+    opts.tol_kkt = kw.get("tol_kkt", 0.0)
+    w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
+    ws = torch.empty(P.solve_workspace_bytes(A.shape[0], A.shape[1], opts), dtype=torch.uint8, device=dev)
+    status, rep = P.solve_weights(At, dt, st, wt, -1.0, opts, w, ws)
+    cws = torch.empty(P.chi2_workspace_bytes(A.shape[1]), dtype=torch.uint8, device=dev)
+    return w.cpu().numpy(), status, rep, (At, w, dt, st, cws)
+
+
+def chi2_gpu(handles, cb, ce):
+    P = lib()
+    At, w, dt, st, cws = handles
+    return P.chi2(At, w, dt, st, cb, ce, cws)
+
+
+@pytest.mark.parametrize("gram", [0, 1, 2], ids=["bf16", "bf16x3", "f32"])
+def test_solve_sparse_lognormal(gpu, gram):
+    n, c = 1500, 600
+    blocks = [(0, 200), (200, c)]
+    A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=6)
+    d, sig, wt = mock_problem(A, blocks, 4, 0.02, 0.02)
+    w_o, mu = oracle_solve(A, d, sig, wt, 1e-2)
+    w_g, status, rep, h = gpu_solve(A, d, sig, wt, 1e-2, gram)
+    print(rep.as_dict())
+    assert status == 0
+    assert rep.mu == pytest.approx(mu, rel=1e-4)
+    l1 = np.abs(w_g - w_o).sum() / np.abs(w_o).sum()
+    x_o = N.chi2(A.astype(np.float64), w_o, d, sig, 200, c)
+    x_g = chi2_gpu(h, 200, c)
+    print("L1", l1, "chi2", x_g, x_o)
+    assert l1 < W_L1_TOL
+    assert abs(x_g / x_o - 1) < CHI2_TOL
+
+
+def test_solve_ragged_larger(gpu):
+    n, c = 3001, 1003
+    blocks = [(0, 300), (300, c)]
+    A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=7)
+    d, sig, wt = mock_problem(A, blocks, 5, 0.02, 0.02)
+    w_o, mu = oracle_solve(A, d, sig, wt, 1e-2)
+    w_g, status, rep, h = gpu_solve(A, d, sig, wt, 1e-2, 1)
+    assert status == 0
+    l1 = np.abs(w_g - w_o).sum() / np.abs(w_o).sum()
+    x_o = N.chi2(A.astype(np.float64), w_o, d, sig, 300, c)
+    assert l1 < W_L1_TOL
+    assert abs(chi2_gpu(h, 300, c) / x_o - 1) < CHI2_TOL
+
+
+def test_small_workload_end_to_end(gpu):
+    """Plummer + MN workload, FP64 on both sides: the GPU builds the orbit matrix,
+    solves and evaluates chi^2; the oracle does all three on its own matrix."""
+    import oracle as O
+    from tests.gpu_common import oracle_integrate
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, ov, dr, fl = gpu_integrate(cfg, ics, dt, cfg["n_steps"], "f64")
+    c_o, *_ = oracle_integrate(cfg, ics, dt, cfg["n_steps"])
+    A_o = O.time_fractions(c_o, cfg["n_steps"])
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A_o, blocks, cfg["mock"]["seed"], cfg["mock"]["noise"], cfg["mock"]["tol"])
+    w_o, mu = oracle_solve(A_o, d, sig, wt, 1e-2)
+    w_g, status, rep, h = gpu_solve(A, d, sig, wt, 1e-2, 1)
+    assert status == 0
+    l1 = np.abs(w_g - w_o).sum() / np.abs(w_o).sum()
+    x_o = N.chi2(A_o, w_o, d, sig, blocks[1][0], blocks[1][1])
+    x_g = chi2_gpu(h, blocks[1][0], blocks[1][1])
+    print("L1", l1, "chi2", x_g, x_o, rep.as_dict())
+    assert l1 < W_L1_TOL
+    assert abs(x_g / x_o - 1) < CHI2_TOL
+
+
+def test_chi2_and_model_observables(gpu):
+    import torch
+    P = lib()
+    rng = np.random.default_rng(3)
+    A = rng.random((777, 345)).astype(np.float32)
+    w = rng.exponential(size=777)
+    d = A.astype(np.float64).T @ w * (1 + 0.01 * rng.normal(size=345))
+    sig = 0.01 * d
+    At = torch.from_numpy(A).cuda()
+    wt = torch.from_numpy(w).cuda()
+    out = torch.empty(345, dtype=torch.float64, device="cuda")
+    P.model_observables(At, wt, out)
+    torch.cuda.synchronize()
+    ref = A.astype(np.float64).T @ w
+    assert np.allclose(out.cpu().numpy(), ref, rtol=1e-12)
+    cws = torch.empty(P.chi2_workspace_bytes(345), dtype=torch.uint8, device="cuda")
+    x = P.chi2(At, wt, torch.from_numpy(d).cuda(), torch.from_numpy(sig).cuda(), 45, 345, cws)
+    assert x == pytest.approx(N.chi2(A.astype(np.float64), w, d, sig, 45, 345), rel=1e-12)
+
+
+def test_solve_batched_matches_oracle_per_problem(gpu):
+    """Three independent problems of different orbit counts solved in one batched call."""
+    import torch
+    P = lib()
+    c = 500
+    blocks = [(0, 150), (150, c)]
+    sizes = [700, 1201, 333]
+    mats, ds, sigs, wts, w_os = [], [], [], [], []
+    for k, n in enumerate(sizes):
+        A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=20 + k)
+        d, sig, wt = mock_problem(A, blocks, 30 + k, 0.02, 0.02)
+        w_o, _ = oracle_solve(A, d, sig, wt, 1e-2)
+        mats.append(A); ds.append(d); sigs.append(sig); wts.append(wt); w_os.append(w_o)
+    A = np.concatenate(mats)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    dev = torch.device("cuda:0")
+    opts = P._lib.SolveOpts()
+    opts.gram = 1
+    opts.nu = 1e-2
+    At = torch.from_numpy(A).to(dev)
+    dt = torch.from_numpy(np.stack(ds)).to(dev)
+    st = torch.from_numpy(np.stack(sigs)).to(dev)
+    w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
+    ws = torch.empty(P.solve_batched_workspace_bytes(off, c, opts), dtype=torch.uint8, device=dev)
+    status, reps = P.solve_weights_batched(At, off, dt, st, wts, -1.0, opts, w, ws)
+    wg = w.cpu().numpy()
+    assert status == 0
+    for k in range(3):
+        wk = wg[off[k]:off[k + 1]]
+        l1 = np.abs(wk - w_os[k]).sum() / np.abs(w_os[k]).sum()
+        x_o = N.chi2(mats[k].astype(np.float64), w_os[k], ds[k], sigs[k], 150, c)
+        x_g = N.chi2(mats[k].astype(np.float64), wk, ds[k], sigs[k], 150, c)
+        print(k, "L1", l1, "chi2", x_g, x_o, reps[k].iters, reps[k].refine_iters, reps[k].kkt)
+        assert l1 < W_L1_TOL
+        assert abs(x_g / x_o - 1) < CHI2_TOL
