@@ -74,7 +74,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="barred", choices=["barred", "small"])
+    ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate"])
+    ap.add_argument("--n-train", type=int, default=20000, help="surrogate: training builds")
+    ap.add_argument("--mcmc-steps", type=int, default=200, help="surrogate: DA-MCMC steps per walker")
     ap.add_argument("--gram", default="bf16x3", choices=["bf16", "bf16x3", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -86,6 +88,10 @@ def main():
     import torch
     import paper_2607_00117_amd as P
 
+    if args.workload == "walkers":
+        return bench_walkers(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     cfg = W.BARRED if args.workload == "barred" else W.SMALL
     dev = torch.device("cuda:0")
     f64 = cfg["dtype"] == "f64"
@@ -134,14 +140,17 @@ def main():
     log(f"workspaces: integrate {iws.numel() / 1e9:.1f} GB, solve {sws.numel() / 1e9:.1f} GB")
 
     reps, chis, t_int = [], [], []
+    stream = torch.cuda.Stream()  # default priority; the solve captures its iterations into HIP graphs on it
+    opts.use_graph = 1
 
     def step():
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        P.integrate_and_bin(pot, [0, n], ic_t, dt_t, n_steps, obs, A, ov, dr, fl, iws)
-        e1.record()
-        st, rep = P.solve_weights(A, d_t, s_t, w_tilde, -1.0, opts, w, sws)
-        x = P.chi2(A, w, d_t, s_t, blocks[1][0], blocks[1][1], cws)
+        with torch.cuda.stream(stream):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            P.integrate_and_bin(pot, [0, n], ic_t, dt_t, n_steps, obs, A, ov, dr, fl, iws)
+            e1.record()
+            st, rep = P.solve_weights(A, d_t, s_t, w_tilde, -1.0, opts, w, sws)
+            x = P.chi2(A, w, d_t, s_t, blocks[1][0], blocks[1][1], cws)
         torch.cuda.synchronize()
         t_int.append(e0.elapsed_time(e1))
         reps.append(rep.as_dict() | {"status": st})
@@ -199,6 +208,195 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+def shared_mock(P, torch, comps, omega, euler, ics, dt, n_steps, obs_d, mock, dev):
+    """Mock data from one build at fixed parameters: binned sum of a seeded 10%
+    orbit subset with Exp(1) weights, optional Gaussian noise."""
+    n = ics.shape[1]
+    pot = P.build_potential(comps, omega, euler)
+    obs = P.obs_spec(obs_d)
+    nc = P.ncon(obs)
+    A = torch.empty((n, nc), dtype=torch.float32, device=dev)
+    ov = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(n, dtype=torch.float64, device=dev)
+    fl = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.integrate_workspace_bytes(obs, 1, n, n_steps, P.SW_F32), dtype=torch.uint8, device=dev)
+    P.integrate_and_bin(pot, [0, n], torch.from_numpy(ics.astype(np.float32)).to(dev),
+                        torch.from_numpy(dt.astype(np.float32)).to(dev), n_steps, obs, A, ov, dr, fl, ws)
+    w = torch.from_numpy(W.mock_draw(n, mock["seed"])).to(dev)
+    d = torch.empty(nc, dtype=torch.float64, device=dev)
+    P.model_observables(A, w, d)
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    if mock["noise"] > 0:
+        d = d * (1 + mock["noise"] * W.noise_draw(nc, mock["seed"]))
+    del A, ws
+    return d
+
+
+def bench_walkers(args):
+    """64 MCMC walkers' trial potentials (barred family, +-30% around the nominal
+    12 parameters), orbit counts uniform in 20k..150k, small-model observables,
+    1,000 FP32 steps over 50 circular periods; one batched integrate_and_bin
+    launch, one batched weight solve, chi^2 per walker.  A step = the 64 builds."""
+    import torch
+    import paper_2607_00117_amd as P
+    from paper_2607_00117_amd import autotune
+    dev = torch.device("cuda:0")
+    n_w, n_steps = 64, 1000
+    thetas = W.walker_thetas(n_w, seed=5)
+    counts = W.walker_orbit_counts(n_w, seed=5)
+    table = W.load_table(W.BARRED["table"])
+    ics, dt = W.disc_ics(table, int(counts.max()), seed=3, n_steps=n_steps)
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n_tot = int(offs[-1])
+    idx = np.concatenate([np.arange(c) for c in counts])
+    obs_d = dict(W.SMALL["obs"])
+    obs = P.obs_spec(obs_d)
+    nc = P.ncon(obs)
+    blocks = W.blocks(obs_d)
+    comps, omega, euler = W.theta_to_model(W.theta_nominal())
+    n_mock = int(np.mean(counts))
+    d = shared_mock(P, torch, comps, omega, euler, ics[:, :n_mock], dt[:n_mock], n_steps, obs_d, W.BARRED["mock"], dev)
+    sig = mock_sigma(d, blocks, W.BARRED["mock"]["tol"])
+    mass = float(np.sum(d[blocks[0][0]:blocks[0][1]]))
+    w_tilde = [mass / float(c) for c in counts]
+    pots = [P.build_potential(*W.theta_to_model(th)) for th in thetas]
+    ic_t = torch.from_numpy(ics[:, idx].astype(np.float32)).to(dev)
+    dt_t = torch.from_numpy(dt[idx].astype(np.float32)).to(dev)
+    A = torch.empty((n_tot, nc), dtype=torch.float32, device=dev)
+    ov = torch.empty((n_tot, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(n_tot, dtype=torch.float64, device=dev)
+    fl = torch.empty(n_tot, dtype=torch.uint8, device=dev)
+    iws = torch.empty(min(P.integrate_workspace_bytes(obs, n_w, n_tot, n_steps, P.SW_F32), 24 << 30),
+                      dtype=torch.uint8, device=dev)
+    log(f"walkers: {n_w} potentials, {n_tot} orbits x {n_steps} steps, {nc} constraints")
+    # autotune the integration launch on a sample of the batch
+    s_off = offs[:9] if offs[8] < 400000 else offs[:2]
+    s_n = int(s_off[-1])
+    s_ws = torch.empty(P.integrate_workspace_bytes(obs, len(s_off) - 1, s_n, 200, P.SW_F32), dtype=torch.uint8,
+                       device=dev)
+
+    def sample():
+        P.integrate_and_bin(pots[:len(s_off) - 1], s_off, ic_t[:, :s_n], dt_t[:s_n], 200, obs, A[:s_n], ov[:s_n],
+                            dr[:s_n], fl[:s_n], s_ws)
+        torch.cuda.synchronize()
+    best, table_t = autotune.tune(sample, autotune.shape_key(obs, len(s_off) - 1, s_n, 200, "f32"), log=log)
+    del s_ws
+    log(f"autotune best {best}")
+    d_t = torch.from_numpy(np.tile(d, (n_w, 1))).to(dev)
+    s_t = torch.from_numpy(np.tile(sig, (n_w, 1))).to(dev)
+    d1, s1 = torch.from_numpy(d).to(dev), torch.from_numpy(sig).to(dev)
+    opts = P._lib.SolveOpts()
+    opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
+    opts.mask = fl.data_ptr()
+    w = torch.empty(n_tot, dtype=torch.float64, device=dev)
+    sws = torch.empty(P.solve_batched_workspace_bytes(offs, nc, opts), dtype=torch.uint8, device=dev)
+    cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+    chis, t_int, t_solve = [], [], []
+
+    def step():
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            P.integrate_and_bin(pots, offs, ic_t, dt_t, n_steps, obs, A, ov, dr, fl, iws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, reps = P.solve_weights_batched(A, offs, d_t, s_t, w_tilde, -1.0, opts, w, sws)
+            x = [P.chi2(A[offs[k]:offs[k + 1]], w[offs[k]:offs[k + 1]], d1, s1, blocks[1][0], blocks[1][1], cws)
+                 for k in range(n_w)]
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        t_int.append(1e3 * (t1 - t0)); t_solve.append(1e3 * (t2 - t1)); chis.append(x)
+        return reps
+
+    for _ in range(args.warmup):
+        step()
+    t_int.clear(); t_solve.clear(); chis.clear()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        reps = step()
+        log(f"step {i}: integrate {t_int[-1]:.1f} ms, solve+chi2 {t_solve[-1]:.1f} ms, "
+            f"iters {max(r.iters for r in reps)}+{max(r.refine_iters for r in reps)}")
+    el = time.perf_counter() - t0
+    out = {"metric": METRIC, "value": n_w * args.steps / el, "unit": "model builds/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "walkers_64_barred_family_20k-150k_orbits_1k_steps", "n_orbits_total": n_tot,
+                      "n_constraints": nc, "autotune": best},
+           "orbit_steps_per_s": n_tot * n_steps * args.steps / el,
+           "integrate_ms": float(np.mean(t_int)), "solve_chi2_ms": float(np.mean(t_solve)),
+           "chi2_range": [float(np.min(chis[-1])), float(np.max(chis[-1]))]}
+    print(json.dumps(out))
+
+
+def bench_surrogate(args):
+    """Learned chi^2 surrogate: Latin-hypercube training builds (small-model
+    size, 2,000 orbits x 1,000 FP32 steps, barred family, +-30% priors), MLP
+    training with the library's kernels, held-out error in units of dchi2, and
+    delayed-acceptance MCMC (32 walkers) against plain Metropolis."""
+    import torch
+    import paper_2607_00117_amd as P
+    from paper_2607_00117_amd import surrogate as S
+    dev = torch.device("cuda:0")
+    n_orb, n_steps, batch = 2000, 1000, 256
+    nominal = W.theta_nominal()
+    lo, hi = 0.7 * nominal, 1.3 * nominal
+    table = W.load_table(W.BARRED["table"])
+    ics, dt = W.disc_ics(table, n_orb, seed=3, n_steps=n_steps)
+    obs_d = dict(W.SMALL["obs"])
+    blocks = W.blocks(obs_d)
+    comps, omega, euler = W.theta_to_model(nominal)
+    d = shared_mock(P, torch, comps, omega, euler, ics, dt, n_steps, obs_d, W.BARRED["mock"], dev)
+    sig = mock_sigma(d, blocks, W.BARRED["mock"]["tol"])
+    wt = float(np.sum(d[blocks[0][0]:blocks[0][1]])) / n_orb
+    opts = P._lib.SolveOpts()
+    opts.use_graph = 1
+    builder = S.ModelBuilder(W.theta_to_model, ics, dt, n_steps, obs_d, d, sig, wt, batch, kin_block=blocks[1],
+                             solve_opts=opts)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        # dchi2: spread of chi^2 at the nominal parameters over independently seeded libraries
+        seeds = []
+        for sd in range(8):
+            ics_s, dt_s = W.disc_ics(table, n_orb, seed=100 + sd, n_steps=n_steps)
+            b2 = S.ModelBuilder(W.theta_to_model, ics_s, dt_s, n_steps, obs_d, d, sig, wt, 1, kin_block=blocks[1],
+                                solve_opts=opts)
+            seeds.append(float(b2.chi2(nominal[None, :])[0]))
+            del b2
+        dchi2 = float(np.std(seeds, ddof=1))
+        log(f"dchi2 = {dchi2:.3g} (chi2 at nominal over 8 seeds: {np.round(seeds, 1).tolist()})")
+        u = W.latin_hypercube(args.n_train, 12, seed=7)
+        thetas = lo + (hi - lo) * u
+        t0 = time.perf_counter()
+        chi = builder.chi2(thetas)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        log(f"{args.n_train} training builds in {t_build:.1f} s ({args.n_train / t_build:.1f} builds/s)")
+        n_tr = int(0.9 * len(thetas))
+        sur = S.Surrogate(lo, hi)
+        t0 = time.perf_counter()
+        sur.fit(thetas[:n_tr], chi[:n_tr], epochs=200, batch=512)
+        t_fit = time.perf_counter() - t0
+        pred = sur.predict(thetas[n_tr:])
+        err = np.abs(pred - chi[n_tr:]) / dchi2
+        log(f"surrogate fit {t_fit:.1f} s; held-out |chi2_s - chi2|/dchi2 median {np.median(err):.3g}, "
+            f"frac<1 {np.mean(err < 1):.3f}")
+        theta0 = W.walker_thetas(32, seed=8, spread=0.05)
+        res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log)
+        res_mh = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=False, log=log)
+    out = {"metric": METRIC, "value": res_da["models_per_s"], "unit": "surrogate-MCMC models/s", "n_gpus": 1,
+           "steps": args.mcmc_steps, "warmup": 0, "ms_per_step": 1e3 * res_da["seconds"] / args.mcmc_steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "surrogate_da_mcmc_32_walkers_small_model_barred_family", "n_train": args.n_train,
+                      "mcmc_steps": args.mcmc_steps},
+           "dchi2": dchi2, "train_builds_per_s": args.n_train / t_build,
+           "heldout_err_over_dchi2_median": float(np.median(err)), "heldout_frac_err_below_dchi2": float(np.mean(err < 1)),
+           "plain_mh_models_per_s": res_mh["models_per_s"],
+           "da": {k: res_da[k] for k in ("n_full_builds", "n_stage1", "n_accepted", "seconds", "proposals")},
+           "mh": {k: res_mh[k] for k in ("n_full_builds", "n_accepted", "seconds", "proposals")}}
     print(json.dumps(out))
 
 

@@ -175,9 +175,12 @@ size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t 
 
 typedef struct {
   int32_t gram;        /* SW_GRAM_* */
-  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 500) */
-  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 300) */
+  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 1000) */
+  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 500) */
   int32_t check_every; /* convergence checked every this many iterations (<= 0: 10) */
+  int32_t use_graph;   /* 1: the iterations between two checks are captured once into a HIP
+                          graph and replayed (needs a non-NULL stream); 0: plain launches */
+  int32_t reserved;
   double rho;          /* ADMM penalty for the scaled problem (<= 0: trace(U U^T) / N) */
   double tol;          /* relative primal/dual tolerance of the FP32 stage (<= 0: 1e-4) */
   double tol_kkt;      /* target relative KKT residual of the FP64 stage (<= 0: 1e-7) */
@@ -186,7 +189,8 @@ typedef struct {
 } sw_solve_opts;
 
 typedef struct {
-  int32_t iters, refine_iters, converged, n_active;
+  int32_t iters, refine_iters, converged;
+  int32_t n_active; /* orbits with positive weight at return */
   double mu;       /* 2 lambda / N in the scaled problem */
   double rho;      /* ADMM penalty used */
   double kkt;      /* relative KKT natural residual at return */
@@ -197,6 +201,7 @@ typedef struct {
      factor = rho' I + blocked Cholesky, admm = q, Ky and the fp32 iterations,
      refine = fp64 refinement, KKT evaluations and output */
   double t_prep_ms, t_gram_ms, t_factor_ms, t_admm_ms, t_refine_ms;
+  double nnz; /* nonzeros of A when the ADMM passes used the compressed copies, else 0 */
 } sw_solve_report;
 
 int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,
@@ -278,6 +283,17 @@ int mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t 
 int mlp_mse_grad(const float* y, const float* t, int64_t B, float* dy, void* stream);
 int mlp_pack_bf16(const float* params, void* packed, void* stream);
 int mlp_infer_bf16(const void* packed, const float* x, int64_t B, float* y, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning (process-wide, not thread-safe; set before launching work):
+ *   "integrate_waves_per_cu"  0: one 64-orbit wave per workgroup over the whole
+ *                             library; k in [1, 64]: persistent grid of k waves
+ *                             per compute unit walking the orbit tiles
+ *   "hist_lds_kb"             LDS budget (KiB, 4..160) of one histogram
+ *                             workgroup; sets how many orbit rows it carries
+ * sw_get_tuning returns the current value (-1 for an unknown key).           */
+int sw_set_tuning(const char* key, int32_t value);
+int32_t sw_get_tuning(const char* key);
 
 /* Thread-local message describing the last failure of this thread. */
 const char* sw_last_error(void);

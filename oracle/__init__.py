@@ -75,6 +75,8 @@ def _declare(L):
     L.orc_ncon.argtypes = [O]; L.orc_ncon.restype = C.c_int
     L.orc_integrate_and_bin.argtypes = [P, O, C.c_long, _dp, _dp, C.c_int, _i32, _i64, _dp, _u8, C.c_int]
     L.orc_integrate_and_bin.restype = None
+    L.orc_integrate_and_bin_f32state.argtypes = L.orc_integrate_and_bin.argtypes
+    L.orc_integrate_and_bin_f32state.restype = None
     L.orc_bin_points_f64.argtypes = [O, C.c_long, _dp, _i32, _i32]; L.orc_bin_points_f64.restype = None
     L.orc_bin_points_f32.argtypes = [O, C.c_long, _fp, _i32, _i32]; L.orc_bin_points_f32.restype = None
 
@@ -163,9 +165,10 @@ def ncon(obs):
     return lib().orc_ncon(C.byref(obs))
 
 
-def integrate_and_bin(pot, obs, ics, dt, nsteps, nthreads=0):
+def integrate_and_bin(pot, obs, ics, dt, nsteps, nthreads=0, f32_state=False):
     """ics: [6][n] float64; dt: [n].  Returns (counts [n][ncon] int32,
-    overflow [n][2] int64, drift [n], flags [n] uint8)."""
+    overflow [n][2] int64, drift [n], flags [n] uint8).  f32_state rounds the
+    state to binary32 after every step (FP64 arithmetic otherwise)."""
     ics = np.ascontiguousarray(ics, dtype=np.float64)
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     n = ics.shape[1]
@@ -174,8 +177,8 @@ def integrate_and_bin(pot, obs, ics, dt, nsteps, nthreads=0):
     ov = np.zeros((n, 2), dtype=np.int64)
     drift = np.zeros(n)
     flags = np.zeros(n, dtype=np.uint8)
-    lib().orc_integrate_and_bin(C.byref(pot), C.byref(obs), n, ics, dt, nsteps, counts, ov, drift, flags,
-                                nthreads)
+    fn = lib().orc_integrate_and_bin_f32state if f32_state else lib().orc_integrate_and_bin
+    fn(C.byref(pot), C.byref(obs), n, ics, dt, nsteps, counts, ov, drift, flags, nthreads)
     return counts, ov, drift, flags
 
 

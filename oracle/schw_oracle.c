@@ -486,9 +486,9 @@ void orc_bin_points_f32(const orc_obs* O, long n, const float* pts, int32_t* mas
   }
 }
 
-void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics,
-                           const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
-                           double* drift, uint8_t* flags, int nthreads) {
+static void integrate_and_bin_impl(const orc_pot* P, const orc_obs* O, long n, const double* ics,
+                                   const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
+                                   double* drift, uint8_t* flags, int nthreads, int round_state) {
   int ncon = orc_ncon(O);
   int nmass = O->nx * O->ny * O->nz;
   int ncopy = O->symmetrize ? 4 : 1;
@@ -506,6 +506,8 @@ void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const dou
     int nonfinite = 0;
     for (int k = 1; k <= nsteps; ++k) {
       orc_step(P, s, dt[i]);
+      if (round_state)
+        for (int j = 0; j < 6; ++j) s[j] = (double)(float)s[j];
       for (int j = 0; j < 6; ++j)
         if (!isfinite(s[j])) nonfinite = 1;
       for (int c = 0; c < ncopy; ++c) {
@@ -527,4 +529,16 @@ void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const dou
     if (nonfinite) f |= 2;
     flags[i] = f;
   }
+}
+
+void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics,
+                           const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
+                           double* drift, uint8_t* flags, int nthreads) {
+  integrate_and_bin_impl(P, O, n, ics, dt, nsteps, counts, overflow, drift, flags, nthreads, 0);
+}
+
+void orc_integrate_and_bin_f32state(const orc_pot* P, const orc_obs* O, long n, const double* ics,
+                                    const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
+                                    double* drift, uint8_t* flags, int nthreads) {
+  integrate_and_bin_impl(P, O, n, ics, dt, nsteps, counts, overflow, drift, flags, nthreads, 1);
 }

@@ -82,6 +82,14 @@ int orc_ncon(const orc_obs* O);
 void orc_integrate_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics,
                            const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
                            double* drift, uint8_t* flags, int nthreads);
+/* Same, except that after every step the six state coordinates are rounded to
+ * the nearest binary32 value (arithmetic stays FP64).  This models only the
+ * state storage of a single-precision integrator: the spread it produces
+ * against the plain FP64 run is the floor any FP32 integration must expect
+ * on chaotic orbits. */
+void orc_integrate_and_bin_f32state(const orc_pot* P, const orc_obs* O, long n, const double* ics,
+                                    const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
+                                    double* drift, uint8_t* flags, int nthreads);
 
 /* Bins the four mirror copies of each phase-space point (bar frame, [6][n]).
  * mass/kin: [n][4] cell indices, -1 when outside the block. */

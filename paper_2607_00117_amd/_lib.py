@@ -47,7 +47,8 @@ class ObsSpec(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("gram", C.c_int32), ("max_iter", C.c_int32), ("refine_iter", C.c_int32),
-                ("check_every", C.c_int32), ("rho", C.c_double), ("tol", C.c_double),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32),
+                ("rho", C.c_double), ("tol", C.c_double),
                 ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p)]
 
 
@@ -56,7 +57,7 @@ class SolveReport(C.Structure):
                 ("n_active", C.c_int32), ("mu", C.c_double), ("rho", C.c_double), ("kkt", C.c_double),
                 ("objective", C.c_double), ("primal_res", C.c_double), ("dual_res", C.c_double),
                 ("t_prep_ms", C.c_double), ("t_gram_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_admm_ms", C.c_double), ("t_refine_ms", C.c_double)]
+                ("t_admm_ms", C.c_double), ("t_refine_ms", C.c_double), ("nnz", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +109,9 @@ def load():
     L.mlp_pack_bf16.argtypes = [vp, vp, vp]
     L.mlp_mse_grad.argtypes = [vp, vp, i64, vp, vp]
     L.mlp_infer_bf16.argtypes = [vp, vp, i64, vp, vp]
+    L.sw_set_tuning.argtypes = [C.c_char_p, i32]
+    L.sw_get_tuning.argtypes = [C.c_char_p]
+    L.sw_get_tuning.restype = i32
     L.sw_last_error.restype = C.c_char_p
     _L = L
     return L
@@ -295,3 +299,11 @@ def mlp_infer_bf16(packed, x, y):
 
 def mlp_mse_grad(y, t, dy):
     _check(load().mlp_mse_grad(_ptr(y), _ptr(t), y.shape[0], _ptr(dy), _stream()))
+
+
+def set_tuning(key, value):
+    _check(load().sw_set_tuning(key.encode(), int(value)))
+
+
+def get_tuning(key):
+    return load().sw_get_tuning(key.encode())

@@ -9,13 +9,17 @@
 //     orbit matrix as time fractions with consecutive, coalesced stores.
 // No global atomics are used: every orbit's row is owned by one workgroup.
 #include <cstring>
+#include <string>
 
 #include "integrate_impl.h"
 
 namespace sw {
 
 constexpr int kHistThreads = 256;
-constexpr int kHistLdsBytes = 64 * 1024;
+
+int g_waves_per_cu = 0;
+int g_hist_lds_kb = 64;
+int g_num_cus = 256;
 
 template <typename T>
 __global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restrict__ ev, int64_t n_chunk,
@@ -93,6 +97,34 @@ static size_t header_bytes(int32_t n_pot) {
 
 using namespace sw;
 
+extern "C" int sw_set_tuning(const char* key, int32_t value) {
+  SW_CHECK(key, "sw_set_tuning: null key");
+  const std::string k(key);
+  if (k == "integrate_waves_per_cu") {
+    SW_CHECK(value >= 0 && value <= 64, "sw_set_tuning: integrate_waves_per_cu in [0, 64]");
+    g_waves_per_cu = value;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                  hipSuccess && cus > 0)
+      g_num_cus = cus;
+    return SW_OK;
+  }
+  if (k == "hist_lds_kb") {
+    SW_CHECK(value >= 4 && value <= 160, "sw_set_tuning: hist_lds_kb in [4, 160]");
+    g_hist_lds_kb = value;
+    return SW_OK;
+  }
+  SW_CHECK(false, "sw_set_tuning: unknown key %s", key);
+}
+
+extern "C" int32_t sw_get_tuning(const char* key) {
+  if (!key) return -1;
+  const std::string k(key);
+  if (k == "integrate_waves_per_cu") return g_waves_per_cu;
+  if (k == "hist_lds_kb") return g_hist_lds_kb;
+  return -1;
+}
+
 extern "C" size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t n_orb, int32_t n_steps,
                                             int32_t dtype) {
   (void)obs;
@@ -107,7 +139,7 @@ static int launch_hist(const uint64_t* ev, int64_t n_chunk, int32_t n_steps, int
                        hipStream_t st) {
   const int wide = (int64_t)ncopy * n_steps > 65535 ? 1 : 0;
   const int nw = wide ? ncell : (ncell + 1) / 2;
-  int opw = kHistLdsBytes / (4 * nw);
+  int opw = (g_hist_lds_kb * 1024) / (4 * nw);
   if (opw < 1) opw = 1;
   if (opw > 32) opw = 32;
   const size_t lds = (size_t)opw * nw * 4;

@@ -56,7 +56,10 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
   __shared__ uint64_t stm[kStage][kWave + 1];
   __shared__ uint64_t stk[kStage][kWave + 1];
   const int lane = threadIdx.x;
-  const int64_t jbase = (int64_t)blockIdx.x * kWave;  // chunk-local index of lane 0
+  const int64_t n_tiles = (n_chunk + kWave - 1) / kWave;
+  // persistent launch: each wave walks the orbit tiles t = blockIdx.x, + gridDim.x, ...
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  const int64_t jbase = tile * kWave;  // chunk-local index of lane 0
   const int64_t j = jbase + lane;
   const bool valid = j < n_chunk;
   const int64_t o = orb0 + (valid ? j : n_chunk - 1);
@@ -69,7 +72,12 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
   const T dt = dts[o];
   const T h = T(0.5) * dt;
   const double th = P.omega * (double)dt;
+  // FP64 rotates with (cos, sin) exactly as the oracle does.  FP32 rotates with
+  // (cos - 1, sin): cos rounded to binary32 would scale the radius by up to one
+  // ulp of 1 per step, a systematic drift over 10^4 steps, whereas cos - 1 =
+  // -2 sin^2(th/2) keeps its full relative precision.
   const T c = (T)cos(th), sn = (T)sin(th);
+  const T cm1 = (T)(-2.0 * sin(0.5 * th) * sin(0.5 * th));
 
   double sd[6];
 #pragma unroll
@@ -88,11 +96,17 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
     s[0] = s[0] + dt * s[3];
     s[1] = s[1] + dt * s[4];
     s[2] = s[2] + dt * s[5];
-    {
+    if constexpr (sizeof(T) == 8) {
       T x = c * s[0] + sn * s[1];
       T y = c * s[1] - sn * s[0];
       T px = c * s[3] + sn * s[4];
       T py = c * s[4] - sn * s[3];
+      s[0] = x; s[1] = y; s[3] = px; s[4] = py;
+    } else {
+      T x = s[0] + (cm1 * s[0] + sn * s[1]);
+      T y = s[1] + (cm1 * s[1] - sn * s[0]);
+      T px = s[3] + (cm1 * s[3] + sn * s[4]);
+      T py = s[4] + (cm1 * s[4] - sn * s[3]);
       s[0] = x; s[1] = y; s[3] = px; s[4] = py;
     }
     Prec<T>::accel(P, s, g);
@@ -141,6 +155,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
       for (int i = 0; i < 6; ++i) final_state[(int64_t)i * n_orb + o] = s[i];
     }
   }
+  }  // tile loop
 }
 
 struct IntegrateLaunch {
@@ -161,9 +176,21 @@ struct IntegrateLaunch {
   bool bin;
 };
 
+// Process-wide launch knobs (set through sw_set_tuning):
+//  g_waves_per_cu  0: one wave per 64-orbit tile; k > 0: persistent grid of k waves per CU
+//  g_hist_lds_kb   LDS budget of one histogram workgroup (orbits per workgroup follow)
+extern int g_waves_per_cu;
+extern int g_hist_lds_kb;
+extern int g_num_cus;
+
 template <typename T>
 hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
-  dim3 grid((unsigned)((L.n_chunk + kWave - 1) / kWave)), block(kWave);
+  int64_t tiles = (L.n_chunk + kWave - 1) / kWave;
+  if (g_waves_per_cu > 0) {
+    const int64_t cap = (int64_t)g_waves_per_cu * g_num_cus;
+    if (tiles > cap) tiles = cap;
+  }
+  dim3 grid((unsigned)tiles), block(kWave);
   const T* ics = (const T*)L.ics;
   const T* dt = (const T*)L.dt;
   T* fs = (T*)L.final_state;

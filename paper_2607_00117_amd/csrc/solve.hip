@@ -28,6 +28,7 @@
 // is frozen by a per-problem flag while the others continue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -54,6 +55,11 @@ __device__ __forceinline__ int find_problem(const int64_t* __restrict__ off, int
     if (off[mid] <= i) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -130,6 +136,130 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compressed copies of A.  The orbit matrix is mostly zeros (an orbit visits a
+// small part of the grid), so the ADMM passes read compressed rows
+// (orbit-major, for the row dots) and compressed columns (constraint-major,
+// one segment per problem, for the column sums) built once per solve from the
+// dense A.  Entries keep A's precision and ascending index order.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C,
+                                                 int64_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const TA* row = A + i * C;
+  int64_t k = 0;
+  for (int64_t c = lane; c < C; c += 64) k += row[c] != TA(0);
+  for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+  if (lane == 0) cnt[i] = k;
+}
+
+// cpart[b][s][c] = number of nonzeros of column c in slab s of problem b
+template <typename TA>
+__global__ __launch_bounds__(kColThreads) void k_col_nnz(const TA* __restrict__ A, int64_t C,
+                                                         const int64_t* __restrict__ off,
+                                                         const int64_t* __restrict__ rps, int32_t* __restrict__ cpart) {
+  const int b = blockIdx.z;
+  const int64_t c0 = (int64_t)blockIdx.x * kColTile, s = blockIdx.y;
+  const int64_t i_beg = off[b] + s * rps[b];
+  int64_t i_end = i_beg + rps[b];
+  if (i_end > off[b + 1]) i_end = off[b + 1];
+  int32_t k[kColsPerThread] = {0, 0, 0, 0};
+  for (int64_t i = i_beg; i < i_end; ++i) {
+#pragma unroll
+    for (int q = 0; q < kColsPerThread; ++q) {
+      const int64_t c = c0 + threadIdx.x + q * kColThreads;
+      if (c < C) k[q] += A[i * C + c] != TA(0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kColsPerThread; ++q) {
+    const int64_t c = c0 + threadIdx.x + q * kColThreads;
+    if (c < C) cpart[((int64_t)b * kSlabs + s) * C + c] = k[q];
+  }
+}
+
+// compressed rows: one wave per orbit, ballot + prefix count keeps column order
+template <typename TA>
+__global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C,
+                                                  const int64_t* __restrict__ ptr, int32_t* __restrict__ col,
+                                                  TA* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const TA* row = A + i * C;
+  int64_t pos = ptr[i];
+  for (int64_t c0 = 0; c0 < C; c0 += 64) {
+    const int64_t c = c0 + lane;
+    const TA v = c < C ? row[c] : TA(0);
+    const uint64_t m = __ballot(v != TA(0));
+    if (v != TA(0)) {
+      const int64_t at = pos + __popcll(m & ((1ull << lane) - 1ull));
+      col[at] = (int32_t)c;
+      val[at] = v;
+    }
+    pos += __popcll(m);
+  }
+}
+
+// compressed columns of problem b: entries of column c start at
+// cbase[b] + cptr[b][c]; slab s of the column starts slab_off[b][s][c] later
+template <typename TA>
+__global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__ A, int64_t C,
+                                                          const int64_t* __restrict__ off,
+                                                          const int64_t* __restrict__ rps,
+                                                          const int64_t* __restrict__ cptr,
+                                                          const int64_t* __restrict__ cbase,
+                                                          const int32_t* __restrict__ slab_off,
+                                                          int32_t* __restrict__ rowi, TA* __restrict__ val) {
+  const int b = blockIdx.z;
+  const int64_t c0 = (int64_t)blockIdx.x * kColTile, s = blockIdx.y;
+  const int64_t i_beg = off[b] + s * rps[b];
+  int64_t i_end = i_beg + rps[b];
+  if (i_end > off[b + 1]) i_end = off[b + 1];
+  int64_t pos[kColsPerThread];
+#pragma unroll
+  for (int q = 0; q < kColsPerThread; ++q) {
+    const int64_t c = c0 + threadIdx.x + q * kColThreads;
+    pos[q] = c < C ? cbase[b] + cptr[(int64_t)b * (C + 1) + c] + slab_off[((int64_t)b * kSlabs + s) * C + c] : 0;
+  }
+  for (int64_t i = i_beg; i < i_end; ++i) {
+#pragma unroll
+    for (int q = 0; q < kColsPerThread; ++q) {
+      const int64_t c = c0 + threadIdx.x + q * kColThreads;
+      if (c < C) {
+        const TA v = A[i * C + c];
+        if (v != TA(0)) {
+          rowi[pos[q]] = (int32_t)i;
+          val[pos[q]] = v;
+          ++pos[q];
+        }
+      }
+    }
+  }
+}
+
+// column sums from compressed columns: one wave per (problem, column);
+// result in part[b][0][c] (the reduction then reads a single slab)
+template <typename TA, typename TV>
+__global__ __launch_bounds__(256) void k_csc_colsum(int64_t C, const int64_t* __restrict__ cptr,
+                                                    const int64_t* __restrict__ cbase, const int32_t* __restrict__ rowi,
+                                                    const TA* __restrict__ val, const TV* __restrict__ v,
+                                                    double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.y;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= C) return;
+  const int64_t base = cbase[b];
+  const int64_t k0 = base + cptr[(int64_t)b * (C + 1) + c], k1 = base + cptr[(int64_t)b * (C + 1) + c + 1];
+  double acc = 0.0;
+  for (int64_t k = k0 + lane; k < k1; k += 64) acc += (double)val[k] * (double)v[rowi[k]];
+  acc = wave_sum(acc);
+  if (lane == 0) part[(int64_t)b * kSlabs * C + c] = acc;
+}
+
 enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
 
 // t_n = (w~/sigma_n) sum_s part[b][s][n] (COL_OBS: no scaling), per problem b = blockIdx.y:
@@ -138,7 +268,7 @@ enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
 //  COL_RESID: outd = t - y,  acc[b][9] += (t - y)^2
 //  COL_OBS:   outd = t
 // Vectors are [nprob][Cp]; entries in [C, Cp) are written as 0.
-__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int64_t C, int64_t Cp,
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int nslab, int64_t C, int64_t Cp,
                                                    const double* __restrict__ sigma, const double* __restrict__ par,
                                                    int op, const float* __restrict__ kyf, const double* __restrict__ y,
                                                    float* __restrict__ outf, double* __restrict__ outd,
@@ -152,7 +282,7 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
     double t = 0.0;
     if (n < C) {
       const double* pb = part + (int64_t)b * kSlabs * C;
-      for (int64_t s = 0; s < kSlabs; ++s) t += pb[s * C + n];
+      for (int64_t s = 0; s < nslab; ++s) t += pb[s * C + n];
       if (op != COL_OBS) t *= wt / sigma[(int64_t)b * C + n];
     }
     switch (op) {
@@ -217,12 +347,12 @@ struct RowArgs {
   // fp64 stage
   double* qd; double* xd; double* zd; double* ud; double* vd; double* rd;
   double* acc;  // per problem [kAcc]: 0 |x-z|^2, 1 |z-zold|^2, 2 |x|^2, 3 |z|^2, 4 |u|^2, 5 max|q|, 6 kkt max, 7 |z|^2, 9 |e|^2
+  // orbit-major compressed rows of A (used when A is stored sparse)
+  const int64_t* csr_ptr;
+  const int32_t* csr_col;
+  const void* csr_val;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
   // non-negative doubles order like their bit patterns
@@ -230,7 +360,7 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
 }
 
 // One wave per orbit row: dot = sum_n A[i][n] sc[b][n], then the row's update.
-template <typename TA>
+template <typename TA, bool SPARSE>
 __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A, int64_t N, int64_t C,
                                                        const double* __restrict__ sc, RowArgs R) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -239,10 +369,16 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
   const int b = find_problem(R.off, R.nprob, i);
   const double* P = R.par + b * kPar;
   if (P[5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
-  const TA* row = A + i * C;
   const double* scb = sc + (int64_t)b * R.Cp;
   double dot = 0.0;
-  for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
+  if constexpr (SPARSE) {
+    const TA* val = (const TA*)R.csr_val;
+    const int64_t k1 = R.csr_ptr[i + 1];
+    for (int64_t k = R.csr_ptr[i] + lane; k < k1; k += 64) dot += (double)val[k] * scb[R.csr_col[k]];
+  } else {
+    const TA* row = A + i * C;
+    for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
+  }
   dot = wave_sum(dot);
   if (lane != 0) return;
   const bool masked = R.mask && R.mask[i];
@@ -297,7 +433,10 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
       const double k = masked ? 0.0 : fabs(fmin(z, g));
       if (acc) {
         if (k > 0.0) atomic_max_pos(&acc[6], k);
-        if (z != 0.0) atomicAdd(&acc[7], z * z);
+        if (z != 0.0) {
+          atomicAdd(&acc[7], z * z);
+          atomicAdd(&acc[8], 1.0);
+        }
       }
       break;
     }
@@ -380,7 +519,11 @@ struct SolveLayout {
   size_t off_qf, off_zf, off_uf, off_vf;
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
-  size_t off_par, off_acc, off_idx, off_bad, total;
+  size_t off_par, off_acc, off_idx, off_bad;
+  // compressed copies (sized for at most cap_nnz nonzeros)
+  int64_t cap_nnz;
+  size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_cbase, off_crow, off_cval;
+  size_t total;
 };
 
 static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
@@ -417,12 +560,28 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   L.off_acc = take((size_t)P * kAcc * 8);
   L.off_idx = take((size_t)(P + 1) * 8 * 4);
   L.off_bad = take(64);
+  // compressed copies: room for 10% density (or 1M entries), 8-byte values
+  const double dense = (double)L.N * (double)L.C;
+  L.cap_nnz = std::max<int64_t>((int64_t)(0.10 * dense), (int64_t)1 << 20);
+  if ((double)L.cap_nnz > dense) L.cap_nnz = (int64_t)dense;
+  L.off_rcnt = take(N * 8);
+  L.off_cpart = take((size_t)P * kSlabs * L.C * 4);
+  L.off_slab = take((size_t)P * kSlabs * L.C * 4);
+  L.off_rptr = take((N + 1) * 8);
+  L.off_rcol = take((size_t)L.cap_nnz * 4);
+  L.off_rval = take((size_t)L.cap_nnz * 8);
+  L.off_cptr = take((size_t)P * (L.C + 1) * 8);
+  L.off_cbase = take((size_t)(P + 1) * 8);
+  L.off_crow = take((size_t)L.cap_nnz * 4);
+  L.off_cval = take((size_t)L.cap_nnz * 8);
   L.total = o;
   return L;
 }
 
 struct Ctx {
   SolveLayout L;
+  bool sparse = false;
+  int64_t nnz = 0;
   char* ws;
   hipStream_t st;
   const void* A;
@@ -435,6 +594,18 @@ struct Ctx {
 
 template <typename TV>
 static hipError_t colsum(const Ctx& X, const TV* v) {
+  if (X.sparse) {
+    dim3 grid((unsigned)((X.L.C + 3) / 4), (unsigned)X.L.P);
+    if (X.dtype == SW_F32)
+      hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(256), 0, X.st, X.L.C, X.p<int64_t>(X.L.off_cptr),
+                         X.p<int64_t>(X.L.off_cbase), X.p<int32_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
+                         X.p<double>(X.L.off_part));
+    else
+      hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(256), 0, X.st, X.L.C, X.p<int64_t>(X.L.off_cptr),
+                         X.p<int64_t>(X.L.off_cbase), X.p<int32_t>(X.L.off_crow), X.p<double>(X.L.off_cval), v,
+                         X.p<double>(X.L.off_part));
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
   if (X.dtype == SW_F32)
     hipLaunchKernelGGL((k_colsum<float, TV>), grid, dim3(kColThreads), 0, X.st, (const float*)X.A, X.L.C, v, X.off_d,
@@ -447,20 +618,98 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
 
 static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
   hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
-                     X.p<double>(X.L.off_part), X.L.C, X.L.Cp, X.sigma, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
+                     X.p<double>(X.L.off_part), X.sparse ? 1 : kSlabs, X.L.C, X.L.Cp, X.sigma, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
                      outd, acc);
   return hipGetLastError();
 }
 
-static hipError_t rowdot(const Ctx& X, const RowArgs& R) {
+static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
   dim3 grid((unsigned)((X.L.N + 3) / 4));
-  if (X.dtype == SW_F32)
-    hipLaunchKernelGGL(k_rowdot<float>, grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C,
-                       X.p<double>(X.L.off_sc), R);
-  else
-    hipLaunchKernelGGL(k_rowdot<double>, grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
-                       X.p<double>(X.L.off_sc), R);
+  RowArgs R = R0;
+  R.csr_ptr = X.p<int64_t>(X.L.off_rptr);
+  R.csr_col = X.p<int32_t>(X.L.off_rcol);
+  R.csr_val = X.p<void>(X.L.off_rval);
+  const double* sc = X.p<double>(X.L.off_sc);
+  if (X.dtype == SW_F32) {
+    if (X.sparse)
+      hipLaunchKernelGGL((k_rowdot<float, true>), grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C, sc, R);
+    else
+      hipLaunchKernelGGL((k_rowdot<float, false>), grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C, sc,
+                         R);
+  } else {
+    if (X.sparse)
+      hipLaunchKernelGGL((k_rowdot<double, true>), grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
+                         sc, R);
+    else
+      hipLaunchKernelGGL((k_rowdot<double, false>), grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
+                         sc, R);
+  }
   return hipGetLastError();
+}
+
+// Builds the compressed copies of A when they fit; sets X.sparse.
+template <typename TA>
+static int build_sparse(Ctx& X) {
+  const SolveLayout& L = X.L;
+  const int P = L.P;
+  const TA* A = (const TA*)X.A;
+  int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
+  int32_t* cpart = X.p<int32_t>(L.off_cpart);
+  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, rcnt);
+  hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
+                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, cpart);
+  SW_HIP(hipGetLastError());
+  std::vector<int64_t> hr(L.N);
+  std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
+  SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
+  SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
+  SW_HIP(hipStreamSynchronize(X.st));
+  int64_t nnz = 0;
+  std::vector<int64_t> rptr(L.N + 1);
+  for (int64_t i = 0; i < L.N; ++i) {
+    rptr[i] = nnz;
+    nnz += hr[i];
+  }
+  rptr[L.N] = nnz;
+  X.sparse = false;
+  // compressed passes pay off below ~25% density
+  if (nnz > L.cap_nnz || (double)nnz > 0.25 * (double)L.N * (double)L.C) return SW_OK;
+  std::vector<int64_t> cptr((size_t)P * (L.C + 1)), cbase(P + 1);
+  std::vector<int32_t>& slab = hc;  // converted in place to per-slab offsets
+  int64_t base = 0;
+  for (int b = 0; b < P; ++b) {
+    cbase[b] = base;
+    int64_t run = 0;
+    for (int64_t c = 0; c < L.C; ++c) {
+      cptr[(size_t)b * (L.C + 1) + c] = run;
+      int32_t acc = 0;
+      for (int s = 0; s < kSlabs; ++s) {
+        int32_t& v = slab[((size_t)b * kSlabs + s) * L.C + c];
+        const int32_t k = v;
+        v = acc;
+        acc += k;
+      }
+      run += acc;
+    }
+    cptr[(size_t)b * (L.C + 1) + L.C] = run;
+    base += run;
+  }
+  cbase[P] = base;
+  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_rptr), rptr.data(), rptr.size() * 8, hipMemcpyHostToDevice, X.st));
+  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cptr), cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, X.st));
+  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cbase), cbase.data(), cbase.size() * 8, hipMemcpyHostToDevice, X.st));
+  SW_HIP(hipMemcpyAsync(X.p<int32_t>(L.off_slab), slab.data(), slab.size() * 4, hipMemcpyHostToDevice, X.st));
+  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C,
+                     X.p<int64_t>(L.off_rptr), X.p<int32_t>(L.off_rcol), X.p<TA>(L.off_rval));
+  hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
+                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, X.p<int64_t>(L.off_cptr),
+                     X.p<int64_t>(L.off_cbase), X.p<int32_t>(L.off_slab), X.p<int32_t>(L.off_crow), X.p<TA>(L.off_cval));
+  SW_HIP(hipGetLastError());
+  // the host vectors must outlive the copies
+  SW_HIP(hipStreamSynchronize(X.st));
+  X.sparse = true;
+  X.nnz = nnz;
+  return SW_OK;
 }
 
 template <typename TS>
@@ -528,8 +777,8 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     set_error("solve_weights: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SW_ENOMEM;
   }
-  const int max_iter = opt->max_iter > 0 ? opt->max_iter : 500;
-  const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 300 : opt->refine_iter);
+  const int max_iter = opt->max_iter > 0 ? opt->max_iter : 1000;
+  const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 500 : opt->refine_iter);
   const int check_every = opt->check_every > 0 ? opt->check_every : 10;
   const double tol = opt->tol > 0.0 ? opt->tol : 1e-4;
   const double tol_kkt = opt->tol_kkt > 0.0 ? opt->tol_kkt : 1e-7;
@@ -592,6 +841,10 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
                          P, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
                          X.p<float>(L.off_xf));
     SW_TRY(hipGetLastError());
+  }
+  {
+    const int rs = dtype == SW_F32 ? build_sparse<float>(X) : build_sparse<double>(X);
+    if (rs != SW_OK) return rs;
   }
   SW_TRY(hipEventRecord(ev[1], X.st));
 
@@ -690,45 +943,74 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   };
 
   // ---- stage 1: fp32 ADMM ----
+  auto admm_iter = [&](double* accp) -> hipError_t {
+    hipError_t e;
+    if ((e = colsum<float>(X, vf)) != hipSuccess) return e;
+    if ((e = colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st)) != hipSuccess) return e;
+    if ((e = colscale<float>(X, s)) != hipSuccess) return e;
+    RowArgs Ri = RA;
+    Ri.op = ROW_ADMM;
+    Ri.acc = accp;
+    return rowdot(X, Ri);
+  };
+  // The iterations between two convergence checks touch only device memory
+  // (per-problem flags included), so they are captured once and replayed.
+  const bool use_graph = opt->use_graph && X.st != nullptr && check_every > 1;
+  auto capture = [&](auto&& body, int reps, hipGraphExec_t* exec) -> hipError_t {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(X.st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < reps; ++k) {
+      e = body();
+      if (e != hipSuccess) break;
+    }
+    hipError_t e2 = hipStreamEndCapture(X.st, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  };
+  struct ExecGuard {
+    hipGraphExec_t e = nullptr;
+    ~ExecGuard() { if (e) (void)hipGraphExecDestroy(e); }
+  } g1, g2;
+  if (use_graph) SW_TRY(capture([&]() { return admm_iter(nullptr); }, check_every - 1, &g1.e));
   std::vector<int> active(P, 1);
   int n_active = P;
   int it = 0;
-  for (it = 1; it <= max_iter && n_active > 0; ++it) {
-    const bool check = (it % check_every == 0) || it == max_iter;
-    SW_TRY(colsum<float>(X, vf));
-    SW_TRY(colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr));
-    SW_TRY(chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st));
-    SW_TRY(colscale<float>(X, s));
-    RowArgs Ri = RA;
-    Ri.op = ROW_ADMM;
-    if (check) {
-      SW_TRY(zero_acc(X));
+  while (it < max_iter && n_active > 0) {
+    const int run = std::min(check_every - 1, max_iter - 1 - it);
+    if (g1.e && run == check_every - 1) {
+      SW_TRY(hipGraphLaunch(g1.e, X.st));
     } else {
-      Ri.acc = nullptr;
+      for (int k = 0; k < run; ++k) SW_TRY(admm_iter(nullptr));
     }
-    SW_TRY(rowdot(X, Ri));
-    if (check) {
-      // stopping rule of Boyd et al. (2011) on this iteration's residuals
-      SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
-      SW_TRY(hipStreamSynchronize(X.st));
-      for (int b = 0; b < P; ++b) {
-        if (!active[b]) continue;
-        const double* a = &hacc[b * kAcc];
-        const double rp = std::sqrt(a[0]), rdl = rho[b] * std::sqrt(a[1]);
-        const double scale_p = std::fmax(std::sqrt(a[2]), std::sqrt(a[3]));
-        R[b].primal_res = rp / (scale_p + 1e-300);
-        R[b].dual_res = rdl / (rho[b] * std::sqrt(a[4]) + 1e-300);
-        R[b].iters = it;
-        if (rp <= tol * scale_p + 1e-300 && rdl <= tol * rho[b] * std::sqrt(a[4]) + 1e-300) {
-          active[b] = 0;
-          --n_active;
-        }
+    it += run;
+    // the checked iteration accumulates this iteration's residual norms
+    SW_TRY(zero_acc(X));
+    SW_TRY(admm_iter(acc));
+    ++it;
+    // stopping rule of Boyd et al. (2011) on the checked iteration's residuals
+    SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
+    SW_TRY(hipStreamSynchronize(X.st));
+    for (int b = 0; b < P; ++b) {
+      if (!active[b]) continue;
+      const double* a = &hacc[b * kAcc];
+      const double rp = std::sqrt(a[0]), rdl = rho[b] * std::sqrt(a[1]);
+      const double scale_p = std::fmax(std::sqrt(a[2]), std::sqrt(a[3]));
+      R[b].primal_res = rp / (scale_p + 1e-300);
+      R[b].dual_res = rdl / (rho[b] * std::sqrt(a[4]) + 1e-300);
+      R[b].iters = it;
+      if (rp <= tol * scale_p + 1e-300 && rdl <= tol * rho[b] * std::sqrt(a[4]) + 1e-300) {
+        active[b] = 0;
+        --n_active;
       }
-      SW_TRY(set_active(active));
     }
+    SW_TRY(set_active(active));
   }
   for (int b = 0; b < P; ++b)
-    if (R[b].iters == 0) R[b].iters = it - 1;
+    if (R[b].iters == 0) R[b].iters = it;
   SW_TRY(hipEventRecord(ev[5], X.st));
 
   // ---- stage 2: fp64 refinement of the ADMM iterates + KKT ----
@@ -738,6 +1020,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, vf, vd, L.N);
   SW_TRY(hipGetLastError());
   std::vector<double> kkt(P, 0.0), obj(P, 0.0);
+  std::vector<int> support(P, 0);
   auto kkt_eval = [&]() -> int {
     SW_TRY(zero_acc(X));
     SW_TRY(colsum<double>(X, zd));
@@ -751,6 +1034,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     for (int b = 0; b < P; ++b) {
       kkt[b] = hacc[b * kAcc + 6] / qmax[b];
       obj[b] = 0.5 * hacc[b * kAcc + 9] + 0.5 * mu[b] * hacc[b * kAcc + 7];
+      support[b] = (int)hacc[b * kAcc + 8];
     }
     return SW_OK;
   };
@@ -760,37 +1044,47 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   n_active = 0;
   for (int b = 0; b < P; ++b) n_active += active[b];
   SW_TRY(set_active(active));
-  std::vector<int> rit(P, 0);
-  for (int k = 1; k <= refine_iter && n_active > 0; ++k) {
+  auto refine_iter_body = [&]() -> hipError_t {
+    hipError_t e;
     // residual of the ridge system at x_old: r = q + rho v - (U^T U + rho' I) x_old
-    SW_TRY(colsum<double>(X, xd));
-    SW_TRY(colreduce(X, COL_PLAIN, nullptr, nullptr, td, nullptr));
-    SW_TRY(colscale<double>(X, td));
+    if ((e = colsum<double>(X, xd)) != hipSuccess) return e;
+    if ((e = colreduce(X, COL_PLAIN, nullptr, nullptr, td, nullptr)) != hipSuccess) return e;
+    if ((e = colscale<double>(X, td)) != hipSuccess) return e;
     RowArgs Rh = RA;
     Rh.op = ROW_H;
     Rh.acc = nullptr;
-    SW_TRY(rowdot(X, Rh));
+    if ((e = rowdot(X, Rh)) != hipSuccess) return e;
     // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
-    SW_TRY(colsum<double>(X, rd));
-    SW_TRY(colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr));
-    SW_TRY(chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st));
-    SW_TRY(colscale<float>(X, s));
+    if ((e = colsum<double>(X, rd)) != hipSuccess) return e;
+    if ((e = colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st)) != hipSuccess) return e;
+    if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Rc = RA;
     Rc.op = ROW_CORR;
     Rc.acc = nullptr;
-    SW_TRY(rowdot(X, Rc));
-    for (int b = 0; b < P; ++b)
-      if (active[b]) rit[b] = k;
-    if (k % check_every == 0 || k == refine_iter) {
-      rc = kkt_eval();
-      if (rc != SW_OK) return rc;
-      for (int b = 0; b < P; ++b)
-        if (active[b] && kkt[b] <= tol_kkt) {
-          active[b] = 0;
-          --n_active;
-        }
-      SW_TRY(set_active(active));
+    return rowdot(X, Rc);
+  };
+  if (use_graph && n_active > 0) SW_TRY(capture(refine_iter_body, check_every, &g2.e));
+  std::vector<int> rit(P, 0);
+  int k_done = 0;
+  while (k_done < refine_iter && n_active > 0) {
+    const int run = std::min(check_every, refine_iter - k_done);
+    if (g2.e && run == check_every) {
+      SW_TRY(hipGraphLaunch(g2.e, X.st));
+    } else {
+      for (int k = 0; k < run; ++k) SW_TRY(refine_iter_body());
     }
+    k_done += run;
+    for (int b = 0; b < P; ++b)
+      if (active[b]) rit[b] = k_done;
+    rc = kkt_eval();
+    if (rc != SW_OK) return rc;
+    for (int b = 0; b < P; ++b)
+      if (active[b] && kkt[b] <= tol_kkt) {
+        active[b] = 0;
+        --n_active;
+      }
+    SW_TRY(set_active(active));
   }
   int all_conv = 1;
   for (int b = 0; b < P; ++b) {
@@ -798,6 +1092,8 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     R[b].kkt = kkt[b];
     R[b].objective = obj[b];
     R[b].converged = kkt[b] <= tol_kkt ? 1 : 0;
+    R[b].n_active = support[b];
+    R[b].nnz = X.sparse ? (double)X.nnz : 0.0;
     all_conv &= R[b].converged;
   }
   hipLaunchKernelGGL(k_scale_out, dim3(blocks_for(L.N)), dim3(256), 0, X.st, zd, L.N, X.off_d, P, X.par, w);

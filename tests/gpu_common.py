@@ -40,13 +40,13 @@ def gpu_integrate(cfg, ics, dt, n_steps, dtype, obs=None, components=None, omega
     return A.cpu().numpy(), ov.cpu().numpy(), dr.cpu().numpy(), fl.cpu().numpy()
 
 
-def oracle_integrate(cfg, ics, dt, n_steps, obs=None, components=None, omega=None, euler=None):
+def oracle_integrate(cfg, ics, dt, n_steps, obs=None, components=None, omega=None, euler=None, f32_state=False):
     import oracle as O
     comps = cfg["components"] if components is None else components
     pot = O.make_pot(comps, cfg["omega"] if omega is None else omega)
     R = O.euler_matrix(*(cfg["euler"] if euler is None else euler))
     ob = O.make_obs(dict(cfg["obs"] if obs is None else obs), R)
-    return O.integrate_and_bin(pot, ob, ics, dt, n_steps)
+    return O.integrate_and_bin(pot, ob, ics, dt, n_steps, f32_state=f32_state)
 
 
 def counts_from_fractions(A, n_steps, ncopy=4):

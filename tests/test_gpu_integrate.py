@@ -110,8 +110,13 @@ def test_ragged_shapes_fp64(gpu, n, n_steps, sym):
 def test_barred_fp32_subsample_vs_fp64_oracle(gpu):
     """Barred model (MN + Ferrers + flattened NFW, 40 km/s/kpc) in FP32 against the
     FP64 oracle on the seeded 1,000-orbit subsample of the 100,000-orbit library,
-    full 10,000 steps: exact per-block normalisation, Jacobi-drift parity and
-    per-orbit time-fraction agreement."""
+    full 10,000 steps.  Exact: per-block normalisation of every row.  Jacobi
+    drift: median |drift_f32 - drift_f64| <= 1e-5.  Time fractions: chaotic
+    orbits of a rotating bar amplify any rounding difference, so the per-orbit
+    L1 distance between GPU and oracle rows is compared with the distance
+    between the oracle and the oracle whose state is rounded to binary32 after
+    every step (the error any FP32 integrator carries): the GPU must not
+    decorrelate much faster than that floor."""
     cfg = W.BARRED
     n_steps = cfg["n_steps"]
     table = W.load_table(cfg["table"])
@@ -119,19 +124,23 @@ def test_barred_fp32_subsample_vs_fp64_oracle(gpu):
     sub = W.subsample_draw(cfg["n_orb"], cfg["subsample"]["n"], cfg["subsample"]["seed"])
     ics32, dt32 = ics[:, sub].astype(np.float32), dt[sub].astype(np.float32)
     A, ov, dr, fl = gpu_integrate(cfg, ics32, dt32, n_steps, "f32")
-    # the oracle integrates the same (fp32-rounded) initial conditions in fp64
-    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ics32.astype(np.float64), dt32.astype(np.float64), n_steps)
+    ic64, dt64 = ics32.astype(np.float64), dt32.astype(np.float64)
+    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ic64, dt64, n_steps)
+    c_p, *_ = oracle_integrate(cfg, ic64, dt64, n_steps, f32_state=True)
     c_g = counts_from_fractions(A, n_steps)
     nm = 30 * 30 * 20
     ovc = np.rint(ov * 4 * n_steps).astype(np.int64)
     assert np.all(c_g[:, :nm].sum(1) + ovc[:, 0] == 4 * n_steps)
     assert np.all(c_g[:, nm:].sum(1) + ovc[:, 1] == 4 * n_steps)
-    A_o = O.time_fractions(c_o, n_steps)
-    l1 = np.abs(A.astype(np.float64) - A_o).sum(1) / 2  # per orbit, both blocks (max 2 -> 1)
+    A_o, A_p = O.time_fractions(c_o, n_steps), O.time_fractions(c_p, n_steps)
+    l1 = np.abs(A.astype(np.float64) - A_o).sum(1) / 2
+    l1_ref = np.abs(A_p - A_o).sum(1) / 2
     ddr = np.abs(dr - dr_o)
-    print(f"row L1 median {np.median(l1):.3g} p90 {np.percentile(l1, 90):.3g}; "
+    print(f"row L1 gpu-vs-oracle median {np.median(l1):.3g} p90 {np.percentile(l1, 90):.3g}; "
+          f"oracle-vs-fp32-state-oracle median {np.median(l1_ref):.3g} p90 {np.percentile(l1_ref, 90):.3g}; "
           f"|drift_f32 - drift_f64| median {np.median(ddr):.3g} p90 {np.percentile(ddr, 90):.3g}; "
-          f"drift median {np.median(dr_o):.3g}; flagged {np.mean(fl & 1):.4f} vs {np.mean(fl_o & 1):.4f}")
+          f"flagged {np.mean(fl & 1):.4f} vs {np.mean(fl_o & 1):.4f}")
     assert np.median(ddr) <= 1e-5
-    assert np.median(l1) < 0.02
+    assert np.median(l1) <= 2.0 * np.median(l1_ref) + 0.01
+    assert np.percentile(l1, 90) <= 2.0 * np.percentile(l1_ref, 90) + 0.02
     assert abs(np.mean(fl & 1) - np.mean(fl_o & 1)) <= 0.01
