@@ -22,9 +22,10 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
 
 // C = beta C + alpha A B^T per problem (fp32 MFMA, fp32 accumulate).
 // M, N, K multiples of 128 (K multiple of 32).  lower: only tiles with tile_m >= tile_n.
+// a_lower: A is lower triangular in 128-tiles (row tile m reads k < 128 (m + 1) only).
 hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, int64_t sA,
                        const float* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
-                       bool lower, int nb, hipStream_t st);
+                       bool lower, int nb, hipStream_t st, bool a_lower = false);
 
 // Blocked right-looking Cholesky of each n x n (n multiple of 128) SPD matrix
 // in the lower triangle of K_b (row-major, ld); the factor overwrites it and
@@ -33,9 +34,16 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
 hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb, hipStream_t st,
                     int* bad);
 
-// Solves (L_b L_b^T) s_b = r_b (fp32, vectors of length n at stride sv);
-// tmp: scratch of the same shape; r is overwritten.
-hipError_t chol_solve(const float* L, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb,
-                      float* r, float* tmp, float* s, int64_t sv, hipStream_t st);
+// Replaces the factor L_b (lower triangle of K_b, as left by cholesky) with
+// S_b = W + W^T - diag(W), W = L_b^-1, filling the whole n x n buffer.
+// Scratch per problem: Pt [128][n] (stride sPt), Xb [n][128] (sX), Dt [128][128] (sDt).
+hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb,
+                         float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, hipStream_t st);
+
+// s_b = (L_b L_b^T)^-1 r_b = W^T (W r_b) from S_b (fp32, vectors of length n at
+// stride sv; tmp: scratch of the same shape).  Problems with act[b * act_stride]
+// == 0 are skipped (act may be null).
+hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb, const float* r, float* tmp, float* s,
+                     int64_t sv, const double* act, int act_stride, hipStream_t st);
 
 }  // namespace sw

@@ -1,6 +1,7 @@
 // MFMA kernels of the weight solve: the constraint-space Gram matrix, the
-// fp32 GEMM used by the blocked Cholesky factorisation, the diagonal-block
-// factor + inverse, and the blocked triangular solves.
+// fp32 GEMM used by the blocked Cholesky factorisation and the inversion of
+// its factor, the diagonal-block factor + inverse, and the matrix-vector
+// products that apply the inverse.
 //
 // Tiling: a 256-thread workgroup (4 waves in a 2 x 2 grid) owns a 128 x 128
 // output tile; each wave owns 64 x 64 = 2 x 2 blocks of the 32 x 32 MFMA
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
                                                           const float* __restrict__ A, int64_t lda, int64_t sA,
                                                           const float* __restrict__ B, int64_t ldb, int64_t sB,
                                                           float beta, float* __restrict__ C, int64_t ldc, int64_t sC,
-                                                          int lower, int64_t n_tiles) {
+                                                          int lower, int a_lower, int64_t n_tiles) {
   A += blockIdx.y * sA;
   B += blockIdx.y * sB;
   C += blockIdx.y * sC;
@@ -173,8 +174,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
       rb[i] = *reinterpret_cast<const float4*>(Bb + (int64_t)r * ldb + k0 + c);
     }
   };
+  // a_lower: A is lower triangular in 128-tiles, so row tile tm needs k < (tm + 1) * 128 only
+  const int64_t Kend = (a_lower && (tm + 1) * kT < K) ? (tm + 1) * kT : K;
   gload(0);
-  for (int64_t k0 = 0; k0 < K; k0 += kBKf) {
+  for (int64_t k0 = 0; k0 < Kend; k0 += kBKf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + kThreads * i;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
       Bs[r][c] = rb[i].x; Bs[r][c + 1] = rb[i].y; Bs[r][c + 2] = rb[i].z; Bs[r][c + 3] = rb[i].w;
     }
     __syncthreads();
-    if (k0 + kBKf < K) gload(k0 + kBKf);
+    if (k0 + kBKf < Kend) gload(k0 + kBKf);
 #pragma unroll
     for (int kk = 0; kk < kBKf; kk += 2) {
       const int kc = kk + (lane >> 5);
@@ -276,70 +279,110 @@ __global__ __launch_bounds__(kThreads) void k_potrf_diag(float* __restrict__ Kd,
 }
 
 // ---------------------------------------------------------------------------
-// Blocked triangular solves.  Step j of the forward solve: every workgroup
-// forms z_j = inv(L_jj) r_j; workgroup 0 stores it, workgroup b >= 1 updates
-// r_{j+b} -= L_{j+b,j} z_j.  The backward solve mirrors it with L^T.
+// Explicit inverse of the Cholesky factor, W = L^-1, and its application.
+// The factor buffer ends up holding S = W + W^T - diag(W): W in the lower
+// triangle, W^T in the upper one (they agree on the diagonal), so that
+//   (L L^T)^-1 r = W^T (W r)
+// is two row-major matrix-vector products over the two halves of S, each a
+// single HBM-bound pass with no dependency chain between row blocks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_trsv_fwd(const float* __restrict__ L, int64_t ld, int64_t sK,
-                                                       const float* __restrict__ dinv, int64_t sD, int64_t j,
-                                                       float* __restrict__ r, float* __restrict__ z, int64_t sv) {
-  __shared__ float rj[kNB], zj[kNB];
-  L += blockIdx.y * sK;
-  dinv += blockIdx.y * sD;
-  r += blockIdx.y * sv;
-  z += blockIdx.y * sv;
-  const int tid = threadIdx.x;
-  if (tid < kNB) rj[tid] = r[j * kNB + tid];
+constexpr int kTT = 64;  // transpose tile
+
+// dst[c][r] = src[r][c] for a rows x cols block (both multiples of 64)
+__global__ __launch_bounds__(kThreads) void k_transpose(const float* __restrict__ src, int64_t lds, int64_t sS,
+                                                        float* __restrict__ dst, int64_t ldd, int64_t sDst,
+                                                        int64_t tiles_c) {
+  __shared__ float t[kTT][kTT + 1];
+  src += blockIdx.y * sS;
+  dst += blockIdx.y * sDst;
+  const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x - tr * tiles_c;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < kTT; i += 4) t[i][tx] = src[(tr * kTT + i) * lds + tc * kTT + tx];
   __syncthreads();
-  const int row = tid >> 1, half = tid & 1;
-  const float* Dj = dinv + j * kNB * kNB;
-  float s = 0.0f;
-  for (int c = half * 64; c < half * 64 + 64; ++c) s += Dj[row * kNB + c] * rj[c];
-  s += __shfl_xor(s, 1, 64);
-  if (half == 0) zj[row] = s;
-  __syncthreads();
-  const int64_t b = blockIdx.x;
-  if (b == 0) {
-    if (tid < kNB) z[j * kNB + tid] = zj[tid];
-    return;
-  }
-  const int64_t i = j + b;
-  const float* Li = L + (i * kNB + row) * ld + j * kNB;
-  float u = 0.0f;
-  for (int c = half * 64; c < half * 64 + 64; ++c) u += Li[c] * zj[c];
-  u += __shfl_xor(u, 1, 64);
-  if (half == 0) r[i * kNB + row] -= u;
+  for (int i = ty; i < kTT; i += 4) dst[(tc * kTT + i) * ldd + tr * kTT + tx] = t[tx][i];
 }
 
-__global__ __launch_bounds__(kThreads) void k_trsv_bwd(const float* __restrict__ L, int64_t ld, int64_t sK,
-                                                       const float* __restrict__ dinv, int64_t sD, int64_t j,
-                                                       float* __restrict__ z, float* __restrict__ x, int64_t sv) {
-  __shared__ float zj[kNB], xj[kNB];
-  L += blockIdx.y * sK;
+// diagonal block j of the factor buffer <- inv(L_jj) (lower, zeros above)
+__global__ __launch_bounds__(kThreads) void k_set_diag_inv(float* __restrict__ K, int64_t ld, int64_t sK,
+                                                           const float* __restrict__ dinv, int64_t sD) {
+  K += blockIdx.y * sK;
   dinv += blockIdx.y * sD;
-  z += blockIdx.y * sv;
-  x += blockIdx.y * sv;
-  const int tid = threadIdx.x;
-  if (tid < kNB) zj[tid] = z[j * kNB + tid];
-  __syncthreads();
-  const float* Dj = dinv + j * kNB * kNB;
-  if (tid < kNB) {  // x_j = inv(L_jj)^T z_j
-    float s = 0.0f;
-    for (int c = tid; c < kNB; ++c) s += Dj[c * kNB + tid] * zj[c];
-    xj[tid] = s;
+  const int64_t j = blockIdx.x;
+  const float* D = dinv + j * kNB * kNB;
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += kThreads) {
+    const int r = idx / kNB, c = idx - r * kNB;
+    K[(j * kNB + r) * ld + j * kNB + c] = D[idx];
   }
+}
+
+// S[c][r] = S[r][c] for r > c: the strictly lower triangle mirrored upward,
+// one 64 x 64 tile on or below the diagonal per workgroup
+__global__ __launch_bounds__(kThreads) void k_mirror_lower(float* __restrict__ S, int64_t ld, int64_t sK) {
+  __shared__ float t[kTT][kTT + 1];
+  S += blockIdx.y * sK;
+  int64_t tr, tc;
+  tri_tile(blockIdx.x, tr, tc);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < kTT; i += 4) t[i][tx] = S[(tr * kTT + i) * ld + tc * kTT + tx];
   __syncthreads();
-  const int64_t b = blockIdx.x;
-  if (b == 0) {
-    if (tid < kNB) x[j * kNB + tid] = xj[tid];
-    return;
+  for (int i = ty; i < kTT; i += 4) {
+    // destination row tc*64+i, column tr*64+tx holds source (tr*64+tx, tc*64+i)
+    if (tr != tc || tx > i) S[(tc * kTT + i) * ld + tr * kTT + tx] = t[tx][i];
   }
-  const int64_t i = j - b;  // column block of L_{j,i}
-  if (tid < kNB) {
-    const int c = tid;
-    float u = 0.0f;
-    for (int rr = 0; rr < kNB; ++rr) u += L[(j * kNB + rr) * ld + i * kNB + c] * xj[rr];
-    z[i * kNB + c] -= u;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// y = T x over one half of S (LOWER: j <= i, else j >= i).  One wave owns the
+// row pair (i, n-1-i), so every wave streams n+1 entries; loads of S bypass
+// the caches (each entry is read once) while x stays resident in L2.
+template <bool LOWER>
+__device__ __forceinline__ float trmv_row(const float* __restrict__ Sr, const float* __restrict__ x, int64_t i,
+                                          int64_t n, int lane) {
+  int64_t j0 = LOWER ? 0 : i, j1 = LOWER ? i + 1 : n;
+  float acc = 0.0f;
+  // unaligned head (UPPER) / tail (LOWER), at most 3 entries
+  const int64_t a0 = (j0 + 3) & ~(int64_t)3, a1 = j1 & ~(int64_t)3;
+  if (lane < a0 - j0) acc += Sr[j0 + lane] * x[j0 + lane];
+  if (lane < j1 - a1 && a1 >= a0) acc += Sr[a1 + lane] * x[a1 + lane];
+  float acc2 = 0.0f;
+  int64_t j = a0 + 4 * lane;
+  for (; j + 256 < a1; j += 512) {
+    const f32x4 s0 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(Sr + j));
+    const f32x4 s1 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(Sr + j + 256));
+    const f32x4 x0 = *reinterpret_cast<const f32x4*>(x + j);
+    const f32x4 x1 = *reinterpret_cast<const f32x4*>(x + j + 256);
+    acc += s0[0] * x0[0] + s0[1] * x0[1] + s0[2] * x0[2] + s0[3] * x0[3];
+    acc2 += s1[0] * x1[0] + s1[1] * x1[1] + s1[2] * x1[2] + s1[3] * x1[3];
+  }
+  if (j < a1) {
+    const f32x4 s0 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(Sr + j));
+    const f32x4 x0 = *reinterpret_cast<const f32x4*>(x + j);
+    acc += s0[0] * x0[0] + s0[1] * x0[1] + s0[2] * x0[2] + s0[3] * x0[3];
+  }
+  acc += acc2;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  return acc;
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(kThreads) void k_trmv(const float* __restrict__ S, int64_t n, int64_t ld, int64_t sK,
+                                                   const float* __restrict__ x, float* __restrict__ y, int64_t sv,
+                                                   const double* __restrict__ act, int act_stride) {
+  const int64_t b = blockIdx.y;
+  if (act && act[b * act_stride] == 0.0) return;
+  S += b * sK;
+  x += b * sv;
+  y += b * sv;
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (wv >= n / 2) return;
+  const int64_t i0 = wv, i1 = n - 1 - wv;
+  const float v0 = trmv_row<LOWER>(S + i0 * ld, x, i0, n, lane);
+  const float v1 = trmv_row<LOWER>(S + i1 * ld, x, i1, n, lane);
+  if (lane == 0) {
+    y[i0] = v0;
+    y[i1] = v1;
   }
 }
 
@@ -371,13 +414,13 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
 
 hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, int64_t sA,
                        const float* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
-                       bool lower, int nb, hipStream_t st) {
+                       bool lower, int nb, hipStream_t st, bool a_lower) {
   const int64_t ntm = M / kT, ntn = N / kT;
   const int64_t n_tiles = lower ? ntm * (ntm + 1) / 2 : ntm * ntn;
   if (n_tiles == 0) return hipSuccess;
   const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
   hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st, ntn, K, alpha, A, lda,
-                     sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, n_tiles);
+                     sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles);
   return hipGetLastError();
 }
 
@@ -405,15 +448,41 @@ hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, in
   return hipSuccess;
 }
 
-hipError_t chol_solve(const float* L, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
-                      float* r, float* tmp, float* s, int64_t sv, hipStream_t st) {
+hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
+                         float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, hipStream_t st) {
   const int64_t nb = n / kNB;
-  for (int64_t j = 0; j < nb; ++j)
-    hipLaunchKernelGGL(k_trsv_fwd, dim3((unsigned)(nb - j), (unsigned)nb_prob), dim3(kThreads), 0, st, L, ld, sK,
-                       dinv, sD, j, r, tmp, sv);
-  for (int64_t j = nb - 1; j >= 0; --j)
-    hipLaunchKernelGGL(k_trsv_bwd, dim3((unsigned)(j + 1), (unsigned)nb_prob), dim3(kThreads), 0, st, L, ld, sK,
-                       dinv, sD, j, tmp, s, sv);
+  hipError_t e;
+  hipLaunchKernelGGL(k_set_diag_inv, dim3((unsigned)nb, (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld, sK, dinv, sD);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // column blocks right to left: W_{>j,j} = -W_{>j,>j} L_{>j,j} inv(L_jj)
+  for (int64_t j = nb - 2; j >= 0; --j) {
+    const int64_t r0 = (j + 1) * kNB, rest = n - r0;
+    float* panel = K + r0 * ld + j * kNB;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)(rest / kTT * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
+                       st, panel, ld, sK, Pt, n, sPt, (int64_t)(kNB / kTT));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = gemm_nt_f32(rest, kNB, rest, 1.0f, K + r0 * ld + r0, ld, sK, Pt, n, sPt, 0.0f, Xb, kNB, sX, false, nb_prob, st,
+                    true);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((kNB / kTT) * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
+                       st, dinv + j * kNB * kNB, (int64_t)kNB, sD, Dt, (int64_t)kNB, sDt, (int64_t)(kNB / kTT));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = gemm_nt_f32(rest, kNB, kNB, -1.0f, Xb, kNB, sX, Dt, kNB, sDt, 0.0f, panel, ld, sK, false, nb_prob, st);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t t = n / kTT;
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)(t * (t + 1) / 2), (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld,
+                     sK);
+  return hipGetLastError();
+}
+
+hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,
+                     float* s, int64_t sv, const double* act, int act_stride, hipStream_t st) {
+  const unsigned g = (unsigned)((n / 2 + kThreads / 64 - 1) / (kThreads / 64));
+  hipLaunchKernelGGL(k_trmv<true>, dim3(g, (unsigned)nb_prob), dim3(kThreads), 0, st, S, n, ld, sK, r, tmp, sv, act,
+                     act_stride);
+  hipLaunchKernelGGL(k_trmv<false>, dim3(g, (unsigned)nb_prob), dim3(kThreads), 0, st, S, n, ld, sK, tmp, s, sv, act,
+                     act_stride);
   return hipGetLastError();
 }
 

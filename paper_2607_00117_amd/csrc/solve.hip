@@ -7,9 +7,11 @@
 //   (U^T U + rho' I) x = q + rho (z - u),  q = U^T y,  rho' = rho + mu,
 // done in constraint space with the Woodbury identity
 //   x = (1/rho') (b - U^T (rho' I + U U^T)^{-1} U b),
-// where U U^T is formed once by the MFMA Gram kernel and factorised once by
-// the blocked Cholesky; the z-update clips to w >= 0 (over-relaxed) and u
-// carries the scaled dual.  Every pass over U streams A itself (orbit-major)
+// where U U^T is formed once by the MFMA Gram kernel, factorised once by the
+// blocked Cholesky, and the factor inverted once (W = L^-1), so that every
+// x-update applies (rho' I + U U^T)^-1 = W^T W as two HBM-bound matrix-vector
+// passes; the z-update clips to w >= 0 (over-relaxed) and u carries the
+// scaled dual.  Every pass over U streams A itself (orbit-major)
 // with the scaling folded into per-constraint multipliers:
 //   column sums   t_n = (w~/sigma_n) sum_i A[i][n] v_i       (U v)
 //   row dots      h_i = sum_n A[i][n] (w~ s_n / sigma_n)     (U^T s)
@@ -519,7 +521,7 @@ struct SolveLayout {
   size_t off_qf, off_zf, off_uf, off_vf;
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
-  size_t off_par, off_acc, off_idx, off_bad;
+  size_t off_par, off_acc, off_idx, off_bad, off_pt, off_xb, off_dt;
   // compressed copies (sized for at most cap_nnz nonzeros)
   int64_t cap_nnz;
   size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_cbase, off_crow, off_cval;
@@ -560,6 +562,9 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   L.off_acc = take((size_t)P * kAcc * 8);
   L.off_idx = take((size_t)(P + 1) * 8 * 4);
   L.off_bad = take(64);
+  L.off_pt = take((size_t)P * kNB * L.Cp * 4);
+  L.off_xb = take((size_t)P * L.Cp * kNB * 4);
+  L.off_dt = take((size_t)P * kNB * kNB * 4);
   // compressed copies: room for 10% density (or 1M entries), 8-byte values
   const double dense = (double)L.N * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(0.10 * dense), (int64_t)1 << 20);
@@ -892,6 +897,8 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, X.st, bad, (int64_t)1, 0);
   float* dinv = X.p<float>(L.off_dinv);
   SW_TRY(cholesky(K, L.Cp, L.Cp, sK, dinv, sD, P, X.st, bad));
+  SW_TRY(invert_factor(K, L.Cp, L.Cp, sK, dinv, sD, P, X.p<float>(L.off_pt), kNB * L.Cp, X.p<float>(L.off_xb),
+                       L.Cp * kNB, X.p<float>(L.off_dt), kNB * kNB, X.st));
   SW_TRY(hipEventRecord(ev[4], X.st));
   int hbad = 0;
   SW_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, X.st));
@@ -947,7 +954,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     hipError_t e;
     if ((e = colsum<float>(X, vf)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st)) != hipSuccess) return e;
+    if ((e = inv_apply(K, L.Cp, L.Cp, sK, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Ri = RA;
     Ri.op = ROW_ADMM;
@@ -1057,7 +1064,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
     if ((e = colsum<double>(X, rd)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = chol_solve(K, L.Cp, L.Cp, sK, dinv, sD, P, r, tmp, s, L.Cp, X.st)) != hipSuccess) return e;
+    if ((e = inv_apply(K, L.Cp, L.Cp, sK, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Rc = RA;
     Rc.op = ROW_CORR;
