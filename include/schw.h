@@ -172,15 +172,18 @@ size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t 
 #define SW_GRAM_BF16 0   /* U rounded to bf16, one MFMA pass, fp32 accumulate         */
 #define SW_GRAM_BF16X3 1 /* U split hi+lo bf16, three MFMA passes, fp32 accumulate    */
 #define SW_GRAM_F32 2    /* fp32 MFMA, fp32 accumulate                                */
+#define SW_SOLVE_DENSE 1 /* sw_solve_opts.flags: keep the dense passes over A          */
 
 typedef struct {
   int32_t gram;        /* SW_GRAM_* */
-  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 1000) */
+  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 1000); the stage also
+                          ends once max(primal, dual) residual stops falling (below 0.9x
+                          its value 5 checks earlier), the FP64 stage then continues */
   int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 500) */
   int32_t check_every; /* convergence checked every this many iterations (<= 0: 10) */
   int32_t use_graph;   /* 1: the iterations between two checks are captured once into a HIP
                           graph and replayed (needs a non-NULL stream); 0: plain launches */
-  int32_t reserved;
+  int32_t flags;       /* SW_SOLVE_DENSE: stream the dense A in every pass (no compressed copy) */
   double rho;          /* ADMM penalty for the scaled problem (<= 0: trace(U U^T) / N) */
   double tol;          /* relative primal/dual tolerance of the FP32 stage (<= 0: 1e-4) */
   double tol_kkt;      /* target relative KKT residual of the FP64 stage (<= 0: 1e-7) */

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 SW_F32, SW_F64 = 1, 2
 SW_GRAM_BF16, SW_GRAM_BF16X3, SW_GRAM_F32 = 0, 1, 2
+SW_SOLVE_DENSE = 1
 SW_FLAG_DRIFT, SW_FLAG_NONFINITE = 1, 2
 KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6}
 
@@ -47,7 +48,7 @@ class ObsSpec(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("gram", C.c_int32), ("max_iter", C.c_int32), ("refine_iter", C.c_int32),
-                ("check_every", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32), ("flags", C.c_int32),
                 ("rho", C.c_double), ("tol", C.c_double),
                 ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p)]
 

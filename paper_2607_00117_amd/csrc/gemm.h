@@ -14,8 +14,10 @@ constexpr int kNB = 128;  // Cholesky / triangular-solve block size, also the GE
 //  mode SW_GRAM_BF16:   X = hi (bf16)
 //  mode SW_GRAM_BF16X3: X = hi + lo (bf16 pair), K ~ hi hi^T + hi lo^T + lo hi^T
 //  mode SW_GRAM_F32:    X = xf (fp32)
-// M (rows of X, multiple of 128), ld = row stride of X; xoff/xlen given on the
-// device (bf16 modes) and on the host (fp32 mode); K_b = K + b * sK.
+// M = rows of K (multiple of 128); X has gram_rows(M) rows (bf16 modes: a
+// multiple of 256, rows past M zero), ld = row stride of X; xoff/xlen given on
+// the device (bf16 modes) and on the host (fp32 mode); K_b = K + b * sK.
+inline int64_t gram_rows(int mode, int64_t M) { return mode == SW_GRAM_F32 ? M : (M + 255) / 256 * 256; }
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
                 const int64_t* xlen_d, const int64_t* xoff_h, const int64_t* xlen_h, int nb, float* K, int64_t ldk,
                 int64_t sK, hipStream_t st);

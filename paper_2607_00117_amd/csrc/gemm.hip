@@ -29,6 +29,19 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   return t;  // may exceed nb - 1 for the last XCD; caller checks
 }
 
+// Super-tiled schedule of a lower-triangular tile grid (nt x nt tiles).  The
+// grid is cut into kSuper x kSuper super-tiles; super-tile s (lower triangle,
+// row-major) is processed by XCD s mod 8 as kSuper^2 consecutive workgroups of
+// that XCD, so the workgroups resident on one XCD at a time share kSuper row
+// panels and kSuper column panels in its L2 instead of streaming a new panel
+// each.  Workgroup ids are dealt to XCDs round-robin (id mod 8).
+constexpr int kSuper = 8;
+
+__device__ __forceinline__ int64_t super_count(int64_t nt) {
+  const int64_t S = (nt + kSuper - 1) / kSuper;
+  return S * (S + 1) / 2;
+}
+
 // tile id -> (row tile, col tile) over the lower triangle, row-major
 __device__ __forceinline__ void tri_tile(int64_t t, int64_t& tm, int64_t& tn) {
   int64_t m = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -38,97 +51,150 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t& tm, int64_t& tn) {
   tn = t - m * (m + 1) / 2;
 }
 
+// workgroup id -> tile of the super-tiled schedule; false when the workgroup
+// has no tile (above the diagonal of a diagonal super-tile, or past the edge)
+__device__ __forceinline__ bool super_tile(int64_t b, int64_t nt, int64_t& tm, int64_t& tn) {
+  const int64_t x = b % kXcd, r = b / kXcd;
+  const int64_t s = (r / (kSuper * kSuper)) * kXcd + x, q = r % (kSuper * kSuper);
+  if (s >= super_count(nt)) return false;
+  int64_t I, J;
+  tri_tile(s, I, J);
+  tm = I * kSuper + q / kSuper;
+  tn = J * kSuper + q % kSuper;
+  return tm < nt && tn <= tm;
+}
+
+// number of workgroups for the super-tiled schedule
+static int64_t super_grid(int64_t nt) {
+  const int64_t S = (nt + kSuper - 1) / kSuper;
+  const int64_t ns = S * (S + 1) / 2;
+  return ((ns + kXcd - 1) / kXcd) * kXcd * kSuper * kSuper;
+}
+
 // ---------------------------------------------------------------------------
 // Gram: K[m][n] = sum_k X[m][k] X[n][k], bf16 operands, fp32 accumulate.
+//
+// A 512-thread workgroup owns a 256 x 256 tile of K; its 8 waves form a
+// 2 x 4 grid of 128 x 64 blocks (4 x 2 MFMA 32x32 outputs each), so a wave
+// issues 24 (X3: hi.hi + hi.lo + lo.hi) MFMAs per 12 operand reads from LDS.
+// Operands stream through LDS in k-stages of 32 (rows padded to 80 bytes so
+// the 16-byte reads of a half-wave hit distinct banks); the next stage is
+// fetched into registers while the current one is consumed.  On diagonal
+// tiles the row and column panels coincide and are staged once.
+// X has Mx rows (a multiple of 256, zero past the constraints); entries of K
+// are stored for rows and columns below M only.
 // ---------------------------------------------------------------------------
-constexpr int kBKb = 64;            // k per LDS stage (bf16)
-constexpr int kPadB = kBKb + 8;     // padded row (elements): 144 B rows
+constexpr int kGT = 256;
+constexpr int kGThreads = 512;
+constexpr int kGBK = 32;
+constexpr int kGPad = kGBK + 8;
 
 template <bool X3>
-__global__ __launch_bounds__(kThreads) void k_gram_bf16(const __bf16* __restrict__ hi, const __bf16* __restrict__ lo,
-                                                        const int64_t* __restrict__ xoff, const int64_t* __restrict__ xlen,
-                                                        int64_t ld, float* __restrict__ Kall, int64_t ldk, int64_t sK,
-                                                        int64_t n_tiles) {
+__global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restrict__ hi, const __bf16* __restrict__ lo,
+                                                         const int64_t* __restrict__ xoff,
+                                                         const int64_t* __restrict__ xlen, int64_t ld,
+                                                         float* __restrict__ Kall, int64_t ldk, int64_t sK, int64_t M,
+                                                         int64_t nt) {
+  constexpr int NM = X3 ? 4 : 2;  // staged panels: A hi, B hi (, A lo, B lo)
+  __shared__ __attribute__((aligned(16))) __bf16 sm[NM][kGT][kGPad];
   const int64_t bp = blockIdx.y;
+  int64_t tm, tn;
+  if (!super_tile(blockIdx.x, nt, tm, tn)) return;
   const int64_t Kd = xlen[bp];
   hi += xoff[bp];
   lo += xoff[bp];
   float* __restrict__ K = Kall + bp * sK;
-  __shared__ __attribute__((aligned(16))) __bf16 sm[X3 ? 4 : 2][kT][kPadB];
-  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
-  int64_t tm, tn;
-  tri_tile(t, tm, tn);
+  const bool diag = tm == tn;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  floatx16 acc[2][2];
+  const int wm = w >> 2, wn = w & 3;  // wave block: rows wm*128.., cols wn*64..
+  floatx16 acc[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-  const __bf16* src[4] = {hi + tm * kT * ld, hi + tn * kT * ld, lo + tm * kT * ld, lo + tn * kT * ld};
-  constexpr int NM = X3 ? 4 : 2;
-  uint4 reg[NM][4];
+  // a panel stage is 256 rows x 32 k = 1024 chunks of 16 B, 2 per thread:
+  // chunk q = tid + 512 j is row q / 4, k offset 8 (q % 4)
+  const int r0 = tid >> 2, r1 = r0 + kGThreads / 4, cc = (tid & 3) * 8;
+  const __bf16* pAh = hi + tm * kGT * ld + cc;
+  const __bf16* pBh = hi + tn * kGT * ld + cc;
+  const __bf16* pAl = lo + tm * kGT * ld + cc;
+  const __bf16* pBl = lo + tn * kGT * ld + cc;
+  uint4 gAh0, gAh1, gBh0, gBh1, gAl0, gAl1, gBl0, gBl1;
   auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int mtx = 0; mtx < NM; ++mtx)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int idx = tid + kThreads * i;
-        const int r = idx >> 3, c = (idx & 7) * 8;
-        reg[mtx][i] = *reinterpret_cast<const uint4*>(src[mtx] + (int64_t)r * ld + k0 + c);
+    gAh0 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r0 * ld + k0);
+    gAh1 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r1 * ld + k0);
+    if (!diag) {
+      gBh0 = *reinterpret_cast<const uint4*>(pBh + (int64_t)r0 * ld + k0);
+      gBh1 = *reinterpret_cast<const uint4*>(pBh + (int64_t)r1 * ld + k0);
+    }
+    if constexpr (X3) {
+      gAl0 = *reinterpret_cast<const uint4*>(pAl + (int64_t)r0 * ld + k0);
+      gAl1 = *reinterpret_cast<const uint4*>(pAl + (int64_t)r1 * ld + k0);
+      if (!diag) {
+        gBl0 = *reinterpret_cast<const uint4*>(pBl + (int64_t)r0 * ld + k0);
+        gBl1 = *reinterpret_cast<const uint4*>(pBl + (int64_t)r1 * ld + k0);
       }
+    }
   };
   gload(0);
-  for (int64_t k0 = 0; k0 < Kd; k0 += kBKb) {
-#pragma unroll
-    for (int mtx = 0; mtx < NM; ++mtx)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int idx = tid + kThreads * i;
-        const int r = idx >> 3, c = (idx & 7) * 8;
-        *reinterpret_cast<uint4*>(&sm[mtx][r][c]) = reg[mtx][i];
+  const int bA = 0, bB = diag ? 0 : 1;  // LDS panels read as A and as B
+  for (int64_t k0 = 0; k0 < Kd; k0 += kGBK) {
+    *reinterpret_cast<uint4*>(&sm[0][r0][cc]) = gAh0;
+    *reinterpret_cast<uint4*>(&sm[0][r1][cc]) = gAh1;
+    if (!diag) {
+      *reinterpret_cast<uint4*>(&sm[1][r0][cc]) = gBh0;
+      *reinterpret_cast<uint4*>(&sm[1][r1][cc]) = gBh1;
+    }
+    if constexpr (X3) {
+      *reinterpret_cast<uint4*>(&sm[2][r0][cc]) = gAl0;
+      *reinterpret_cast<uint4*>(&sm[2][r1][cc]) = gAl1;
+      if (!diag) {
+        *reinterpret_cast<uint4*>(&sm[3][r0][cc]) = gBl0;
+        *reinterpret_cast<uint4*>(&sm[3][r1][cc]) = gBl1;
       }
+    }
     __syncthreads();
-    if (k0 + kBKb < Kd) gload(k0 + kBKb);
+    if (k0 + kGBK < Kd) gload(k0 + kGBK);
 #pragma unroll
-    for (int ks = 0; ks < kBKb / 16; ++ks) {
+    for (int ks = 0; ks < kGBK / 16; ++ks) {
       const int kc = ks * 16 + 8 * (lane >> 5);
-      bf16x8 am[2], bn[2], aml[2], bnl[2];
+      bf16x8 bn[2], bnl[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        am[a] = *reinterpret_cast<const bf16x8*>(&sm[0][wm * 64 + a * 32 + (lane & 31)][kc]);
-        bn[a] = *reinterpret_cast<const bf16x8*>(&sm[1][wn * 64 + a * 32 + (lane & 31)][kc]);
-        if constexpr (X3) {
-          aml[a] = *reinterpret_cast<const bf16x8*>(&sm[2][wm * 64 + a * 32 + (lane & 31)][kc]);
-          bnl[a] = *reinterpret_cast<const bf16x8*>(&sm[3][wn * 64 + a * 32 + (lane & 31)][kc]);
-        }
+      for (int b = 0; b < 2; ++b) {
+        bn[b] = *reinterpret_cast<const bf16x8*>(&sm[bB][wn * 64 + b * 32 + (lane & 31)][kc]);
+        if constexpr (X3) bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
       }
+      // one row block's operands at a time keeps the live fragments few
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a) {
+        const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm[bA][wm * 128 + a * 32 + (lane & 31)][kc]);
+        bf16x8 aml;
+        if constexpr (X3) aml = *reinterpret_cast<const bf16x8*>(&sm[bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bn[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bn[b], acc[a][b], 0, 0, 0);
           if constexpr (X3) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bnl[b], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml[a], bn[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bnl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml, bn[b], acc[a][b], 0, 0, 0);
           }
         }
+      }
     }
     __syncthreads();
   }
+  const bool edge = (tm + 1) * kGT > M;  // only the last tile row/column can cross M
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int64_t row = tm * kT + wm * 64 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int64_t col = tn * kT + wn * 64 + b * 32 + (lane & 31);
-        K[row * ldk + col] = acc[a][b][i];
+        const int64_t row = tm * kGT + wm * 128 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int64_t col = tn * kGT + wn * 64 + b * 32 + (lane & 31);
+        if (!edge || (row < M && col < M)) K[row * ldk + col] = acc[a][b][i];
       }
 }
 
@@ -400,15 +466,14 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
     }
     return hipSuccess;
   }
-  const int64_t nt = M / kT;
-  const int64_t n_tiles = nt * (nt + 1) / 2;
-  const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
+  const int64_t nt = (M + kGT - 1) / kGT;
+  const int64_t grid = super_grid(nt);
   if (mode == SW_GRAM_BF16X3)
-    hipLaunchKernelGGL(k_gram_bf16<true>, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, n_tiles);
+    hipLaunchKernelGGL(k_gram_bf16<true>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
+                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt);
   else
-    hipLaunchKernelGGL(k_gram_bf16<false>, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, n_tiles);
+    hipLaunchKernelGGL(k_gram_bf16<false>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
+                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt);
   return hipGetLastError();
 }
 

@@ -17,15 +17,20 @@ namespace sw {
 constexpr int kStage = 16;
 constexpr int kWave = 64;
 
+// lamw: the single-precision path's warm-start state of the bar's lam (unused in double)
 template <typename T>
 struct Prec;
 template <>
 struct Prec<float> {
-  __device__ static void accel(const PotK& P, const float* s, float* g) { accel_f32(P, s[0], s[1], s[2], g[0], g[1], g[2]); }
+  __device__ static void accel(const PotK& P, const float* s, float* g, float& lamw) {
+    accel_f32(P, s[0], s[1], s[2], g[0], g[1], g[2], lamw);
+  }
+  __device__ static double jacobi(const PotK& P, const double* sd, float lamw) { return jacobi_f64_drift(P, sd, lamw); }
 };
 template <>
 struct Prec<double> {
-  __device__ static void accel(const PotK& P, const double* s, double* g) { accel_f64(P, s, g); }
+  __device__ static void accel(const PotK& P, const double* s, double* g, float&) { accel_f64(P, s, g); }
+  __device__ static double jacobi(const PotK& P, const double* sd, float) { return jacobi_f64(P, sd); }
 };
 
 __device__ __forceinline__ uint64_t pack4(const int* c) {
@@ -79,15 +84,16 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
   const T c = (T)cos(th), sn = (T)sin(th);
   const T cm1 = (T)(-2.0 * sin(0.5 * th) * sin(0.5 * th));
 
+  float lamw = -1.0f;
+  T g[3];
+  Prec<T>::accel(P, s, g, lamw);
   double sd[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
-  const double E0 = jacobi_f64(P, sd);
+  const double E0 = Prec<T>::jacobi(P, sd, lamw);
   double dmax = 0.0;
   const int de = O.drift_every;
 
-  T g[3];
-  Prec<T>::accel(P, s, g);
   int slot = 0;
   for (int k = 1; k <= n_steps; ++k) {
     s[3] = s[3] + h * g[0];
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
       T py = s[4] + (cm1 * s[4] - sn * s[3]);
       s[0] = x; s[1] = y; s[3] = px; s[4] = py;
     }
-    Prec<T>::accel(P, s, g);
+    Prec<T>::accel(P, s, g, lamw);
     s[3] = s[3] + h * g[0];
     s[4] = s[4] + h * g[1];
     s[5] = s[5] + h * g[2];
@@ -117,7 +123,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_pot
     if (de > 0 && k % de == 0) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
-      double e = fabs(jacobi_f64(P, sd) / E0 - 1.0);
+      double e = fabs(Prec<T>::jacobi(P, sd, lamw) / E0 - 1.0);
       if (!(e <= dmax)) dmax = e;
     }
     if constexpr (BIN) {

@@ -24,22 +24,30 @@ __device__ __forceinline__ float rsqf_(float x) { return __builtin_amdgcn_rsqf(x
 // with m_n^2 = sum_j (x_j^2 / K) / e_j.  The scaling by K keeps every
 // product in range for any radius.
 // ---------------------------------------------------------------------------
-constexpr int kNewton32 = 7;
+constexpr int kNewton32 = 7;      // Newton steps from the left bracket
+constexpr int kNewtonWarm32 = 3;  // Newton steps from the previous step's lam
 
+// lam_io < 0: cold start from the left bracket max(0, r^2 - a_max^2).
+// lam_io >= 0: warm start from that value (the root at the orbit's previous
+// position); m^2(lam) is convex and decreasing, so a start right of the root
+// lands left of it after one step and then rises monotonically.  lam_io
+// returns the root found.
 __device__ __forceinline__ void ferrers_accel_f32(const CompK& C, const float* gq, const float* gw, float x,
-                                                  float y, float z, float& gx, float& gy, float& gz) {
+                                                  float y, float z, float& gx, float& gy, float& gz,
+                                                  float& lam_io) {
   const float A0 = C.f[0], A1 = C.f[1], A2 = C.f[2], Amin = C.f[3], kF = C.f[4], Amax = C.f[6];
   const float x2 = x * x, y2 = y * y, z2 = z * z;
-  float lam = fmaxf(0.0f, x2 + y2 + z2 - Amax);
-  // m^2(lam) is convex and decreasing: Newton from the left bracket rises monotonically.
-#pragma unroll
-  for (int it = 0; it < kNewton32; ++it) {
+  const bool cold = lam_io < 0.0f;
+  float lam = cold ? fmaxf(0.0f, x2 + y2 + z2 - Amax) : lam_io;
+  const int n_it = cold ? kNewton32 : kNewtonWarm32;
+  for (int it = 0; it < n_it; ++it) {
     float i0 = rcpf_(A0 + lam), i1 = rcpf_(A1 + lam), i2 = rcpf_(A2 + lam);
     float t0 = x2 * i0, t1 = y2 * i1, t2 = z2 * i2;
     float f = (t0 + t1) + (t2 - 1.0f);
     float fp = t0 * i0 + t1 * i1 + t2 * i2;
     lam = fmaxf(0.0f, lam + f * rcpf_(fp));
   }
+  lam_io = lam;
   const float K = Amin + lam;
   const float iK = rcpf_(K);
   const float D0 = (A0 + lam) * iK, D1 = (A1 + lam) * iK, D2 = (A2 + lam) * iK;
@@ -116,10 +124,13 @@ __device__ inline void ferrers_f64(const CompK& C, const double* gq, const doubl
 // ---------------------------------------------------------------------------
 // Single-precision acceleration (fast path).
 // ---------------------------------------------------------------------------
+// lamw: warm-start state of the first bar component (< 0: none yet); a
+// second bar component, if any, always starts cold.
 __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float z, float& gx, float& gy,
-                                          float& gz) {
+                                          float& gz, float& lamw) {
   gx = 0.0f; gy = 0.0f; gz = 0.0f;
   const int nc = P.n_comp;
+  bool first_bar = true;
   for (int i = 0; i < nc; ++i) {
     const CompK& C = P.comp[i];
     switch (C.kind) {
@@ -172,7 +183,13 @@ __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float
         break;
       }
       case SW_FERRERS2:
-        ferrers_accel_f32(C, P.gq32, P.gw32, x, y, z, gx, gy, gz);
+        if (first_bar) {
+          ferrers_accel_f32(C, P.gq32, P.gw32, x, y, z, gx, gy, gz, lamw);
+          first_bar = false;
+        } else {
+          float cold = -1.0f;
+          ferrers_accel_f32(C, P.gq32, P.gw32, x, y, z, gx, gy, gz, cold);
+        }
         break;
       default:
         break;
@@ -241,44 +258,49 @@ __device__ inline void accel_f64(const PotK& P, const double* xv, double* g) {
   }
 }
 
+// Potential of one analytic (non-bar) component.
+__device__ inline double phi_analytic_f64(const CompK& C, double x, double y, double z) {
+  double v = 0.0;
+  switch (C.kind) {
+    case SW_KEPLER:
+      v = -C.c[0] / sqrt(x * x + y * y + z * z);
+      break;
+    case SW_ISOCHRONE: {
+      double r2 = x * x + y * y + z * z;
+      v = -C.c[0] / (C.c[1] + sqrt(C.c[2] + r2));
+      break;
+    }
+    case SW_PLUMMER: {
+      double r2 = x * x + y * y + z * z;
+      v = -C.c[0] / sqrt(r2 + C.c[1]);
+      break;
+    }
+    case SW_MN: {
+      double R2 = x * x + y * y;
+      double zeta = sqrt(z * z + C.c[2]);
+      double sm = C.c[1] + zeta;
+      v = -C.c[0] / sqrt(R2 + sm * sm);
+      break;
+    }
+    case SW_NFW_Q: {
+      double m = sqrt(x * x + y * y + z * z / C.c[3]);
+      v = (m == 0.0) ? -C.c[0] / C.c[1] : -C.c[0] * log1p(m / C.c[1]) / m;
+      break;
+    }
+    default:
+      break;
+  }
+  return v;
+}
+
 __device__ inline double phi_f64(const PotK& P, const double* xv) {
   const double x = xv[0], y = xv[1], z = xv[2];
   double s = 0.0;
   for (int i = 0; i < P.n_comp; ++i) {
     const CompK& C = P.comp[i];
     double v = 0.0;
-    switch (C.kind) {
-      case SW_KEPLER:
-        v = -C.c[0] / sqrt(x * x + y * y + z * z);
-        break;
-      case SW_ISOCHRONE: {
-        double r2 = x * x + y * y + z * z;
-        v = -C.c[0] / (C.c[1] + sqrt(C.c[2] + r2));
-        break;
-      }
-      case SW_PLUMMER: {
-        double r2 = x * x + y * y + z * z;
-        v = -C.c[0] / sqrt(r2 + C.c[1]);
-        break;
-      }
-      case SW_MN: {
-        double R2 = x * x + y * y;
-        double zeta = sqrt(z * z + C.c[2]);
-        double sm = C.c[1] + zeta;
-        v = -C.c[0] / sqrt(R2 + sm * sm);
-        break;
-      }
-      case SW_NFW_Q: {
-        double m = sqrt(x * x + y * y + z * z / C.c[3]);
-        v = (m == 0.0) ? -C.c[0] / C.c[1] : -C.c[0] * log1p(m / C.c[1]) / m;
-        break;
-      }
-      case SW_FERRERS2:
-        ferrers_f64(C, P.gq64, P.gw64, x, y, z, &v, nullptr);
-        break;
-      default:
-        break;
-    }
+    if (C.kind == SW_FERRERS2) ferrers_f64(C, P.gq64, P.gw64, x, y, z, &v, nullptr);
+    else v = phi_analytic_f64(C, x, y, z);
     s = s + v;
   }
   return s;
@@ -289,6 +311,69 @@ __device__ inline double jacobi_f64(const PotK& P, const double* s6) {
   double kin = 0.5 * (s6[3] * s6[3] + s6[4] * s6[4] + s6[5] * s6[5]);
   double Lz = s6[0] * s6[4] - s6[1] * s6[3];
   return kin + phi_f64(P, s6) - P.omega * Lz;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi energy for the drift check of the single-precision integrator, in
+// double precision.  The bar uses that integrator's own 16-node rule (nodes
+// and weights widened to double: a fixed rule, so E_J(t) and E_J(0) see the
+// same quadrature), lam refined by two double Newton steps from the
+// integrator's lam at the same point, and the hardware reciprocal square
+// root refined by two Newton-Raphson steps; the analytic components are as
+// in phi_f64.  Its error against phi_f64 is far below the drift it checks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsq_f64(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+  y = y * (1.5 - 0.5 * v * y * y);
+  y = y * (1.5 - 0.5 * v * y * y);
+  return y;
+}
+
+__device__ inline double ferrers_phi_drift(const CompK& C, const float* gq, const float* gw, double x, double y,
+                                           double z, double lam) {
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  for (int it = 0; it < 2; ++it) {
+    const double i0 = 1.0 / (C.c[0] + lam), i1 = 1.0 / (C.c[1] + lam), i2 = 1.0 / (C.c[2] + lam);
+    const double t0 = x2 * i0, t1 = y2 * i1, t2 = z2 * i2;
+    const double f = t0 + t1 + t2 - 1.0;
+    const double fp = t0 * i0 + t1 * i1 + t2 * i2;
+    lam = fmax(0.0, lam + f / fp);
+  }
+  const double K = C.c[3] + lam, iK = 1.0 / K;
+  const double D0 = (C.c[0] + lam) * iK, D1 = (C.c[1] + lam) * iK, D2 = (C.c[2] + lam) * iK;
+  const double xs = x2 * iK, ys = y2 * iK, zs = z2 * iK;
+  double Fp = 0.0;
+  for (int n = 0; n < kGL32; ++n) {
+    const double q = (double)gq[n], W = (double)gw[n];
+    const double e0 = D0 + q, e1 = D1 + q, e2 = D2 + q;
+    const double e12 = e1 * e2;
+    const double sv = rsq_f64(e0 * e12);
+    const double iP = sv * sv;
+    const double w = fmax(1.0 - (xs * e12 + ys * e0 * e2 + zs * e0 * e1) * iP, 0.0);
+    Fp += W * (w * w * w) * sv;
+  }
+  return -C.c[5] * Fp * rsq_f64(K);
+}
+
+__device__ inline double jacobi_f64_drift(const PotK& P, const double* s6, float lamw) {
+  const double x = s6[0], y = s6[1], z = s6[2];
+  double phi = 0.0;
+  bool first_bar = true;
+  for (int i = 0; i < P.n_comp; ++i) {
+    const CompK& C = P.comp[i];
+    double v;
+    if (C.kind == SW_FERRERS2) {
+      const double lam = (first_bar && lamw >= 0.0f) ? (double)lamw : ferrers_lambda_f64(C, x * x, y * y, z * z);
+      first_bar = false;
+      v = ferrers_phi_drift(C, P.gq32, P.gw32, x, y, z, lam);
+    } else {
+      v = phi_analytic_f64(C, x, y, z);
+    }
+    phi = phi + v;
+  }
+  const double kin = 0.5 * (s6[3] * s6[3] + s6[4] * s6[4] + s6[5] * s6[5]);
+  const double Lz = s6[0] * s6[4] - s6[1] * s6[3];
+  return kin + phi - P.omega * Lz;
 }
 
 // ---------------------------------------------------------------------------

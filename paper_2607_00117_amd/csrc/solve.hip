@@ -46,6 +46,8 @@ constexpr int kColTile = kColThreads * kColsPerThread;
 constexpr int kSlabs = 256;       // orbit slabs per problem in the column-sum reduction
 constexpr int kPar = 8;           // per-problem scalars: wt, rho, rho', mu, alpha, active
 constexpr int kAcc = 16;          // per-problem accumulators
+constexpr int kStallChecks = 5;   // stage 1 stalls when max(primal, dual) residual has not
+constexpr double kStallRatio = 0.9;  // dropped below 0.9x its value kStallChecks checks earlier
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -142,20 +144,46 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A
 // Compressed copies of A.  The orbit matrix is mostly zeros (an orbit visits a
 // small part of the grid), so the ADMM passes read compressed rows
 // (orbit-major, for the row dots) and compressed columns (constraint-major,
-// one segment per problem, for the column sums) built once per solve from the
-// dense A.  Entries keep A's precision and ascending index order.
+// for the column sums), built once per solve from the dense A.
+//
+// Both are blocked so that the vector they gather from fits in LDS: a
+// gather from L2 costs one cache request per lane and caps a pass at the L2
+// request rate, a gather from LDS does not.
+//  * rows: column blocks of kBlk constraints; segment (i, cb) holds the
+//    entries of row i in block cb, at [rptr[i*ncb + cb], rptr[i*ncb + cb + 1]);
+//    16-bit column index within the block.
+//  * columns: per problem, row blocks of whole orbit slabs (at most kBlk
+//    orbits); segment (b, rb, c) at [cptr[(b*nrb + rb)*(C+1) + c], ... + 1);
+//    16-bit orbit index within the block.
+// Every segment is padded with zero entries (index 0) to a whole quad of 4,
+// so entries are read four at a time with one vector load.
 // ---------------------------------------------------------------------------
+constexpr int kBlk = 16384;       // gathered entries staged in LDS (fp64: 128 KB)
+constexpr int kSpThreads = 1024;  // workgroup of the blocked passes (16 waves)
+constexpr int kSpWaves = kSpThreads / 64;
+constexpr int kRowsPerWave = 8;   // row dots: 128 rows per workgroup
+constexpr int kColsPerWave = 4;   // column sums: 64 columns per workgroup
+
+// orbit rows per column-block segment: slabs of rps rows, whole slabs per block
+__host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps) {
+  return rps >= kBlk ? 1 : kBlk / rps;
+}
+
+// cnt[i][cb] = nonzeros of row i in column block cb (one wave per row)
 template <typename TA>
-__global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C,
+__global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C, int ncb,
                                                  int64_t* __restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const TA* row = A + i * C;
-  int64_t k = 0;
-  for (int64_t c = lane; c < C; c += 64) k += row[c] != TA(0);
-  for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-  if (lane == 0) cnt[i] = k;
+  for (int cb = 0; cb < ncb; ++cb) {
+    const int64_t c1 = (int64_t)(cb + 1) * kBlk < C ? (int64_t)(cb + 1) * kBlk : C;
+    int64_t k = 0;
+    for (int64_t c = (int64_t)cb * kBlk + lane; c < c1; c += 64) k += row[c] != TA(0);
+    for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+    if (lane == 0) cnt[i * ncb + cb] = k;
+  }
 }
 
 // cpart[b][s][c] = number of nonzeros of column c in slab s of problem b
@@ -183,49 +211,59 @@ __global__ __launch_bounds__(kColThreads) void k_col_nnz(const TA* __restrict__ 
   }
 }
 
-// compressed rows: one wave per orbit, ballot + prefix count keeps column order
+// compressed rows: one wave per orbit; ballot + prefix count keeps column
+// order; each segment's padding is written as zero entries
 template <typename TA>
-__global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C,
-                                                  const int64_t* __restrict__ ptr, int32_t* __restrict__ col,
+__global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C, int ncb,
+                                                  const int64_t* __restrict__ ptr, uint16_t* __restrict__ col,
                                                   TA* __restrict__ val) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const TA* row = A + i * C;
-  int64_t pos = ptr[i];
-  for (int64_t c0 = 0; c0 < C; c0 += 64) {
-    const int64_t c = c0 + lane;
-    const TA v = c < C ? row[c] : TA(0);
-    const uint64_t m = __ballot(v != TA(0));
-    if (v != TA(0)) {
-      const int64_t at = pos + __popcll(m & ((1ull << lane) - 1ull));
-      col[at] = (int32_t)c;
-      val[at] = v;
+  for (int cb = 0; cb < ncb; ++cb) {
+    const int64_t cbeg = (int64_t)cb * kBlk;
+    const int64_t c1 = cbeg + kBlk < C ? cbeg + kBlk : C;
+    int64_t pos = ptr[i * ncb + cb];
+    for (int64_t c0 = cbeg; c0 < c1; c0 += 64) {
+      const int64_t c = c0 + lane;
+      const TA v = c < c1 ? row[c] : TA(0);
+      const uint64_t m = __ballot(v != TA(0));
+      if (v != TA(0)) {
+        const int64_t at = pos + __popcll(m & ((1ull << lane) - 1ull));
+        col[at] = (uint16_t)(c - cbeg);
+        val[at] = v;
+      }
+      pos += __popcll(m);
     }
-    pos += __popcll(m);
+    if (pos + lane < ptr[i * ncb + cb + 1]) {
+      col[pos + lane] = 0;
+      val[pos + lane] = TA(0);
+    }
   }
 }
 
-// compressed columns of problem b: entries of column c start at
-// cbase[b] + cptr[b][c]; slab s of the column starts slab_off[b][s][c] later
+// compressed columns: slab s of problem b writes its entries of column c
+// from the absolute position slab_at[b][s][c] on (padding is pre-cleared)
 template <typename TA>
 __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__ A, int64_t C,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ rps,
-                                                          const int64_t* __restrict__ cptr,
-                                                          const int64_t* __restrict__ cbase,
-                                                          const int32_t* __restrict__ slab_off,
-                                                          int32_t* __restrict__ rowi, TA* __restrict__ val) {
+                                                          const int64_t* __restrict__ slab_at,
+                                                          uint16_t* __restrict__ rowi, TA* __restrict__ val) {
   const int b = blockIdx.z;
   const int64_t c0 = (int64_t)blockIdx.x * kColTile, s = blockIdx.y;
   const int64_t i_beg = off[b] + s * rps[b];
   int64_t i_end = i_beg + rps[b];
   if (i_end > off[b + 1]) i_end = off[b + 1];
+  // first orbit of this slab's row block
+  const int64_t spb = slabs_per_block(rps[b]);
+  const int64_t blk0 = off[b] + (s / spb) * spb * rps[b];
   int64_t pos[kColsPerThread];
 #pragma unroll
   for (int q = 0; q < kColsPerThread; ++q) {
     const int64_t c = c0 + threadIdx.x + q * kColThreads;
-    pos[q] = c < C ? cbase[b] + cptr[(int64_t)b * (C + 1) + c] + slab_off[((int64_t)b * kSlabs + s) * C + c] : 0;
+    pos[q] = c < C ? slab_at[((int64_t)b * kSlabs + s) * C + c] : 0;
   }
   for (int64_t i = i_beg; i < i_end; ++i) {
 #pragma unroll
@@ -234,7 +272,7 @@ __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__
       if (c < C) {
         const TA v = A[i * C + c];
         if (v != TA(0)) {
-          rowi[pos[q]] = (int32_t)i;
+          rowi[pos[q]] = (uint16_t)(i - blk0);
           val[pos[q]] = v;
           ++pos[q];
         }
@@ -243,23 +281,94 @@ __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__
   }
 }
 
-// column sums from compressed columns: one wave per (problem, column);
-// result in part[b][0][c] (the reduction then reads a single slab)
+// Quads of compressed entries: values and indices of four consecutive
+// entries in one vector load each; the streams are read once per pass, so
+// the loads are non-temporal.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void quad_val(const float* p, double v[4]) {
+  const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+}
+__device__ __forceinline__ void quad_val(const double* p, double v[4]) {
+  const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+  const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+  v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+}
+__device__ __forceinline__ void quad_idx(const uint16_t* p, uint32_t c[4]) {
+  const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+  c[0] = q[0]; c[1] = q[1]; c[2] = q[2]; c[3] = q[3];
+}
+
+// lane-partial sum_k val[k] xs[idx[k]] over the segment [k0, k1) (multiples
+// of 4) with xs in LDS: lane-strided quads, two in flight per lane
+template <typename TA>
+__device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint16_t* __restrict__ idx, int64_t k0,
+                                          int64_t k1, const double* xs, int lane) {
+  double a0 = 0.0, a1 = 0.0;
+  int64_t k = k0 + 4 * lane;
+  for (; k + 256 < k1; k += 512) {
+    double v[4], w[4];
+    uint32_t c[4], d[4];
+    quad_val(val + k, v);
+    quad_idx(idx + k, c);
+    quad_val(val + k + 256, w);
+    quad_idx(idx + k + 256, d);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a0 += v[q] * xs[c[q]];
+      a1 += w[q] * xs[d[q]];
+    }
+  }
+  if (k < k1) {
+    double v[4];
+    uint32_t c[4];
+    quad_val(val + k, v);
+    quad_idx(idx + k, c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a0 += v[q] * xs[c[q]];
+  }
+  return a0 + a1;
+}
+
+// column sums from the compressed columns: workgroup (column group, problem
+// b), 4 columns per wave, the problem's orbit vector staged block by block
+// in LDS; result in part[b][0][c] (the reduction then reads a single slab)
 template <typename TA, typename TV>
-__global__ __launch_bounds__(256) void k_csc_colsum(int64_t C, const int64_t* __restrict__ cptr,
-                                                    const int64_t* __restrict__ cbase, const int32_t* __restrict__ rowi,
-                                                    const TA* __restrict__ val, const TV* __restrict__ v,
-                                                    double* __restrict__ part) {
-  const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, const int64_t* __restrict__ off,
+                                                          const int64_t* __restrict__ rps, int nrb,
+                                                          const int64_t* __restrict__ cptr,
+                                                          const uint16_t* __restrict__ rowi,
+                                                          const TA* __restrict__ val, const TV* __restrict__ v,
+                                                          double* __restrict__ part) {
+  __shared__ double xs[kBlk];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.y;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= C) return;
-  const int64_t base = cbase[b];
-  const int64_t k0 = base + cptr[(int64_t)b * (C + 1) + c], k1 = base + cptr[(int64_t)b * (C + 1) + c + 1];
-  double acc = 0.0;
-  for (int64_t k = k0 + lane; k < k1; k += 64) acc += (double)val[k] * (double)v[rowi[k]];
-  acc = wave_sum(acc);
-  if (lane == 0) part[(int64_t)b * kSlabs * C + c] = acc;
+  const int64_t n0 = off[b], nb = off[b + 1] - n0;
+  const int64_t brows = slabs_per_block(rps[b]) * rps[b];
+  const int64_t cw = (int64_t)blockIdx.x * (kSpWaves * kColsPerWave) + w;
+  double acc[kColsPerWave] = {0.0, 0.0, 0.0, 0.0};
+  for (int rb = 0; rb < nrb && (int64_t)rb * brows < nb; ++rb) {
+    const int64_t r0 = (int64_t)rb * brows;
+    const int64_t len = nb - r0 < brows ? nb - r0 : brows;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = (double)v[n0 + r0 + j];
+    __syncthreads();
+    const int64_t* cp = cptr + ((int64_t)b * nrb + rb) * (C + 1);
+#pragma unroll
+    for (int q = 0; q < kColsPerWave; ++q) {
+      const int64_t c = cw + q * kSpWaves;
+      if (c < C) acc[q] += seg_dot(val, rowi, cp[c], cp[c + 1], xs, lane);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kColsPerWave; ++q) {
+    const int64_t c = cw + q * kSpWaves;
+    const double t = wave_sum(acc[q]);
+    if (lane == 0 && c < C) part[(int64_t)b * kSlabs * C + c] = t;
+  }
 }
 
 enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
@@ -351,7 +460,7 @@ struct RowArgs {
   double* acc;  // per problem [kAcc]: 0 |x-z|^2, 1 |z-zold|^2, 2 |x|^2, 3 |z|^2, 4 |u|^2, 5 max|q|, 6 kkt max, 7 |z|^2, 9 |e|^2
   // orbit-major compressed rows of A (used when A is stored sparse)
   const int64_t* csr_ptr;
-  const int32_t* csr_col;
+  const void* csr_col;  // uint16_t column index within the column block
   const void* csr_val;
 };
 
@@ -361,28 +470,9 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
 }
 
-// One wave per orbit row: dot = sum_n A[i][n] sc[b][n], then the row's update.
-template <typename TA, bool SPARSE>
-__global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A, int64_t N, int64_t C,
-                                                       const double* __restrict__ sc, RowArgs R) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * (kRowsBlock / 64) + w;
-  if (i >= N) return;
-  const int b = find_problem(R.off, R.nprob, i);
+// The update of orbit row i of problem b once its dot with sc is known.
+__device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, double dot) {
   const double* P = R.par + b * kPar;
-  if (P[5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
-  const double* scb = sc + (int64_t)b * R.Cp;
-  double dot = 0.0;
-  if constexpr (SPARSE) {
-    const TA* val = (const TA*)R.csr_val;
-    const int64_t k1 = R.csr_ptr[i + 1];
-    for (int64_t k = R.csr_ptr[i] + lane; k < k1; k += 64) dot += (double)val[k] * scb[R.csr_col[k]];
-  } else {
-    const TA* row = A + i * C;
-    for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
-  }
-  dot = wave_sum(dot);
-  if (lane != 0) return;
   const bool masked = R.mask && R.mask[i];
   const double rho = P[1], rhop = P[2], mu = P[3], alpha = P[4];
   double* acc = R.acc ? R.acc + b * kAcc : nullptr;
@@ -442,6 +532,61 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
       }
       break;
     }
+  }
+}
+
+// Dense rows: one wave per orbit row, dot = sum_n A[i][n] sc[b][n].
+template <typename TA>
+__global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A, int64_t N, int64_t C,
+                                                       const double* __restrict__ sc, RowArgs R) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * (kRowsBlock / 64) + w;
+  if (i >= N) return;
+  const int b = find_problem(R.off, R.nprob, i);
+  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
+  const double* scb = sc + (int64_t)b * R.Cp;
+  const TA* row = A + i * C;
+  double dot = 0.0;
+  for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
+  dot = wave_sum(dot);
+  if (lane == 0) row_update(R, i, b, dot);
+}
+
+// Compressed rows: workgroup (row group, problem b), 8 rows per wave, sc of
+// problem b staged column block by column block in LDS.
+template <typename TA>
+__global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, const double* __restrict__ sc,
+                                                           RowArgs R) {
+  __shared__ double xs[kBlk];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.y;
+  const int64_t i_end = R.off[b + 1];
+  const int64_t i0 = R.off[b] + (int64_t)blockIdx.x * (kSpWaves * kRowsPerWave);
+  if (i0 >= i_end) return;
+  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
+  const double* scb = sc + (int64_t)b * R.Cp;
+  const TA* val = (const TA*)R.csr_val;
+  const uint16_t* col = (const uint16_t*)R.csr_col;
+  double acc[kRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0.0;
+  for (int cb = 0; cb < ncb; ++cb) {
+    const int64_t c0 = (int64_t)cb * kBlk;
+    const int64_t len = C - c0 < kBlk ? C - c0 : kBlk;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = scb[c0 + j];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      const int64_t i = i0 + w + r * kSpWaves;
+      if (i < i_end) acc[r] += seg_dot(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, lane);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int64_t i = i0 + w + r * kSpWaves;
+    const double dot = wave_sum(acc[r]);
+    if (lane == 0 && i < i_end) row_update(R, i, b, dot);
   }
 }
 
@@ -522,9 +667,11 @@ struct SolveLayout {
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
   size_t off_par, off_acc, off_idx, off_bad, off_pt, off_xb, off_dt;
-  // compressed copies (sized for at most cap_nnz nonzeros)
+  // compressed copies (sized for at most cap_nnz entries): ncb column blocks
+  // of the rows, nrb row blocks per problem of the columns
   int64_t cap_nnz;
-  size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_cbase, off_crow, off_cval;
+  int ncb, nrb;
+  size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_crow, off_cval;
   size_t total;
 };
 
@@ -545,7 +692,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += a256(bytes); return at; };
-  const size_t xe = (size_t)L.Cp * L.Npt;
+  const size_t xe = (size_t)gram_rows(gram_mode, L.Cp) * L.Npt;
   const size_t N = (size_t)L.N, VP = (size_t)P * L.Cp;
   L.off_hi = take(gram_mode == SW_GRAM_F32 ? 0 : xe * 2);
   L.off_lo = take(gram_mode == SW_GRAM_BF16X3 ? xe * 2 : 0);
@@ -569,15 +716,20 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   const double dense = (double)L.N * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(0.10 * dense), (int64_t)1 << 20);
   if ((double)L.cap_nnz > dense) L.cap_nnz = (int64_t)dense;
-  L.off_rcnt = take(N * 8);
+  L.ncb = (int)((L.C + kBlk - 1) / kBlk);
+  L.nrb = 1;
+  for (int b = 0; b < P; ++b) {
+    const int64_t spb = slabs_per_block(L.rps[b]);
+    L.nrb = std::max<int>(L.nrb, (int)((kSlabs + spb - 1) / spb));
+  }
+  L.off_rcnt = take(N * L.ncb * 8);
   L.off_cpart = take((size_t)P * kSlabs * L.C * 4);
-  L.off_slab = take((size_t)P * kSlabs * L.C * 4);
-  L.off_rptr = take((N + 1) * 8);
-  L.off_rcol = take((size_t)L.cap_nnz * 4);
+  L.off_slab = take((size_t)P * kSlabs * L.C * 8);
+  L.off_rptr = take((N * L.ncb + 1) * 8);
+  L.off_rcol = take((size_t)L.cap_nnz * 2);
   L.off_rval = take((size_t)L.cap_nnz * 8);
-  L.off_cptr = take((size_t)P * (L.C + 1) * 8);
-  L.off_cbase = take((size_t)(P + 1) * 8);
-  L.off_crow = take((size_t)L.cap_nnz * 4);
+  L.off_cptr = take((size_t)P * L.nrb * (L.C + 1) * 8);
+  L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
   L.total = o;
   return L;
@@ -600,15 +752,15 @@ struct Ctx {
 template <typename TV>
 static hipError_t colsum(const Ctx& X, const TV* v) {
   if (X.sparse) {
-    dim3 grid((unsigned)((X.L.C + 3) / 4), (unsigned)X.L.P);
+    dim3 grid((unsigned)((X.L.C + kSpWaves * kColsPerWave - 1) / (kSpWaves * kColsPerWave)), (unsigned)X.L.P);
     if (X.dtype == SW_F32)
-      hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(256), 0, X.st, X.L.C, X.p<int64_t>(X.L.off_cptr),
-                         X.p<int64_t>(X.L.off_cbase), X.p<int32_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
+      hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d, X.L.nrb,
+                         X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
                          X.p<double>(X.L.off_part));
     else
-      hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(256), 0, X.st, X.L.C, X.p<int64_t>(X.L.off_cptr),
-                         X.p<int64_t>(X.L.off_cbase), X.p<int32_t>(X.L.off_crow), X.p<double>(X.L.off_cval), v,
-                         X.p<double>(X.L.off_part));
+      hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d,
+                         X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<double>(X.L.off_cval),
+                         v, X.p<double>(X.L.off_part));
     return hipGetLastError();
   }
   dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
@@ -628,27 +780,28 @@ static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf,
   return hipGetLastError();
 }
 
+template <typename TA>
+static void launch_rowdot(const Ctx& X, const RowArgs& R) {
+  const double* sc = X.p<double>(X.L.off_sc);
+  if (X.sparse) {
+    int64_t nmax = 1;
+    for (int b = 0; b < X.L.P; ++b) nmax = std::max<int64_t>(nmax, X.L.off[b + 1] - X.L.off[b]);
+    const int64_t per = kSpWaves * kRowsPerWave;
+    hipLaunchKernelGGL(k_rowdot_csr<TA>, dim3((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P), dim3(kSpThreads),
+                       0, X.st, X.L.C, X.L.ncb, sc, R);
+  } else {
+    hipLaunchKernelGGL(k_rowdot<TA>, dim3((unsigned)((X.L.N + 3) / 4)), dim3(kRowsBlock), 0, X.st, (const TA*)X.A,
+                       X.L.N, X.L.C, sc, R);
+  }
+}
+
 static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
-  dim3 grid((unsigned)((X.L.N + 3) / 4));
   RowArgs R = R0;
   R.csr_ptr = X.p<int64_t>(X.L.off_rptr);
-  R.csr_col = X.p<int32_t>(X.L.off_rcol);
+  R.csr_col = X.p<void>(X.L.off_rcol);
   R.csr_val = X.p<void>(X.L.off_rval);
-  const double* sc = X.p<double>(X.L.off_sc);
-  if (X.dtype == SW_F32) {
-    if (X.sparse)
-      hipLaunchKernelGGL((k_rowdot<float, true>), grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C, sc, R);
-    else
-      hipLaunchKernelGGL((k_rowdot<float, false>), grid, dim3(kRowsBlock), 0, X.st, (const float*)X.A, X.L.N, X.L.C, sc,
-                         R);
-  } else {
-    if (X.sparse)
-      hipLaunchKernelGGL((k_rowdot<double, true>), grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
-                         sc, R);
-    else
-      hipLaunchKernelGGL((k_rowdot<double, false>), grid, dim3(kRowsBlock), 0, X.st, (const double*)X.A, X.L.N, X.L.C,
-                         sc, R);
-  }
+  if (X.dtype == SW_F32) launch_rowdot<float>(X, R);
+  else launch_rowdot<double>(X, R);
   return hipGetLastError();
 }
 
@@ -656,59 +809,69 @@ static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
 template <typename TA>
 static int build_sparse(Ctx& X) {
   const SolveLayout& L = X.L;
-  const int P = L.P;
+  const int P = L.P, ncb = L.ncb, nrb = L.nrb;
   const TA* A = (const TA*)X.A;
+  X.sparse = false;
+  for (int b = 0; b < P; ++b)
+    if (L.rps[b] > kBlk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
   int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
   int32_t* cpart = X.p<int32_t>(L.off_cpart);
-  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, rcnt);
+  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, ncb, rcnt);
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
                      dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
-  std::vector<int64_t> hr(L.N);
+  std::vector<int64_t> hr((size_t)L.N * ncb);
   std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
   SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipStreamSynchronize(X.st));
-  int64_t nnz = 0;
-  std::vector<int64_t> rptr(L.N + 1);
-  for (int64_t i = 0; i < L.N; ++i) {
-    rptr[i] = nnz;
-    nnz += hr[i];
+  // segments are padded to whole quads (4 entries)
+  auto quad = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
+  int64_t nnz = 0, at = 0;
+  std::vector<int64_t> rptr((size_t)L.N * ncb + 1);
+  for (size_t k = 0; k < hr.size(); ++k) {
+    rptr[k] = at;
+    nnz += hr[k];
+    at += quad(hr[k]);
   }
-  rptr[L.N] = nnz;
-  X.sparse = false;
+  rptr[hr.size()] = at;
   // compressed passes pay off below ~25% density
-  if (nnz > L.cap_nnz || (double)nnz > 0.25 * (double)L.N * (double)L.C) return SW_OK;
-  std::vector<int64_t> cptr((size_t)P * (L.C + 1)), cbase(P + 1);
-  std::vector<int32_t>& slab = hc;  // converted in place to per-slab offsets
-  int64_t base = 0;
+  if (at > L.cap_nnz || (double)nnz > 0.25 * (double)L.N * (double)L.C) return SW_OK;
+  // columns: segment (b, rb, c) = the slabs of row block rb; slab_at[b][s][c]
+  // = absolute position of slab s's first entry of column c
+  std::vector<int64_t> cptr((size_t)P * nrb * (L.C + 1), 0), slab_at((size_t)P * kSlabs * L.C);
+  int64_t pos = 0;
   for (int b = 0; b < P; ++b) {
-    cbase[b] = base;
-    int64_t run = 0;
-    for (int64_t c = 0; c < L.C; ++c) {
-      cptr[(size_t)b * (L.C + 1) + c] = run;
-      int32_t acc = 0;
-      for (int s = 0; s < kSlabs; ++s) {
-        int32_t& v = slab[((size_t)b * kSlabs + s) * L.C + c];
-        const int32_t k = v;
-        v = acc;
-        acc += k;
+    const int64_t spb = slabs_per_block(L.rps[b]);
+    for (int rb = 0; rb < nrb; ++rb) {
+      int64_t* cp = &cptr[((size_t)b * nrb + rb) * (L.C + 1)];
+      const int s0 = (int)std::min<int64_t>(kSlabs, rb * spb), s1 = (int)std::min<int64_t>(kSlabs, (rb + 1) * spb);
+      for (int64_t c = 0; c < L.C; ++c) {
+        cp[c] = pos;
+        int64_t run = pos;
+        for (int s = s0; s < s1; ++s) {
+          const size_t k = ((size_t)b * kSlabs + s) * L.C + c;
+          slab_at[k] = run;
+          run += hc[k];
+        }
+        pos += quad(run - pos);
       }
-      run += acc;
+      cp[L.C] = pos;
     }
-    cptr[(size_t)b * (L.C + 1) + L.C] = run;
-    base += run;
   }
-  cbase[P] = base;
+  if (pos > L.cap_nnz) return SW_OK;
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_rptr), rptr.data(), rptr.size() * 8, hipMemcpyHostToDevice, X.st));
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cptr), cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, X.st));
-  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cbase), cbase.data(), cbase.size() * 8, hipMemcpyHostToDevice, X.st));
-  SW_HIP(hipMemcpyAsync(X.p<int32_t>(L.off_slab), slab.data(), slab.size() * 4, hipMemcpyHostToDevice, X.st));
-  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C,
-                     X.p<int64_t>(L.off_rptr), X.p<int32_t>(L.off_rcol), X.p<TA>(L.off_rval));
+  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_slab), slab_at.data(), slab_at.size() * 8, hipMemcpyHostToDevice, X.st));
+  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, ncb,
+                     X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
+  // column padding: clear the compressed columns, then fill the entries
+  const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words, 0);
   hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
-                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, X.p<int64_t>(L.off_cptr),
-                     X.p<int64_t>(L.off_cbase), X.p<int32_t>(L.off_slab), X.p<int32_t>(L.off_crow), X.p<TA>(L.off_cval));
+                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, X.p<int64_t>(L.off_slab),
+                     X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
   SW_HIP(hipGetLastError());
   // the host vectors must outlive the copies
   SW_HIP(hipStreamSynchronize(X.st));
@@ -836,7 +999,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   hipLaunchKernelGGL(k_scaled_data, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, d, sigma, L.C, L.Cp,
                      X.p<double>(L.off_ys));
   {
-    dim3 grid((unsigned)(L.Cp / 64), (unsigned)(L.Npt / 64));
+    dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
     if (dtype == SW_F32)
       hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.off_d, X.xoff_d, P,
                          sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
@@ -847,7 +1010,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
                          X.p<float>(L.off_xf));
     SW_TRY(hipGetLastError());
   }
-  {
+  if (!(opt->flags & SW_SOLVE_DENSE)) {
     const int rs = dtype == SW_F32 ? build_sparse<float>(X) : build_sparse<double>(X);
     if (rs != SW_OK) return rs;
   }
@@ -984,6 +1147,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   } g1, g2;
   if (use_graph) SW_TRY(capture([&]() { return admm_iter(nullptr); }, check_every - 1, &g1.e));
   std::vector<int> active(P, 1);
+  std::vector<std::vector<double>> hist(P);
   int n_active = P;
   int it = 0;
   while (it < max_iter && n_active > 0) {
@@ -1009,7 +1173,14 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
       R[b].primal_res = rp / (scale_p + 1e-300);
       R[b].dual_res = rdl / (rho[b] * std::sqrt(a[4]) + 1e-300);
       R[b].iters = it;
-      if (rp <= tol * scale_p + 1e-300 && rdl <= tol * rho[b] * std::sqrt(a[4]) + 1e-300) {
+      // stage 1 also ends once it stalls: single-precision iterates reach a
+      // floor set by the fp32 inverse, below which only stage 2 makes progress
+      const double r = std::fmax(R[b].primal_res, R[b].dual_res);
+      std::vector<double>& h = hist[b];
+      h.push_back(r);
+      const size_t n_h = h.size();
+      const bool stalled = n_h > kStallChecks && r > kStallRatio * h[n_h - 1 - kStallChecks];
+      if ((rp <= tol * scale_p + 1e-300 && rdl <= tol * rho[b] * std::sqrt(a[4]) + 1e-300) || stalled) {
         active[b] = 0;
         --n_active;
       }

@@ -192,3 +192,42 @@ def test_solve_dense_matrix_path(gpu):
     x_o = N.chi2(A.astype(np.float64), w_o, d, sig, 100, c)
     assert l1 < W_L1_TOL
     assert abs(chi2_gpu(h, 100, c) / x_o - 1) < CHI2_TOL
+
+
+def test_compressed_blocks_match_dense_passes(gpu):
+    """A problem large enough that the compressed copies split into several
+    LDS blocks (20,000 constraints = 2 column blocks; 40,000 orbits = 3 row
+    blocks): the solve with compressed passes must agree with the solve that
+    streams the dense matrix in every pass."""
+    import torch
+    P = lib()
+    dev = torch.device("cuda:0")
+    n, c = 40000, 20000
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    A = torch.rand((n, c), generator=g, device=dev) < 0.03
+    A = torch.where(A, torch.exp(torch.randn((n, c), generator=g, device=dev)), torch.zeros((), device=dev))
+    A = (A / A.sum(1, keepdim=True).clamp(min=1e-30)).to(torch.float32).contiguous()
+    wtrue = torch.zeros(n, dtype=torch.float64, device=dev)
+    pick = torch.randperm(n, generator=g, device=dev)[: n // 10]
+    wtrue[pick] = torch.empty(n // 10, dtype=torch.float64, device=dev).exponential_(1.0, generator=g)
+    d = A.double().T @ wtrue
+    sig = 0.02 * torch.clamp(d, min=1e-3 * float(d.max()))
+    wt = float(d.sum()) / n
+    res = []
+    for flags in (0, P.SW_SOLVE_DENSE):
+        opts = P._lib.SolveOpts()
+        opts.gram, opts.nu, opts.flags = P.SW_GRAM_BF16X3, 1e-2, flags
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        ws = torch.empty(P.solve_workspace_bytes(n, c, opts), dtype=torch.uint8, device=dev)
+        status, rep = P.solve_weights(A, d, sig, wt, -1.0, opts, w, ws)
+        cws = torch.empty(P.chi2_workspace_bytes(c), dtype=torch.uint8, device=dev)
+        x2 = P.chi2(A, w, d, sig, 0, c, cws)
+        print(flags, status, rep.as_dict(), x2)
+        res.append((w.cpu().numpy(), status, rep, x2))
+        del ws
+    (w_s, st_s, rep_s, x_s), (w_d, st_d, rep_d, x_d) = res
+    assert rep_s.nnz > 0 and rep_d.nnz == 0
+    assert st_s == 0 and st_d == 0
+    assert np.abs(w_s - w_d).sum() / np.abs(w_d).sum() < 1e-3
+    assert abs(x_s / x_d - 1) < 1e-6
