@@ -177,9 +177,9 @@ size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t 
 typedef struct {
   int32_t gram;        /* SW_GRAM_* */
   int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 1000); the stage also
-                          ends once max(primal, dual) residual stops falling (below 0.9x
-                          its value 5 checks earlier), the FP64 stage then continues */
-  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 500) */
+                          ends once max(primal, dual) residual stops falling (below 0.95x
+                          its value 10 checks earlier), the FP64 stage then continues */
+  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 2000) */
   int32_t check_every; /* convergence checked every this many iterations (<= 0: 10) */
   int32_t use_graph;   /* 1: the iterations between two checks are captured once into a HIP
                           graph and replayed (needs a non-NULL stream); 0: plain launches */

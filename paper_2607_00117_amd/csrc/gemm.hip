@@ -285,10 +285,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal block: unblocked Cholesky of the 128 x 128 block in LDS, then the
-// inverse of the factor, one column per thread by forward substitution.
-// A non-positive pivot sets *bad and is replaced by a tiny positive value so
-// the factor stays finite.
+// Diagonal block of the factorisation: unblocked right-looking Cholesky of a
+// 128 x 128 block in LDS, then the inverse of the factor by right-looking
+// forward substitution on the identity; the factor overwrites the block and
+// its inverse goes to dinv.  Thread pair (i, h) owns row i and, within it, the
+// columns of parity h, so every step is a short loop with no index
+// arithmetic beyond a stride of 2.  A non-positive pivot sets *bad and is
+// replaced by a tiny positive value so the factor stays finite.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_potrf_diag(float* __restrict__ Kd, int64_t ld, int64_t sK,
                                                          float* __restrict__ dinv, int64_t sD, int* __restrict__ bad) {
@@ -297,9 +300,11 @@ __global__ __launch_bounds__(kThreads) void k_potrf_diag(float* __restrict__ Kd,
   __shared__ float a[kNB][kNB + 1];
   __shared__ float x[kNB][kNB + 1];
   const int tid = threadIdx.x;
+  const int i = tid >> 1, h = tid & 1;
   for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx / kNB, j = idx % kNB;
-    a[i][j] = (j <= i) ? Kd[(int64_t)i * ld + j] : 0.0f;
+    const int r = idx / kNB, c = idx % kNB;
+    a[r][c] = (c <= r) ? Kd[(int64_t)r * ld + c] : 0.0f;
+    x[r][c] = (r == c) ? 1.0f : 0.0f;
   }
   __syncthreads();
   for (int k = 0; k < kNB; ++k) {
@@ -312,35 +317,28 @@ __global__ __launch_bounds__(kThreads) void k_potrf_diag(float* __restrict__ Kd,
       a[k][k] = sqrtf(p);
     }
     __syncthreads();
-    const float piv = a[k][k];
-    for (int i = k + 1 + tid; i < kNB; i += kThreads) a[i][k] /= piv;
+    if (h == 0 && i > k) a[i][k] /= a[k][k];
     __syncthreads();
-    const int rem = kNB - 1 - k;
-    for (int idx = tid; idx < rem * rem; idx += kThreads) {
-      const int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
-      if (j <= i) a[i][j] -= a[i][k] * a[j][k];
+    if (i > k) {
+      const float lik = a[i][k];
+      for (int j = k + 1 + h; j <= i; j += 2) a[i][j] -= lik * a[j][k];
     }
     __syncthreads();
   }
-  if (tid < kNB) {
-    const int c = tid;
-    for (int i = 0; i < kNB; ++i) {
-      float v;
-      if (i < c) v = 0.0f;
-      else if (i == c) v = 1.0f / a[c][c];
-      else {
-        float s = 0.0f;
-        for (int k = c; k < i; ++k) s += a[i][k] * x[k][c];
-        v = -s / a[i][i];
-      }
-      x[i][c] = v;
+  // x holds I - sum_{m<k} L[i][m] X[m][:] for rows i >= k; row k is then final up to 1/L[k][k]
+  for (int k = 0; k < kNB; ++k) {
+    if (tid <= k) x[k][tid] /= a[k][k];
+    __syncthreads();
+    if (i > k) {
+      const float lik = a[i][k];
+      for (int c = h; c <= k; c += 2) x[i][c] -= lik * x[k][c];
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
-    const int i = idx / kNB, j = idx % kNB;
-    Kd[(int64_t)i * ld + j] = (j <= i) ? a[i][j] : 0.0f;
-    dinv[idx] = x[i][j];
+    const int r = idx / kNB, c = idx % kNB;
+    Kd[(int64_t)r * ld + c] = (c <= r) ? a[r][c] : 0.0f;
+    dinv[idx] = x[r][c];
   }
 }
 
@@ -489,7 +487,7 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
   return hipGetLastError();
 }
 
-hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb_prob, hipStream_t st,
+static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb_prob, hipStream_t st,
                     int* bad) {
   const int64_t nb = n / kNB;
   for (int64_t j = 0; j < nb; ++j) {
@@ -513,7 +511,7 @@ hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, in
   return hipSuccess;
 }
 
-hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
+static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
                          float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, hipStream_t st) {
   const int64_t nb = n / kNB;
   hipError_t e;
@@ -539,6 +537,15 @@ hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const floa
   hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)(t * (t + 1) / 2), (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld,
                      sK);
   return hipGetLastError();
+}
+
+int64_t inverse_factor_scratch(int64_t n) { return 2 * kNB * n + kNB * kNB; }
+
+hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb,
+                              float* tmp, int64_t sT, int* bad, hipStream_t st) {
+  hipError_t e = cholesky(S, n, ld, sK, dinv, sD, nb, st, bad);
+  if (e != hipSuccess) return e;
+  return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, tmp + kNB * n, sT, tmp + 2 * kNB * n, sT, st);
 }
 
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,

@@ -7,10 +7,10 @@
 //   (U^T U + rho' I) x = q + rho (z - u),  q = U^T y,  rho' = rho + mu,
 // done in constraint space with the Woodbury identity
 //   x = (1/rho') (b - U^T (rho' I + U U^T)^{-1} U b),
-// where U U^T is formed once by the MFMA Gram kernel, factorised once by the
-// blocked Cholesky, and the factor inverted once (W = L^-1), so that every
-// x-update applies (rho' I + U U^T)^-1 = W^T W as two HBM-bound matrix-vector
-// passes; the z-update clips to w >= 0 (over-relaxed) and u carries the
+// where U U^T is formed once by the MFMA Gram kernel, then factorised
+// (blocked Cholesky) and its factor inverted once (W = L^-1, recursive blocks
+// on MFMA GEMMs), so that every x-update applies (rho' I + U U^T)^-1 = W^T W
+// as two HBM-bound matrix-vector passes; the z-update clips to w >= 0 (over-relaxed) and u carries the
 // scaled dual.  Every pass over U streams A itself (orbit-major)
 // with the scaling folded into per-constraint multipliers:
 //   column sums   t_n = (w~/sigma_n) sum_i A[i][n] v_i       (U v)
@@ -46,8 +46,9 @@ constexpr int kColTile = kColThreads * kColsPerThread;
 constexpr int kSlabs = 256;       // orbit slabs per problem in the column-sum reduction
 constexpr int kPar = 8;           // per-problem scalars: wt, rho, rho', mu, alpha, active
 constexpr int kAcc = 16;          // per-problem accumulators
-constexpr int kStallChecks = 5;   // stage 1 stalls when max(primal, dual) residual has not
-constexpr double kStallRatio = 0.9;  // dropped below 0.9x its value kStallChecks checks earlier
+constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
+constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) residual has not
+constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -666,7 +667,7 @@ struct SolveLayout {
   size_t off_qf, off_zf, off_uf, off_vf;
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
-  size_t off_par, off_acc, off_idx, off_bad, off_pt, off_xb, off_dt;
+  size_t off_par, off_acc, off_idx, off_bad, off_ftmp;
   // compressed copies (sized for at most cap_nnz entries): ncb column blocks
   // of the rows, nrb row blocks per problem of the columns
   int64_t cap_nnz;
@@ -709,12 +710,10 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   L.off_acc = take((size_t)P * kAcc * 8);
   L.off_idx = take((size_t)(P + 1) * 8 * 4);
   L.off_bad = take(64);
-  L.off_pt = take((size_t)P * kNB * L.Cp * 4);
-  L.off_xb = take((size_t)P * L.Cp * kNB * 4);
-  L.off_dt = take((size_t)P * kNB * kNB * 4);
-  // compressed copies: room for 10% density (or 1M entries), 8-byte values
+  L.off_ftmp = take((size_t)P * inverse_factor_scratch(L.Cp) * 4);
+  // compressed copies: room for kMaxDensity (or 1M entries), 8-byte values
   const double dense = (double)L.N * (double)L.C;
-  L.cap_nnz = std::max<int64_t>((int64_t)(0.10 * dense), (int64_t)1 << 20);
+  L.cap_nnz = std::max<int64_t>((int64_t)(kMaxDensity * dense), (int64_t)1 << 20);
   if ((double)L.cap_nnz > dense) L.cap_nnz = (int64_t)dense;
   L.ncb = (int)((L.C + kBlk - 1) / kBlk);
   L.nrb = 1;
@@ -835,8 +834,9 @@ static int build_sparse(Ctx& X) {
     at += quad(hr[k]);
   }
   rptr[hr.size()] = at;
-  // compressed passes pay off below ~25% density
-  if (at > L.cap_nnz || (double)nnz > 0.25 * (double)L.N * (double)L.C) return SW_OK;
+  // a compressed entry costs 6 bytes per pass against 4 (fp32) dense: the
+  // compressed passes pay off well below 2/3 density; copies are kept up to kMaxDensity
+  if (at > L.cap_nnz || (double)nnz > kMaxDensity * (double)L.N * (double)L.C) return SW_OK;
   // columns: segment (b, rb, c) = the slabs of row block rb; slab_at[b][s][c]
   // = absolute position of slab s's first entry of column c
   std::vector<int64_t> cptr((size_t)P * nrb * (L.C + 1), 0), slab_at((size_t)P * kSlabs * L.C);
@@ -946,7 +946,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     return SW_ENOMEM;
   }
   const int max_iter = opt->max_iter > 0 ? opt->max_iter : 1000;
-  const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 500 : opt->refine_iter);
+  const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 2000 : opt->refine_iter);
   const int check_every = opt->check_every > 0 ? opt->check_every : 10;
   const double tol = opt->tol > 0.0 ? opt->tol : 1e-4;
   const double tol_kkt = opt->tol_kkt > 0.0 ? opt->tol_kkt : 1e-7;
@@ -1018,7 +1018,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
 
   // ---- Gram K_b = U_b U_b^T (lower tiles) ----
   float* K = X.p<float>(L.off_K);
-  const int64_t sK = L.Cp * L.Cp, sD = L.Cp * kNB;
+  const int64_t sK = L.Cp * L.Cp;
   SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
               L.xoff.data(), L.xlen.data(), P, K, L.Cp, sK, X.st));
   SW_TRY(hipEventRecord(ev[2], X.st));
@@ -1058,10 +1058,8 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   hipLaunchKernelGGL(k_add_diag, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, K, L.Cp, sK, L.Cp, X.par);
   int* bad = X.p<int>(L.off_bad);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, X.st, bad, (int64_t)1, 0);
-  float* dinv = X.p<float>(L.off_dinv);
-  SW_TRY(cholesky(K, L.Cp, L.Cp, sK, dinv, sD, P, X.st, bad));
-  SW_TRY(invert_factor(K, L.Cp, L.Cp, sK, dinv, sD, P, X.p<float>(L.off_pt), kNB * L.Cp, X.p<float>(L.off_xb),
-                       L.Cp * kNB, X.p<float>(L.off_dt), kNB * kNB, X.st));
+  SW_TRY(spd_inverse_factor(K, L.Cp, L.Cp, sK, X.p<float>(L.off_dinv), L.Cp * kNB, P, X.p<float>(L.off_ftmp),
+                            inverse_factor_scratch(L.Cp), bad, X.st));
   SW_TRY(hipEventRecord(ev[4], X.st));
   int hbad = 0;
   SW_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, X.st));
