@@ -26,7 +26,15 @@ METRIC = "orbit-steps/s and model builds/s vs FP64 oracle; surrogate-MCMC models
 PEAK_HBM = 8.0e12           # bytes/s
 PEAK_BF16 = 2.5e15          # dense MFMA flop/s
 PEAK_F32_MFMA = 157.3e12
-PEAK_F32_VALU_UNPACKED = 256 * 4 * 16 * 2 * 2.4e9  # 78.6 TFLOP/s: FMA on 64 lanes/CU/clk without packed fp32
+PEAK_F32_VALU = 157.3e12     # vector FP32 with packed FP32 (this build compiles without it: 78.6)
+PEAK_F64_VALU = 78.6e12
+# FP32 (FP64 for the small model) flops per orbit-step of each workload's
+# integrate-and-bin, counted from the kernel's formulas (FMA = 2)
+FLOP_PER_ORBIT_STEP = {"mn_ferrers_nfwq_100k_orbits_10k_steps_f32": 686.0,
+                       "plummer_mn_2k_orbits_1k_steps_f64": 168.0}
+# HBM bytes per build measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (calibrated on a
+# 4 GiB copy), per stage, for the kernels as they stand; None where not measured
+TRAFFIC = {("mn_ferrers_nfwq_100k_orbits_10k_steps_f32", "factorise"): 2.35e12}
 
 
 def log(*a):
@@ -171,26 +179,45 @@ def main():
     orbit_steps = n * n_steps
     value = orbit_steps * args.steps / el
 
-    # roofline of the dominant kernel
+    # rooflines per stage (algorithmic work per build / the stage's HIP-event time on the solve stream)
     t_gram = float(np.mean([r["t_gram_ms"] for r in reps]))
     t_factor = float(np.mean([r["t_factor_ms"] for r in reps]))
     t_admm = float(np.mean([r["t_admm_ms"] for r in reps]))
     t_ref = float(np.mean([r["t_refine_ms"] for r in reps]))
     t_i = float(np.mean(t_int))
-    Cp = (nc + 127) // 128 * 128
-    Np = (n + 63) // 64 * 64
+    it1 = float(np.mean([r["iters"] for r in reps]))
+    it2 = float(np.mean([r["refine_iters"] for r in reps]))
+    nnz = float(reps[-1]["nnz"])
+    C, N = float(nc), float(n)
     passes = {"bf16": 1, "bf16x3": 3, "f32": 1}[args.gram]
-    gram_flops = passes * Np * Cp * (Cp + 128)  # lower 128x128 tiles incl. diagonal tiles, 2 flop per MAC
-    stages = {"integrate_and_bin": t_i, "gram": t_gram, "cholesky": t_factor, "admm_fp32": t_admm,
+    stages = {"integrate_and_bin": t_i, "gram": t_gram, "factorise": t_factor, "admm_fp32": t_admm,
               "refine_fp64": t_ref}
+    # bytes of one compressed pass (fp32 value + 16-bit index per entry) or of a dense pass over A
+    pass_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
+    tri_bytes = 4.0 * C * (C + 1)  # both triangles of the fp32 inverse factor
+    rooflines = {
+        "integrate_and_bin": {"kernel": "k_integrate + k_hist", "bound": "alu", "unit": "TFLOP/s",
+                              "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
+                              "work": FLOP_PER_ORBIT_STEP[cfg["name"]] * N * n_steps, "ms": t_i},
+        "gram": {"kernel": f"k_gram_bf16 ({args.gram})" if args.gram != "f32" else "k_gemm_nt_f32 (Gram)",
+                 "bound": "mfma", "unit": "TFLOP/s",
+                 "peak": (PEAK_BF16 if args.gram != "f32" else PEAK_F32_MFMA) / 1e12,
+                 "work": passes * C * (C + 1) * N, "ms": t_gram},
+        "factorise": {"kernel": "k_potrf_diag + k_gemm_nt_f32 (Cholesky, inverse factor)", "bound": "mfma",
+                      "unit": "TFLOP/s", "peak": PEAK_F32_MFMA / 1e12, "work": 2.0 * C ** 3 / 3.0, "ms": t_factor},
+        "admm_fp32": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
+                      "peak": PEAK_HBM / 1e9, "work": it1 * (2 * pass_bytes + tri_bytes), "ms": t_admm},
+        "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
+                        "peak": PEAK_HBM / 1e9, "work": it2 * (4 * pass_bytes + tri_bytes), "ms": t_ref},
+    }
+    for k, r in rooflines.items():
+        scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
+        r["achieved"] = round(r["work"] / (r["ms"] * 1e-3) / scale, 3) if r["ms"] > 0 else None
+        r["frac"] = round(r["achieved"] / r["peak"], 4) if r["achieved"] is not None else None
+        r["traffic"] = TRAFFIC.get((cfg["name"], k))
+        r["work"] = float(r["work"])
     dominant = max(stages, key=stages.get)
-    if args.gram == "f32":
-        roof = {"kernel": "k_gemm_nt_f32 (Gram, fp32 MFMA)", "bound": "mfma", "peak": PEAK_F32_MFMA / 1e12}
-    else:
-        roof = {"kernel": f"k_gram_bf16 ({args.gram})", "bound": "mfma", "peak": PEAK_BF16 / 1e12}
-    ach = gram_flops / (t_gram * 1e-3) / 1e12
-    roof.update({"achieved": round(ach, 2), "unit": "TFLOP/s", "frac": round(ach / roof["peak"], 4),
-                 "traffic": None, "work_per_launch_flop": gram_flops, "avg_launch_ms": round(t_gram, 3)})
+    roof = dict(rooflines[dominant], stage=dominant)
 
     out = {
         "metric": METRIC, "value": value, "unit": "orbit-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -205,6 +232,7 @@ def main():
         "chi2": chis[-1],
         "integrate_orbit_steps_per_s": orbit_steps / (t_i * 1e-3),
         "roofline": roof,
+        "rooflines": rooflines,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
@@ -318,8 +346,14 @@ def bench_walkers(args):
     t0 = time.perf_counter()
     for i in range(args.steps):
         reps = step()
+        its = np.array([r.iters for r in reps]); rits = np.array([r.refine_iters for r in reps])
+        kkts = np.array([r.kkt for r in reps])
         log(f"step {i}: integrate {t_int[-1]:.1f} ms, solve+chi2 {t_solve[-1]:.1f} ms, "
-            f"iters {max(r.iters for r in reps)}+{max(r.refine_iters for r in reps)}")
+            f"iters max {its.max()}+{rits.max()} median {int(np.median(its))}+{int(np.median(rits))}, "
+            f"converged {sum(r.converged for r in reps)}/{len(reps)}, kkt max {kkts.max():.2e}, nnz {reps[0].nnz:.3g}")
+        slow = np.argsort(-(its + 2 * rits))[:4]
+        log("slowest walkers: " + "; ".join(f"#{k} n={offs[k + 1] - offs[k]} it={its[k]}+{rits[k]} kkt={kkts[k]:.1e} "
+                                            f"chi2={chis[-1][k]:.4g}" for k in slow))
     el = time.perf_counter() - t0
     out = {"metric": METRIC, "value": n_w * args.steps / el, "unit": "model builds/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
@@ -366,8 +400,11 @@ def bench_surrogate(args):
                                 solve_opts=opts)
             seeds.append(float(b2.chi2(nominal[None, :])[0]))
             del b2
-        dchi2 = float(np.std(seeds, ddof=1))
-        log(f"dchi2 = {dchi2:.3g} (chi2 at nominal over 8 seeds: {np.round(seeds, 1).tolist()})")
+        seed_spread = float(np.std(seeds, ddof=1))
+        n_ap = obs_d["npx"] * obs_d["npy"]
+        dchi2, jk = builder.jackknife_dchi2(nominal, n_ap, obs_d["nv"])
+        log(f"dchi2 (aperture jackknife, {n_ap} solves) = {dchi2:.4g}; chi2 spread over 8 library seeds "
+            f"{seed_spread:.4g} (values {np.round(seeds, 1).tolist()})")
         u = W.latin_hypercube(args.n_train, 12, seed=7)
         thetas = lo + (hi - lo) * u
         t0 = time.perf_counter()
@@ -387,14 +424,29 @@ def bench_surrogate(args):
         theta0 = W.walker_thetas(32, seed=8, spread=0.05)
         res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log)
         res_mh = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=False, log=log)
+        # the plain single-model path: one trial potential per build, no batching, no surrogate
+        single = S.ModelBuilder(W.theta_to_model, ics, dt, n_steps, obs_d, d, sig, wt, 1, kin_block=blocks[1],
+                                solve_opts=opts)
+        single.chi2(theta0[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_single = 16
+        single.chi2(theta0[:n_single])
+        torch.cuda.synchronize()
+        single_per_s = n_single / (time.perf_counter() - t0)
+        del single
+        log(f"plain single-model path: {single_per_s:.2f} models/s; batched MH {res_mh['models_per_s']:.2f}; "
+            f"DA {res_da['models_per_s']:.2f}")
     out = {"metric": METRIC, "value": res_da["models_per_s"], "unit": "surrogate-MCMC models/s", "n_gpus": 1,
            "steps": args.mcmc_steps, "warmup": 0, "ms_per_step": 1e3 * res_da["seconds"] / args.mcmc_steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "surrogate_da_mcmc_32_walkers_small_model_barred_family", "n_train": args.n_train,
                       "mcmc_steps": args.mcmc_steps},
-           "dchi2": dchi2, "train_builds_per_s": args.n_train / t_build,
+           "dchi2": dchi2, "dchi2_rule": "aperture jackknife", "chi2_seed_spread": seed_spread,
+           "train_builds_per_s": args.n_train / t_build,
            "heldout_err_over_dchi2_median": float(np.median(err)), "heldout_frac_err_below_dchi2": float(np.mean(err < 1)),
-           "plain_mh_models_per_s": res_mh["models_per_s"],
+           "plain_mh_models_per_s": res_mh["models_per_s"], "single_model_path_per_s": single_per_s,
+           "speedup_vs_single_model_path": res_da["models_per_s"] / single_per_s,
            "da": {k: res_da[k] for k in ("n_full_builds", "n_stage1", "n_accepted", "seconds", "proposals")},
            "mh": {k: res_mh[k] for k in ("n_full_builds", "n_accepted", "seconds", "proposals")}}
     print(json.dumps(out))

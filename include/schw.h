@@ -184,7 +184,8 @@ typedef struct {
   int32_t use_graph;   /* 1: the iterations between two checks are captured once into a HIP
                           graph and replayed (needs a non-NULL stream); 0: plain launches */
   int32_t flags;       /* SW_SOLVE_DENSE: stream the dense A in every pass (no compressed copy) */
-  double rho;          /* ADMM penalty for the scaled problem (<= 0: trace(U U^T) / N) */
+  double rho;          /* ADMM penalty for the scaled problem: > 0 absolute; 0: trace(U U^T) / N
+                          of each problem; < 0: -rho times that */
   double tol;          /* relative primal/dual tolerance of the FP32 stage (<= 0: 1e-4) */
   double tol_kkt;      /* target relative KKT residual of the FP64 stage (<= 0: 1e-7) */
   double nu;           /* relative regularisation used when lambda < 0 */
@@ -286,6 +287,26 @@ int mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t 
 int mlp_mse_grad(const float* y, const float* t, int64_t B, float* dy, void* stream);
 int mlp_pack_bf16(const float* params, void* packed, void* stream);
 int mlp_infer_bf16(const void* packed, const float* x, int64_t B, float* y, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Gauss-Hermite moments (Sec. 2.2.4, Eq. 2) of the orbits' velocity histograms.
+ * Eq. 2 expands an LOSVD about a reference Gaussian (centre v0, width s) in the
+ * modified Hermite polynomials H_m; the linear moments
+ *   g_m = 2 sqrt(pi) int f(v) alpha(w) H_m(w) dv,  w = (v - v0)/s,
+ * equal gamma h_m (g_0 = gamma) and add over weighted orbits.  A histogram bin
+ * is read as mass spread uniformly over the bin:
+ *   out[i][a][m] = sum_k A[i][kin0 + a nv + k] 2 sqrt(pi) (1/dv) int_{bin k} alpha H_m dv
+ *   A          device [n_orb][n_con], SW_F32 | SW_F64; cells kin0 + a nv + k, k < nv,
+ *              the nv velocity bins of [vlo, vhi) of aperture a (kin0 + n_ap nv <= n_con)
+ *   v0, s      host [n_ap], s > 0: reference Gaussian per aperture
+ *   n_gh       highest order, 0..8
+ *   out        device [n_orb][n_ap][n_gh + 1] double
+ *   workspace  device, >= gh_workspace_bytes(n_ap, nv, n_gh) (the per-bin maps)
+ * Synchronises the stream.  Returns SW_OK, SW_EINVAL, SW_ENOMEM or SW_EHIP.   */
+size_t gh_workspace_bytes(int32_t n_ap, int32_t nv, int32_t n_gh);
+int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64_t kin0, int32_t n_ap,
+               int32_t nv, double vlo, double vhi, const double* v0, const double* s, int32_t n_gh,
+               double* out, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Launch tuning (process-wide, not thread-safe; set before launching work):

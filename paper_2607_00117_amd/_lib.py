@@ -110,6 +110,10 @@ def load():
     L.mlp_pack_bf16.argtypes = [vp, vp, vp]
     L.mlp_mse_grad.argtypes = [vp, vp, i64, vp, vp]
     L.mlp_infer_bf16.argtypes = [vp, vp, i64, vp, vp]
+    L.gh_workspace_bytes.argtypes = [i32, i32, i32]
+    L.gh_workspace_bytes.restype = sz
+    L.gh_moments.argtypes = [vp, i32, i64, i64, i64, i32, i32, C.c_double, C.c_double, C.POINTER(C.c_double),
+                             C.POINTER(C.c_double), i32, vp, vp, sz, vp]
     L.sw_set_tuning.argtypes = [C.c_char_p, i32]
     L.sw_get_tuning.argtypes = [C.c_char_p]
     L.sw_get_tuning.restype = i32
@@ -250,6 +254,20 @@ def chi2(A, w, d, sigma, col_begin, col_end, workspace):
                        int(col_end), C.byref(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                        _stream()))
     return out.value
+
+
+def gh_workspace_bytes(n_ap, nv, n_gh=4):
+    return load().gh_workspace_bytes(int(n_ap), int(nv), int(n_gh))
+
+
+def gh_moments(A, kin0, n_ap, nv, vlo, vhi, v0, s, out, workspace, n_gh=4):
+    """out: device [n_orb][n_ap][n_gh + 1] double; v0, s: sequences of n_ap floats."""
+    n_orb, n_con = A.shape
+    v0a = (C.c_double * n_ap)(*[float(v) for v in v0])
+    sa = (C.c_double * n_ap)(*[float(v) for v in s])
+    _check(load().gh_moments(_ptr(A), _dtype_code(A), n_orb, n_con, int(kin0), int(n_ap), int(nv), float(vlo),
+                             float(vhi), v0a, sa, int(n_gh), _ptr(out), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream()))
 
 
 def model_observables(A, w, out):

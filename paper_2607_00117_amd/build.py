@@ -25,6 +25,7 @@ SOURCES = {
     "solve.hip": [],
     "gemm.hip": [],
     "mlp.hip": [],
+    "gh.hip": [],
 }
 
 

@@ -115,8 +115,10 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
 template <typename TA, typename TV>
 __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A, int64_t C,
                                                         const TV* __restrict__ v, const int64_t* __restrict__ off,
-                                                        const int64_t* __restrict__ rps, double* __restrict__ part) {
+                                                        const int64_t* __restrict__ rps, const double* __restrict__ par,
+                                                        double* __restrict__ part) {
   const int b = blockIdx.z;
+  if (par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
   const int64_t c0 = (int64_t)blockIdx.x * kColTile;
   const int64_t s = blockIdx.y;
   const int64_t i_beg = off[b] + s * rps[b];
@@ -343,10 +345,11 @@ __global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, const int6
                                                           const int64_t* __restrict__ cptr,
                                                           const uint16_t* __restrict__ rowi,
                                                           const TA* __restrict__ val, const TV* __restrict__ v,
-                                                          double* __restrict__ part) {
+                                                          const double* __restrict__ par, double* __restrict__ part) {
   __shared__ double xs[kBlk];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.y;
+  if (par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
   const int64_t n0 = off[b], nb = off[b + 1] - n0;
   const int64_t brows = slabs_per_block(rps[b]) * rps[b];
   const int64_t cw = (int64_t)blockIdx.x * (kSpWaves * kColsPerWave) + w;
@@ -544,7 +547,7 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
   const int64_t i = (int64_t)blockIdx.x * (kRowsBlock / 64) + w;
   if (i >= N) return;
   const int b = find_problem(R.off, R.nprob, i);
-  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
+  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q) return;  // converged problem: frozen
   const double* scb = sc + (int64_t)b * R.Cp;
   const TA* row = A + i * C;
   double dot = 0.0;
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, c
   const int64_t i_end = R.off[b + 1];
   const int64_t i0 = R.off[b] + (int64_t)blockIdx.x * (kSpWaves * kRowsPerWave);
   if (i0 >= i_end) return;
-  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q && R.op != ROW_KKT) return;  // converged problem: frozen
+  if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q) return;  // converged problem: frozen
   const double* scb = sc + (int64_t)b * R.Cp;
   const TA* val = (const TA*)R.csr_val;
   const uint16_t* col = (const uint16_t*)R.csr_col;
@@ -754,21 +757,21 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
     dim3 grid((unsigned)((X.L.C + kSpWaves * kColsPerWave - 1) / (kSpWaves * kColsPerWave)), (unsigned)X.L.P);
     if (X.dtype == SW_F32)
       hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d, X.L.nrb,
-                         X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
+                         X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v, X.par,
                          X.p<double>(X.L.off_part));
     else
       hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d,
                          X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<double>(X.L.off_cval),
-                         v, X.p<double>(X.L.off_part));
+                         v, X.par, X.p<double>(X.L.off_part));
     return hipGetLastError();
   }
   dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
   if (X.dtype == SW_F32)
     hipLaunchKernelGGL((k_colsum<float, TV>), grid, dim3(kColThreads), 0, X.st, (const float*)X.A, X.L.C, v, X.off_d,
-                       X.rps_d, X.p<double>(X.L.off_part));
+                       X.rps_d, X.par, X.p<double>(X.L.off_part));
   else
     hipLaunchKernelGGL((k_colsum<double, TV>), grid, dim3(kColThreads), 0, X.st, (const double*)X.A, X.L.C, v,
-                       X.off_d, X.rps_d, X.p<double>(X.L.off_part));
+                       X.off_d, X.rps_d, X.par, X.p<double>(X.L.off_part));
   return hipGetLastError();
 }
 
@@ -1046,7 +1049,8 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     if (n_eff == 0) n_eff = 1;
     const double mean_col = trace[b] / (double)n_eff;
     mu[b] = lambda >= 0.0 ? 2.0 * lambda / (double)n_eff : opt->nu * mean_col;
-    rho[b] = opt->rho > 0.0 ? opt->rho : (mean_col > 0.0 ? mean_col : 1.0);
+    const double base = mean_col > 0.0 ? mean_col : 1.0;
+    rho[b] = opt->rho > 0.0 ? opt->rho : (opt->rho < 0.0 ? -opt->rho * base : base);
     hpar[b * kPar + 1] = rho[b];
     hpar[b * kPar + 2] = rho[b] + mu[b];
     hpar[b * kPar + 3] = mu[b];
@@ -1197,6 +1201,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   SW_TRY(hipGetLastError());
   std::vector<double> kkt(P, 0.0), obj(P, 0.0);
   std::vector<int> support(P, 0);
+  // the KKT evaluation covers the active problems; a frozen problem keeps its last values
   auto kkt_eval = [&]() -> int {
     SW_TRY(zero_acc(X));
     SW_TRY(colsum<double>(X, zd));
@@ -1208,12 +1213,15 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     SW_TRY(hipMemcpyAsync(hacc.data(), acc, hacc.size() * 8, hipMemcpyDeviceToHost, X.st));
     SW_TRY(hipStreamSynchronize(X.st));
     for (int b = 0; b < P; ++b) {
+      if (!active[b]) continue;
       kkt[b] = hacc[b * kAcc + 6] / qmax[b];
       obj[b] = 0.5 * hacc[b * kAcc + 9] + 0.5 * mu[b] * hacc[b * kAcc + 7];
       support[b] = (int)hacc[b * kAcc + 8];
     }
     return SW_OK;
   };
+  for (int b = 0; b < P; ++b) active[b] = 1;
+  SW_TRY(set_active(active));
   int rc = kkt_eval();
   if (rc != SW_OK) return rc;
   for (int b = 0; b < P; ++b) active[b] = kkt[b] > tol_kkt ? 1 : 0;

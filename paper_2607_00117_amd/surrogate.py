@@ -6,10 +6,11 @@ the C ABI; the surrogate is trained and evaluated with the library's MLP
 kernels.  The control flow of the sampler (proposals, accept/reject) lives
 here on the host.
 
-Likelihood (Sec. 2.4, Eq. 7): ln L = -chi^2 / dchi2.  dchi2, the scale of the
-intrinsic stochasticity of chi^2 (Sec. 2.4), is measured as the standard
-deviation of chi^2 at fixed parameters over independently seeded orbit
-libraries.
+Likelihood (Sec. 2.4, Eq. 7): ln L = -chi^2 / dchi2.  dchi2 is the paper's
+jackknife scale (Sec. 2.4): the weights are solved again once per aperture
+with that aperture's kinematic constraints left out, and dchi2 is the
+jackknife standard deviation of the resulting chi^2 values.  The spread of
+chi^2 over independently seeded orbit libraries is reported beside it.
 
 Sampler: random-walk Metropolis with delayed acceptance (Christen & Fox 2005):
 a proposal must first pass the surrogate screen min(1, L~(theta')/L~(theta));
@@ -77,6 +78,39 @@ class ModelBuilder:
         for k0 in range(0, len(thetas), self.max_batch):
             out.extend(self._chi2_batch(thetas[k0:k0 + self.max_batch]))
         return np.array(out)
+
+    def jackknife_dchi2(self, theta, n_ap, nv):
+        """Sec. 2.4: one build at theta, then n_ap weight solves of the same
+        matrix, solve a without aperture a's nv kinematic constraints (their
+        sigma set so large that they carry no weight), all in one batched
+        call; chi^2_a is taken over the kinematic constraints that solve a
+        kept.  Returns (dchi2, chi2 values)."""
+        torch = self.torch
+        if n_ap > self.max_batch:
+            raise ValueError("jackknife needs n_ap <= max_batch")
+        self._chi2_batch(np.asarray(theta, dtype=np.float64)[None, :])
+        n, k0 = self.n, self.kin[0]
+        for a in range(1, n_ap):
+            self.A[a * n:(a + 1) * n].copy_(self.A[:n])
+            self.fl[a * n:(a + 1) * n].copy_(self.fl[:n])
+        sig = self.sig[:n_ap].clone()
+        for a in range(n_ap):
+            sig[a, k0 + a * nv:k0 + (a + 1) * nv] = 1e30 * float(self.s1.max())
+        offs = [n * j for j in range(n_ap + 1)]
+        A = self.A[:n * n_ap]
+        self.opts.mask = self.fl.data_ptr() if self.drift_mask else None
+        P.solve_weights_batched(A, offs, self.d[:n_ap], sig, [self.w_tilde] * n_ap, -1.0, self.opts,
+                                self.w[:n * n_ap], self.sws)
+        cb, ce = self.kin
+        chi = []
+        for a in range(n_ap):
+            Aa, wa = A[offs[a]:offs[a + 1]], self.w[offs[a]:offs[a + 1]]
+            full = P.chi2(Aa, wa, self.d1, self.s1, cb, ce, self.cws)
+            held = P.chi2(Aa, wa, self.d1, self.s1, k0 + a * nv, k0 + (a + 1) * nv, self.cws)
+            chi.append(full - held)
+        chi = np.array(chi)
+        dchi2 = math.sqrt((n_ap - 1) / n_ap * float(np.sum((chi - chi.mean()) ** 2)))
+        return dchi2, chi
 
     def _chi2_batch(self, thetas):
         k = len(thetas)

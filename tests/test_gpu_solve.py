@@ -231,3 +231,35 @@ def test_compressed_blocks_match_dense_passes(gpu):
     assert st_s == 0 and st_d == 0
     assert np.abs(w_s - w_d).sum() / np.abs(w_d).sum() < 1e-3
     assert abs(x_s / x_d - 1) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gh_moments_match_oracle(gpu, dtype):
+    """Gauss-Hermite moments (Eq. 2) of the kinematic block of the small model's
+    orbit matrix against the oracle's quadrature, per orbit and aperture."""
+    import torch
+    from oracle import gh as OG
+    P = lib()
+    cfg = W.SMALL
+    n_steps = 300
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=n_steps)
+    ics, dt = ics[:, ::4], dt[::4]
+    A, _, _, _ = gpu_integrate(cfg, ics, dt, n_steps, "f64")
+    if dtype == "f32":
+        A = A.astype(np.float32)
+    o = cfg["obs"]
+    n_ap, nv, kin0 = o["npx"] * o["npy"], o["nv"], o["nx"] * o["ny"] * o["nz"]
+    rng = np.random.default_rng(5)
+    v0 = rng.uniform(-60, 60, n_ap)
+    s = rng.uniform(40, 160, n_ap)
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    out = torch.empty((A.shape[0], n_ap, 5), dtype=torch.float64, device=dev)
+    ws = torch.empty(P.gh_workspace_bytes(n_ap, nv), dtype=torch.uint8, device=dev)
+    P.gh_moments(At, kin0, n_ap, nv, o["vlo"], o["vhi"], v0, s, out, ws)
+    g = out.cpu().numpy()
+    ref = OG.orbit_moments(A[:, kin0:kin0 + n_ap * nv].astype(np.float64), n_ap, nv, o["vlo"], o["vhi"], v0, s)
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref).max() / scale
+    print("gh max rel err", err)
+    assert err < 1e-12
