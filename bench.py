@@ -34,7 +34,7 @@ FLOP_PER_ORBIT_STEP = {"mn_ferrers_nfwq_100k_orbits_10k_steps_f32": 686.0,
                        "plummer_mn_2k_orbits_1k_steps_f64": 168.0}
 # HBM bytes per build measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (calibrated on a
 # 4 GiB copy), per stage, for the kernels as they stand; None where not measured
-TRAFFIC = {("mn_ferrers_nfwq_100k_orbits_10k_steps_f32", "factorise"): 2.35e12}
+TRAFFIC = {}
 
 
 def log(*a):
@@ -87,6 +87,11 @@ def main():
     ap.add_argument("--mcmc-steps", type=int, default=200, help="surrogate: DA-MCMC steps per walker")
     ap.add_argument("--gram", default="bf16x3", choices=["bf16", "bf16x3", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=0, help="cap of the FP32 ADMM stage (0: library default)")
+    ap.add_argument("--refine-iter", type=int, default=0, help="cap of the FP64 stage (0: library default)")
+    ap.add_argument("--no-graph", action="store_true", help="launch the solve iterations one by one")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a 4 GiB device-to-device copy (scale for the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -149,7 +154,9 @@ def main():
 
     reps, chis, t_int = [], [], []
     stream = torch.cuda.Stream()  # default priority; the solve captures its iterations into HIP graphs on it
-    opts.use_graph = 1
+    opts.use_graph = 0 if args.no_graph else 1
+    opts.max_iter = args.max_iter
+    opts.refine_iter = args.refine_iter
 
     def step():
         with torch.cuda.stream(stream):
@@ -236,6 +243,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
+    if args.calibration_copy:
+        src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(json.dumps(out))
 
 

@@ -56,6 +56,13 @@ void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 
+// Workgroup shape of the compressed passes of the weight solve, set through
+// sw_set_tuning (0 = automatic):
+//  g_sparse_rows   orbits per row-dot workgroup
+//  g_sparse_cols   constraints per column-sum workgroup
+extern int g_sparse_rows;
+extern int g_sparse_cols;
+
 }  // namespace sw
 
 #define SW_HIP(call)                                              \

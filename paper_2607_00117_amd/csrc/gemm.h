@@ -36,10 +36,10 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
 // updates by fp32 MFMA; then its inverse W = L_b^-1 column block by column
 // block from the right, W_{>j,j} = -W_{>j,>j} L_{>j,j} inv(L_jj), which only
 // ever multiplies by the inverse of one 128 x 128 block.  S_b ends as
-// W + W^T - diag(W) over the whole buffer.  tmp: inverse_factor_scratch(n)
+// W + W^T - diag(W) over the whole buffer.  tmp: inverse_factor_scratch(n, nb)
 // floats per problem at stride sT.  bad: device int set to 1 when a pivot is
 // not positive (the factor stays finite).
-int64_t inverse_factor_scratch(int64_t n);
+int64_t inverse_factor_scratch(int64_t n, int nb);
 hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb,
                               float* tmp, int64_t sT, int* bad, hipStream_t st);
 

@@ -10,6 +10,8 @@
 // launch only the tiles on or below the diagonal, and consecutive workgroup
 // ids are spread so that each XCD (ids congruent mod 8) works on a
 // contiguous run of tiles, which share operand panels in that XCD's L2.
+#include <algorithm>
+
 #include "gemm.h"
 
 namespace sw {
@@ -203,12 +205,14 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
 // ---------------------------------------------------------------------------
 constexpr int kBKf = 32;
 constexpr int kPadF = kBKf + 1;
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K, float alpha,
                                                           const float* __restrict__ A, int64_t lda, int64_t sA,
                                                           const float* __restrict__ B, int64_t ldb, int64_t sB,
                                                           float beta, float* __restrict__ C, int64_t ldc, int64_t sC,
-                                                          int lower, int a_lower, int64_t n_tiles) {
+                                                          int lower, int a_lower, int64_t n_tiles, int64_t kc,
+                                                          int64_t sPart) {
   A += blockIdx.y * sA;
   B += blockIdx.y * sB;
   C += blockIdx.y * sC;
@@ -241,9 +245,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
     }
   };
   // a_lower: A is lower triangular in 128-tiles, so row tile tm needs k < (tm + 1) * 128 only
-  const int64_t Kend = (a_lower && (tm + 1) * kT < K) ? (tm + 1) * kT : K;
-  gload(0);
-  for (int64_t k0 = 0; k0 < Kend; k0 += kBKf) {
+  int64_t Kend = (a_lower && (tm + 1) * kT < K) ? (tm + 1) * kT : K;
+  int64_t kbeg = 0;
+  if (kc > 0) {  // split K: chunk z covers [z kc, (z+1) kc) and writes its own partial product
+    kbeg = (int64_t)blockIdx.z * kc;
+    if (kbeg >= Kend) return;
+    Kend = kbeg + kc < Kend ? kbeg + kc : Kend;
+    C += (int64_t)blockIdx.z * sPart;
+  }
+  gload(kbeg);
+  for (int64_t k0 = kbeg; k0 < Kend; k0 += kBKf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + kThreads * i;
@@ -284,62 +295,130 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
       }
 }
 
+// Sum of the split-K partials of an M x 128 product whose row tile tm has
+// min((tm + 1) 128, K) inner terms (a lower-triangular left operand): out =
+// sum over the chunks that tile has, in chunk order.
+__global__ __launch_bounds__(kThreads) void k_sum_parts(const float* __restrict__ parts, int64_t sPart, int64_t sP,
+                                                        int64_t M, int64_t K, int64_t kc, float* __restrict__ out,
+                                                        int64_t sOut) {
+  parts += blockIdx.y * sP;
+  out += blockIdx.y * sOut;
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // float4 index
+  if (q >= M * (kT / 4)) return;
+  const int64_t r = q / (kT / 4);
+  const int64_t tm = r / kT;
+  const int64_t kend = (tm + 1) * kT < K ? (tm + 1) * kT : K;
+  const int64_t nc = (kend + kc - 1) / kc;
+  const f32x4v* p = reinterpret_cast<const f32x4v*>(parts) + q;
+  f32x4v acc = p[0];
+  for (int64_t c = 1; c < nc; ++c) acc += p[c * (sPart / 4)];
+  reinterpret_cast<f32x4v*>(out)[q] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Diagonal block of the factorisation: unblocked right-looking Cholesky of a
-// 128 x 128 block in LDS, then the inverse of the factor by right-looking
+// 128 x 128 block fused with the inverse of its factor by right-looking
 // forward substitution on the identity; the factor overwrites the block and
-// its inverse goes to dinv.  Thread pair (i, h) owns row i and, within it, the
-// columns of parity h, so every step is a short loop with no index
-// arithmetic beyond a stride of 2.  A non-positive pivot sets *bad and is
-// replaced by a tiny positive value so the factor stays finite.
+// its inverse goes to dinv.  The block lives in registers: thread (ty, tx) of
+// a 32 x 32 grid owns the elements (ty + 32p, tx + 32q), p, q < 4, a cyclic
+// layout that keeps every thread busy down to the last columns.  Step k
+// finishes column k of the factor and row k of the inverse, broadcasts them
+// through LDS with the entries that must not change set to zero, and applies
+// both rank-1 updates as 32 unconditional fused multiply-adds per thread,
+// which leave finished rows and columns exactly as they are.  A non-positive
+// pivot sets *bad and is replaced by a tiny positive value so the factor stays
+// finite.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_potrf_diag(float* __restrict__ Kd, int64_t ld, int64_t sK,
-                                                         float* __restrict__ dinv, int64_t sD, int* __restrict__ bad) {
+constexpr int kPotrfThreads = 1024;
+
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(float* __restrict__ Kd, int64_t ld, int64_t sK,
+                                                              float* __restrict__ dinv, int64_t sD,
+                                                              int* __restrict__ bad) {
   Kd += blockIdx.x * sK;
   dinv += blockIdx.x * sD;
-  __shared__ float a[kNB][kNB + 1];
-  __shared__ float x[kNB][kNB + 1];
-  const int tid = threadIdx.x;
-  const int i = tid >> 1, h = tid & 1;
-  for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
-    const int r = idx / kNB, c = idx % kNB;
-    a[r][c] = (c <= r) ? Kd[(int64_t)r * ld + c] : 0.0f;
-    x[r][c] = (r == c) ? 1.0f : 0.0f;
-  }
+  __shared__ float col[kNB];  // column k of the factor below the diagonal, 0 elsewhere
+  __shared__ float row[kNB];  // row k of the inverse
+  __shared__ float dg[kNB];   // pending pivot of each step
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  float a[4][4], x[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 32 * p, j = tx + 32 * q;
+      a[p][q] = (j <= i) ? Kd[(int64_t)i * ld + j] : 0.0f;
+      x[p][q] = (i == j) ? 1.0f : 0.0f;
+    }
+  if (threadIdx.x == 0) dg[0] = a[0][0];
   __syncthreads();
   for (int k = 0; k < kNB; ++k) {
-    if (tid == 0) {
-      float p = a[k][k];
-      if (!(p > 0.0f)) {
-        atomicExch(bad, 1);
-        p = 1e-30f;
+    const int pk = k >> 5, rk = k & 31;
+    float piv = dg[k];
+    if (!(piv > 0.0f)) {
+      if (threadIdx.x == 0) atomicExch(bad, 1);
+      piv = 1e-30f;
+    }
+    piv = sqrtf(piv);
+    const float ip = 1.0f / piv;
+    if (tx == rk) {  // owners of column k
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q != pk) continue;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int i = ty + 32 * p;
+          const float v = (i > k) ? a[p][q] * ip : 0.0f;
+          if (i > k) a[p][q] = v;
+          if (i == k) a[p][q] = piv;
+          col[i] = v;
+        }
       }
-      a[k][k] = sqrtf(p);
+    }
+    if (ty == rk) {  // owners of row k of the inverse: final once scaled by 1/L_kk
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (p != pk) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[p][q] *= ip;
+          row[tx + 32 * q] = x[p][q];
+        }
+      }
     }
     __syncthreads();
-    if (h == 0 && i > k) a[i][k] /= a[k][k];
-    __syncthreads();
-    if (i > k) {
-      const float lik = a[i][k];
-      for (int j = k + 1 + h; j <= i; j += 2) a[i][j] -= lik * a[j][k];
+    float ci[4], cj[4], rj[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) ci[p] = col[ty + 32 * p];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cj[q] = col[tx + 32 * q];
+      rj[q] = row[tx + 32 * q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[p][q] -= ci[p] * cj[q];
+        x[p][q] -= ci[p] * rj[q];
+      }
+    if (k + 1 < kNB) {
+      const int k1 = k + 1, r1 = k1 & 31, p1 = k1 >> 5;
+      if (tx == r1 && ty == r1) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          if (p == p1) dg[k1] = a[p][p];
+      }
     }
     __syncthreads();
   }
-  // x holds I - sum_{m<k} L[i][m] X[m][:] for rows i >= k; row k is then final up to 1/L[k][k]
-  for (int k = 0; k < kNB; ++k) {
-    if (tid <= k) x[k][tid] /= a[k][k];
-    __syncthreads();
-    if (i > k) {
-      const float lik = a[i][k];
-      for (int c = h; c <= k; c += 2) x[i][c] -= lik * x[k][c];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 32 * p, j = tx + 32 * q;
+      Kd[(int64_t)i * ld + j] = (j <= i) ? a[p][q] : 0.0f;
+      dinv[i * kNB + j] = (j <= i) ? x[p][q] : 0.0f;
     }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
-    const int r = idx / kNB, c = idx % kNB;
-    Kd[(int64_t)r * ld + c] = (c <= r) ? a[r][c] : 0.0f;
-    dinv[idx] = x[r][c];
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -483,28 +562,86 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
   if (n_tiles == 0) return hipSuccess;
   const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
   hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st, ntn, K, alpha, A, lda,
-                     sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles);
+                     sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles, (int64_t)0,
+                     (int64_t)0);
   return hipGetLastError();
 }
 
-static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb_prob, hipStream_t st,
-                    int* bad) {
+// Chunk length of the split-K product in the factor inversion: with rows
+// tiles of a lower-triangular M x M operand, about (M/128)^2 128 / (2 kc)
+// chunks per problem; kc is chosen so that all nb problems together give a
+// few thousand workgroups, and is at least 512.  kc >= M means no split.
+static int64_t split_kc(int64_t M, int nb) {
+  const int64_t nt = M / kT;
+  int64_t kc = (nt * nt * (int64_t)nb) / 32;
+  kc = ((kc + 511) / 512) * 512;
+  return kc < 512 ? 512 : kc;
+}
+
+static int64_t split_parts_floats(int64_t M, int nb) {
+  const int64_t kc = split_kc(M, nb);
+  return kc >= M ? 0 : ((M + kc - 1) / kc) * M * kT;
+}
+
+// X = W P^T for the factor inversion: W (M x M, lower triangular in 128-tiles),
+// P (128 x M), X (M x 128), split over K into chunks reduced by k_sum_parts.
+static hipError_t gemm_lower_split(int64_t M, const float* W, int64_t ldw, int64_t sW, const float* Pt, int64_t ldp,
+                                   int64_t sPt, float* X, int64_t sX, float* parts, int64_t sParts, int nb,
+                                   hipStream_t st) {
+  const int64_t kc = split_kc(M, nb);
+  if (kc >= M) return gemm_nt_f32(M, kT, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, kT, sX, false, nb, st, true);
+  const int64_t n_tiles = M / kT, nchunk = (M + kc - 1) / kc;
+  const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
+  hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kThreads), 0, st,
+                     (int64_t)1, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, (int64_t)kT, sParts, 0, 1, n_tiles, kc,
+                     M * kT);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nq = M * (kT / 4);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nq + kThreads - 1) / kThreads), (unsigned)nb), dim3(kThreads), 0,
+                     st, parts, M * kT, sParts, M, M, kc, X, sX);
+  return hipGetLastError();
+}
+
+// Blocked right-looking Cholesky with the trailing update deferred over a
+// group of kCholGroup block columns: inside a group each block column is
+// first brought up to date by the group's earlier panels (left-looking, a
+// narrow product), then factorised; the rest of the matrix is updated once
+// per group with a rank-(kCholGroup * 128) product, which reads and writes the
+// trailing matrix kCholGroup times less often than one update per block.
+static int kCholGroup = 8;
+
+static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb_prob,
+                           hipStream_t st, int* bad) {
   const int64_t nb = n / kNB;
-  for (int64_t j = 0; j < nb; ++j) {
-    float* Kjj = K + j * kNB * ld + j * kNB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)nb_prob), dim3(kThreads), 0, st, Kjj, ld, sK,
-                       dinv + j * kNB * kNB, sD, bad);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t rest = n - (j + 1) * kNB;
+  hipError_t e;
+  for (int64_t j0 = 0; j0 < nb; j0 += kCholGroup) {
+    const int64_t j1 = std::min(nb, j0 + (int64_t)kCholGroup);
+    for (int64_t j = j0; j < j1; ++j) {
+      float* Kjj = K + j * kNB * ld + j * kNB;
+      if (j > j0) {
+        // block column j (rows from its diagonal down) -= its rows of the group's panels times theirs
+        const float* Pg = K + j * kNB * ld + j0 * kNB;
+        e = gemm_nt_f32(n - j * kNB, kNB, (j - j0) * kNB, -1.0f, Pg, ld, sK, Pg, ld, sK, 1.0f, Kjj, ld, sK, false,
+                        nb_prob, st);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)nb_prob), dim3(kPotrfThreads), 0, st, Kjj, ld, sK,
+                         dinv + j * kNB * kNB, sD, bad);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int64_t rest = n - (j + 1) * kNB;
+      if (rest == 0) break;
+      float* Pj = K + (j + 1) * kNB * ld + j * kNB;  // panel below the diagonal block
+      // L_panel = K_panel inv(L_jj)^T  (each workgroup owns its row block: in place)
+      e = gemm_nt_f32(rest, kNB, kNB, 1.0f, Pj, ld, sK, dinv + j * kNB * kNB, kNB, sD, 0.0f, Pj, ld, sK, false,
+                      nb_prob, st);
+      if (e != hipSuccess) return e;
+    }
+    const int64_t rest = n - j1 * kNB;
     if (rest == 0) break;
-    float* Pj = K + (j + 1) * kNB * ld + j * kNB;  // panel below the diagonal block
-    // L_panel = K_panel inv(L_jj)^T  (each workgroup owns its row block: in place)
-    e = gemm_nt_f32(rest, kNB, kNB, 1.0f, Pj, ld, sK, dinv + j * kNB * kNB, kNB, sD, 0.0f, Pj, ld, sK, false, nb_prob,
-                    st);
-    if (e != hipSuccess) return e;
-    // trailing update K_22 -= L_panel L_panel^T (lower tiles)
-    e = gemm_nt_f32(rest, rest, kNB, -1.0f, Pj, ld, sK, Pj, ld, sK, 1.0f, K + (j + 1) * kNB * ld + (j + 1) * kNB, ld,
+    // trailing update K_22 -= L_g L_g^T over the group's panels (lower tiles)
+    const float* Pg = K + j1 * kNB * ld + j0 * kNB;
+    e = gemm_nt_f32(rest, rest, (j1 - j0) * kNB, -1.0f, Pg, ld, sK, Pg, ld, sK, 1.0f, K + j1 * kNB * ld + j1 * kNB, ld,
                     sK, true, nb_prob, st);
     if (e != hipSuccess) return e;
   }
@@ -512,7 +649,8 @@ static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* d
 }
 
 static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
-                         float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, hipStream_t st) {
+                         float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, float* parts,
+                         int64_t sParts, hipStream_t st) {
   const int64_t nb = n / kNB;
   hipError_t e;
   hipLaunchKernelGGL(k_set_diag_inv, dim3((unsigned)nb, (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld, sK, dinv, sD);
@@ -524,8 +662,7 @@ static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, con
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)(rest / kTT * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
                        st, panel, ld, sK, Pt, n, sPt, (int64_t)(kNB / kTT));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = gemm_nt_f32(rest, kNB, rest, 1.0f, K + r0 * ld + r0, ld, sK, Pt, n, sPt, 0.0f, Xb, kNB, sX, false, nb_prob, st,
-                    true);
+    e = gemm_lower_split(rest, K + r0 * ld + r0, ld, sK, Pt, n, sPt, Xb, sX, parts, sParts, nb_prob, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)((kNB / kTT) * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
                        st, dinv + j * kNB * kNB, (int64_t)kNB, sD, Dt, (int64_t)kNB, sDt, (int64_t)(kNB / kTT));
@@ -539,13 +676,18 @@ static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, con
   return hipGetLastError();
 }
 
-int64_t inverse_factor_scratch(int64_t n) { return 2 * kNB * n + kNB * kNB; }
+int64_t inverse_factor_scratch(int64_t n, int nb) {
+  int64_t parts = 0;
+  for (int64_t rest = kNB; rest < n; rest += kNB) parts = std::max(parts, split_parts_floats(rest, nb));
+  return 2 * kNB * n + kNB * kNB + parts;
+}
 
 hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb,
                               float* tmp, int64_t sT, int* bad, hipStream_t st) {
   hipError_t e = cholesky(S, n, ld, sK, dinv, sD, nb, st, bad);
   if (e != hipSuccess) return e;
-  return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, tmp + kNB * n, sT, tmp + 2 * kNB * n, sT, st);
+  return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, tmp + kNB * n, sT, tmp + 2 * kNB * n, sT,
+                       tmp + 2 * kNB * n + kNB * kNB, sT, st);
 }
 
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,

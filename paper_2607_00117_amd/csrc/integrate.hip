@@ -114,6 +114,12 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_hist_lds_kb = value;
     return SW_OK;
   }
+  if (k == "sparse_rows_per_wg" || k == "sparse_cols_per_wg") {
+    SW_CHECK(value >= 0 && value <= 512 && value % 16 == 0, "sw_set_tuning: %s: 0 (automatic) or a multiple of 16 "
+             "up to 512", key);
+    (k == "sparse_rows_per_wg" ? g_sparse_rows : g_sparse_cols) = value;
+    return SW_OK;
+  }
   SW_CHECK(false, "sw_set_tuning: unknown key %s", key);
 }
 
@@ -122,6 +128,8 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   const std::string k(key);
   if (k == "integrate_waves_per_cu") return g_waves_per_cu;
   if (k == "hist_lds_kb") return g_hist_lds_kb;
+  if (k == "sparse_rows_per_wg") return g_sparse_rows;
+  if (k == "sparse_cols_per_wg") return g_sparse_cols;
   return -1;
 }
 

@@ -50,14 +50,15 @@ __device__ __forceinline__ int pot_index(const int64_t* offsets, int n_pot, int6
   return lo;
 }
 
+// At most 168 registers, so that three waves share a SIMD (the default
+// allocation lands one register above that, at two waves); no spills.
 template <typename T, bool BATCHED, bool BIN>
-__global__ __launch_bounds__(kWave) void k_integrate(const PotK p0, const sw_potential* __restrict__ pots,
-                                                    const int64_t* __restrict__ offsets, int32_t n_pot, ObsK O,
-                                                    const T* __restrict__ ics, const T* __restrict__ dts,
-                                                    int64_t n_orb, int64_t orb0, int64_t n_chunk, int32_t n_steps,
-                                                    uint64_t* __restrict__ ev_m, uint64_t* __restrict__ ev_k,
-                                                    double* __restrict__ drift, uint8_t* __restrict__ flags,
-                                                    T* __restrict__ final_state) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int64_t* __restrict__ offsets,
+                 int32_t n_pot, ObsK O, const T* __restrict__ ics, const T* __restrict__ dts, int64_t n_orb,
+                 int64_t orb0, int64_t n_chunk, int32_t n_steps, uint64_t* __restrict__ ev_m,
+                 uint64_t* __restrict__ ev_k, double* __restrict__ drift, uint8_t* __restrict__ flags,
+                 T* __restrict__ final_state) {
   __shared__ uint64_t stm[kStage][kWave + 1];
   __shared__ uint64_t stk[kStage][kWave + 1];
   const int lane = threadIdx.x;

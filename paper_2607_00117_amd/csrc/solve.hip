@@ -50,6 +50,9 @@ constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
 constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) residual has not
 constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
 
+int g_sparse_rows = 0;
+int g_sparse_cols = 0;
+
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // last b with off[b] <= i
@@ -164,8 +167,7 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A
 constexpr int kBlk = 16384;       // gathered entries staged in LDS (fp64: 128 KB)
 constexpr int kSpThreads = 1024;  // workgroup of the blocked passes (16 waves)
 constexpr int kSpWaves = kSpThreads / 64;
-constexpr int kRowsPerWave = 8;   // row dots: 128 rows per workgroup
-constexpr int kColsPerWave = 4;   // column sums: 64 columns per workgroup
+constexpr int kMaxRowsWG = 512;   // blocked passes: at most 512 rows (row dots) or columns per workgroup
 
 // orbit rows per column-block segment: slabs of rps rows, whole slabs per block
 __host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps) {
@@ -306,26 +308,32 @@ __device__ __forceinline__ void quad_idx(const uint16_t* p, uint32_t c[4]) {
 }
 
 // lane-partial sum_k val[k] xs[idx[k]] over the segment [k0, k1) (multiples
-// of 4) with xs in LDS: lane-strided quads, two in flight per lane
+// of 4) with xs in LDS: lane-strided quads, four in flight per lane
 template <typename TA>
 __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint16_t* __restrict__ idx, int64_t k0,
                                           int64_t k1, const double* xs, int lane) {
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int64_t k = k0 + 4 * lane;
-  for (; k + 256 < k1; k += 512) {
-    double v[4], w[4];
-    uint32_t c[4], d[4];
-    quad_val(val + k, v);
-    quad_idx(idx + k, c);
-    quad_val(val + k + 256, w);
-    quad_idx(idx + k + 256, d);
+  for (; k + 768 < k1; k += 1024) {
+    double v0[4], v1[4], v2[4], v3[4];
+    uint32_t c0[4], c1[4], c2[4], c3[4];
+    quad_val(val + k, v0);
+    quad_idx(idx + k, c0);
+    quad_val(val + k + 256, v1);
+    quad_idx(idx + k + 256, c1);
+    quad_val(val + k + 512, v2);
+    quad_idx(idx + k + 512, c2);
+    quad_val(val + k + 768, v3);
+    quad_idx(idx + k + 768, c3);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      a0 += v[q] * xs[c[q]];
-      a1 += w[q] * xs[d[q]];
+      a0 += v0[q] * xs[c0[q]];
+      a1 += v1[q] * xs[c1[q]];
+      a2 += v2[q] * xs[c2[q]];
+      a3 += v3[q] * xs[c3[q]];
     }
   }
-  if (k < k1) {
+  for (; k < k1; k += 256) {
     double v[4];
     uint32_t c[4];
     quad_val(val + k, v);
@@ -333,27 +341,32 @@ __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint
 #pragma unroll
     for (int q = 0; q < 4; ++q) a0 += v[q] * xs[c[q]];
   }
-  return a0 + a1;
+  return (a0 + a1) + (a2 + a3);
 }
 
-// column sums from the compressed columns: workgroup (column group, problem
-// b), 4 columns per wave, the problem's orbit vector staged block by block
-// in LDS; result in part[b][0][c] (the reduction then reads a single slab)
+// column sums from the compressed columns: workgroup (column group of cpw
+// columns, problem b), column c owned by wave c mod 16, the problem's orbit
+// vector staged block by block in LDS; result in part[b][0][c] (the
+// reduction then reads a single slab)
 template <typename TA, typename TV>
-__global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, int cpw, const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ rps, int nrb,
                                                           const int64_t* __restrict__ cptr,
                                                           const uint16_t* __restrict__ rowi,
                                                           const TA* __restrict__ val, const TV* __restrict__ v,
                                                           const double* __restrict__ par, double* __restrict__ part) {
   __shared__ double xs[kBlk];
+  __shared__ double cacc[kMaxRowsWG];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.y;
   if (par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
   const int64_t n0 = off[b], nb = off[b + 1] - n0;
   const int64_t brows = slabs_per_block(rps[b]) * rps[b];
-  const int64_t cw = (int64_t)blockIdx.x * (kSpWaves * kColsPerWave) + w;
-  double acc[kColsPerWave] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t c0 = (int64_t)blockIdx.x * cpw;
+  if (c0 >= C) return;
+  const int nc = (int)(C - c0 < cpw ? C - c0 : cpw);
+  for (int q = w; q < nc; q += kSpWaves)
+    if (lane == 0) cacc[q] = 0.0;
   for (int rb = 0; rb < nrb && (int64_t)rb * brows < nb; ++rb) {
     const int64_t r0 = (int64_t)rb * brows;
     const int64_t len = nb - r0 < brows ? nb - r0 : brows;
@@ -361,18 +374,14 @@ __global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, const int6
     for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = (double)v[n0 + r0 + j];
     __syncthreads();
     const int64_t* cp = cptr + ((int64_t)b * nrb + rb) * (C + 1);
-#pragma unroll
-    for (int q = 0; q < kColsPerWave; ++q) {
-      const int64_t c = cw + q * kSpWaves;
-      if (c < C) acc[q] += seg_dot(val, rowi, cp[c], cp[c + 1], xs, lane);
+    for (int q = w; q < nc; q += kSpWaves) {
+      const int64_t c = c0 + q;
+      const double t = wave_sum(seg_dot(val, rowi, cp[c], cp[c + 1], xs, lane));
+      if (lane == 0) cacc[q] += t;
     }
   }
-#pragma unroll
-  for (int q = 0; q < kColsPerWave; ++q) {
-    const int64_t c = cw + q * kSpWaves;
-    const double t = wave_sum(acc[q]);
-    if (lane == 0 && c < C) part[(int64_t)b * kSlabs * C + c] = t;
-  }
+  for (int q = w; q < nc; q += kSpWaves)
+    if (lane == 0) part[(int64_t)b * kSlabs * C + c0 + q] = cacc[q];
 }
 
 enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
@@ -474,18 +483,24 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
 }
 
+// Per-row contributions to the accumulators of a pass, summed by the caller
+// into 9 doubles: [0..4] ADMM |x-z|^2, |z-z0|^2, |x|^2, |z|^2, |u|^2;
+// [5] KKT |z|^2, [6] KKT support size, [7] max |q|, [8] max KKT residual.
+// The problem's accumulators receive them once per workgroup.
+constexpr int kRowSums = 9;
+
 // The update of orbit row i of problem b once its dot with sc is known.
-__device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, double dot) {
+__device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, double dot, double* a) {
   const double* P = R.par + b * kPar;
   const bool masked = R.mask && R.mask[i];
   const double rho = P[1], rhop = P[2], mu = P[3], alpha = P[4];
-  double* acc = R.acc ? R.acc + b * kAcc : nullptr;
+  const bool acc = R.acc != nullptr;
   switch (R.op) {
     case ROW_Q: {
       const double q = masked ? 0.0 : dot;
       R.qd[i] = q;
       R.qf[i] = (float)q;
-      if (acc && q != 0.0) atomic_max_pos(&acc[5], fabs(q));
+      if (acc) a[7] = fmax(a[7], fabs(q));
       break;
     }
     case ROW_ADMM: {
@@ -498,11 +513,11 @@ __device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, d
       R.uf[i] = (float)u;
       R.vf[i] = (float)(z - u);
       if (acc) {
-        atomicAdd(&acc[0], (x - z) * (x - z));
-        atomicAdd(&acc[1], (z - z0) * (z - z0));
-        atomicAdd(&acc[2], x * x);
-        atomicAdd(&acc[3], z * z);
-        atomicAdd(&acc[4], u * u);
+        a[0] += (x - z) * (x - z);
+        a[1] += (z - z0) * (z - z0);
+        a[2] += x * x;
+        a[3] += z * z;
+        a[4] += u * u;
       }
       break;
     }
@@ -528,15 +543,30 @@ __device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, d
       const double g = dot + mu * z;
       const double k = masked ? 0.0 : fabs(fmin(z, g));
       if (acc) {
-        if (k > 0.0) atomic_max_pos(&acc[6], k);
+        a[8] = fmax(a[8], k);
         if (z != 0.0) {
-          atomicAdd(&acc[7], z * z);
-          atomicAdd(&acc[8], 1.0);
+          a[5] += z * z;
+          a[6] += 1.0;
         }
       }
       break;
     }
   }
+}
+
+// Adds row contributions t[kRowSums] to problem b's accumulators.
+__device__ __forceinline__ void add_row_sums(const RowArgs& R, int b, const double* t) {
+  double* acc = R.acc + b * kAcc;
+  if (R.op == ROW_ADMM)
+    for (int k = 0; k < 5; ++k) atomicAdd(&acc[k], t[k]);
+  if (R.op == ROW_KKT) {
+    if (t[8] > 0.0) atomic_max_pos(&acc[6], t[8]);
+    if (t[6] > 0.0) {
+      atomicAdd(&acc[7], t[5]);
+      atomicAdd(&acc[8], t[6]);
+    }
+  }
+  if (R.op == ROW_Q && t[7] > 0.0) atomic_max_pos(&acc[5], t[7]);
 }
 
 // Dense rows: one wave per orbit row, dot = sum_n A[i][n] sc[b][n].
@@ -553,44 +583,59 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
   double dot = 0.0;
   for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
   dot = wave_sum(dot);
-  if (lane == 0) row_update(R, i, b, dot);
+  double a[kRowSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (lane == 0) row_update(R, i, b, dot, a);
+  if (lane == 0 && R.acc) add_row_sums(R, b, a);  // one row per wave: added directly
 }
 
 // Compressed rows: workgroup (row group, problem b), 8 rows per wave, sc of
 // problem b staged column block by column block in LDS.
 template <typename TA>
-__global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, const double* __restrict__ sc,
+__global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, int rpw, const double* __restrict__ sc,
                                                            RowArgs R) {
   __shared__ double xs[kBlk];
+  __shared__ double racc[kMaxRowsWG];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.y;
   const int64_t i_end = R.off[b + 1];
-  const int64_t i0 = R.off[b] + (int64_t)blockIdx.x * (kSpWaves * kRowsPerWave);
+  const int64_t i0 = R.off[b] + (int64_t)blockIdx.x * rpw;
   if (i0 >= i_end) return;
   if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q) return;  // converged problem: frozen
+  const int nr = (int)(i_end - i0 < rpw ? i_end - i0 : rpw);
   const double* scb = sc + (int64_t)b * R.Cp;
   const TA* val = (const TA*)R.csr_val;
   const uint16_t* col = (const uint16_t*)R.csr_col;
-  double acc[kRowsPerWave];
-#pragma unroll
-  for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0.0;
+  // row r belongs to wave r mod 16 throughout, so racc[r] needs no barrier
+  for (int r = w; r < nr; r += kSpWaves)
+    if (lane == 0) racc[r] = 0.0;
   for (int cb = 0; cb < ncb; ++cb) {
     const int64_t c0 = (int64_t)cb * kBlk;
     const int64_t len = C - c0 < kBlk ? C - c0 : kBlk;
     __syncthreads();
     for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = scb[c0 + j];
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
-      const int64_t i = i0 + w + r * kSpWaves;
-      if (i < i_end) acc[r] += seg_dot(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, lane);
+    for (int r = w; r < nr; r += kSpWaves) {
+      const int64_t i = i0 + r;
+      const double part = wave_sum(seg_dot(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, lane));
+      if (lane == 0) racc[r] += part;
     }
   }
-#pragma unroll
-  for (int r = 0; r < kRowsPerWave; ++r) {
-    const int64_t i = i0 + w + r * kSpWaves;
-    const double dot = wave_sum(acc[r]);
-    if (lane == 0 && i < i_end) row_update(R, i, b, dot);
+  // row contributions: per wave in LDS, then combined in wave order
+  __shared__ double sums[kSpWaves][kRowSums];
+  if (lane == 0)
+    for (int k = 0; k < kRowSums; ++k) sums[w][k] = 0.0;
+  for (int r = w; r < nr; r += kSpWaves)
+    if (lane == 0) row_update(R, i0 + r, b, racc[r], sums[w]);
+  if (R.acc) {
+    __syncthreads();
+    const int k = threadIdx.x;  // thread k combines accumulator k over the waves
+    if (k < kRowSums) {
+      double t = sums[0][k];
+      for (int v = 1; v < kSpWaves; ++v) t = k >= 7 ? fmax(t, sums[v][k]) : t + sums[v][k];
+      sums[0][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) add_row_sums(R, b, sums[0]);
   }
 }
 
@@ -713,7 +758,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   L.off_acc = take((size_t)P * kAcc * 8);
   L.off_idx = take((size_t)(P + 1) * 8 * 4);
   L.off_bad = take(64);
-  L.off_ftmp = take((size_t)P * inverse_factor_scratch(L.Cp) * 4);
+  L.off_ftmp = take((size_t)P * inverse_factor_scratch(L.Cp, P) * 4);
   // compressed copies: room for kMaxDensity (or 1M entries), 8-byte values
   const double dense = (double)L.N * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(kMaxDensity * dense), (int64_t)1 << 20);
@@ -754,15 +799,21 @@ struct Ctx {
 template <typename TV>
 static hipError_t colsum(const Ctx& X, const TV* v) {
   if (X.sparse) {
-    dim3 grid((unsigned)((X.L.C + kSpWaves * kColsPerWave - 1) / (kSpWaves * kColsPerWave)), (unsigned)X.L.P);
+    // 64 columns per workgroup (several rounds of 128 KB workgroups over the
+    // 256 CUs balance the uneven column lengths); narrower groups only when
+    // that would leave CUs idle
+    int64_t cpw = 64;
+    if (X.L.C * X.L.P < 64 * 256) cpw = std::max<int64_t>(kSpWaves, (X.L.C * X.L.P + 255) / 256 / kSpWaves * kSpWaves);
+    if (g_sparse_cols > 0) cpw = g_sparse_cols;
+    dim3 grid((unsigned)((X.L.C + cpw - 1) / cpw), (unsigned)X.L.P);
     if (X.dtype == SW_F32)
-      hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d, X.L.nrb,
-                         X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v, X.par,
-                         X.p<double>(X.L.off_part));
+      hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d, X.rps_d,
+                         X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
+                         X.par, X.p<double>(X.L.off_part));
     else
-      hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.off_d, X.rps_d,
-                         X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<double>(X.L.off_cval),
-                         v, X.par, X.p<double>(X.L.off_part));
+      hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d,
+                         X.rps_d, X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow),
+                         X.p<double>(X.L.off_cval), v, X.par, X.p<double>(X.L.off_part));
     return hipGetLastError();
   }
   dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
@@ -788,9 +839,13 @@ static void launch_rowdot(const Ctx& X, const RowArgs& R) {
   if (X.sparse) {
     int64_t nmax = 1;
     for (int b = 0; b < X.L.P; ++b) nmax = std::max<int64_t>(nmax, X.L.off[b + 1] - X.L.off[b]);
-    const int64_t per = kSpWaves * kRowsPerWave;
+    // one 128 KB workgroup per CU: rows per workgroup chosen so that a single
+    // problem fills the 256 CUs in one round (no tail round), at most 512
+    int64_t per = (nmax + 255) / 256;
+    per = std::min<int64_t>(kMaxRowsWG, std::max<int64_t>(kSpWaves, (per + kSpWaves - 1) / kSpWaves * kSpWaves));
+    if (g_sparse_rows > 0) per = g_sparse_rows;
     hipLaunchKernelGGL(k_rowdot_csr<TA>, dim3((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P), dim3(kSpThreads),
-                       0, X.st, X.L.C, X.L.ncb, sc, R);
+                       0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
   } else {
     hipLaunchKernelGGL(k_rowdot<TA>, dim3((unsigned)((X.L.N + 3) / 4)), dim3(kRowsBlock), 0, X.st, (const TA*)X.A,
                        X.L.N, X.L.C, sc, R);
@@ -1063,7 +1118,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   int* bad = X.p<int>(L.off_bad);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, X.st, bad, (int64_t)1, 0);
   SW_TRY(spd_inverse_factor(K, L.Cp, L.Cp, sK, X.p<float>(L.off_dinv), L.Cp * kNB, P, X.p<float>(L.off_ftmp),
-                            inverse_factor_scratch(L.Cp), bad, X.st));
+                            inverse_factor_scratch(L.Cp, P), bad, X.st));
   SW_TRY(hipEventRecord(ev[4], X.st));
   int hbad = 0;
   SW_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, X.st));
