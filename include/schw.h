@@ -315,6 +315,12 @@ int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64
  *                             per compute unit walking the orbit tiles
  *   "hist_lds_kb"             LDS budget (KiB, 4..160) of one histogram
  *                             workgroup; sets how many orbit rows it carries
+ *   "sparse_rows_per_wg"      orbit rows per row-dot workgroup of the weight
+ *                             solve's compressed passes (0: automatic, else a
+ *                             multiple of 16 up to 512)
+ *   "sparse_cols_per_wg"      constraints per column-sum workgroup (same range)
+ *   "sparse_lanes_per_row"    lanes that share one row in the row dots (0:
+ *                             automatic from the mean row length, 16 or 64)
  * sw_get_tuning returns the current value (-1 for an unknown key).           */
 int sw_set_tuning(const char* key, int32_t value);
 int32_t sw_get_tuning(const char* key);

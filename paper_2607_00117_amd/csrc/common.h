@@ -60,8 +60,10 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 // sw_set_tuning (0 = automatic):
 //  g_sparse_rows   orbits per row-dot workgroup
 //  g_sparse_cols   constraints per column-sum workgroup
+//  g_sparse_lanes  lanes per row in the row dots (16 or 64)
 extern int g_sparse_rows;
 extern int g_sparse_cols;
+extern int g_sparse_lanes;
 
 }  // namespace sw
 

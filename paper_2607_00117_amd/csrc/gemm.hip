@@ -223,6 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
   int64_t tm, tn;
   if (lower) tri_tile(t, tm, tn);
   else { tm = t / ntn; tn = t - tm * ntn; }
+  if (a_lower && !lower) tm = n_tiles / ntn - 1 - tm;  // longest inner loops first
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   floatx16 acc[2][2];
@@ -295,24 +296,37 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
       }
 }
 
-// Sum of the split-K partials of an M x 128 product whose row tile tm has
-// min((tm + 1) 128, K) inner terms (a lower-triangular left operand): out =
-// sum over the chunks that tile has, in chunk order.
+// Sum of the split-K partials of an M x N product (partials compact, ld N)
+// whose row tile tm has min((tm + 1) 128, K) inner terms (a lower-triangular
+// left operand): out (ld ldo) = sum over the chunks that tile has, in chunk
+// order.
 __global__ __launch_bounds__(kThreads) void k_sum_parts(const float* __restrict__ parts, int64_t sPart, int64_t sP,
-                                                        int64_t M, int64_t K, int64_t kc, float* __restrict__ out,
-                                                        int64_t sOut) {
+                                                        int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                        float* __restrict__ out, int64_t ldo, int64_t sOut) {
   parts += blockIdx.y * sP;
   out += blockIdx.y * sOut;
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // float4 index
-  if (q >= M * (kT / 4)) return;
-  const int64_t r = q / (kT / 4);
+  const int64_t n4 = N / 4;
+  if (q >= M * n4) return;
+  const int64_t r = q / n4, c4 = q - r * n4;
   const int64_t tm = r / kT;
   const int64_t kend = (tm + 1) * kT < K ? (tm + 1) * kT : K;
   const int64_t nc = (kend + kc - 1) / kc;
   const f32x4v* p = reinterpret_cast<const f32x4v*>(parts) + q;
   f32x4v acc = p[0];
   for (int64_t c = 1; c < nc; ++c) acc += p[c * (sPart / 4)];
-  reinterpret_cast<f32x4v*>(out)[q] = acc;
+  reinterpret_cast<f32x4v*>(out + r * ldo)[c4] = acc;
+}
+
+// out[r][c] = 0 for a rows x cols block (cols multiple of 4), ld ldo
+__global__ __launch_bounds__(kThreads) void k_zero_block(float* __restrict__ out, int64_t ldo, int64_t sOut,
+                                                         int64_t rows, int64_t cols) {
+  out += blockIdx.y * sOut;
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t c4 = cols / 4;
+  if (q >= rows * c4) return;
+  const int64_t r = q / c4;
+  reinterpret_cast<f32x4v*>(out + r * ldo)[q - r * c4] = f32x4v{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
 // ---------------------------------------------------------------------------
@@ -567,39 +581,40 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
   return hipGetLastError();
 }
 
-// Chunk length of the split-K product in the factor inversion: with rows
-// tiles of a lower-triangular M x M operand, about (M/128)^2 128 / (2 kc)
-// chunks per problem; kc is chosen so that all nb problems together give a
-// few thousand workgroups, and is at least 512.  kc >= M means no split.
-static int64_t split_kc(int64_t M, int nb) {
+// Chunk length of the split-K product in the factor inversion: with row
+// tiles of a lower-triangular M x M operand and ntn column tiles, about
+// (M/128)^2 ntn 128 / (2 kc) chunks per problem; kc is chosen so that all nb
+// problems together give a few thousand workgroups, and is at least 512.
+// kc >= M means no split.
+static int64_t split_kc(int64_t M, int64_t ntn, int nb) {
   const int64_t nt = M / kT;
-  int64_t kc = (nt * nt * (int64_t)nb) / 32;
+  int64_t kc = (nt * nt * ntn * (int64_t)nb) / 32;
   kc = ((kc + 511) / 512) * 512;
   return kc < 512 ? 512 : kc;
 }
 
-static int64_t split_parts_floats(int64_t M, int nb) {
-  const int64_t kc = split_kc(M, nb);
-  return kc >= M ? 0 : ((M + kc - 1) / kc) * M * kT;
+static int64_t split_parts_floats(int64_t M, int64_t N, int nb) {
+  const int64_t kc = split_kc(M, N / kT, nb);
+  return kc >= M ? 0 : ((M + kc - 1) / kc) * M * N;
 }
 
 // X = W P^T for the factor inversion: W (M x M, lower triangular in 128-tiles),
-// P (128 x M), X (M x 128), split over K into chunks reduced by k_sum_parts.
-static hipError_t gemm_lower_split(int64_t M, const float* W, int64_t ldw, int64_t sW, const float* Pt, int64_t ldp,
-                                   int64_t sPt, float* X, int64_t sX, float* parts, int64_t sParts, int nb,
-                                   hipStream_t st) {
-  const int64_t kc = split_kc(M, nb);
-  if (kc >= M) return gemm_nt_f32(M, kT, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, kT, sX, false, nb, st, true);
-  const int64_t n_tiles = M / kT, nchunk = (M + kc - 1) / kc;
+// P (N x M), X (M x N, ld ldx), split over K into chunks reduced by k_sum_parts.
+static hipError_t gemm_lower_split(int64_t M, int64_t N, const float* W, int64_t ldw, int64_t sW, const float* Pt,
+                                   int64_t ldp, int64_t sPt, float* X, int64_t ldx, int64_t sX, float* parts,
+                                   int64_t sParts, int nb, hipStream_t st) {
+  const int64_t ntn = N / kT;
+  const int64_t kc = split_kc(M, ntn, nb);
+  if (kc >= M) return gemm_nt_f32(M, N, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, ldx, sX, false, nb, st, true);
+  const int64_t n_tiles = (M / kT) * ntn, nchunk = (M + kc - 1) / kc;
   const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
-  hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kThreads), 0, st,
-                     (int64_t)1, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, (int64_t)kT, sParts, 0, 1, n_tiles, kc,
-                     M * kT);
+  hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kThreads), 0, st, ntn,
+                     M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles, kc, M * N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t nq = M * (kT / 4);
+  const int64_t nq = M * (N / 4);
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nq + kThreads - 1) / kThreads), (unsigned)nb), dim3(kThreads), 0,
-                     st, parts, M * kT, sParts, M, M, kc, X, sX);
+                     st, parts, M * N, sParts, M, N, M, kc, X, ldx, sX);
   return hipGetLastError();
 }
 
@@ -648,27 +663,82 @@ static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* d
   return hipSuccess;
 }
 
+// Factor inversion, column blocks from the right in groups J = [j0, j1) of
+// kInvGroup blocks.  For j in J,
+//   W_{>j,j} = -(W_{>j,T} L_{T,j} + W_{>j,(j,j1)} L_{(j,j1),j}) W_jj,
+// T = the blocks right of the group (already final; W_{J,T} = 0).  The first
+// product is formed for the whole group at once (a kInvGroup * 128 wide
+// product that reads W_{T,T} once per group instead of once per block), the
+// second block by block inside the group; the terms are the same as in one
+// product per block, only summed in two parts.
+static int kInvGroup = 8;
+
+static int64_t inv_group(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(kInvGroup, n / kNB)); }
+
+struct InvScratch {  // per-problem scratch of the factor inversion (floats)
+  int64_t xg, pt, lt, dt, parts, total;
+  InvScratch(int64_t n, int nb) {
+    const int64_t G = inv_group(n), w = G * kNB;
+    int64_t pmax = 0;  // the largest split-K partial set over the groups, as invert_factor forms them
+    for (int64_t j1 = n / kNB; j1 > 0; j1 -= G) {
+      const int64_t gw = (j1 - std::max<int64_t>(0, j1 - G)) * kNB, tn = n - j1 * kNB;
+      if (tn > 0) pmax = std::max(pmax, split_parts_floats(tn, gw, nb));
+    }
+    xg = 0;
+    pt = xg + n * w;
+    lt = pt + w * n;
+    dt = lt + kNB * w;
+    parts = dt + kNB * kNB;
+    total = parts + pmax;
+  }
+};
+
 static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, const float* dinv, int64_t sD, int nb_prob,
-                         float* Pt, int64_t sPt, float* Xb, int64_t sX, float* Dt, int64_t sDt, float* parts,
-                         int64_t sParts, hipStream_t st) {
-  const int64_t nb = n / kNB;
+                                float* tmp, int64_t sT, hipStream_t st) {
+  const int64_t nb = n / kNB, G = inv_group(n), w = G * kNB;
+  const InvScratch L(n, nb_prob);
+  float *XG = tmp + L.xg, *Pt = tmp + L.pt, *Lt = tmp + L.lt, *Dt = tmp + L.dt, *parts = tmp + L.parts;
   hipError_t e;
   hipLaunchKernelGGL(k_set_diag_inv, dim3((unsigned)nb, (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld, sK, dinv, sD);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // column blocks right to left: W_{>j,j} = -W_{>j,>j} L_{>j,j} inv(L_jj)
-  for (int64_t j = nb - 2; j >= 0; --j) {
-    const int64_t r0 = (j + 1) * kNB, rest = n - r0;
-    float* panel = K + r0 * ld + j * kNB;
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)(rest / kTT * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
-                       st, panel, ld, sK, Pt, n, sPt, (int64_t)(kNB / kTT));
+  for (int64_t j1 = nb; j1 > 0; j1 -= G) {
+    const int64_t j0 = std::max<int64_t>(0, j1 - G), gw = (j1 - j0) * kNB;
+    const int64_t t0 = j1 * kNB, tn = n - t0;
+    // rows of the group in XG start at zero (W_{J,T} = 0)
+    const int64_t nz = gw * (gw / 4);
+    hipLaunchKernelGGL(k_zero_block, dim3((unsigned)((nz + kThreads - 1) / kThreads), (unsigned)nb_prob),
+                       dim3(kThreads), 0, st, XG + j0 * kNB * w, w, sT, gw, gw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = gemm_lower_split(rest, K + r0 * ld + r0, ld, sK, Pt, n, sPt, Xb, sX, parts, sParts, nb_prob, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((kNB / kTT) * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
-                       st, dinv + j * kNB * kNB, (int64_t)kNB, sD, Dt, (int64_t)kNB, sDt, (int64_t)(kNB / kTT));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = gemm_nt_f32(rest, kNB, kNB, -1.0f, Xb, kNB, sX, Dt, kNB, sDt, 0.0f, panel, ld, sK, false, nb_prob, st);
-    if (e != hipSuccess) return e;
+    if (tn > 0) {
+      // XG[T rows, J cols] = W_{T,T} L_{T,J}
+      hipLaunchKernelGGL(k_transpose, dim3((unsigned)(tn / kTT * (gw / kTT)), (unsigned)nb_prob), dim3(kThreads), 0,
+                         st, K + t0 * ld + j0 * kNB, ld, sK, Pt, n, sT, (int64_t)(gw / kTT));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      e = gemm_lower_split(tn, gw, K + t0 * ld + t0, ld, sK, Pt, n, sT, XG + t0 * w, w, sT, parts, sT, nb_prob, st);
+      if (e != hipSuccess) return e;
+    }
+    for (int64_t j = j1 - 1; j >= j0; --j) {
+      const int64_t r1 = (j + 1) * kNB, rest = n - r1;
+      if (rest == 0) continue;
+      float* C = XG + r1 * w + (j - j0) * kNB;  // rows > j of column block j of the group
+      const int64_t kin = (j1 - j - 1) * kNB;
+      if (kin > 0) {
+        // C += W_{>j,(j,j1)} L_{(j,j1),j}
+        hipLaunchKernelGGL(k_transpose, dim3((unsigned)(kin / kTT * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads),
+                           0, st, K + r1 * ld + j * kNB, ld, sK, Lt, kin, sT, (int64_t)(kNB / kTT));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = gemm_nt_f32(rest, kNB, kin, 1.0f, K + r1 * ld + r1, ld, sK, Lt, kin, sT, 1.0f, C, w, sT, false, nb_prob, st,
+                        true);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_transpose, dim3((unsigned)((kNB / kTT) * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads),
+                         0, st, dinv + j * kNB * kNB, (int64_t)kNB, sD, Dt, (int64_t)kNB, sT, (int64_t)(kNB / kTT));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      // W_{>j,j} = -C W_jj
+      e = gemm_nt_f32(rest, kNB, kNB, -1.0f, C, w, sT, Dt, kNB, sT, 0.0f, K + r1 * ld + j * kNB, ld, sK, false, nb_prob,
+                      st);
+      if (e != hipSuccess) return e;
+    }
   }
   const int64_t t = n / kTT;
   hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)(t * (t + 1) / 2), (unsigned)nb_prob), dim3(kThreads), 0, st, K, ld,
@@ -676,18 +746,13 @@ static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, con
   return hipGetLastError();
 }
 
-int64_t inverse_factor_scratch(int64_t n, int nb) {
-  int64_t parts = 0;
-  for (int64_t rest = kNB; rest < n; rest += kNB) parts = std::max(parts, split_parts_floats(rest, nb));
-  return 2 * kNB * n + kNB * kNB + parts;
-}
+int64_t inverse_factor_scratch(int64_t n, int nb) { return InvScratch(n, nb).total; }
 
 hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float* dinv, int64_t sD, int nb,
                               float* tmp, int64_t sT, int* bad, hipStream_t st) {
   hipError_t e = cholesky(S, n, ld, sK, dinv, sD, nb, st, bad);
   if (e != hipSuccess) return e;
-  return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, tmp + kNB * n, sT, tmp + 2 * kNB * n, sT,
-                       tmp + 2 * kNB * n + kNB * kNB, sT, st);
+  return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, st);
 }
 
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,

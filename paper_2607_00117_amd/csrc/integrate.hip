@@ -120,6 +120,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     (k == "sparse_rows_per_wg" ? g_sparse_rows : g_sparse_cols) = value;
     return SW_OK;
   }
+  if (k == "sparse_lanes_per_row") {
+    SW_CHECK(value == 0 || value == 16 || value == 64, "sw_set_tuning: sparse_lanes_per_row: 0 (automatic), 16 or 64");
+    g_sparse_lanes = value;
+    return SW_OK;
+  }
   SW_CHECK(false, "sw_set_tuning: unknown key %s", key);
 }
 
@@ -130,6 +135,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "hist_lds_kb") return g_hist_lds_kb;
   if (k == "sparse_rows_per_wg") return g_sparse_rows;
   if (k == "sparse_cols_per_wg") return g_sparse_cols;
+  if (k == "sparse_lanes_per_row") return g_sparse_lanes;
   return -1;
 }
 

@@ -52,6 +52,7 @@ constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChe
 
 int g_sparse_rows = 0;
 int g_sparse_cols = 0;
+int g_sparse_lanes = 0;
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -308,23 +309,25 @@ __device__ __forceinline__ void quad_idx(const uint16_t* p, uint32_t c[4]) {
 }
 
 // lane-partial sum_k val[k] xs[idx[k]] over the segment [k0, k1) (multiples
-// of 4) with xs in LDS: lane-strided quads, four in flight per lane
-template <typename TA>
+// of 4) with xs in LDS, for a group of LPR lanes (lane = index in the group):
+// lane-strided quads, four in flight per lane
+template <int LPR = 64, typename TA>
 __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint16_t* __restrict__ idx, int64_t k0,
                                           int64_t k1, const double* xs, int lane) {
+  constexpr int S = 4 * LPR;  // entries per quad row of the group
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int64_t k = k0 + 4 * lane;
-  for (; k + 768 < k1; k += 1024) {
+  for (; k + 3 * S < k1; k += 4 * S) {
     double v0[4], v1[4], v2[4], v3[4];
     uint32_t c0[4], c1[4], c2[4], c3[4];
     quad_val(val + k, v0);
     quad_idx(idx + k, c0);
-    quad_val(val + k + 256, v1);
-    quad_idx(idx + k + 256, c1);
-    quad_val(val + k + 512, v2);
-    quad_idx(idx + k + 512, c2);
-    quad_val(val + k + 768, v3);
-    quad_idx(idx + k + 768, c3);
+    quad_val(val + k + S, v1);
+    quad_idx(idx + k + S, c1);
+    quad_val(val + k + 2 * S, v2);
+    quad_idx(idx + k + 2 * S, c2);
+    quad_val(val + k + 3 * S, v3);
+    quad_idx(idx + k + 3 * S, c3);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       a0 += v0[q] * xs[c0[q]];
@@ -333,7 +336,7 @@ __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint
       a3 += v3[q] * xs[c3[q]];
     }
   }
-  for (; k < k1; k += 256) {
+  for (; k < k1; k += S) {
     double v[4];
     uint32_t c[4];
     quad_val(val + k, v);
@@ -342,6 +345,13 @@ __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint
     for (int q = 0; q < 4; ++q) a0 += v[q] * xs[c[q]];
   }
   return (a0 + a1) + (a2 + a3);
+}
+
+// sum over the aligned group of LPR lanes (result in every lane of the group)
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 // column sums from the compressed columns: workgroup (column group of cpw
@@ -588,50 +598,61 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
   if (lane == 0 && R.acc) add_row_sums(R, b, a);  // one row per wave: added directly
 }
 
-// Compressed rows: workgroup (row group, problem b), 8 rows per wave, sc of
-// problem b staged column block by column block in LDS.
-template <typename TA>
+// Compressed rows: workgroup (row group of rpw rows, problem b); a row is
+// taken by a group of LPR lanes (64 for long rows, fewer for short ones, so
+// that a wave works on 64 / LPR rows at once); sc of problem b is staged
+// column block by column block in LDS.
+template <typename TA, int LPR>
 __global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, int rpw, const double* __restrict__ sc,
                                                            RowArgs R) {
+  constexpr int G = 64 / LPR;          // rows in flight per wave
+  constexpr int NS = kSpWaves * G;     // row slots of the workgroup
   __shared__ double xs[kBlk];
   __shared__ double racc[kMaxRowsWG];
+  __shared__ double sums[NS][kRowSums];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int sl = lane % LPR, slot = w * G + lane / LPR;
   const int b = blockIdx.y;
   const int64_t i_end = R.off[b + 1];
   const int64_t i0 = R.off[b] + (int64_t)blockIdx.x * rpw;
   if (i0 >= i_end) return;
   if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q) return;  // converged problem: frozen
   const int nr = (int)(i_end - i0 < rpw ? i_end - i0 : rpw);
+  const int n_pass = (nr + NS - 1) / NS;  // the same for every lane, so the group sums see whole waves
   const double* scb = sc + (int64_t)b * R.Cp;
   const TA* val = (const TA*)R.csr_val;
   const uint16_t* col = (const uint16_t*)R.csr_col;
-  // row r belongs to wave r mod 16 throughout, so racc[r] needs no barrier
-  for (int r = w; r < nr; r += kSpWaves)
-    if (lane == 0) racc[r] = 0.0;
+  // row r belongs to slot r mod NS throughout, so racc[r] needs no barrier
+  for (int r = slot; r < nr; r += NS)
+    if (sl == 0) racc[r] = 0.0;
   for (int cb = 0; cb < ncb; ++cb) {
     const int64_t c0 = (int64_t)cb * kBlk;
     const int64_t len = C - c0 < kBlk ? C - c0 : kBlk;
     __syncthreads();
     for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = scb[c0 + j];
     __syncthreads();
-    for (int r = w; r < nr; r += kSpWaves) {
-      const int64_t i = i0 + r;
-      const double part = wave_sum(seg_dot(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, lane));
-      if (lane == 0) racc[r] += part;
+    for (int p = 0; p < n_pass; ++p) {
+      const int r = slot + p * NS;
+      double part = 0.0;
+      if (r < nr) {
+        const int64_t i = i0 + r;
+        part = seg_dot<LPR>(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, sl);
+      }
+      part = group_sum<LPR>(part);
+      if (sl == 0 && r < nr) racc[r] += part;
     }
   }
-  // row contributions: per wave in LDS, then combined in wave order
-  __shared__ double sums[kSpWaves][kRowSums];
-  if (lane == 0)
-    for (int k = 0; k < kRowSums; ++k) sums[w][k] = 0.0;
-  for (int r = w; r < nr; r += kSpWaves)
-    if (lane == 0) row_update(R, i0 + r, b, racc[r], sums[w]);
+  // row contributions: per slot in LDS, then combined in slot order
+  if (sl == 0)
+    for (int k = 0; k < kRowSums; ++k) sums[slot][k] = 0.0;
+  for (int r = slot; r < nr; r += NS)
+    if (sl == 0) row_update(R, i0 + r, b, racc[r], sums[slot]);
   if (R.acc) {
     __syncthreads();
-    const int k = threadIdx.x;  // thread k combines accumulator k over the waves
+    const int k = threadIdx.x;  // thread k combines accumulator k over the slots
     if (k < kRowSums) {
       double t = sums[0][k];
-      for (int v = 1; v < kSpWaves; ++v) t = k >= 7 ? fmax(t, sums[v][k]) : t + sums[v][k];
+      for (int v = 1; v < NS; ++v) t = k >= 7 ? fmax(t, sums[v][k]) : t + sums[v][k];
       sums[0][k] = t;
     }
     __syncthreads();
@@ -844,8 +865,14 @@ static void launch_rowdot(const Ctx& X, const RowArgs& R) {
     int64_t per = (nmax + 255) / 256;
     per = std::min<int64_t>(kMaxRowsWG, std::max<int64_t>(kSpWaves, (per + kSpWaves - 1) / kSpWaves * kSpWaves));
     if (g_sparse_rows > 0) per = g_sparse_rows;
-    hipLaunchKernelGGL(k_rowdot_csr<TA>, dim3((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P), dim3(kSpThreads),
-                       0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
+    // rows with short segments (mean below 512 entries per column block) are
+    // taken by 16 lanes each, four rows per wave
+    const dim3 grid((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P);
+    const bool short_rows = g_sparse_lanes > 0 ? g_sparse_lanes == 16 : X.nnz < 512 * X.L.N * X.L.ncb;
+    if (short_rows)
+      hipLaunchKernelGGL((k_rowdot_csr<TA, 16>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
+    else
+      hipLaunchKernelGGL((k_rowdot_csr<TA, 64>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
   } else {
     hipLaunchKernelGGL(k_rowdot<TA>, dim3((unsigned)((X.L.N + 3) / 4)), dim3(kRowsBlock), 0, X.st, (const TA*)X.A,
                        X.L.N, X.L.C, sc, R);

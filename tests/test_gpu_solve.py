@@ -215,7 +215,10 @@ def test_compressed_blocks_match_dense_passes(gpu):
     sig = 0.02 * torch.clamp(d, min=1e-3 * float(d.max()))
     wt = float(d.sum()) / n
     res = []
-    for flags in (0, P.SW_SOLVE_DENSE):
+    # compressed passes with the automatic row-dot shape, then with 64 and 16
+    # lanes per row forced; last the dense passes
+    for flags, lanes in ((0, 0), (0, 64), (0, 16), (P.SW_SOLVE_DENSE, 0)):
+        P.set_tuning("sparse_lanes_per_row", lanes)
         opts = P._lib.SolveOpts()
         opts.gram, opts.nu, opts.flags = P.SW_GRAM_BF16X3, 1e-2, flags
         w = torch.empty(n, dtype=torch.float64, device=dev)
@@ -223,14 +226,16 @@ def test_compressed_blocks_match_dense_passes(gpu):
         status, rep = P.solve_weights(A, d, sig, wt, -1.0, opts, w, ws)
         cws = torch.empty(P.chi2_workspace_bytes(c), dtype=torch.uint8, device=dev)
         x2 = P.chi2(A, w, d, sig, 0, c, cws)
-        print(flags, status, rep.as_dict(), x2)
+        print(flags, lanes, status, rep.as_dict(), x2)
         res.append((w.cpu().numpy(), status, rep, x2))
         del ws
-    (w_s, st_s, rep_s, x_s), (w_d, st_d, rep_d, x_d) = res
-    assert rep_s.nnz > 0 and rep_d.nnz == 0
-    assert st_s == 0 and st_d == 0
-    assert np.abs(w_s - w_d).sum() / np.abs(w_d).sum() < 1e-3
-    assert abs(x_s / x_d - 1) < 1e-6
+    P.set_tuning("sparse_lanes_per_row", 0)
+    w_d, st_d, rep_d, x_d = res[-1]
+    assert rep_d.nnz == 0 and st_d == 0
+    for w_s, st_s, rep_s, x_s in res[:-1]:
+        assert rep_s.nnz > 0 and st_s == 0
+        assert np.abs(w_s - w_d).sum() / np.abs(w_d).sum() < 1e-3
+        assert abs(x_s / x_d - 1) < 1e-6
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
