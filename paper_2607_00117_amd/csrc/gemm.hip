@@ -218,12 +218,25 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
   C += blockIdx.y * sC;
   __shared__ float As[kT][kPadF];
   __shared__ float Bs[kT][kPadF];
-  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
   int64_t tm, tn;
-  if (lower) tri_tile(t, tm, tn);
-  else { tm = t / ntn; tn = t - tm * ntn; }
-  if (a_lower && !lower) tm = n_tiles / ntn - 1 - tm;  // longest inner loops first
+  if (a_lower && !lower) {
+    // lower-triangular A: row tile tm has (tm + 1) * 128 inner terms.  Row tiles
+    // are dealt to the XCDs round-robin from the longest down (XCD x gets the
+    // k-th longest for k = x mod 8), each XCD taking all column tiles of its
+    // row tiles: every XCD gets an equal share of long and short tiles, and
+    // an A row panel is read by one XCD only.
+    const int64_t ntm = n_tiles / ntn;
+    const int64_t x = blockIdx.x % kXcd, r = blockIdx.x / kXcd, i = r / ntn;
+    const int64_t k = i * kXcd + x;
+    if (k >= ntm) return;
+    tm = ntm - 1 - k;
+    tn = r - i * ntn;
+  } else {
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= n_tiles) return;
+    if (lower) tri_tile(t, tm, tn);
+    else { tm = t / ntn; tn = t - tm * ntn; }
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   floatx16 acc[2][2];
@@ -574,7 +587,8 @@ hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float
   const int64_t ntm = M / kT, ntn = N / kT;
   const int64_t n_tiles = lower ? ntm * (ntm + 1) / 2 : ntm * ntn;
   if (n_tiles == 0) return hipSuccess;
-  const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
+  const int64_t grid = (a_lower && !lower) ? kXcd * ((ntm + kXcd - 1) / kXcd) * ntn
+                                           : ((n_tiles + kXcd - 1) / kXcd) * kXcd;
   hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st, ntn, K, alpha, A, lda,
                      sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles, (int64_t)0,
                      (int64_t)0);
@@ -606,8 +620,8 @@ static hipError_t gemm_lower_split(int64_t M, int64_t N, const float* W, int64_t
   const int64_t ntn = N / kT;
   const int64_t kc = split_kc(M, ntn, nb);
   if (kc >= M) return gemm_nt_f32(M, N, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, ldx, sX, false, nb, st, true);
-  const int64_t n_tiles = (M / kT) * ntn, nchunk = (M + kc - 1) / kc;
-  const int64_t grid = ((n_tiles + kXcd - 1) / kXcd) * kXcd;
+  const int64_t ntm = M / kT, n_tiles = ntm * ntn, nchunk = (M + kc - 1) / kc;
+  const int64_t grid = kXcd * ((ntm + kXcd - 1) / kXcd) * ntn;
   hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kThreads), 0, st, ntn,
                      M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles, kc, M * N);
   hipError_t e = hipGetLastError();
