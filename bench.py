@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--max-iter", type=int, default=0, help="cap of the FP32 ADMM stage (0: library default)")
     ap.add_argument("--refine-iter", type=int, default=0, help="cap of the FP64 stage (0: library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch the solve iterations one by one")
+    ap.add_argument("--no-accel", action="store_true", help="plain ADMM (no Anderson acceleration)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a 4 GiB device-to-device copy (scale for the HBM traffic counters)")
     args = ap.parse_args()
@@ -157,6 +158,8 @@ def main():
     opts.use_graph = 0 if args.no_graph else 1
     opts.max_iter = args.max_iter
     opts.refine_iter = args.refine_iter
+    if args.no_accel:
+        opts.flags |= P.SW_SOLVE_NO_ACCEL
 
     def step():
         with torch.cuda.stream(stream):
@@ -202,6 +205,9 @@ def main():
     # bytes of one compressed pass (fp32 value + 16-bit index per entry) or of a dense pass over A
     pass_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
     tri_bytes = 4.0 * C * (C + 1)  # both triangles of the fp32 inverse factor
+    # Anderson mixing per FP64 iteration: 91 vectors of N doubles read or written (the
+    # history of 10 three-part entries read twice, iterates, residuals, newest entries)
+    aa_bytes = 0.0 if args.no_accel else 91.0 * N * 8.0
     rooflines = {
         "integrate_and_bin": {"kernel": "k_integrate + k_hist", "bound": "alu", "unit": "TFLOP/s",
                               "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
@@ -214,8 +220,8 @@ def main():
                       "unit": "TFLOP/s", "peak": PEAK_F32_MFMA / 1e12, "work": 2.0 * C ** 3 / 3.0, "ms": t_factor},
         "admm_fp32": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
                       "peak": PEAK_HBM / 1e9, "work": it1 * (2 * pass_bytes + tri_bytes), "ms": t_admm},
-        "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
-                        "peak": PEAK_HBM / 1e9, "work": it2 * (4 * pass_bytes + tri_bytes), "ms": t_ref},
+        "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
+                        "peak": PEAK_HBM / 1e9, "work": it2 * (4 * pass_bytes + tri_bytes + aa_bytes), "ms": t_ref},
     }
     for k, r in rooflines.items():
         scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
@@ -333,6 +339,8 @@ def bench_walkers(args):
     opts = P._lib.SolveOpts()
     opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
     opts.mask = fl.data_ptr()
+    if args.no_accel:
+        opts.flags |= P.SW_SOLVE_NO_ACCEL
     w = torch.empty(n_tot, dtype=torch.float64, device=dev)
     sws = torch.empty(P.solve_batched_workspace_bytes(offs, nc, opts), dtype=torch.uint8, device=dev)
     cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)

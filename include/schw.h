@@ -173,17 +173,21 @@ size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_pot, int64_t 
 #define SW_GRAM_BF16X3 1 /* U split hi+lo bf16, three MFMA passes, fp32 accumulate    */
 #define SW_GRAM_F32 2    /* fp32 MFMA, fp32 accumulate                                */
 #define SW_SOLVE_DENSE 1 /* sw_solve_opts.flags: keep the dense passes over A          */
+#define SW_SOLVE_NO_ACCEL 2 /* sw_solve_opts.flags: plain ADMM in the FP64 stage (no Anderson
+                               acceleration); the FP32 stage then runs by default        */
 
 typedef struct {
   int32_t gram;        /* SW_GRAM_* */
-  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: 1000); the stage also
-                          ends once max(primal, dual) residual stops falling (below 0.95x
-                          its value 10 checks earlier), the FP64 stage then continues */
-  int32_t refine_iter; /* FP64 refinement iteration cap (< 0: none, 0: 2000) */
+  int32_t max_iter;    /* ADMM iteration cap of the FP32 stage (<= 0: none with the
+                          accelerated FP64 stage, 1000 with SW_SOLVE_NO_ACCEL); the stage
+                          also ends once max(primal, dual) residual stops falling (below
+                          0.95x its value 10 checks earlier), the FP64 stage then continues */
+  int32_t refine_iter; /* FP64 stage iteration cap (< 0: none, 0: 2000) */
   int32_t check_every; /* convergence checked every this many iterations (<= 0: 10) */
   int32_t use_graph;   /* 1: the iterations between two checks are captured once into a HIP
                           graph and replayed (needs a non-NULL stream); 0: plain launches */
-  int32_t flags;       /* SW_SOLVE_DENSE: stream the dense A in every pass (no compressed copy) */
+  int32_t flags;       /* SW_SOLVE_DENSE: stream the dense A in every pass (no compressed copy);
+                          SW_SOLVE_NO_ACCEL: no Anderson acceleration of the FP64 stage */
   double rho;          /* ADMM penalty for the scaled problem: > 0 absolute; 0: trace(U U^T) / N
                           of each problem; < 0: -rho times that */
   double tol;          /* relative primal/dual tolerance of the FP32 stage (<= 0: 1e-4) */

@@ -47,6 +47,10 @@ constexpr int kSlabs = 256;       // orbit slabs per problem in the column-sum r
 constexpr int kPar = 8;           // per-problem scalars: wt, rho, rho', mu, alpha, active
 constexpr int kAcc = 16;          // per-problem accumulators
 constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
+constexpr int kAAMem = 10;          // Anderson acceleration: iterations kept in the history
+constexpr int kAAThreads = 256, kAAPer = 4, kAAChunk = kAAThreads * kAAPer;  // AA passes: orbits per workgroup
+constexpr int kAADots = 2 * kAAMem + 1;
+constexpr double kAARestart = 10.0;  // history cleared when the residual exceeds this many times its minimum
 constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) residual has not
 constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
 
@@ -728,6 +732,217 @@ static unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 
 // ---------------------------------------------------------------------------
 // Workspace layout.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Anderson acceleration (type II, Walker & Ni 2011) of the FP64 stage.  The
+// stage is a fixed-point iteration w <- g(w) on w = (x, z, u); with f = g(w) - w
+// and the last m differences dF_j of f and dW_j of w, the next iterate is
+//   w+ = g(w) - sum_j gamma_j (dW_j + dF_j),  gamma = argmin |f - dF gamma|,
+// from the normal equations (regularised by 1e-10 of their trace).  The
+// history is cleared when |f| exceeds kAARestart times its smallest value
+// since the last clearing.  Vectors are [3][N] (x, z, u), problem b owns
+// indices off[b]..off[b+1]-1 of each; per-problem state (iteration, history
+// length, smallest |f|) lives on the device so the steps can be captured.
+// ---------------------------------------------------------------------------
+struct AAArgs {
+  double *x, *z, *u, *v;  // the iterate of the FP64 stage
+  double *w, *wp, *fp;    // [3][N] current iterate, previous iterate, previous residual
+  double *df, *y;         // [kAAMem][3][N] history: dF_j and dW_j + dF_j
+  double *G, *gam, *st;   // per problem: [kAAMem][kAAMem] dF_i . dF_j, [kAAMem] gamma, {it, count, min |f|}
+  double* part;           // [P][nbx][kAADots] block partials of the dot products
+  const int64_t* off;
+  const double* par;
+  int64_t N;
+  int nbx, P;
+};
+
+// w = the iterate entering the FP64 stage, empty history
+__global__ __launch_bounds__(256) void k_aa_init(AAArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < a.N) {
+    a.w[i] = a.x[i];
+    a.w[a.N + i] = a.z[i];
+    a.w[2 * a.N + i] = a.u[i];
+    for (int64_t k = 0; k < 3 * (int64_t)kAAMem; ++k) a.df[k * a.N + i] = 0.0;
+  }
+  if (i < a.P) {
+    a.st[i * 4 + 0] = 0.0;
+    a.st[i * 4 + 1] = 0.0;
+    a.st[i * 4 + 2] = INFINITY;
+  }
+}
+
+// f = g(w) - w, the newest history entries, and the block partials of
+// dF_s . dF_j, dF_j . f (j < m) and f . f
+__global__ __launch_bounds__(kAAThreads) void k_aa_dots(AAArgs a) {
+  const int b = blockIdx.y;
+  if (a.par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
+  const int64_t n0 = a.off[b], nb = a.off[b + 1] - n0;
+  if ((int64_t)blockIdx.x * kAAChunk >= nb) return;
+  const int64_t it = (int64_t)a.st[b * 4 + 0];
+  const bool hist = it >= 1;
+  const int s = hist ? (int)((it - 1) % kAAMem) : 0;
+  const int64_t V = 3 * a.N;
+  double dots[kAADots];
+#pragma unroll
+  for (int k = 0; k < kAADots; ++k) dots[k] = 0.0;
+  for (int q = 0; q < kAAPer; ++q) {
+    const int64_t j = (int64_t)blockIdx.x * kAAChunk + q * kAAThreads + threadIdx.x;
+    if (j >= nb) break;
+    const int64_t i = n0 + j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double g = c == 0 ? a.x[i] : (c == 1 ? a.z[i] : a.u[i]);
+      const int64_t e = c * a.N + i;
+      const double wv = a.w[e], f = g - wv;
+      if (hist) {
+        const double d = f - a.fp[e];
+        a.df[s * V + e] = d;
+        a.y[s * V + e] = (wv - a.wp[e]) + d;
+#pragma unroll
+        for (int k = 0; k < kAAMem; ++k) {
+          const double dk = k == s ? d : a.df[k * V + e];
+          dots[k] += d * dk;
+          dots[kAAMem + k] += dk * f;
+        }
+      }
+      a.fp[e] = f;
+      a.wp[e] = wv;
+      dots[2 * kAAMem] += f * f;
+    }
+  }
+  __shared__ double red[kAAThreads / 64][kAADots];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kAADots; ++k) {
+    const double t = wave_sum(dots[k]);
+    if (lane == 0) red[wv][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kAADots) {
+    double t = 0.0;
+    for (int v = 0; v < kAAThreads / 64; ++v) t += red[v][threadIdx.x];
+    a.part[((int64_t)b * a.nbx + blockIdx.x) * kAADots + threadIdx.x] = t;
+  }
+}
+
+// per problem (one thread): the history Gram row of the newest entry, the
+// restart rule, and gamma from the regularised normal equations (plain != 0:
+// gamma = 0, the plain step g(w), used before a convergence check)
+__global__ void k_aa_solve(AAArgs a, int plain) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.P || a.par[b * kPar + 5] == 0.0) return;
+  const int64_t nb = a.off[b + 1] - a.off[b];
+  const int nbx = (int)((nb + kAAChunk - 1) / kAAChunk);
+  double t[kAADots];
+  for (int k = 0; k < kAADots; ++k) t[k] = 0.0;
+  for (int bx = 0; bx < nbx; ++bx)
+    for (int k = 0; k < kAADots; ++k) t[k] += a.part[((int64_t)b * a.nbx + bx) * kAADots + k];
+  double* G = a.G + (int64_t)b * kAAMem * kAAMem;
+  double* gam = a.gam + (int64_t)b * kAAMem;
+  const int64_t it = (int64_t)a.st[b * 4 + 0];
+  int cnt = (int)a.st[b * 4 + 1];
+  double fmin = a.st[b * 4 + 2];
+  const int m = kAAMem;
+  const int s = it >= 1 ? (int)((it - 1) % m) : 0;
+  if (it >= 1) {
+    for (int k = 0; k < m; ++k) {
+      G[s * kAAMem + k] = t[k];
+      G[k * kAAMem + s] = t[k];
+    }
+    cnt = cnt + 1 < m ? cnt + 1 : m;
+  }
+  const double fn = sqrt(t[2 * kAAMem]);
+  if (cnt > 0 && fn > kAARestart * fmin) {
+    cnt = 0;
+    fmin = fn;
+  } else {
+    fmin = fn < fmin ? fn : fmin;
+  }
+  for (int k = 0; k < kAAMem; ++k) gam[k] = 0.0;
+  if (!plain && cnt > 0) {
+    // slots newest first; M = G restricted to them, Cholesky in place
+    double M[kAAMem][kAAMem], r[kAAMem];
+    int sl[kAAMem];
+    double tr = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+      sl[i] = (s - i + m) % m;
+      tr += G[sl[i] * kAAMem + sl[i]];
+    }
+    for (int i = 0; i < cnt; ++i) {
+      for (int j = 0; j < cnt; ++j) M[i][j] = G[sl[i] * kAAMem + sl[j]];
+      M[i][i] += 1e-10 * tr + 1e-300;
+      r[i] = t[kAAMem + sl[i]];
+    }
+    bool ok = true;
+    for (int j = 0; j < cnt && ok; ++j) {
+      double dj = M[j][j];
+      for (int k = 0; k < j; ++k) dj -= M[j][k] * M[j][k];
+      if (!(dj > 0.0)) { ok = false; break; }
+      dj = sqrt(dj);
+      M[j][j] = dj;
+      for (int i = j + 1; i < cnt; ++i) {
+        double v = M[i][j];
+        for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
+        M[i][j] = v / dj;
+      }
+    }
+    if (ok) {
+      for (int i = 0; i < cnt; ++i) {  // L y = r, then L^T gamma = y
+        double v = r[i];
+        for (int k = 0; k < i; ++k) v -= M[i][k] * r[k];
+        r[i] = v / M[i][i];
+      }
+      for (int i = cnt - 1; i >= 0; --i) {
+        double v = r[i];
+        for (int k = i + 1; k < cnt; ++k) v -= M[k][i] * r[k];
+        r[i] = v / M[i][i];
+      }
+      for (int i = 0; i < cnt; ++i) gam[sl[i]] = r[i];
+    } else {
+      cnt = 0;
+    }
+  }
+  a.st[b * 4 + 0] = (double)(it + 1);
+  a.st[b * 4 + 1] = (double)cnt;
+  a.st[b * 4 + 2] = fmin;
+}
+
+// w+ = g(w) - sum_j gamma_j y_j, written to the iterate and to w; v = z - u
+__global__ __launch_bounds__(kAAThreads) void k_aa_mix(AAArgs a) {
+  const int b = blockIdx.y;
+  if (a.par[b * kPar + 5] == 0.0) return;
+  const int64_t n0 = a.off[b], nb = a.off[b + 1] - n0;
+  const int64_t V = 3 * a.N;
+  double gm[kAAMem];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < kAAMem; ++k) {
+    gm[k] = a.gam[b * kAAMem + k];
+    any |= gm[k] != 0.0;
+  }
+  for (int q = 0; q < kAAPer; ++q) {
+    const int64_t j = (int64_t)blockIdx.x * kAAChunk + q * kAAThreads + threadIdx.x;
+    if (j >= nb) break;
+    const int64_t i = n0 + j;
+    double x = a.x[i], z = a.z[i], u = a.u[i];
+    if (any) {
+#pragma unroll
+      for (int k = 0; k < kAAMem; ++k) {
+        x -= gm[k] * a.y[k * V + i];
+        z -= gm[k] * a.y[k * V + a.N + i];
+        u -= gm[k] * a.y[k * V + 2 * a.N + i];
+      }
+      a.x[i] = x;
+      a.z[i] = z;
+      a.u[i] = u;
+      a.v[i] = z - u;
+    }
+    a.w[i] = x;
+    a.w[a.N + i] = z;
+    a.w[2 * a.N + i] = u;
+  }
+}
+
 struct SolveLayout {
   int P;
   int64_t N, C, Cp, Npt;
@@ -737,6 +952,9 @@ struct SolveLayout {
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
   size_t off_par, off_acc, off_idx, off_bad, off_ftmp;
+  // Anderson acceleration of the FP64 stage (aa = history length, 0 = off)
+  int aa, aa_nbx;
+  size_t off_aw, off_awp, off_afp, off_adf, off_ay, off_ag, off_agam, off_ast, off_apart;
   // compressed copies (sized for at most cap_nnz entries): ncb column blocks
   // of the rows, nrb row blocks per problem of the columns
   int64_t cap_nnz;
@@ -745,7 +963,7 @@ struct SolveLayout {
   size_t total;
 };
 
-static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
+static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, int aa) {
   SolveLayout L;
   L.P = P;
   L.C = C;
@@ -780,6 +998,19 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode) {
   L.off_idx = take((size_t)(P + 1) * 8 * 4);
   L.off_bad = take(64);
   L.off_ftmp = take((size_t)P * inverse_factor_scratch(L.Cp, P) * 4);
+  {
+    int64_t nmax = 1;
+    for (int b = 0; b < P; ++b) nmax = std::max<int64_t>(nmax, off[b + 1] - off[b]);
+    L.aa = aa;
+    L.aa_nbx = (int)((nmax + kAAChunk - 1) / kAAChunk);
+    const size_t v3 = aa ? 3 * N * 8 : 0;
+    L.off_aw = take(v3); L.off_awp = take(v3); L.off_afp = take(v3);
+    L.off_adf = take(v3 * aa); L.off_ay = take(v3 * aa);
+    L.off_ag = take((size_t)P * kAAMem * kAAMem * 8);
+    L.off_agam = take((size_t)P * kAAMem * 8);
+    L.off_ast = take((size_t)P * 4 * 8);
+    L.off_apart = take(aa ? (size_t)P * L.aa_nbx * kAADots * 8 : 0);
+  }
   // compressed copies: room for kMaxDensity (or 1M entries), 8-byte values
   const double dense = (double)L.N * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(kMaxDensity * dense), (int64_t)1 << 20);
@@ -992,7 +1223,8 @@ extern "C" size_t solve_batched_workspace_bytes(int32_t n_prob, const int64_t* o
                                                 const sw_solve_opts* opt) {
   if (n_prob < 1 || !orbit_offsets || n_con <= 0) return 0;
   const int mode = opt ? opt->gram : SW_GRAM_BF16X3;
-  return layout(n_prob, orbit_offsets, n_con, mode).total;
+  const int aa = opt && (opt->flags & SW_SOLVE_NO_ACCEL) ? 0 : kAAMem;
+  return layout(n_prob, orbit_offsets, n_con, mode, aa).total;
 }
 
 extern "C" size_t solve_workspace_bytes(int64_t n_orb, int64_t n_con, const sw_solve_opts* opt) {
@@ -1030,7 +1262,10 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     set_error("solve_weights: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SW_ENOMEM;
   }
-  const int max_iter = opt->max_iter > 0 ? opt->max_iter : 1000;
+  // Anderson-accelerated FP64 stage unless switched off; the FP32 stage then
+  // runs only when asked for (max_iter > 0)
+  const int aa = (opt->flags & SW_SOLVE_NO_ACCEL) ? 0 : kAAMem;
+  const int max_iter = opt->max_iter > 0 ? opt->max_iter : (aa ? 0 : 1000);
   const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 2000 : opt->refine_iter);
   const int check_every = opt->check_every > 0 ? opt->check_every : 10;
   const double tol = opt->tol > 0.0 ? opt->tol : 1e-4;
@@ -1038,7 +1273,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   const int P = n_prob;
 
   Ctx X;
-  X.L = layout(P, orbit_offsets, n_con, opt->gram);
+  X.L = layout(P, orbit_offsets, n_con, opt->gram, aa);
   const SolveLayout& L = X.L;
   X.ws = (char*)workspace;
   X.st = (hipStream_t)stream;
@@ -1229,7 +1464,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     hipGraphExec_t e = nullptr;
     ~ExecGuard() { if (e) (void)hipGraphExecDestroy(e); }
   } g1, g2;
-  if (use_graph) SW_TRY(capture([&]() { return admm_iter(nullptr); }, check_every - 1, &g1.e));
+  if (use_graph && max_iter > 0) SW_TRY(capture([&]() { return admm_iter(nullptr); }, check_every - 1, &g1.e));
   std::vector<int> active(P, 1);
   std::vector<std::vector<double>> hist(P);
   int n_active = P;
@@ -1281,6 +1516,17 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, zf, xd, L.N);
   hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, vf, vd, L.N);
   SW_TRY(hipGetLastError());
+  AAArgs AA;
+  AA.x = xd; AA.z = zd; AA.u = ud; AA.v = vd;
+  AA.w = X.p<double>(L.off_aw); AA.wp = X.p<double>(L.off_awp); AA.fp = X.p<double>(L.off_afp);
+  AA.df = X.p<double>(L.off_adf); AA.y = X.p<double>(L.off_ay);
+  AA.G = X.p<double>(L.off_ag); AA.gam = X.p<double>(L.off_agam); AA.st = X.p<double>(L.off_ast);
+  AA.part = X.p<double>(L.off_apart);
+  AA.off = X.off_d; AA.par = X.par; AA.N = L.N; AA.nbx = L.aa_nbx; AA.P = P;
+  if (aa) {
+    hipLaunchKernelGGL(k_aa_init, dim3(blocks_for(std::max<int64_t>(L.N, P))), dim3(256), 0, X.st, AA);
+    SW_TRY(hipGetLastError());
+  }
   std::vector<double> kkt(P, 0.0), obj(P, 0.0);
   std::vector<int> support(P, 0);
   // the KKT evaluation covers the active problems; a frozen problem keeps its last values
@@ -1330,7 +1576,25 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     Rc.acc = nullptr;
     return rowdot(X, Rc);
   };
-  if (use_graph && n_active > 0) SW_TRY(capture(refine_iter_body, check_every, &g2.e));
+  // one step: the refinement iteration, then (accelerated) the Anderson
+  // mixing; the step before a convergence check is the plain one, so the
+  // checked iterate is a projected ADMM iterate
+  auto refine_step = [&](bool plain) -> hipError_t {
+    hipError_t e = refine_iter_body();
+    if (e != hipSuccess || !aa) return e;
+    hipLaunchKernelGGL(k_aa_dots, dim3((unsigned)L.aa_nbx, (unsigned)P), dim3(kAAThreads), 0, X.st, AA);
+    hipLaunchKernelGGL(k_aa_solve, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, X.st, AA, plain ? 1 : 0);
+    hipLaunchKernelGGL(k_aa_mix, dim3((unsigned)L.aa_nbx, (unsigned)P), dim3(kAAThreads), 0, X.st, AA);
+    return hipGetLastError();
+  };
+  auto refine_batch = [&](int run) -> hipError_t {
+    for (int k = 0; k < run; ++k) {
+      hipError_t e = refine_step(k == run - 1);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  if (use_graph && n_active > 0) SW_TRY(capture([&]() { return refine_batch(check_every); }, 1, &g2.e));
   std::vector<int> rit(P, 0);
   int k_done = 0;
   while (k_done < refine_iter && n_active > 0) {
@@ -1338,7 +1602,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     if (g2.e && run == check_every) {
       SW_TRY(hipGraphLaunch(g2.e, X.st));
     } else {
-      for (int k = 0; k < run; ++k) SW_TRY(refine_iter_body());
+      SW_TRY(refine_batch(run));
     }
     k_done += run;
     for (int b = 0; b < P; ++b)

@@ -49,6 +49,7 @@ def gpu_solve(A, d, sig, wt, nu, gram, **kw):
     opts.refine_iter = kw.get("refine_iter", 0)
     opts.tol = kw.get("tol", 0.0)
     opts.tol_kkt = kw.get("tol_kkt", 0.0)
+    opts.flags = kw.get("flags", 0)
     w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
     ws = torch.empty(P.solve_workspace_bytes(A.shape[0], A.shape[1], opts), dtype=torch.uint8, device=dev)
     status, rep = P.solve_weights(At, dt, st, wt, -1.0, opts, w, ws)
@@ -116,6 +117,34 @@ def test_small_workload_end_to_end(gpu):
     print("L1", l1, "chi2", x_g, x_o, rep.as_dict())
     assert l1 < W_L1_TOL
     assert abs(x_g / x_o - 1) < CHI2_TOL
+
+
+def test_anderson_and_plain_admm_agree(gpu):
+    """The Anderson-accelerated FP64 stage (the default) and plain ADMM (the FP32
+    stage, then the FP64 stage without acceleration) reach the same weights,
+    both within the oracle tolerance, and the accelerated solve needs fewer
+    iterations."""
+    import oracle as O
+    from tests.gpu_common import oracle_integrate
+    P = lib()
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, ov, dr, fl = gpu_integrate(cfg, ics, dt, cfg["n_steps"], "f64")
+    c_o, *_ = oracle_integrate(cfg, ics, dt, cfg["n_steps"])
+    A_o = O.time_fractions(c_o, cfg["n_steps"])
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A_o, blocks, cfg["mock"]["seed"], cfg["mock"]["noise"], cfg["mock"]["tol"])
+    w_o, mu = oracle_solve(A_o, d, sig, wt, 1e-2)
+    w_a, st_a, rep_a, _ = gpu_solve(A, d, sig, wt, 1e-2, 1)
+    w_p, st_p, rep_p, _ = gpu_solve(A, d, sig, wt, 1e-2, 1, flags=P.SW_SOLVE_NO_ACCEL)
+    print("accelerated", rep_a.as_dict())
+    print("plain", rep_p.as_dict())
+    for w_g, st, rep in ((w_a, st_a, rep_a), (w_p, st_p, rep_p)):
+        assert st == 0 and rep.converged == 1
+        assert np.abs(w_g - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
+    assert np.abs(w_a - w_p).sum() / np.abs(w_p).sum() < W_L1_TOL
+    assert rep_a.iters == 0 and rep_p.iters > 0
+    assert rep_a.refine_iters < rep_p.iters + rep_p.refine_iters
 
 
 def test_chi2_and_model_observables(gpu):
