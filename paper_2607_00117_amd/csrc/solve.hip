@@ -755,14 +755,18 @@ struct AAArgs {
   int nbx, P;
 };
 
-// w = the iterate entering the FP64 stage, empty history
+// w = the iterate entering the FP64 stage, empty history (zeroed: the workspace
+// may hold anything, and 0 * NaN would poison the mixing)
 __global__ __launch_bounds__(256) void k_aa_init(AAArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < a.N) {
     a.w[i] = a.x[i];
     a.w[a.N + i] = a.z[i];
     a.w[2 * a.N + i] = a.u[i];
-    for (int64_t k = 0; k < 3 * (int64_t)kAAMem; ++k) a.df[k * a.N + i] = 0.0;
+    for (int64_t k = 0; k < 3 * (int64_t)kAAMem; ++k) {  // unused history slots must hold finite values
+      a.df[k * a.N + i] = 0.0;
+      a.y[k * a.N + i] = 0.0;
+    }
   }
   if (i < a.P) {
     a.st[i * 4 + 0] = 0.0;
@@ -928,6 +932,7 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_mix(AAArgs a) {
     if (any) {
 #pragma unroll
       for (int k = 0; k < kAAMem; ++k) {
+        if (gm[k] == 0.0) continue;  // slots outside the history
         x -= gm[k] * a.y[k * V + i];
         z -= gm[k] * a.y[k * V + a.N + i];
         u -= gm[k] * a.y[k * V + 2 * a.N + i];

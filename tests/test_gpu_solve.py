@@ -52,6 +52,8 @@ def gpu_solve(A, d, sig, wt, nu, gram, **kw):
     opts.flags = kw.get("flags", 0)
     w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
     ws = torch.empty(P.solve_workspace_bytes(A.shape[0], A.shape[1], opts), dtype=torch.uint8, device=dev)
+    if "fill" in kw:  # byte pattern written over the whole workspace first
+        ws.fill_(kw["fill"])
     status, rep = P.solve_weights(At, dt, st, wt, -1.0, opts, w, ws)
     cws = torch.empty(P.chi2_workspace_bytes(A.shape[1]), dtype=torch.uint8, device=dev)
     return w.cpu().numpy(), status, rep, (At, w, dt, st, cws)
@@ -80,6 +82,23 @@ def test_solve_sparse_lognormal(gpu, gram):
     print("L1", l1, "chi2", x_g, x_o)
     assert l1 < W_L1_TOL
     assert abs(x_g / x_o - 1) < CHI2_TOL
+
+
+def test_workspace_contents_do_not_matter(gpu):
+    """The solve must not read workspace memory it has not written: a workspace
+    filled with NaN bytes (0xFF) gives the same weights as a zeroed one, with
+    and without the Anderson acceleration."""
+    P = lib()
+    n, c = 1500, 600
+    blocks = [(0, 200), (200, c)]
+    A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=6)
+    d, sig, wt = mock_problem(A, blocks, 4, 0.02, 0.02)
+    for flags in (0, P.SW_SOLVE_NO_ACCEL):
+        w0, st0, rep0, _ = gpu_solve(A, d, sig, wt, 1e-2, 1, flags=flags, fill=0)
+        w1, st1, rep1, _ = gpu_solve(A, d, sig, wt, 1e-2, 1, flags=flags, fill=255)
+        print(flags, rep0.as_dict(), rep1.as_dict())
+        assert st0 == 0 and st1 == 0 and np.all(np.isfinite(w1))
+        assert np.abs(w1 - w0).sum() <= 1e-9 * np.abs(w0).sum()
 
 
 def test_solve_ragged_larger(gpu):
