@@ -32,9 +32,13 @@ PEAK_F64_VALU = 78.6e12
 # integrate-and-bin, counted from the kernel's formulas (FMA = 2)
 FLOP_PER_ORBIT_STEP = {"mn_ferrers_nfwq_100k_orbits_10k_steps_f32": 686.0,
                        "plummer_mn_2k_orbits_1k_steps_f64": 168.0}
-# HBM bytes per build measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (calibrated on a
-# 4 GiB copy), per stage, for the kernels as they stand; None where not measured
-TRAFFIC = {}
+# HBM bytes measured by rocprofv3 FETCH_SIZE + WRITE_SIZE (calibrated on a 4 GiB
+# copy) for the kernels as they stand: per build for the factorisation, per
+# iteration for the ADMM stages; stages not listed were not measured
+BARRED = "mn_ferrers_nfwq_100k_orbits_10k_steps_f32"
+TRAFFIC = {(BARRED, "factorise"): 1496 * (0.8811e9 + 0.0636e9)}
+TRAFFIC_PER_ITER = {(BARRED, "admm_fp32"): 2.852e9 + 2.796e9 + 4.787e9 + 4.614e9,
+                    (BARRED, "refine_fp64"): 2 * 2.852e9 + 2 * 2.799e9 + 4.787e9 + 4.614e9 + 0.062e9}
 
 
 def log(*a):
@@ -223,11 +227,15 @@ def main():
         "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
                         "peak": PEAK_HBM / 1e9, "work": it2 * (4 * pass_bytes + tri_bytes + aa_bytes), "ms": t_ref},
     }
+    if it1 == 0:
+        del rooflines["admm_fp32"], stages["admm_fp32"]  # the FP32 stage did not run (accelerated FP64 stage only)
     for k, r in rooflines.items():
         scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
         r["achieved"] = round(r["work"] / (r["ms"] * 1e-3) / scale, 3) if r["ms"] > 0 else None
         r["frac"] = round(r["achieved"] / r["peak"], 4) if r["achieved"] is not None else None
         r["traffic"] = TRAFFIC.get((cfg["name"], k))
+        if (cfg["name"], k) in TRAFFIC_PER_ITER:
+            r["traffic"] = TRAFFIC_PER_ITER[(cfg["name"], k)] * (it1 if k == "admm_fp32" else it2)
         r["work"] = float(r["work"])
     dominant = max(stages, key=stages.get)
     roof = dict(rooflines[dominant], stage=dominant)

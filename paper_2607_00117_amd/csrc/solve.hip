@@ -829,18 +829,26 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_dots(AAArgs a) {
   }
 }
 
-// per problem (one thread): the history Gram row of the newest entry, the
-// restart rule, and gamma from the regularised normal equations (plain != 0:
-// gamma = 0, the plain step g(w), used before a convergence check)
-__global__ void k_aa_solve(AAArgs a, int plain) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.P || a.par[b * kPar + 5] == 0.0) return;
+// per problem (one wave; the small solve by its first lane): the history Gram
+// row of the newest entry, the restart rule, and gamma from the regularised
+// normal equations (plain != 0: gamma = 0, the plain step g(w), used before a
+// convergence check)
+__global__ __launch_bounds__(64) void k_aa_solve(AAArgs a, int plain) {
+  const int b = blockIdx.x;
+  if (a.par[b * kPar + 5] == 0.0) return;
   const int64_t nb = a.off[b + 1] - a.off[b];
   const int nbx = (int)((nb + kAAChunk - 1) / kAAChunk);
+  __shared__ double ts[kAADots];
+  // the block partials: lane l sums blocks l, l + 64, ..., then a fixed-order wave sum
+  for (int k = 0; k < kAADots; ++k) {
+    double v = 0.0;
+    for (int bx = threadIdx.x; bx < nbx; bx += 64) v += a.part[((int64_t)b * a.nbx + bx) * kAADots + k];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) ts[k] = v;
+  }
+  if (threadIdx.x != 0) return;
   double t[kAADots];
-  for (int k = 0; k < kAADots; ++k) t[k] = 0.0;
-  for (int bx = 0; bx < nbx; ++bx)
-    for (int k = 0; k < kAADots; ++k) t[k] += a.part[((int64_t)b * a.nbx + bx) * kAADots + k];
+  for (int k = 0; k < kAADots; ++k) t[k] = ts[k];
   double* G = a.G + (int64_t)b * kAAMem * kAAMem;
   double* gam = a.gam + (int64_t)b * kAAMem;
   const int64_t it = (int64_t)a.st[b * 4 + 0];
@@ -1588,7 +1596,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     hipError_t e = refine_iter_body();
     if (e != hipSuccess || !aa) return e;
     hipLaunchKernelGGL(k_aa_dots, dim3((unsigned)L.aa_nbx, (unsigned)P), dim3(kAAThreads), 0, X.st, AA);
-    hipLaunchKernelGGL(k_aa_solve, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, X.st, AA, plain ? 1 : 0);
+    hipLaunchKernelGGL(k_aa_solve, dim3((unsigned)P), dim3(64), 0, X.st, AA, plain ? 1 : 0);
     hipLaunchKernelGGL(k_aa_mix, dim3((unsigned)L.aa_nbx, (unsigned)P), dim3(kAAThreads), 0, X.st, AA);
     return hipGetLastError();
   };
