@@ -317,6 +317,9 @@ int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64
  *   "integrate_waves_per_cu"  0: one 64-orbit wave per workgroup over the whole
  *                             library; k in [1, 64]: persistent grid of k waves
  *                             per compute unit walking the orbit tiles
+ *   "integrate_lanes_per_orbit" 1, or 2: two lanes share each orbit of the
+ *                             single-precision binned integration (each takes
+ *                             half of the bar's quadrature nodes)
  *   "hist_lds_kb"             LDS budget (KiB, 4..160) of one histogram
  *                             workgroup; sets how many orbit rows it carries
  *   "sparse_rows_per_wg"      orbit rows per row-dot workgroup of the weight

@@ -2,7 +2,8 @@
 
 Times integrate_and_bin on a sample of the workload for each candidate of
   integrate_waves_per_cu (0 = one wave per 64-orbit tile, k = persistent grid
-  of k waves per CU) and hist_lds_kb (LDS budget of a histogram workgroup),
+  of k waves per CU), integrate_lanes_per_orbit (1 or 2 lanes share an orbit's
+  force evaluation) and hist_lds_kb (LDS budget of a histogram workgroup),
 keeps the fastest, and caches it per workload shape in a JSON file
 ($SCHW_TUNE_CACHE, default ~/.cache/schw_tune.json).
 """
@@ -13,6 +14,7 @@ import time
 from . import _lib as P
 
 CANDIDATES_WAVES = (0, 2, 4, 8)
+CANDIDATES_LANES = (1, 2)
 CANDIDATES_LDS = (32, 64, 128)
 
 
@@ -34,6 +36,7 @@ def load_cache():
 
 def apply(cfg):
     P.set_tuning("integrate_waves_per_cu", cfg["integrate_waves_per_cu"])
+    P.set_tuning("integrate_lanes_per_orbit", cfg.get("integrate_lanes_per_orbit", 1))
     P.set_tuning("hist_lds_kb", cfg["hist_lds_kb"])
 
 
@@ -46,19 +49,20 @@ def tune(run, key, repeats=2, log=None):
         return cache[key]["best"], cache[key]["table"]
     table = []
     for wpc in CANDIDATES_WAVES:
-        for lds in CANDIDATES_LDS:
-            cfg = {"integrate_waves_per_cu": wpc, "hist_lds_kb": lds}
-            apply(cfg)
-            run()  # warm
-            t0 = time.perf_counter()
-            for _ in range(repeats):
-                run()
-            ms = 1e3 * (time.perf_counter() - t0) / repeats
-            table.append(dict(cfg, ms=ms))
-            if log:
-                log(f"autotune {cfg}: {ms:.2f} ms")
+        for lanes in CANDIDATES_LANES:
+            for lds in CANDIDATES_LDS:
+                cfg = {"integrate_waves_per_cu": wpc, "integrate_lanes_per_orbit": lanes, "hist_lds_kb": lds}
+                apply(cfg)
+                run()  # warm
+                t0 = time.perf_counter()
+                for _ in range(repeats):
+                    run()
+                ms = 1e3 * (time.perf_counter() - t0) / repeats
+                table.append(dict(cfg, ms=ms))
+                if log:
+                    log(f"autotune {cfg}: {ms:.2f} ms")
     best = min(table, key=lambda r: r["ms"])
-    best = {"integrate_waves_per_cu": best["integrate_waves_per_cu"], "hist_lds_kb": best["hist_lds_kb"]}
+    best = {k: best[k] for k in ("integrate_waves_per_cu", "integrate_lanes_per_orbit", "hist_lds_kb")}
     apply(best)
     cache[key] = {"best": best, "table": table}
     try:

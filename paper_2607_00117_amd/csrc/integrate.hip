@@ -19,6 +19,7 @@ constexpr int kHistThreads = 256;
 
 int g_waves_per_cu = 0;
 int g_hist_lds_kb = 64;
+int g_lanes_per_orbit = 1;
 int g_num_cus = 256;
 
 template <typename T>
@@ -114,6 +115,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_hist_lds_kb = value;
     return SW_OK;
   }
+  if (k == "integrate_lanes_per_orbit") {
+    SW_CHECK(value == 1 || value == 2, "sw_set_tuning: integrate_lanes_per_orbit is 1 or 2");
+    g_lanes_per_orbit = value;
+    return SW_OK;
+  }
   if (k == "sparse_rows_per_wg" || k == "sparse_cols_per_wg") {
     SW_CHECK(value >= 0 && value <= 512 && value % 16 == 0, "sw_set_tuning: %s: 0 (automatic) or a multiple of 16 "
              "up to 512", key);
@@ -133,6 +139,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   const std::string k(key);
   if (k == "integrate_waves_per_cu") return g_waves_per_cu;
   if (k == "hist_lds_kb") return g_hist_lds_kb;
+  if (k == "integrate_lanes_per_orbit") return g_lanes_per_orbit;
   if (k == "sparse_rows_per_wg") return g_sparse_rows;
   if (k == "sparse_cols_per_wg") return g_sparse_cols;
   if (k == "sparse_lanes_per_row") return g_sparse_lanes;

@@ -22,14 +22,27 @@ template <typename T>
 struct Prec;
 template <>
 struct Prec<float> {
-  __device__ static void accel(const PotK& P, const float* s, float* g, float& lamw) {
-    accel_f32(P, s[0], s[1], s[2], g[0], g[1], g[2], lamw);
+  // LPO lanes per orbit: each lane's share, then the sum over the lane group
+  // (the same sum in every lane of the group, so their states stay identical)
+  template <int LPO = 1>
+  __device__ static void accel(const PotK& P, const float* s, float* g, float& lamw, int part = 0) {
+    float gb[3];
+    accel_f32<LPO>(P, s[0], s[1], s[2], g[0], g[1], g[2], gb, lamw, part);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if constexpr (LPO == 2) gb[k] += __shfl_xor(gb[k], 1, 64);
+      g[k] += gb[k];
+    }
   }
   __device__ static double jacobi(const PotK& P, const double* sd, float lamw) { return jacobi_f64_drift(P, sd, lamw); }
 };
 template <>
 struct Prec<double> {
-  __device__ static void accel(const PotK& P, const double* s, double* g, float&) { accel_f64(P, s, g); }
+  template <int LPO = 1>
+  __device__ static void accel(const PotK& P, const double* s, double* g, float&, int = 0) {
+    static_assert(LPO == 1, "the double-precision path runs one lane per orbit");
+    accel_f64(P, s, g);
+  }
   __device__ static double jacobi(const PotK& P, const double* sd, float) { return jacobi_f64(P, sd); }
 };
 
@@ -52,21 +65,28 @@ __device__ __forceinline__ int pot_index(const int64_t* offsets, int n_pot, int6
 
 // At most 168 registers, so that three waves share a SIMD (the default
 // allocation lands one register above that, at two waves); no spills.
-template <typename T, bool BATCHED, bool BIN>
+//
+// LPO lanes per orbit (1, or 2 in single precision): a wave carries 64 / LPO
+// orbits; the lanes of a pair hold the same state, each evaluates its share of
+// the force and the pair adds the shares, so both advance identically; the
+// first lane of the pair writes the orbit's events and results.
+template <typename T, bool BATCHED, bool BIN, int LPO = 1>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int64_t* __restrict__ offsets,
                  int32_t n_pot, ObsK O, const T* __restrict__ ics, const T* __restrict__ dts, int64_t n_orb,
                  int64_t orb0, int64_t n_chunk, int32_t n_steps, uint64_t* __restrict__ ev_m,
                  uint64_t* __restrict__ ev_k, double* __restrict__ drift, uint8_t* __restrict__ flags,
                  T* __restrict__ final_state) {
-  __shared__ uint64_t stm[kStage][kWave + 1];
-  __shared__ uint64_t stk[kStage][kWave + 1];
+  constexpr int OPW = kWave / LPO;  // orbits per wave
+  __shared__ uint64_t stm[kStage][OPW + 1];
+  __shared__ uint64_t stk[kStage][OPW + 1];
   const int lane = threadIdx.x;
-  const int64_t n_tiles = (n_chunk + kWave - 1) / kWave;
+  const int part = lane % LPO, lo = lane / LPO;  // share and orbit of this lane
+  const int64_t n_tiles = (n_chunk + OPW - 1) / OPW;
   // persistent launch: each wave walks the orbit tiles t = blockIdx.x, + gridDim.x, ...
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-  const int64_t jbase = tile * kWave;  // chunk-local index of lane 0
-  const int64_t j = jbase + lane;
+  const int64_t jbase = tile * OPW;  // chunk-local index of the tile's first orbit
+  const int64_t j = jbase + lo;
   const bool valid = j < n_chunk;
   const int64_t o = orb0 + (valid ? j : n_chunk - 1);
   const int kpot = BATCHED ? pot_index(offsets, n_pot, o) : 0;
@@ -87,7 +107,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
 
   float lamw = -1.0f;
   T g[3];
-  Prec<T>::accel(P, s, g, lamw);
+  Prec<T>::template accel<LPO>(P, s, g, lamw, part);
   double sd[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
@@ -116,7 +136,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
       T py = s[4] + (cm1 * s[4] - sn * s[3]);
       s[0] = x; s[1] = y; s[3] = px; s[4] = py;
     }
-    Prec<T>::accel(P, s, g, lamw);
+    Prec<T>::template accel<LPO>(P, s, g, lamw, part);
     s[3] = s[3] + h * g[0];
     s[4] = s[4] + h * g[1];
     s[5] = s[5] + h * g[2];
@@ -130,13 +150,15 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
     if constexpr (BIN) {
       int mc[4], kc[4];
       cells4<T>(P, O, s, mc, kc);
-      stm[slot][lane] = pack4(mc);
-      stk[slot][lane] = pack4(kc);
+      if (part == 0) {
+        stm[slot][lo] = pack4(mc);
+        stk[slot][lo] = pack4(kc);
+      }
       ++slot;
       if (slot == kStage || k == n_steps) {
         __syncthreads();
         const int64_t step0 = k - slot;
-        const int total = slot * kWave;
+        const int total = slot * OPW;
         for (int idx = lane; idx < total; idx += kWave) {
           const int jj = idx / slot, ss = idx - jj * slot;
           const int64_t jo = jbase + jj;
@@ -151,7 +173,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
       }
     }
   }
-  if (valid) {
+  if (valid && part == 0) {
     bool nonfinite = false;
 #pragma unroll
     for (int i = 0; i < 6; ++i) nonfinite |= !isfinite(s[i]);
@@ -188,11 +210,13 @@ struct IntegrateLaunch {
 //  g_hist_lds_kb   LDS budget of one histogram workgroup (orbits per workgroup follow)
 extern int g_waves_per_cu;
 extern int g_hist_lds_kb;
+extern int g_lanes_per_orbit;  // 1 or 2 lanes per orbit (single precision with binning)
 extern int g_num_cus;
 
 template <typename T>
 hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
-  int64_t tiles = (L.n_chunk + kWave - 1) / kWave;
+  const int lpo = (sizeof(T) == 4 && L.bin && g_lanes_per_orbit == 2) ? 2 : 1;
+  int64_t tiles = (L.n_chunk + kWave / lpo - 1) / (kWave / lpo);
   if (g_waves_per_cu > 0) {
     const int64_t cap = (int64_t)g_waves_per_cu * g_num_cus;
     if (tiles > cap) tiles = cap;
@@ -202,6 +226,19 @@ hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
   const T* dt = (const T*)L.dt;
   T* fs = (T*)L.final_state;
   if (L.bin) {
+    if constexpr (sizeof(T) == 4) {
+      if (lpo == 2) {
+        if (L.n_pot > 1)
+          hipLaunchKernelGGL((k_integrate<T, true, true, 2>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,
+                             L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift,
+                             L.flags, fs);
+        else
+          hipLaunchKernelGGL((k_integrate<T, false, true, 2>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,
+                             L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift,
+                             L.flags, fs);
+        return hipGetLastError();
+      }
+    }
     if (L.n_pot > 1)
       hipLaunchKernelGGL((k_integrate<T, true, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev, L.n_pot, L.obs,
                          ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift, L.flags, fs);

@@ -32,9 +32,13 @@ constexpr int kNewtonWarm32 = 3;  // Newton steps from the previous step's lam
 // position); m^2(lam) is convex and decreasing, so a start right of the root
 // lands left of it after one step and then rises monotonically.  lam_io
 // returns the root found.
+// With LPO > 1 lanes per orbit, lane `part` of the group takes the nodes
+// n = part, part + LPO, ... and returns its share of the force (the shares
+// add up across the group); every lane computes lam.
+template <int LPO = 1>
 __device__ __forceinline__ void ferrers_accel_f32(const CompK& C, const float* gq, const float* gw, float x,
                                                   float y, float z, float& gx, float& gy, float& gz,
-                                                  float& lam_io) {
+                                                  float& lam_io, int part = 0) {
   const float A0 = C.f[0], A1 = C.f[1], A2 = C.f[2], Amin = C.f[3], kF = C.f[4], Amax = C.f[6];
   const float x2 = x * x, y2 = y * y, z2 = z * z;
   const bool cold = lam_io < 0.0f;
@@ -54,8 +58,13 @@ __device__ __forceinline__ void ferrers_accel_f32(const CompK& C, const float* g
   const float xs = x2 * iK, ys = y2 * iK, zs = z2 * iK;
   float F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
 #pragma unroll
-  for (int n = 0; n < kGL32; ++n) {
-    const float q = gq[n], W = gw[n];
+  for (int m = 0; m < kGL32 / LPO; ++m) {
+    // the node of this lane, chosen between uniform loads (no per-lane index)
+    float q = gq[m * LPO], W = gw[m * LPO];
+    if constexpr (LPO == 2) {
+      q = part ? gq[m * LPO + 1] : q;
+      W = part ? gw[m * LPO + 1] : W;
+    }
     float e0 = D0 + q, e1 = D1 + q, e2 = D2 + q;
     float e12 = e1 * e2, e02 = e0 * e2, e01 = e0 * e1;
     float s = rsqf_(e0 * e12);
@@ -126,9 +135,15 @@ __device__ inline void ferrers_f64(const CompK& C, const double* gq, const doubl
 // ---------------------------------------------------------------------------
 // lamw: warm-start state of the first bar component (< 0: none yet); a
 // second bar component, if any, always starts cold.
+// With LPO lanes per orbit every lane evaluates the analytic components in
+// full (into g) and its share of every bar's quadrature nodes (into gb): the
+// force is g + the sum of gb over the lane group.  With LPO = 1, gb is the
+// whole bar force and the caller adds it.
+template <int LPO = 1>
 __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float z, float& gx, float& gy,
-                                          float& gz, float& lamw) {
+                                          float& gz, float* gb, float& lamw, int part = 0) {
   gx = 0.0f; gy = 0.0f; gz = 0.0f;
+  gb[0] = 0.0f; gb[1] = 0.0f; gb[2] = 0.0f;
   const int nc = P.n_comp;
   bool first_bar = true;
   for (int i = 0; i < nc; ++i) {
@@ -184,11 +199,11 @@ __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float
       }
       case SW_FERRERS2:
         if (first_bar) {
-          ferrers_accel_f32(C, P.gq32, P.gw32, x, y, z, gx, gy, gz, lamw);
+          ferrers_accel_f32<LPO>(C, P.gq32, P.gw32, x, y, z, gb[0], gb[1], gb[2], lamw, part);
           first_bar = false;
         } else {
           float cold = -1.0f;
-          ferrers_accel_f32(C, P.gq32, P.gw32, x, y, z, gx, gy, gz, cold);
+          ferrers_accel_f32<LPO>(C, P.gq32, P.gw32, x, y, z, gb[0], gb[1], gb[2], cold, part);
         }
         break;
       default:

@@ -140,6 +140,18 @@ def test_tuning_knobs():
     P.set_tuning("hist_lds_kb", 32)
     assert P.get_tuning("hist_lds_kb") == 32
     P.set_tuning("hist_lds_kb", old)
+    # every knob: its default reads back, an out-of-range value is refused and leaves it unchanged
+    for key, good, bad in [("integrate_waves_per_cu", 8, 65), ("integrate_lanes_per_orbit", 2, 3),
+                           ("sparse_rows_per_wg", 64, 17), ("sparse_cols_per_wg", 512, 1024),
+                           ("sparse_lanes_per_row", 16, 32)]:
+        old = P.get_tuning(key)
+        assert old >= 0
+        P.set_tuning(key, good)
+        assert P.get_tuning(key) == good
+        with pytest.raises(P.SchwError):
+            P.set_tuning(key, bad)
+        assert P.get_tuning(key) == good
+        P.set_tuning(key, old)
 
 
 def test_mlp_param_count_matches_architecture():

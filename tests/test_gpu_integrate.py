@@ -107,7 +107,18 @@ def test_ragged_shapes_fp64(gpu, n, n_steps, sym):
     assert np.array_equal(dr, dr_o) and np.array_equal(fl, fl_o)
 
 
-def test_barred_fp32_subsample_vs_fp64_oracle(gpu):
+_ORACLE_CACHE = {}
+
+
+def _barred_oracle(ic64, dt64, n_steps, f32_state):
+    key = f32_state
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle_integrate(W.BARRED, ic64, dt64, n_steps, f32_state=f32_state)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_barred_fp32_subsample_vs_fp64_oracle(gpu, lanes):
     """Barred model (MN + Ferrers + flattened NFW, 40 km/s/kpc) in FP32 against the
     FP64 oracle on the seeded 1,000-orbit subsample of the 100,000-orbit library,
     full 10,000 steps.  Exact: per-block normalisation of every row.  Jacobi
@@ -116,17 +127,23 @@ def test_barred_fp32_subsample_vs_fp64_oracle(gpu):
     L1 distance between GPU and oracle rows is compared with the distance
     between the oracle and the oracle whose state is rounded to binary32 after
     every step (the error any FP32 integrator carries): the GPU must not
-    decorrelate much faster than that floor."""
+    decorrelate much faster than that floor.  Run with one and with two lanes
+    per orbit."""
     cfg = W.BARRED
     n_steps = cfg["n_steps"]
     table = W.load_table(cfg["table"])
     ics, dt = W.disc_ics(table, cfg["n_orb"], seed=cfg["ic_seed"], n_steps=n_steps)
     sub = W.subsample_draw(cfg["n_orb"], cfg["subsample"]["n"], cfg["subsample"]["seed"])
     ics32, dt32 = ics[:, sub].astype(np.float32), dt[sub].astype(np.float32)
-    A, ov, dr, fl = gpu_integrate(cfg, ics32, dt32, n_steps, "f32")
+    P = lib()
+    P.set_tuning("integrate_lanes_per_orbit", lanes)
+    try:
+        A, ov, dr, fl = gpu_integrate(cfg, ics32, dt32, n_steps, "f32")
+    finally:
+        P.set_tuning("integrate_lanes_per_orbit", 1)
     ic64, dt64 = ics32.astype(np.float64), dt32.astype(np.float64)
-    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ic64, dt64, n_steps)
-    c_p, *_ = oracle_integrate(cfg, ic64, dt64, n_steps, f32_state=True)
+    c_o, ov_o, dr_o, fl_o = _barred_oracle(ic64, dt64, n_steps, False)
+    c_p, *_ = _barred_oracle(ic64, dt64, n_steps, True)
     c_g = counts_from_fractions(A, n_steps)
     nm = 30 * 30 * 20
     ovc = np.rint(ov * 4 * n_steps).astype(np.int64)

@@ -56,14 +56,15 @@ def test_surrogate_screen_saves_full_builds(gpu):
     n_ap = obs_d["npx"] * obs_d["npy"]
     dchi2, jk = builder.jackknife_dchi2(nominal, n_ap, obs_d["nv"])
     assert np.all(np.isfinite(jk)) and dchi2 > 0
-    thetas = lo + (hi - lo) * W.latin_hypercube(448, 12, seed=7)
+    n_fit, n_test = 1024, 128
+    thetas = lo + (hi - lo) * W.latin_hypercube(n_fit + n_test, 12, seed=7)
     chi = builder.chi2(thetas)
     assert np.all(np.isfinite(chi)) and np.all(chi > 0)
     assert np.unique(np.round(chi, 6)).size > 0.9 * len(chi)  # every build is its own model
     sur = S.Surrogate(lo, hi)
-    sur.fit(thetas[:384], chi[:384], epochs=150, batch=128)
-    err = np.abs(sur.predict(thetas[384:]) - chi[384:]) / dchi2
-    base = np.abs(np.median(chi[:384]) - chi[384:]) / dchi2   # the method without the network: a constant guess
+    sur.fit(thetas[:n_fit], chi[:n_fit], epochs=300, batch=128)
+    err = np.abs(sur.predict(thetas[n_fit:]) - chi[n_fit:]) / dchi2
+    base = np.abs(np.median(chi[:n_fit]) - chi[n_fit:]) / dchi2  # the method without the network: a constant guess
     print(f"dchi2 {dchi2:.4g}; held-out |chi2_s - chi2| / dchi2: median {np.median(err):.3g} "
           f"(constant guess {np.median(base):.3g})")
     assert np.median(err) < 0.5 * np.median(base)
