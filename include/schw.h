@@ -235,6 +235,42 @@ size_t solve_batched_workspace_bytes(int32_t n_prob, const int64_t* orbit_offset
                                      const sw_solve_opts* opt);
 
 /* ---------------------------------------------------------------------------
+ * solve_weights_multi: n_rhs weight problems of Eq. 4 that share the orbit
+ * matrix, sigma, w_tilde and lambda and differ only in the data vector, e.g.
+ * the bootstrap realisations of the observed maps (Sec. 2.3: the realisations
+ * share the library and U, only y changes).  The Gram matrix is formed and
+ * factorised once; every ADMM pass covers all data vectors, and each one stops
+ * iterating when it meets the tolerances.
+ *   A device [n_orb][n_con] (dtype); d device [n_rhs][n_con] double; sigma
+ *   device [n_con] double (shared); w device [n_rhs][n_orb] double (output,
+ *   row b = the weights for d + b*n_con); rep host [n_rhs] or NULL.
+ * Options, status codes (SW_ENOTCONV if any data vector did not converge) and
+ * stopping rule as solve_weights; workspace >= solve_multi_workspace_bytes. */
+int solve_weights_multi(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int32_t n_rhs, const double* d,
+                        const double* sigma, double w_tilde, double lambda, const sw_solve_opts* opt, double* w,
+                        sw_solve_report* rep, void* workspace, size_t ws_bytes, void* stream);
+size_t solve_multi_workspace_bytes(int64_t n_orb, int64_t n_con, int32_t n_rhs, const sw_solve_opts* opt);
+
+/* ---------------------------------------------------------------------------
+ * bootstrap_data (Sec. 2.3): n_rhs bootstrap realisations of the data,
+ * out[b][n] = d[n] + sigma[n] eps[b][n] for n in [col_begin, col_end) (the
+ * observed surface-density and kinematic maps) and out[b][n] = d[n] elsewhere
+ * (the intrinsic density constraint is not resampled).
+ *   d, sigma device [n_con] double; eps device [n_rhs][n_con] double, standard
+ *   normal deviates drawn by the caller; out device [n_rhs][n_con] double.
+ * Asynchronous on stream; SW_EINVAL for a bad range or n_rhs > 65535. */
+int bootstrap_data(const double* d, const double* sigma, const double* eps, int64_t n_con, int32_t n_rhs,
+                   int64_t col_begin, int64_t col_end, double* out, void* stream);
+
+/* chi2_model (Sec. 2.4, Eq. 6): the bootstrap-marginalised chi^2 of n values
+ * chi2_b (chi^2 of Eq. 5 for each realisation's weights against the observed
+ * data), read as chi2_min - 2 ln[(1/n) sum_b exp(-(chi2_b - chi2_min)/2)]: the
+ * printed form lies in [0, ln n] whatever the fit, and the constant is fixed
+ * so that n equal values give that value.  chi2_b, out: host.  Host only (no
+ * device work); SW_EINVAL for n < 1 or a negative or non-finite value. */
+int chi2_model(const double* chi2_b, int32_t n, double* out);
+
+/* ---------------------------------------------------------------------------
  * chi2 (Sec. 2.4, Eq. 5): sum over n in [col_begin, col_end) of
  * ((sum_i w_i A[i][n] - d_n) / sigma_n)^2, accumulated in double precision.
  * With the column range of the kinematic block this is chi^2_lum + chi^2_kine

@@ -11,5 +11,5 @@ from ._lib import (  # noqa: F401
     solve_workspace_bytes, solve_weights_batched, solve_batched_workspace_bytes, chi2, chi2_workspace_bytes, model_observables, bin_points, integrate_orbits,
     obs_spec, ncon, library_path, load, mlp_param_count, mlp_workspace_bytes, mlp_forward, mlp_backward,
     mlp_adam_step, mlp_pack_bf16, mlp_infer_bf16, mlp_mse_grad, set_tuning, get_tuning, gh_moments,
-    gh_workspace_bytes,
+    gh_workspace_bytes, solve_weights_multi, solve_multi_workspace_bytes, bootstrap_data, chi2_model,
 )

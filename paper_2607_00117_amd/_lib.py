@@ -96,6 +96,12 @@ def load():
                                         C.c_double, C.POINTER(SolveOpts), vp, C.POINTER(SolveReport), vp, sz, vp]
     L.solve_batched_workspace_bytes.argtypes = [i32, C.POINTER(C.c_int64), i64, C.POINTER(SolveOpts)]
     L.solve_batched_workspace_bytes.restype = sz
+    L.solve_weights_multi.argtypes = [vp, i32, i64, i64, i32, vp, vp, C.c_double, C.c_double, C.POINTER(SolveOpts),
+                                      vp, C.POINTER(SolveReport), vp, sz, vp]
+    L.solve_multi_workspace_bytes.argtypes = [i64, i64, i32, C.POINTER(SolveOpts)]
+    L.solve_multi_workspace_bytes.restype = sz
+    L.bootstrap_data.argtypes = [vp, vp, vp, i64, i32, i64, i64, vp, vp]
+    L.chi2_model.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double)]
     L.chi2.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp, sz, vp]
     L.chi2_workspace_bytes.argtypes = [i64]
     L.chi2_workspace_bytes.restype = sz
@@ -242,6 +248,38 @@ def solve_weights_batched(A, offsets, d, sigma, w_tilde, lam, opts, w, workspace
     if st not in (0, -4):
         _check(st)
     return st, list(reps)
+
+
+def solve_multi_workspace_bytes(n_orb, n_con, n_rhs, opts):
+    return load().solve_multi_workspace_bytes(int(n_orb), int(n_con), int(n_rhs), C.byref(opts))
+
+
+def solve_weights_multi(A, d, sigma, w_tilde, lam, opts, w, workspace):
+    """d: device [n_rhs][n_con]; sigma: device [n_con]; w: device [n_rhs][n_orb]."""
+    n_orb, n_con = A.shape
+    n_rhs = d.shape[0]
+    reps = (SolveReport * n_rhs)()
+    st = load().solve_weights_multi(_ptr(A), _dtype_code(A), n_orb, n_con, n_rhs, _ptr(d), _ptr(sigma),
+                                    float(w_tilde), float(lam), C.byref(opts), _ptr(w), reps, _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), _stream())
+    if st not in (0, -4):
+        _check(st)
+    return st, list(reps)
+
+
+def bootstrap_data(d, sigma, eps, col_begin, col_end, out):
+    """d, sigma: device [n_con]; eps, out: device [n_rhs][n_con]."""
+    n_rhs, n_con = eps.shape
+    _check(load().bootstrap_data(_ptr(d), _ptr(sigma), _ptr(eps), int(n_con), int(n_rhs), int(col_begin),
+                                 int(col_end), _ptr(out), _stream()))
+
+
+def chi2_model(chi2_b):
+    vals = [float(v) for v in chi2_b]
+    arr = (C.c_double * max(1, len(vals)))(*vals)
+    out = C.c_double(0.0)
+    _check(load().chi2_model(arr, len(vals), C.byref(out)))
+    return out.value
 
 
 def chi2_workspace_bytes(n_con):

@@ -26,6 +26,7 @@ SOURCES = {
     "gemm.hip": [],
     "mlp.hip": [],
     "gh.hip": [],
+    "bootstrap.hip": [],
 }
 
 

@@ -124,7 +124,7 @@ template <typename TA, typename TV>
 __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A, int64_t C,
                                                         const TV* __restrict__ v, const int64_t* __restrict__ off,
                                                         const int64_t* __restrict__ rps, const double* __restrict__ par,
-                                                        double* __restrict__ part) {
+                                                        int shared, double* __restrict__ part) {
   const int b = blockIdx.z;
   if (par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
   const int64_t c0 = (int64_t)blockIdx.x * kColTile;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const TA* __restrict__ A
   for (int64_t i = i_beg; i < i_end; ++i) {
     const double vi = (double)v[i];
     if (vi == 0.0) continue;
-    const TA* row = A + i * C;
+    const TA* row = A + (shared ? i - off[b] : i) * C;
 #pragma unroll
     for (int k = 0; k < kColsPerThread; ++k) {
       const int64_t c = c0 + threadIdx.x + k * kColThreads;
@@ -368,7 +368,8 @@ __global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, int cpw, c
                                                           const int64_t* __restrict__ cptr,
                                                           const uint16_t* __restrict__ rowi,
                                                           const TA* __restrict__ val, const TV* __restrict__ v,
-                                                          const double* __restrict__ par, double* __restrict__ part) {
+                                                          const double* __restrict__ par, int shared,
+                                                          double* __restrict__ part) {
   __shared__ double xs[kBlk];
   __shared__ double cacc[kMaxRowsWG];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, int cpw, c
     __syncthreads();
     for (int64_t j = threadIdx.x; j < len; j += kSpThreads) xs[j] = (double)v[n0 + r0 + j];
     __syncthreads();
-    const int64_t* cp = cptr + ((int64_t)b * nrb + rb) * (C + 1);
+    const int64_t* cp = cptr + ((int64_t)(shared ? 0 : b) * nrb + rb) * (C + 1);
     for (int q = w; q < nc; q += kSpWaves) {
       const int64_t c = c0 + q;
       const double t = wave_sum(seg_dot(val, rowi, cp[c], cp[c + 1], xs, lane));
@@ -407,7 +408,8 @@ enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
 //  COL_OBS:   outd = t
 // Vectors are [nprob][Cp]; entries in [C, Cp) are written as 0.
 __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int nslab, int64_t C, int64_t Cp,
-                                                   const double* __restrict__ sigma, const double* __restrict__ par,
+                                                   const double* __restrict__ sigma, int64_t sS,
+                                                   const double* __restrict__ par,
                                                    int op, const float* __restrict__ kyf, const double* __restrict__ y,
                                                    float* __restrict__ outf, double* __restrict__ outd,
                                                    double* __restrict__ acc) {
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
     if (n < C) {
       const double* pb = part + (int64_t)b * kSlabs * C;
       for (int64_t s = 0; s < nslab; ++s) t += pb[s * C + n];
-      if (op != COL_OBS) t *= wt / sigma[(int64_t)b * C + n];
+      if (op != COL_OBS) t *= wt / sigma[b * sS + n];
     }
     switch (op) {
       case COL_PLAIN:
@@ -455,20 +457,21 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
 }
 
 // sc[b][n] = w~_b s[b][n] / sigma[b][n]: the multiplier of column n in a row dot
+// (sigma of problem b at sigma + b * sS: sS = 0 when the problems share one)
 template <typename TS>
 __global__ void k_colscale(const TS* __restrict__ s, int64_t C, int64_t Cp, const double* __restrict__ sigma,
-                           const double* __restrict__ par, double* __restrict__ sc) {
+                           int64_t sS, const double* __restrict__ par, double* __restrict__ sc) {
   const int b = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < C) sc[(int64_t)b * Cp + n] = par[b * kPar + 0] * (double)s[(int64_t)b * Cp + n] / sigma[(int64_t)b * C + n];
+  if (n < C) sc[(int64_t)b * Cp + n] = par[b * kPar + 0] * (double)s[(int64_t)b * Cp + n] / sigma[b * sS + n];
 }
 
 // y[b][n] = d[b][n] / sigma[b][n] (zero padded to Cp)
-__global__ void k_scaled_data(const double* __restrict__ d, const double* __restrict__ sigma, int64_t C, int64_t Cp,
-                              double* __restrict__ y) {
+__global__ void k_scaled_data(const double* __restrict__ d, const double* __restrict__ sigma, int64_t sS, int64_t C,
+                              int64_t Cp, double* __restrict__ y) {
   const int b = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < Cp) y[(int64_t)b * Cp + n] = n < C ? d[(int64_t)b * C + n] / sigma[(int64_t)b * C + n] : 0.0;
+  if (n < Cp) y[(int64_t)b * Cp + n] = n < C ? d[(int64_t)b * C + n] / sigma[b * sS + n] : 0.0;
 }
 
 enum RowOp { ROW_Q = 0, ROW_ADMM = 1, ROW_H = 2, ROW_CORR = 3, ROW_KKT = 4 };
@@ -476,6 +479,7 @@ enum RowOp { ROW_Q = 0, ROW_ADMM = 1, ROW_H = 2, ROW_CORR = 3, ROW_KKT = 4 };
 struct RowArgs {
   int op;
   int nprob;
+  int shared;  // every problem's orbits are rows 0.. of A (vector index i - off[b])
   int64_t Cp;
   const int64_t* off;
   const double* par;
@@ -506,7 +510,7 @@ constexpr int kRowSums = 9;
 // The update of orbit row i of problem b once its dot with sc is known.
 __device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, double dot, double* a) {
   const double* P = R.par + b * kPar;
-  const bool masked = R.mask && R.mask[i];
+  const bool masked = R.mask && R.mask[R.shared ? i - R.off[b] : i];
   const double rho = P[1], rhop = P[2], mu = P[3], alpha = P[4];
   const bool acc = R.acc != nullptr;
   switch (R.op) {
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(kRowsBlock) void k_rowdot(const TA* __restrict__ A,
   const int b = find_problem(R.off, R.nprob, i);
   if (R.par[b * kPar + 5] == 0.0 && R.op != ROW_Q) return;  // converged problem: frozen
   const double* scb = sc + (int64_t)b * R.Cp;
-  const TA* row = A + i * C;
+  const TA* row = A + (R.shared ? i - R.off[b] : i) * C;
   double dot = 0.0;
   for (int64_t c = lane; c < C; c += 64) dot += (double)row[c] * scb[c];
   dot = wave_sum(dot);
@@ -626,6 +630,7 @@ __global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, i
   const double* scb = sc + (int64_t)b * R.Cp;
   const TA* val = (const TA*)R.csr_val;
   const uint16_t* col = (const uint16_t*)R.csr_col;
+  const int64_t ash = R.shared ? R.off[b] : 0;  // row of A = vector index - ash
   // row r belongs to slot r mod NS throughout, so racc[r] needs no barrier
   for (int r = slot; r < nr; r += NS)
     if (sl == 0) racc[r] = 0.0;
@@ -640,7 +645,8 @@ __global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, i
       double part = 0.0;
       if (r < nr) {
         const int64_t i = i0 + r;
-        part = seg_dot<LPR>(val, col, R.csr_ptr[i * ncb + cb], R.csr_ptr[i * ncb + cb + 1], xs, sl);
+        const int64_t* seg = R.csr_ptr + (i - ash) * ncb + cb;
+        part = seg_dot<LPR>(val, col, seg[0], seg[1], xs, sl);
       }
       part = group_sum<LPR>(part);
       if (sl == 0 && r < nr) racc[r] += part;
@@ -960,6 +966,12 @@ struct SolveLayout {
   int P;
   int64_t N, C, Cp, Npt;
   std::vector<int64_t> off, xoff, xlen, rps;
+  // the matrices behind the problems: PA = P distinct orbit sets (rows aoff[a]..aoff[a+1]-1
+  // of A), or PA = 1 shared by every problem (right-hand sides of one U); NA rows of A
+  bool shared;
+  int PA;
+  int64_t NA;
+  std::vector<int64_t> aoff;
   size_t off_hi, off_lo, off_xf, off_K, off_dinv, off_part;
   size_t off_qf, off_zf, off_uf, off_vf;
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
@@ -976,30 +988,37 @@ struct SolveLayout {
   size_t total;
 };
 
-static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, int aa) {
+// off: [P + 1] offsets of the problems' orbit vectors; shared: every problem
+// has the orbits of rows 0..off[1]-1 of A (equal lengths)
+static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, int aa, bool shared = false) {
   SolveLayout L;
   L.P = P;
   L.C = C;
   L.Cp = (C + kNB - 1) / kNB * kNB;
   L.off.assign(off, off + P + 1);
   L.N = off[P];
+  L.shared = shared;
+  L.PA = shared ? 1 : P;
+  L.aoff.assign(off, off + L.PA + 1);
+  L.NA = L.aoff[L.PA];
   L.Npt = 0;
   for (int b = 0; b < P; ++b) {
     const int64_t nb = off[b + 1] - off[b];
+    L.rps.push_back(nb > 0 ? (nb + kSlabs - 1) / kSlabs : 1);
+    if (b >= L.PA) continue;
     L.xoff.push_back(L.Npt);
     L.xlen.push_back((nb + 63) / 64 * 64);
-    L.rps.push_back(nb > 0 ? (nb + kSlabs - 1) / kSlabs : 1);
     L.Npt += L.xlen.back();
   }
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += a256(bytes); return at; };
   const size_t xe = (size_t)gram_rows(gram_mode, L.Cp) * L.Npt;
-  const size_t N = (size_t)L.N, VP = (size_t)P * L.Cp;
+  const size_t N = (size_t)L.N, VP = (size_t)P * L.Cp, PA = (size_t)L.PA;
   L.off_hi = take(gram_mode == SW_GRAM_F32 ? 0 : xe * 2);
   L.off_lo = take(gram_mode == SW_GRAM_BF16X3 ? xe * 2 : 0);
   L.off_xf = take(gram_mode == SW_GRAM_F32 ? xe * 4 : 0);
-  L.off_K = take((size_t)P * L.Cp * L.Cp * 4);
-  L.off_dinv = take((size_t)P * L.Cp * kNB * 4);
+  L.off_K = take(PA * L.Cp * L.Cp * 4);
+  L.off_dinv = take(PA * L.Cp * kNB * 4);
   L.off_part = take((size_t)P * kSlabs * L.C * 8);
   L.off_qf = take(N * 4); L.off_zf = take(N * 4); L.off_uf = take(N * 4); L.off_vf = take(N * 4);
   L.off_qd = take(N * 8); L.off_xd = take(N * 8); L.off_zd = take(N * 8); L.off_ud = take(N * 8);
@@ -1008,9 +1027,9 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_sc = take(VP * 8); L.off_td = take(VP * 8); L.off_ys = take(VP * 8);
   L.off_par = take((size_t)P * kPar * 8);
   L.off_acc = take((size_t)P * kAcc * 8);
-  L.off_idx = take((size_t)(P + 1) * 8 * 4);
+  L.off_idx = take((size_t)(P + 1) * 8 * 5);
   L.off_bad = take(64);
-  L.off_ftmp = take((size_t)P * inverse_factor_scratch(L.Cp, P) * 4);
+  L.off_ftmp = take(PA * inverse_factor_scratch(L.Cp, L.PA) * 4);
   {
     int64_t nmax = 1;
     for (int b = 0; b < P; ++b) nmax = std::max<int64_t>(nmax, off[b + 1] - off[b]);
@@ -1025,22 +1044,23 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
     L.off_apart = take(aa ? (size_t)P * L.aa_nbx * kAADots * 8 : 0);
   }
   // compressed copies: room for kMaxDensity (or 1M entries), 8-byte values
-  const double dense = (double)L.N * (double)L.C;
+  const double dense = (double)L.NA * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(kMaxDensity * dense), (int64_t)1 << 20);
   if ((double)L.cap_nnz > dense) L.cap_nnz = (int64_t)dense;
   L.ncb = (int)((L.C + kBlk - 1) / kBlk);
   L.nrb = 1;
-  for (int b = 0; b < P; ++b) {
+  for (int b = 0; b < L.PA; ++b) {
     const int64_t spb = slabs_per_block(L.rps[b]);
     L.nrb = std::max<int>(L.nrb, (int)((kSlabs + spb - 1) / spb));
   }
-  L.off_rcnt = take(N * L.ncb * 8);
-  L.off_cpart = take((size_t)P * kSlabs * L.C * 4);
-  L.off_slab = take((size_t)P * kSlabs * L.C * 8);
-  L.off_rptr = take((N * L.ncb + 1) * 8);
+  const size_t NA = (size_t)L.NA;
+  L.off_rcnt = take(NA * L.ncb * 8);
+  L.off_cpart = take(PA * kSlabs * L.C * 4);
+  L.off_slab = take(PA * kSlabs * L.C * 8);
+  L.off_rptr = take((NA * L.ncb + 1) * 8);
   L.off_rcol = take((size_t)L.cap_nnz * 2);
   L.off_rval = take((size_t)L.cap_nnz * 8);
-  L.off_cptr = take((size_t)P * L.nrb * (L.C + 1) * 8);
+  L.off_cptr = take(PA * L.nrb * (L.C + 1) * 8);
   L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
   L.total = o;
@@ -1056,7 +1076,8 @@ struct Ctx {
   const void* A;
   int dtype;
   const double* sigma;
-  const int64_t *off_d, *xoff_d, *xlen_d, *rps_d;
+  int64_t sS;  // sigma of problem b at sigma + b * sS
+  const int64_t *off_d, *xoff_d, *xlen_d, *rps_d, *aoff_d;
   double* par;
   template <typename T> T* p(size_t o) const { return reinterpret_cast<T*>(ws + o); }
 };
@@ -1074,26 +1095,26 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
     if (X.dtype == SW_F32)
       hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d, X.rps_d,
                          X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
-                         X.par, X.p<double>(X.L.off_part));
+                         X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
     else
       hipLaunchKernelGGL((k_csc_colsum<double, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d,
                          X.rps_d, X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow),
-                         X.p<double>(X.L.off_cval), v, X.par, X.p<double>(X.L.off_part));
+                         X.p<double>(X.L.off_cval), v, X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
     return hipGetLastError();
   }
   dim3 grid((unsigned)((X.L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)X.L.P);
   if (X.dtype == SW_F32)
     hipLaunchKernelGGL((k_colsum<float, TV>), grid, dim3(kColThreads), 0, X.st, (const float*)X.A, X.L.C, v, X.off_d,
-                       X.rps_d, X.par, X.p<double>(X.L.off_part));
+                       X.rps_d, X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
   else
     hipLaunchKernelGGL((k_colsum<double, TV>), grid, dim3(kColThreads), 0, X.st, (const double*)X.A, X.L.C, v,
-                       X.off_d, X.rps_d, X.par, X.p<double>(X.L.off_part));
+                       X.off_d, X.rps_d, X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
   return hipGetLastError();
 }
 
 static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
   hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
-                     X.p<double>(X.L.off_part), X.sparse ? 1 : kSlabs, X.L.C, X.L.Cp, X.sigma, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
+                     X.p<double>(X.L.off_part), X.sparse ? 1 : kSlabs, X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
                      outd, acc);
   return hipGetLastError();
 }
@@ -1112,7 +1133,7 @@ static void launch_rowdot(const Ctx& X, const RowArgs& R) {
     // rows with short segments (mean below 512 entries per column block) are
     // taken by 16 lanes each, four rows per wave
     const dim3 grid((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P);
-    const bool short_rows = g_sparse_lanes > 0 ? g_sparse_lanes == 16 : X.nnz < 512 * X.L.N * X.L.ncb;
+    const bool short_rows = g_sparse_lanes > 0 ? g_sparse_lanes == 16 : X.nnz < 512 * X.L.NA * X.L.ncb;
     if (short_rows)
       hipLaunchKernelGGL((k_rowdot_csr<TA, 16>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
     else
@@ -1137,18 +1158,19 @@ static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
 template <typename TA>
 static int build_sparse(Ctx& X) {
   const SolveLayout& L = X.L;
-  const int P = L.P, ncb = L.ncb, nrb = L.nrb;
+  const int P = L.PA, ncb = L.ncb, nrb = L.nrb;  // the distinct matrices
+  const int64_t NA = L.NA;
   const TA* A = (const TA*)X.A;
   X.sparse = false;
   for (int b = 0; b < P; ++b)
     if (L.rps[b] > kBlk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
   int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
   int32_t* cpart = X.p<int32_t>(L.off_cpart);
-  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, ncb, rcnt);
+  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, rcnt);
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
-                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, cpart);
+                     dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
-  std::vector<int64_t> hr((size_t)L.N * ncb);
+  std::vector<int64_t> hr((size_t)NA * ncb);
   std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
   SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
@@ -1156,7 +1178,7 @@ static int build_sparse(Ctx& X) {
   // segments are padded to whole quads (4 entries)
   auto quad = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
   int64_t nnz = 0, at = 0;
-  std::vector<int64_t> rptr((size_t)L.N * ncb + 1);
+  std::vector<int64_t> rptr((size_t)NA * ncb + 1);
   for (size_t k = 0; k < hr.size(); ++k) {
     rptr[k] = at;
     nnz += hr[k];
@@ -1165,7 +1187,7 @@ static int build_sparse(Ctx& X) {
   rptr[hr.size()] = at;
   // a compressed entry costs 6 bytes per pass against 4 (fp32) dense: the
   // compressed passes pay off well below 2/3 density; copies are kept up to kMaxDensity
-  if (at > L.cap_nnz || (double)nnz > kMaxDensity * (double)L.N * (double)L.C) return SW_OK;
+  if (at > L.cap_nnz || (double)nnz > kMaxDensity * (double)NA * (double)L.C) return SW_OK;
   // columns: segment (b, rb, c) = the slabs of row block rb; slab_at[b][s][c]
   // = absolute position of slab s's first entry of column c
   std::vector<int64_t> cptr((size_t)P * nrb * (L.C + 1), 0), slab_at((size_t)P * kSlabs * L.C);
@@ -1192,14 +1214,14 @@ static int build_sparse(Ctx& X) {
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_rptr), rptr.data(), rptr.size() * 8, hipMemcpyHostToDevice, X.st));
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cptr), cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, X.st));
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_slab), slab_at.data(), slab_at.size() * 8, hipMemcpyHostToDevice, X.st));
-  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((L.N + 3) / 4)), dim3(256), 0, X.st, A, L.N, L.C, ncb,
+  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb,
                      X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
   // column padding: clear the compressed columns, then fill the entries
   const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words, 0);
   hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
-                     dim3(kColThreads), 0, X.st, A, L.C, X.off_d, X.rps_d, X.p<int64_t>(L.off_slab),
+                     dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab),
                      X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
   SW_HIP(hipGetLastError());
   // the host vectors must outlive the copies
@@ -1212,7 +1234,7 @@ static int build_sparse(Ctx& X) {
 template <typename TS>
 static hipError_t colscale(const Ctx& X, const TS* s) {
   hipLaunchKernelGGL(k_colscale<TS>, dim3(blocks_for(X.L.C), (unsigned)X.L.P), dim3(256), 0, X.st, s, X.L.C, X.L.Cp,
-                     X.sigma, X.par, X.p<double>(X.L.off_sc));
+                     X.sigma, X.sS, X.par, X.p<double>(X.L.off_sc));
   return hipGetLastError();
 }
 
@@ -1251,13 +1273,17 @@ extern "C" size_t chi2_workspace_bytes(int64_t n_con) {
   return a256((size_t)kSlabs * n_con * 8) + a256((size_t)n_con * 8) + 256;
 }
 
-extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_prob, const int64_t* orbit_offsets,
-                                     int64_t n_con, const double* d, const double* sigma, const double* w_tilde,
-                                     double lambda, const sw_solve_opts* opt, double* w, sw_solve_report* rep,
-                                     void* workspace, size_t ws_bytes, void* stream) {
+// The solver behind every entry point: n_prob problems whose orbit vectors are
+// [orbit_offsets[b], orbit_offsets[b+1]); shared = every problem's matrix is rows
+// 0..orbit_offsets[1]-1 of A (one Gram and one factorisation, per-problem data).
+static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_t* orbit_offsets, bool shared,
+                      int64_t n_con, const double* d, const double* sigma, const double* w_tilde, double lambda,
+                      const sw_solve_opts* opt, double* w, sw_solve_report* rep, void* workspace, size_t ws_bytes,
+                      void* stream) {
   SW_CHECK(opt && orbit_offsets && w_tilde, "solve_weights: null argument");
   SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "solve_weights: dtype must be SW_F32 or SW_F64");
   SW_CHECK(n_prob >= 1 && n_con > 0, "solve_weights: need n_prob >= 1 and n_con > 0");
+  SW_CHECK(n_prob <= 65535, "solve_weights: at most 65535 problems per call");
   SW_CHECK(orbit_offsets[0] == 0, "solve_weights: orbit_offsets[0] must be 0");
   for (int b = 0; b < n_prob; ++b) {
     SW_CHECK(orbit_offsets[b + 1] > orbit_offsets[b], "solve_weights: every problem needs at least one orbit");
@@ -1270,14 +1296,14 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
            "solve_weights: unknown gram mode %d", opt->gram);
   SW_CHECK(A && d && sigma && w, "solve_weights: null device buffer");
   SW_CHECK(workspace, "solve_weights: null workspace");
-  const size_t need = solve_batched_workspace_bytes(n_prob, orbit_offsets, n_con, opt);
+  // Anderson-accelerated FP64 stage unless switched off; the FP32 stage then
+  // runs only when asked for (max_iter > 0)
+  const int aa = (opt->flags & SW_SOLVE_NO_ACCEL) ? 0 : kAAMem;
+  const size_t need = layout(n_prob, orbit_offsets, n_con, opt->gram, aa, shared).total;
   if (ws_bytes < need) {
     set_error("solve_weights: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SW_ENOMEM;
   }
-  // Anderson-accelerated FP64 stage unless switched off; the FP32 stage then
-  // runs only when asked for (max_iter > 0)
-  const int aa = (opt->flags & SW_SOLVE_NO_ACCEL) ? 0 : kAAMem;
   const int max_iter = opt->max_iter > 0 ? opt->max_iter : (aa ? 0 : 1000);
   const int refine_iter = opt->refine_iter < 0 ? 0 : (opt->refine_iter == 0 ? 2000 : opt->refine_iter);
   const int check_every = opt->check_every > 0 ? opt->check_every : 10;
@@ -1286,19 +1312,22 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   const int P = n_prob;
 
   Ctx X;
-  X.L = layout(P, orbit_offsets, n_con, opt->gram, aa);
+  X.L = layout(P, orbit_offsets, n_con, opt->gram, aa, shared);
   const SolveLayout& L = X.L;
+  const int PA = L.PA;
   X.ws = (char*)workspace;
   X.st = (hipStream_t)stream;
   X.A = A;
   X.dtype = dtype;
   X.sigma = sigma;
+  X.sS = shared ? 0 : n_con;
   X.par = X.p<double>(L.off_par);
   int64_t* idx = X.p<int64_t>(L.off_idx);
   X.off_d = idx;
   X.xoff_d = idx + (P + 1);
   X.xlen_d = idx + 2 * (P + 1);
   X.rps_d = idx + 3 * (P + 1);
+  X.aoff_d = idx + 4 * (P + 1);
   const uint8_t* mask = opt->mask;
 
   // stage boundaries are timed with HIP events on the solve's stream
@@ -1310,14 +1339,15 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   } ev_guard{ev};
 
   // ---- index arrays and per-problem scalars ----
-  std::vector<int64_t> hidx(4 * (P + 1), 0);
+  std::vector<int64_t> hidx(5 * (P + 1), 0);
   for (int b = 0; b <= P; ++b) hidx[b] = L.off[b];
-  for (int b = 0; b < P; ++b) {
-    hidx[(P + 1) + b] = L.xoff[b];
-    hidx[2 * (P + 1) + b] = L.xlen[b];
-    hidx[3 * (P + 1) + b] = L.rps[b];
+  for (int b = 0; b < P; ++b) hidx[3 * (P + 1) + b] = L.rps[b];
+  for (int a = 0; a < PA; ++a) {  // the Gram operand: one block of columns per matrix
+    hidx[(P + 1) + a] = L.xoff[a];
+    hidx[2 * (P + 1) + a] = L.xlen[a];
   }
-  hidx[(P + 1) + P] = L.Npt;
+  hidx[(P + 1) + PA] = L.Npt;
+  for (int a = 0; a <= PA; ++a) hidx[4 * (P + 1) + a] = L.aoff[a];
   std::vector<double> hpar((size_t)P * kPar, 0.0);
   for (int b = 0; b < P; ++b) {
     hpar[b * kPar + 0] = w_tilde[b];
@@ -1329,17 +1359,17 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   SW_TRY(hipEventRecord(ev[0], X.st));
 
   // ---- scaled data and the transposed operand of the Gram ----
-  hipLaunchKernelGGL(k_scaled_data, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, d, sigma, L.C, L.Cp,
-                     X.p<double>(L.off_ys));
+  hipLaunchKernelGGL(k_scaled_data, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, d, sigma, X.sS, L.C,
+                     L.Cp, X.p<double>(L.off_ys));
   {
     dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
     if (dtype == SW_F32)
-      hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.off_d, X.xoff_d, P,
-                         sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
+      hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d, X.xoff_d,
+                         PA, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
                          X.p<float>(L.off_xf));
     else
-      hipLaunchKernelGGL(k_prep_x<double>, grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt, X.off_d, X.xoff_d,
-                         P, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
+      hipLaunchKernelGGL(k_prep_x<double>, grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt, X.aoff_d,
+                         X.xoff_d, PA, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
                          X.p<float>(L.off_xf));
     SW_TRY(hipGetLastError());
   }
@@ -1352,32 +1382,34 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   // ---- Gram K_b = U_b U_b^T (lower tiles) ----
   float* K = X.p<float>(L.off_K);
   const int64_t sK = L.Cp * L.Cp;
+  const int64_t sKi = shared ? 0 : sK;  // the inverse applied for problem b
   SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
-              L.xoff.data(), L.xlen.data(), P, K, L.Cp, sK, X.st));
+              L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st));
   SW_TRY(hipEventRecord(ev[2], X.st));
   double* acc = X.p<double>(L.off_acc);
   SW_TRY(zero_acc(X));
   double* trace_d = X.p<double>(L.off_td);  // borrowed scratch
-  hipLaunchKernelGGL(k_trace, dim3((unsigned)P), dim3(256), 0, X.st, K, L.Cp, sK, L.C, trace_d);
-  std::vector<double> trace(P);
-  SW_TRY(hipMemcpyAsync(trace.data(), trace_d, P * 8, hipMemcpyDeviceToHost, X.st));
+  hipLaunchKernelGGL(k_trace, dim3((unsigned)PA), dim3(256), 0, X.st, K, L.Cp, sK, L.C, trace_d);
+  std::vector<double> trace(PA);
+  SW_TRY(hipMemcpyAsync(trace.data(), trace_d, PA * 8, hipMemcpyDeviceToHost, X.st));
   std::vector<uint8_t> hmask;
   if (mask) {
-    hmask.resize(L.N);
-    SW_TRY(hipMemcpyAsync(hmask.data(), mask, L.N, hipMemcpyDeviceToHost, X.st));
+    hmask.resize(L.NA);
+    SW_TRY(hipMemcpyAsync(hmask.data(), mask, L.NA, hipMemcpyDeviceToHost, X.st));
   }
   SW_TRY(hipStreamSynchronize(X.st));
 
   // ---- regularisation and penalty per problem ----
   std::vector<double> mu(P), rho(P);
   for (int b = 0; b < P; ++b) {
-    int64_t n_eff = L.off[b + 1] - L.off[b];
+    const int ab = shared ? 0 : b;  // the matrix of problem b
+    int64_t n_eff = L.aoff[ab + 1] - L.aoff[ab];
     if (mask) {
       n_eff = 0;
-      for (int64_t i = L.off[b]; i < L.off[b + 1]; ++i) n_eff += hmask[i] ? 0 : 1;
+      for (int64_t i = L.aoff[ab]; i < L.aoff[ab + 1]; ++i) n_eff += hmask[i] ? 0 : 1;
     }
     if (n_eff == 0) n_eff = 1;
-    const double mean_col = trace[b] / (double)n_eff;
+    const double mean_col = trace[ab] / (double)n_eff;
     mu[b] = lambda >= 0.0 ? 2.0 * lambda / (double)n_eff : opt->nu * mean_col;
     const double base = mean_col > 0.0 ? mean_col : 1.0;
     rho[b] = opt->rho > 0.0 ? opt->rho : (opt->rho < 0.0 ? -opt->rho * base : base);
@@ -1389,11 +1421,11 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
 
   // ---- factorise rho' I + K_b ----
   SW_TRY(hipEventRecord(ev[3], X.st));
-  hipLaunchKernelGGL(k_add_diag, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, K, L.Cp, sK, L.Cp, X.par);
+  hipLaunchKernelGGL(k_add_diag, dim3(blocks_for(L.Cp), (unsigned)PA), dim3(256), 0, X.st, K, L.Cp, sK, L.Cp, X.par);
   int* bad = X.p<int>(L.off_bad);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, X.st, bad, (int64_t)1, 0);
-  SW_TRY(spd_inverse_factor(K, L.Cp, L.Cp, sK, X.p<float>(L.off_dinv), L.Cp * kNB, P, X.p<float>(L.off_ftmp),
-                            inverse_factor_scratch(L.Cp, P), bad, X.st));
+  SW_TRY(spd_inverse_factor(K, L.Cp, L.Cp, sK, X.p<float>(L.off_dinv), L.Cp * kNB, PA, X.p<float>(L.off_ftmp),
+                            inverse_factor_scratch(L.Cp, PA), bad, X.st));
   SW_TRY(hipEventRecord(ev[4], X.st));
   int hbad = 0;
   SW_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, X.st));
@@ -1414,6 +1446,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
   RowArgs RA;
   std::memset(&RA, 0, sizeof RA);
   RA.nprob = P;
+  RA.shared = shared ? 1 : 0;
   RA.Cp = L.Cp;
   RA.off = X.off_d;
   RA.par = X.par;
@@ -1449,7 +1482,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     hipError_t e;
     if ((e = colsum<float>(X, vf)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = inv_apply(K, L.Cp, L.Cp, sK, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
+    if ((e = inv_apply(K, L.Cp, L.Cp, sKi, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Ri = RA;
     Ri.op = ROW_ADMM;
@@ -1582,7 +1615,7 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
     if ((e = colsum<double>(X, rd)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = inv_apply(K, L.Cp, L.Cp, sK, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
+    if ((e = inv_apply(K, L.Cp, L.Cp, sKi, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Rc = RA;
     Rc.op = ROW_CORR;
@@ -1660,6 +1693,39 @@ extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_pro
     return SW_ENOTCONV;
   }
   return SW_OK;
+}
+
+extern "C" int solve_weights_batched(const void* A, int32_t dtype, int32_t n_prob, const int64_t* orbit_offsets,
+                                     int64_t n_con, const double* d, const double* sigma, const double* w_tilde,
+                                     double lambda, const sw_solve_opts* opt, double* w, sw_solve_report* rep,
+                                     void* workspace, size_t ws_bytes, void* stream) {
+  return solve_core(A, dtype, n_prob, orbit_offsets, false, n_con, d, sigma, w_tilde, lambda, opt, w, rep, workspace,
+                    ws_bytes, stream);
+}
+
+static std::vector<int64_t> rhs_offsets(int32_t n_rhs, int64_t n_orb) {
+  std::vector<int64_t> off((size_t)n_rhs + 1);
+  for (int32_t b = 0; b <= n_rhs; ++b) off[b] = (int64_t)b * n_orb;
+  return off;
+}
+
+extern "C" size_t solve_multi_workspace_bytes(int64_t n_orb, int64_t n_con, int32_t n_rhs, const sw_solve_opts* opt) {
+  if (n_orb <= 0 || n_con <= 0 || n_rhs < 1) return 0;
+  const int mode = opt ? opt->gram : SW_GRAM_BF16X3;
+  const int aa = opt && (opt->flags & SW_SOLVE_NO_ACCEL) ? 0 : kAAMem;
+  return layout(n_rhs, rhs_offsets(n_rhs, n_orb).data(), n_con, mode, aa, true).total;
+}
+
+extern "C" int solve_weights_multi(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int32_t n_rhs,
+                                   const double* d, const double* sigma, double w_tilde, double lambda,
+                                   const sw_solve_opts* opt, double* w, sw_solve_report* rep, void* workspace,
+                                   size_t ws_bytes, void* stream) {
+  SW_CHECK(n_orb > 0, "solve_weights_multi: need n_orb > 0");
+  SW_CHECK(n_rhs >= 1, "solve_weights_multi: need n_rhs >= 1");
+  const std::vector<int64_t> off = rhs_offsets(n_rhs, n_orb);
+  const std::vector<double> wt((size_t)n_rhs, w_tilde);
+  return solve_core(A, dtype, n_rhs, off.data(), true, n_con, d, sigma, wt.data(), lambda, opt, w, rep, workspace,
+                    ws_bytes, stream);
 }
 
 extern "C" int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,

@@ -152,6 +152,11 @@ def noise_draw(n, seed):
     return np.random.default_rng(seed + 1000).normal(size=n)
 
 
+def bootstrap_eps(n_rhs, n_con, seed=9):
+    """Standard normal deviates [n_rhs][n_con] for the bootstrap realisations of the data."""
+    return np.random.default_rng(seed + 2000).normal(size=(n_rhs, n_con))
+
+
 def subsample_draw(n_orb, n, seed):
     return np.sort(np.random.default_rng(seed).choice(n_orb, size=n, replace=False))
 
