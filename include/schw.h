@@ -364,6 +364,11 @@ int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64
  *   "sparse_cols_per_wg"      constraints per column-sum workgroup (same range)
  *   "sparse_lanes_per_row"    lanes that share one row in the row dots (0:
  *                             automatic from the mean row length, 16 or 64)
+ *   "rhs_per_group"           solve_weights_multi: data vectors that one
+ *                             workgroup of a compressed pass takes at once
+ *                             (0: automatic = up to 4; 1, 2, 4 or 8; it sets
+ *                             the block sizes of the compressed copies, so
+ *                             query solve_multi_workspace_bytes after it)
  * sw_get_tuning returns the current value (-1 for an unknown key).           */
 int sw_set_tuning(const char* key, int32_t value);
 int32_t sw_get_tuning(const char* key);

@@ -61,9 +61,11 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 //  g_sparse_rows   orbits per row-dot workgroup
 //  g_sparse_cols   constraints per column-sum workgroup
 //  g_sparse_lanes  lanes per row in the row dots (16 or 64)
+//  g_rhs_group     right-hand sides of one shared matrix per workgroup (1, 2, 4, 8)
 extern int g_sparse_rows;
 extern int g_sparse_cols;
 extern int g_sparse_lanes;
+extern int g_rhs_group;
 
 }  // namespace sw
 

@@ -49,4 +49,12 @@ hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb, const float* r, float* tmp, float* s,
                      int64_t sv, const double* act, int act_stride, hipStream_t st);
 
+// The same for P right-hand sides of one S (r, tmp, s: [P] vectors at stride
+// sv): from kTrmmMinRhs of them on, two MFMA passes that read each half of S
+// once for all of them (every right-hand side is computed, act is not read);
+// below that, one matrix-vector pass per right-hand side.
+constexpr int kTrmmMinRhs = 8;
+hipError_t inv_apply_rhs(const float* S, int64_t n, int64_t ld, int P, const float* r, float* tmp, float* s,
+                         int64_t sv, const double* act, int act_stride, hipStream_t st);
+
 }  // namespace sw

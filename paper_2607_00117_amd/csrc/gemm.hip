@@ -557,6 +557,99 @@ __global__ __launch_bounds__(kThreads) void k_trmv(const float* __restrict__ S, 
 }
 
 // ---------------------------------------------------------------------------
+// Many right-hand sides against one S: Y[b][i] = sum_j T[i][j] X[b][j] for
+// b < P, T = the lower (j <= i) or upper (j >= i) half of S, as an fp32 MFMA
+// product.  A workgroup owns a pair of 128-row tiles of T, tm and ntm-1-tm, so
+// every workgroup streams the same number of entries (the two halves of the
+// triangle it covers add up to ntm + 1 tiles of 128 columns), and an RHS tile of
+// 128 (blockIdx.y).  Entries of the diagonal tiles outside the half are zeroed as
+// they are staged.  4 waves as 2 x 2 blocks of 64 x 64 (MFMA 32x32x2 f32).
+// ---------------------------------------------------------------------------
+template <bool LOWER>
+__global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__ S, int64_t n, int64_t ld,
+                                                       const float* __restrict__ X, float* __restrict__ Y,
+                                                       int64_t sv, int P) {
+  __shared__ float Ts[kT][kPadF];
+  __shared__ float Xs[kT][kPadF];
+  const int64_t ntm = n / kT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t b0 = (int64_t)blockIdx.y * kT;
+  for (int half = 0; half < 2; ++half) {
+    const int64_t tm = half == 0 ? (int64_t)blockIdx.x : ntm - 1 - (int64_t)blockIdx.x;
+    if (half == 1 && tm == (int64_t)blockIdx.x) break;  // odd tile count: the middle tile has no partner
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[a][c][i] = 0.0f;
+    const int64_t kbeg = LOWER ? 0 : tm * kT, kend = LOWER ? (tm + 1) * kT : n;
+    const float* Tb = S + tm * kT * ld;
+    float4 ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int idx = tid + kThreads * i;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        ra[i] = *reinterpret_cast<const float4*>(Tb + (int64_t)r * ld + k0 + c);
+        rb[i] = b0 + r < P ? *reinterpret_cast<const float4*>(X + (b0 + r) * sv + k0 + c)
+                           : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    };
+    gload(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kBKf) {
+      const bool diag = k0 >= tm * kT && k0 < (tm + 1) * kT;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int idx = tid + kThreads * i;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        float t[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+        if (diag) {
+          const int64_t row = tm * kT + r;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t col = k0 + c + q;
+            if (LOWER ? col > row : col < row) t[q] = 0.0f;
+          }
+        }
+        Ts[r][c] = t[0]; Ts[r][c + 1] = t[1]; Ts[r][c + 2] = t[2]; Ts[r][c + 3] = t[3];
+        Xs[r][c] = rb[i].x; Xs[r][c + 1] = rb[i].y; Xs[r][c + 2] = rb[i].z; Xs[r][c + 3] = rb[i].w;
+      }
+      __syncthreads();
+      if (k0 + kBKf < kend) gload(k0 + kBKf);
+#pragma unroll
+      for (int kk = 0; kk < kBKf; kk += 2) {
+        const int kc = kk + (lane >> 5);
+        float am[2], bn[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          am[a] = Ts[wm * 64 + a * 32 + (lane & 31)][kc];
+          bn[a] = Xs[wn * 64 + a * 32 + (lane & 31)][kc];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(am[a], bn[c], acc[a][c], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int64_t row = tm * kT + wm * 64 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+          const int64_t b = b0 + wn * 64 + c * 32 + (lane & 31);
+          if (b < P) Y[b * sv + row] = acc[a][c][i];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
@@ -767,6 +860,15 @@ hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float
   hipError_t e = cholesky(S, n, ld, sK, dinv, sD, nb, st, bad);
   if (e != hipSuccess) return e;
   return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, st);
+}
+
+hipError_t inv_apply_rhs(const float* S, int64_t n, int64_t ld, int P, const float* r, float* tmp, float* s,
+                         int64_t sv, const double* act, int act_stride, hipStream_t st) {
+  if (P < kTrmmMinRhs) return inv_apply(S, n, ld, 0, P, r, tmp, s, sv, act, act_stride, st);
+  const dim3 grid((unsigned)((n / kT + 1) / 2), (unsigned)((P + kT - 1) / kT));
+  hipLaunchKernelGGL(k_trmm_rhs<true>, grid, dim3(kThreads), 0, st, S, n, ld, r, tmp, sv, P);
+  hipLaunchKernelGGL(k_trmm_rhs<false>, grid, dim3(kThreads), 0, st, S, n, ld, tmp, s, sv, P);
+  return hipGetLastError();
 }
 
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,

@@ -131,6 +131,12 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_sparse_lanes = value;
     return SW_OK;
   }
+  if (k == "rhs_per_group") {
+    SW_CHECK(value == 0 || value == 1 || value == 2 || value == 4 || value == 8,
+             "sw_set_tuning: rhs_per_group: 0 (automatic), 1, 2, 4 or 8");
+    g_rhs_group = value;
+    return SW_OK;
+  }
   SW_CHECK(false, "sw_set_tuning: unknown key %s", key);
 }
 
@@ -143,6 +149,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "sparse_rows_per_wg") return g_sparse_rows;
   if (k == "sparse_cols_per_wg") return g_sparse_cols;
   if (k == "sparse_lanes_per_row") return g_sparse_lanes;
+  if (k == "rhs_per_group") return g_rhs_group;
   return -1;
 }
 

@@ -57,6 +57,7 @@ constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChe
 int g_sparse_rows = 0;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
+int g_rhs_group = 0;
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -173,24 +174,32 @@ constexpr int kBlk = 16384;       // gathered entries staged in LDS (fp64: 128 K
 constexpr int kSpThreads = 1024;  // workgroup of the blocked passes (16 waves)
 constexpr int kSpWaves = kSpThreads / 64;
 constexpr int kMaxRowsWG = 512;   // blocked passes: at most 512 rows (row dots) or columns per workgroup
+constexpr int kRhsGroup = 4;      // right-hand sides per workgroup in the passes of a shared matrix (at most 8)
+constexpr int kRhsItems = 1024;   // rows (row dots) or columns (column sums) per workgroup of those passes
+// Block of those passes: R interleaved values per index at a stride of R + 1
+// doubles (an odd stride spreads the random gathers over the LDS banks; at a
+// stride of R = 8 doubles every lane's first 16 bytes would fall in one of
+// two bank groups), sized to about 150 KB of LDS
+__host__ __device__ constexpr int64_t rhs_blk(int R) { return R <= 2 ? 6400 : (R <= 4 ? 3840 : 2048); }
 
-// orbit rows per column-block segment: slabs of rps rows, whole slabs per block
-__host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps) {
-  return rps >= kBlk ? 1 : kBlk / rps;
+// orbit rows per column-block segment: slabs of rps rows, whole slabs per
+// block of blk rows (kBlk, or rhs_blk(R) when R right-hand sides share the LDS)
+__host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps, int64_t blk = kBlk) {
+  return rps >= blk ? 1 : blk / rps;
 }
 
 // cnt[i][cb] = nonzeros of row i in column block cb (one wave per row)
 template <typename TA>
-__global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C, int ncb,
+__global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C, int ncb, int64_t blk,
                                                  int64_t* __restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const TA* row = A + i * C;
   for (int cb = 0; cb < ncb; ++cb) {
-    const int64_t c1 = (int64_t)(cb + 1) * kBlk < C ? (int64_t)(cb + 1) * kBlk : C;
+    const int64_t c1 = (int64_t)(cb + 1) * blk < C ? (int64_t)(cb + 1) * blk : C;
     int64_t k = 0;
-    for (int64_t c = (int64_t)cb * kBlk + lane; c < c1; c += 64) k += row[c] != TA(0);
+    for (int64_t c = (int64_t)cb * blk + lane; c < c1; c += 64) k += row[c] != TA(0);
     for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
     if (lane == 0) cnt[i * ncb + cb] = k;
   }
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(kColThreads) void k_col_nnz(const TA* __restrict__ 
 // compressed rows: one wave per orbit; ballot + prefix count keeps column
 // order; each segment's padding is written as zero entries
 template <typename TA>
-__global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C, int ncb,
+__global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C, int ncb, int64_t blk,
                                                   const int64_t* __restrict__ ptr, uint16_t* __restrict__ col,
                                                   TA* __restrict__ val) {
   const int lane = threadIdx.x & 63;
@@ -232,8 +241,8 @@ __global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int6
   if (i >= N) return;
   const TA* row = A + i * C;
   for (int cb = 0; cb < ncb; ++cb) {
-    const int64_t cbeg = (int64_t)cb * kBlk;
-    const int64_t c1 = cbeg + kBlk < C ? cbeg + kBlk : C;
+    const int64_t cbeg = (int64_t)cb * blk;
+    const int64_t c1 = cbeg + blk < C ? cbeg + blk : C;
     int64_t pos = ptr[i * ncb + cb];
     for (int64_t c0 = cbeg; c0 < c1; c0 += 64) {
       const int64_t c = c0 + lane;
@@ -259,7 +268,7 @@ template <typename TA>
 __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__ A, int64_t C,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ rps,
-                                                          const int64_t* __restrict__ slab_at,
+                                                          const int64_t* __restrict__ slab_at, int64_t blk,
                                                           uint16_t* __restrict__ rowi, TA* __restrict__ val) {
   const int b = blockIdx.z;
   const int64_t c0 = (int64_t)blockIdx.x * kColTile, s = blockIdx.y;
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__
   int64_t i_end = i_beg + rps[b];
   if (i_end > off[b + 1]) i_end = off[b + 1];
   // first orbit of this slab's row block
-  const int64_t spb = slabs_per_block(rps[b]);
+  const int64_t spb = slabs_per_block(rps[b], blk);
   const int64_t blk0 = off[b] + (s / spb) * spb * rps[b];
   int64_t pos[kColsPerThread];
 #pragma unroll
@@ -358,6 +367,157 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Sums R values over an aligned group of LPR lanes (R <= LPR, powers of 2) as
+// a reduce-scatter: each halving step trades half of the values with the
+// partner lane, so it takes R - 1 + log2(LPR / R) exchanges instead of
+// R log2(LPR).  Returns the group total of value `which` (set here); the lanes
+// with sl % (LPR / R) == 0 hold the R totals between them.
+template <int LPR, int R>
+__device__ __forceinline__ double group_scatter_sum(double (&a)[R], int sl, int& which) {
+  which = 0;
+  int m = LPR / 2;
+#pragma unroll
+  for (int lev = 0; (R >> lev) > 1; ++lev) {
+    const int half = R >> (lev + 1);
+    const bool up = (sl & m) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const double send = up ? a[j] : a[j + half];
+      const double keep = up ? a[j + half] : a[j];
+      a[j] = keep + __shfl_xor(send, m, 64);
+    }
+    if (up) which += half;
+    m >>= 1;
+  }
+  double v = a[0];
+  for (; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// The segments of one group of LPR lanes, items p = 0 .. n_pass-1 (rows or
+// columns), each dotted with R interleaved right-hand sides in LDS:
+// acc[r] = sum_k val[k] xs[idx[k] (R + 1) + r] over [beg_p, end_p) (a
+// multiple of 4), lane-strided quads.  Segments are short (a few quads per
+// lane), so a lane loads the first Q quads of an item at once, and the loads
+// of item p + 1 (and the pointers of item p + 2) are issued before item p is
+// summed.  Every load is issued unconditionally (an index past the segment
+// reads entry 0 and the quad is weighted by zero): vector-memory counters
+// complete in order, and a load skipped on some paths would make the compiler
+// wait for the prefetches as well.
+//   seg(p, beg, end): bounds of item p (beg = end past the group's items);
+//   out(p, which, total) receives the group total of right-hand side `which`
+//   (lanes sl % (LPR/R) == 0).
+// xs[j (R + 1) + r] = src_r[j] for j < len (src_r = base + off_r, r < R; rows
+// of right-hand sides past P read as 0).  All of a thread's loads are issued
+// before the first store (clamped addresses, no branches), so the staging
+// costs one memory latency rather than one per value.
+template <int R, int64_t BLK, typename TV>
+__device__ __forceinline__ void rhs_stage(double* xs, const TV* __restrict__ base, const int64_t* roff, int P, int b0,
+                                          int len) {
+  constexpr int JT = (int)((BLK + kSpThreads - 1) / kSpThreads);
+  double t[JT][R];
+#pragma unroll
+  for (int jj = 0; jj < JT; ++jj) {
+    const int j = (int)threadIdx.x + jj * kSpThreads;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = j < len && b0 + r < P;
+      t[jj][r] = (double)base[ok ? roff[r] + j : 0];
+      if (!ok) t[jj][r] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < JT; ++jj) {
+    const int j = (int)threadIdx.x + jj * kSpThreads;
+    if (j < len)
+#pragma unroll
+      for (int r = 0; r < R; ++r) xs[j * (R + 1) + r] = t[jj][r];
+  }
+}
+
+template <int LPR, int R, int Q, typename TA>
+struct RhsChunk {
+  TA v[Q][4];
+  uint16_t c[Q][4];
+  bool ok[Q];
+};
+
+template <int LPR, int R, int Q, typename TA>
+__device__ __forceinline__ void rhs_load(const TA* __restrict__ val, const uint16_t* __restrict__ idx, int64_t base,
+                                         int64_t end, int sl, RhsChunk<LPR, R, Q, TA>& ch) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t k = base + 4 * sl + (int64_t)i * 4 * LPR;
+    ch.ok[i] = k < end;
+    const int64_t kk = ch.ok[i] ? k : 0;
+    if constexpr (sizeof(TA) == 4) {
+      const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(val + kk));
+      ch.v[i][0] = q[0]; ch.v[i][1] = q[1]; ch.v[i][2] = q[2]; ch.v[i][3] = q[3];
+    } else {
+      const f64x2 q0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(val + kk));
+      const f64x2 q1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(val + kk + 2));
+      ch.v[i][0] = q0[0]; ch.v[i][1] = q0[1]; ch.v[i][2] = q1[0]; ch.v[i][3] = q1[1];
+    }
+    const u16x4 c = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(idx + kk));
+    ch.c[i][0] = c[0]; ch.c[i][1] = c[1]; ch.c[i][2] = c[2]; ch.c[i][3] = c[3];
+  }
+}
+
+template <int LPR, int R, int Q, typename TA>
+__device__ __forceinline__ void rhs_use(const RhsChunk<LPR, R, Q, TA>& ch, const double* xs, double acc[R]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double w = ch.ok[i] ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double v = w * (double)ch.v[i][q];
+      const double* x = xs + (uint32_t)ch.c[i][q] * (R + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += v * x[r];
+    }
+  }
+}
+
+template <int LPR, int R, typename TA, typename SegF, typename OutF>
+__device__ __forceinline__ void seg_stream_rhs(const TA* __restrict__ val, const uint16_t* __restrict__ idx,
+                                               const double* xs, int sl, int n_pass, SegF seg, OutF out) {
+  constexpr int Q = sizeof(TA) == 4 ? 4 : 2;  // quads per lane loaded at once
+  constexpr int64_t CH = (int64_t)Q * 4 * LPR;  // entries of the group per chunk
+  int64_t b0, e0, b1, e1;
+  seg(0, b0, e0);
+  seg(1, b1, e1);
+  // two chunk buffers in alternating roles (no register copies, which would
+  // have to wait for the prefetched loads)
+  RhsChunk<LPR, R, Q, TA> ca, cb;
+  rhs_load(val, idx, b0, e0, sl, ca);
+  auto step = [&](RhsChunk<LPR, R, Q, TA>& use, RhsChunk<LPR, R, Q, TA>& fill, int p) {
+    int64_t b2, e2;
+    seg(p + 2, b2, e2);
+    rhs_load(val, idx, b1, e1, sl, fill);
+    // keep the prefetch ahead of the arithmetic (the scheduler would otherwise sink the loads below it)
+    __builtin_amdgcn_sched_barrier(0);
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    rhs_use(use, xs, acc);
+    for (int64_t base = b0 + CH; base < e0; base += CH) {  // items longer than one chunk
+      rhs_load(val, idx, base, e0, sl, use);
+      rhs_use(use, xs, acc);
+    }
+    int which;
+    const double t = group_scatter_sum<LPR, R>(acc, sl, which);
+    out(p, which, t);
+    b0 = b1;
+    e0 = e1;
+    b1 = b2;
+    e1 = e2;
+  };
+  for (int p = 0; p < n_pass; p += 2) {
+    step(ca, cb, p);
+    if (p + 1 < n_pass) step(cb, ca, p + 1);
+  }
+}
+
 // column sums from the compressed columns: workgroup (column group of cpw
 // columns, problem b), column c owned by wave c mod 16, the problem's orbit
 // vector staged block by block in LDS; result in part[b][0][c] (the
@@ -397,6 +557,68 @@ __global__ __launch_bounds__(kSpThreads) void k_csc_colsum(int64_t C, int cpw, c
   }
   for (int q = w; q < nc; q += kSpWaves)
     if (lane == 0) part[(int64_t)b * kSlabs * C + c0 + q] = cacc[q];
+}
+
+// Column sums for R right-hand sides of one shared matrix: workgroup (column
+// chunk, row block rb, right-hand sides g R .. g R + R - 1).  The R orbit
+// vectors of the row block (at most blk = rhs_blk(R) orbits) are staged
+// interleaved once; a group of 16 lanes takes a column segment, so every
+// compressed entry is read once for all R.  Output: the partial sum over the
+// row block, part[b][rb][c]; the reduction adds the nrb partials in order.
+template <typename TA, typename TV, int R>
+__global__ __launch_bounds__(kSpThreads) void k_csc_colsum_rhs(int64_t C, int64_t cpc, int P,
+                                                              const int64_t* __restrict__ off,
+                                                              const int64_t* __restrict__ rps,
+                                                              const int64_t* __restrict__ cptr,
+                                                              const uint16_t* __restrict__ rowi,
+                                                              const TA* __restrict__ val, const TV* __restrict__ v,
+                                                              const double* __restrict__ par,
+                                                              double* __restrict__ part) {
+  constexpr int LPR = 16, G = 64 / LPR, NS = kSpWaves * G;
+  constexpr int64_t blk = rhs_blk(R);
+  __shared__ double xs[blk * (R + 1)];
+  __shared__ int32_t sp[kRhsItems + 1];  // segment bounds relative to the first (from LDS: the
+                                         // pointer reads do not queue behind the data loads)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int sl = lane % LPR, slot = w * G + lane / LPR;
+  const int b0 = blockIdx.z * R;
+  bool any = false;
+  for (int r = 0; r < R; ++r) any |= b0 + r < P && par[(b0 + r) * kPar + 5] != 0.0;
+  if (!any) return;  // every right-hand side of the group has converged
+  const int64_t nb = off[1] - off[0];  // orbits of the shared matrix
+  const int64_t brows = slabs_per_block(rps[0], blk) * rps[0];
+  const int rb = blockIdx.y;
+  const int64_t r0 = (int64_t)rb * brows;
+  const int64_t c0 = (int64_t)blockIdx.x * cpc;
+  if (r0 >= nb || c0 >= C) return;
+  const int len = (int)(nb - r0 < brows ? nb - r0 : brows);  // at most blk
+  const int64_t nc = C - c0 < cpc ? C - c0 : cpc;
+  {
+    int64_t ro[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ro[r] = (b0 + r < P ? off[b0 + r] : 0) + r0;
+    rhs_stage<R, blk>(xs, v, ro, P, b0, len);
+  }
+  const int64_t* cp = cptr + (int64_t)rb * (C + 1) + c0;
+  const int64_t base = cp[0];
+  for (int q = threadIdx.x; q <= nc; q += kSpThreads) sp[q] = (int32_t)(cp[q] - base);
+  __syncthreads();
+  const int n_pass = (int)((nc + NS - 1) / NS);  // equal for every lane: the group sums see whole waves
+  seg_stream_rhs<LPR, R>(
+      val, rowi, xs, sl, n_pass,
+      [&](int p, int64_t& beg, int64_t& end) {
+        const int q = slot + p * NS;
+        const int qq = q < nc ? q : 0;
+        const int32_t b_ = sp[qq], e_ = sp[qq + 1];
+        beg = base + b_;
+        end = base + (q < nc ? e_ : b_);
+      },
+      [&](int p, int which, double t) {
+        const int64_t q = slot + (int64_t)p * NS;
+        const int b = b0 + which;
+        if (q < nc && sl % (LPR / R) == 0 && b < P && par[b * kPar + 5] != 0.0)
+          part[((int64_t)b * kSlabs + rb) * C + c0 + q] = t;
+      });
 }
 
 enum ColOp { COL_PLAIN = 0, COL_ADMM = 1, COL_RESID = 3, COL_OBS = 4 };
@@ -668,6 +890,94 @@ __global__ __launch_bounds__(kSpThreads) void k_rowdot_csr(int64_t C, int ncb, i
     __syncthreads();
     if (threadIdx.x == 0) add_row_sums(R, b, sums[0]);
   }
+}
+
+// Row dots for R right-hand sides of one shared matrix: workgroup (rows
+// [x rpw, x rpw + rpw) of the matrix, column block cb, right-hand sides
+// g R .. g R + R - 1).  The R multiplier vectors of the column block (blk =
+// rhs_blk(R) columns) are staged interleaved once, so every compressed entry is
+// read once for all R; the partial dots go to pd[b][cb][row], and
+// k_rowdot_fin adds the ncb partials in order and applies the row update.
+template <typename TA, int LPR, int R>
+__global__ __launch_bounds__(kSpThreads) void k_rowdot_csr_rhs(int64_t C, int ncb, int rpw, int P,
+                                                               const double* __restrict__ sc, RowArgs Ra,
+                                                               double* __restrict__ pd) {
+  constexpr int G = 64 / LPR;
+  constexpr int NS = kSpWaves * G;
+  constexpr int64_t blk = rhs_blk(R);
+  __shared__ double xs[blk * (R + 1)];
+  __shared__ int32_t sp[2 * kRhsItems];  // segment bounds relative to the first row's (from LDS)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int sl = lane % LPR, slot = w * G + lane / LPR;
+  const int b0 = blockIdx.z * R;
+  bool any = false;
+  for (int r = 0; r < R; ++r) any |= b0 + r < P && (Ra.op == ROW_Q || Ra.par[(b0 + r) * kPar + 5] != 0.0);
+  if (!any) return;  // every right-hand side of the group has converged
+  const int64_t n_a = Ra.off[1] - Ra.off[0];  // orbits of the shared matrix
+  const int64_t a0 = (int64_t)blockIdx.x * rpw;
+  const int cb = blockIdx.y;
+  if (a0 >= n_a) return;
+  const int nr = (int)(n_a - a0 < rpw ? n_a - a0 : rpw);
+  const int n_pass = (nr + NS - 1) / NS;
+  const TA* val = (const TA*)Ra.csr_val;
+  const uint16_t* col = (const uint16_t*)Ra.csr_col;
+  const int64_t c0 = (int64_t)cb * blk;
+  const int len = (int)(C - c0 < blk ? C - c0 : blk);
+  {
+    int64_t ro[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ro[r] = (int64_t)(b0 + r < P ? b0 + r : 0) * Ra.Cp + c0;
+    rhs_stage<R, blk>(xs, sc, ro, P, b0, len);
+  }
+  const int64_t* rp = Ra.csr_ptr + a0 * ncb + cb;
+  const int64_t base = rp[0];
+  for (int row = threadIdx.x; row < nr; row += kSpThreads) {
+    sp[2 * row] = (int32_t)(rp[(int64_t)row * ncb] - base);
+    sp[2 * row + 1] = (int32_t)(rp[(int64_t)row * ncb + 1] - base);
+  }
+  __syncthreads();
+  seg_stream_rhs<LPR, R>(
+      val, col, xs, sl, n_pass,
+      [&](int p, int64_t& beg, int64_t& end) {
+        const int row = slot + p * NS;
+        const int rr = row < nr ? row : 0;
+        const int32_t b_ = sp[2 * rr], e_ = sp[2 * rr + 1];
+        beg = base + b_;
+        end = base + (row < nr ? e_ : b_);
+      },
+      [&](int p, int which, double t) {
+        const int row = slot + p * NS;
+        const int b = b0 + which;
+        if (row < nr && sl % (LPR / R) == 0 && b < P) pd[((int64_t)b * ncb + cb) * n_a + a0 + row] = t;
+      });
+}
+
+// dot of row i of problem b = sum over the column blocks of pd[b][cb][i] (in
+// order), then the row update; the workgroup's accumulator contributions are
+// combined in LDS and added once.  Grid (rows / 256, P).
+__global__ __launch_bounds__(256) void k_rowdot_fin(int ncb, const double* __restrict__ pd, RowArgs Ra) {
+  __shared__ double red[256][kRowSums];
+  const int b = blockIdx.y;
+  if (Ra.op != ROW_Q && Ra.par[b * kPar + 5] == 0.0) return;  // converged problem: frozen
+  const int64_t n_a = Ra.off[1] - Ra.off[0];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double a[kRowSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < n_a) {
+    double dot = 0.0;
+    for (int cb = 0; cb < ncb; ++cb) dot += pd[((int64_t)b * ncb + cb) * n_a + i];
+    row_update(Ra, Ra.off[b] + i, b, dot, a);
+  }
+  if (!Ra.acc) return;
+  for (int k = 0; k < kRowSums; ++k) red[threadIdx.x][k] = a[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < kRowSums; ++k)
+        red[threadIdx.x][k] = k >= 7 ? fmax(red[threadIdx.x][k], red[threadIdx.x + o][k])
+                                     : red[threadIdx.x][k] + red[threadIdx.x + o][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) add_row_sums(Ra, b, red[0]);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
@@ -984,6 +1294,10 @@ struct SolveLayout {
   // of the rows, nrb row blocks per problem of the columns
   int64_t cap_nnz;
   int ncb, nrb;
+  int rg;       // right-hand sides per workgroup in the compressed passes (1: one problem each)
+  int64_t blk;  // compressed block: columns per row segment, orbits per column segment (kBlk, or rhs_blk(rg))
+  int nrb_a;    // rg > 1: row blocks that hold orbits (partials per column)
+  size_t off_pd;  // rg > 1: partial row dots [P][ncb][NA]
   size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_crow, off_cval;
   size_t total;
 };
@@ -1047,10 +1361,20 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   const double dense = (double)L.NA * (double)L.C;
   L.cap_nnz = std::max<int64_t>((int64_t)(kMaxDensity * dense), (int64_t)1 << 20);
   if ((double)L.cap_nnz > dense) L.cap_nnz = (int64_t)dense;
-  L.ncb = (int)((L.C + kBlk - 1) / kBlk);
+  // right-hand sides of one matrix go through the compressed passes rg at a time
+  // (rg = 2, 4 or 8, as long as an orbit slab still fits a block of rhs_blk(rg))
+  L.rg = 1;
+  if (shared)
+    while (L.rg < (g_rhs_group > 0 ? g_rhs_group : kRhsGroup) && L.rg < P && L.rps[0] <= rhs_blk(2 * L.rg)) L.rg *= 2;
+  L.blk = L.rg > 1 ? rhs_blk(L.rg) : kBlk;
+  L.ncb = (int)((L.C + L.blk - 1) / L.blk);
+  {
+    const int64_t brows = slabs_per_block(L.rps[0], L.blk) * L.rps[0];
+    L.nrb_a = (int)((L.NA + brows - 1) / brows);
+  }
   L.nrb = 1;
   for (int b = 0; b < L.PA; ++b) {
-    const int64_t spb = slabs_per_block(L.rps[b]);
+    const int64_t spb = slabs_per_block(L.rps[b], L.blk);
     L.nrb = std::max<int>(L.nrb, (int)((kSlabs + spb - 1) / spb));
   }
   const size_t NA = (size_t)L.NA;
@@ -1063,6 +1387,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_cptr = take(PA * L.nrb * (L.C + 1) * 8);
   L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
+  L.off_pd = take(L.rg > 1 ? (size_t)P * L.ncb * NA * 8 : 0);
   L.total = o;
   return L;
 }
@@ -1082,8 +1407,35 @@ struct Ctx {
   template <typename T> T* p(size_t o) const { return reinterpret_cast<T*>(ws + o); }
 };
 
+// compressed column sums of a shared matrix, R right-hand sides per workgroup:
+// one workgroup per (column chunk, row block, group of R); chunks of 64 to
+// kRhsItems columns, enough of them for about 1,024 workgroups
+template <typename TA, typename TV, int R>
+static void launch_colsum_rhs(const Ctx& X, const TV* v) {
+  const int G = (X.L.P + R - 1) / R;
+  const int64_t want = std::max<int64_t>(1, (1024 + (int64_t)X.L.nrb_a * G - 1) / ((int64_t)X.L.nrb_a * G));
+  int64_t cpc = std::min<int64_t>(kRhsItems, std::max<int64_t>(64, (X.L.C + want - 1) / want));
+  if (g_sparse_cols > 0) cpc = std::min<int64_t>(kRhsItems, g_sparse_cols);
+  const dim3 grid((unsigned)((X.L.C + cpc - 1) / cpc), (unsigned)X.L.nrb_a, (unsigned)G);
+  hipLaunchKernelGGL((k_csc_colsum_rhs<TA, TV, R>), grid, dim3(kSpThreads), 0, X.st, X.L.C, cpc, X.L.P, X.off_d,
+                     X.rps_d, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<TA>(X.L.off_cval), v,
+                     X.par, X.p<double>(X.L.off_part));
+}
+
+template <typename TA, typename TV>
+static void colsum_rhs(const Ctx& X, const TV* v) {
+  if (X.L.rg == 2) launch_colsum_rhs<TA, TV, 2>(X, v);
+  else if (X.L.rg == 4) launch_colsum_rhs<TA, TV, 4>(X, v);
+  else launch_colsum_rhs<TA, TV, 8>(X, v);
+}
+
 template <typename TV>
 static hipError_t colsum(const Ctx& X, const TV* v) {
+  if (X.sparse && X.L.rg > 1) {
+    if (X.dtype == SW_F32) colsum_rhs<float, TV>(X, v);
+    else colsum_rhs<double, TV>(X, v);
+    return hipGetLastError();
+  }
   if (X.sparse) {
     // 64 columns per workgroup (several rounds of 128 KB workgroups over the
     // 256 CUs balance the uneven column lengths); narrower groups only when
@@ -1114,14 +1466,38 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
 
 static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
   hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
-                     X.p<double>(X.L.off_part), X.sparse ? 1 : kSlabs, X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
+                     X.p<double>(X.L.off_part), X.sparse ? (X.L.rg > 1 ? X.L.nrb_a : 1) : kSlabs, X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
                      outd, acc);
   return hipGetLastError();
+}
+
+// compressed row dots of a shared matrix, RG right-hand sides per workgroup:
+// one workgroup per (row group, column block, group of RG), rows per group
+// chosen for about 1,024 workgroups (64 to kRhsItems), then the ordered finish
+template <typename TA, int RG>
+static void launch_rowdot_rhs(const Ctx& X, const RowArgs& R) {
+  const int64_t n_a = X.L.NA;
+  const int G = (X.L.P + RG - 1) / RG;
+  int64_t per = n_a * X.L.ncb * G / 1024;
+  per = std::min<int64_t>(kRhsItems, std::max<int64_t>(64, (per + 15) / 16 * 16));
+  if (g_sparse_rows > 0) per = std::min<int64_t>(kRhsItems, g_sparse_rows);
+  double* pd = X.p<double>(X.L.off_pd);
+  const dim3 grid((unsigned)((n_a + per - 1) / per), (unsigned)X.L.ncb, (unsigned)G);
+  hipLaunchKernelGGL((k_rowdot_csr_rhs<TA, 16, RG>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, X.L.P,
+                     X.p<double>(X.L.off_sc), R, pd);
+  hipLaunchKernelGGL(k_rowdot_fin, dim3(blocks_for(n_a), (unsigned)X.L.P), dim3(256), 0, X.st, X.L.ncb,
+                     (const double*)pd, R);
 }
 
 template <typename TA>
 static void launch_rowdot(const Ctx& X, const RowArgs& R) {
   const double* sc = X.p<double>(X.L.off_sc);
+  if (X.sparse && X.L.rg > 1) {
+    if (X.L.rg == 2) launch_rowdot_rhs<TA, 2>(X, R);
+    else if (X.L.rg == 4) launch_rowdot_rhs<TA, 4>(X, R);
+    else launch_rowdot_rhs<TA, 8>(X, R);
+    return;
+  }
   if (X.sparse) {
     int64_t nmax = 1;
     for (int b = 0; b < X.L.P; ++b) nmax = std::max<int64_t>(nmax, X.L.off[b + 1] - X.L.off[b]);
@@ -1163,10 +1539,11 @@ static int build_sparse(Ctx& X) {
   const TA* A = (const TA*)X.A;
   X.sparse = false;
   for (int b = 0; b < P; ++b)
-    if (L.rps[b] > kBlk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
+    if (L.rps[b] > L.blk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
   int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
   int32_t* cpart = X.p<int32_t>(L.off_cpart);
-  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, rcnt);
+  hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
+                     rcnt);
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
                      dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
@@ -1193,7 +1570,7 @@ static int build_sparse(Ctx& X) {
   std::vector<int64_t> cptr((size_t)P * nrb * (L.C + 1), 0), slab_at((size_t)P * kSlabs * L.C);
   int64_t pos = 0;
   for (int b = 0; b < P; ++b) {
-    const int64_t spb = slabs_per_block(L.rps[b]);
+    const int64_t spb = slabs_per_block(L.rps[b], L.blk);
     for (int rb = 0; rb < nrb; ++rb) {
       int64_t* cp = &cptr[((size_t)b * nrb + rb) * (L.C + 1)];
       const int s0 = (int)std::min<int64_t>(kSlabs, rb * spb), s1 = (int)std::min<int64_t>(kSlabs, (rb + 1) * spb);
@@ -1214,14 +1591,14 @@ static int build_sparse(Ctx& X) {
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_rptr), rptr.data(), rptr.size() * 8, hipMemcpyHostToDevice, X.st));
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cptr), cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, X.st));
   SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_slab), slab_at.data(), slab_at.size() * 8, hipMemcpyHostToDevice, X.st));
-  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb,
+  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
                      X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
   // column padding: clear the compressed columns, then fill the entries
   const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words, 0);
   hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
-                     dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab),
+                     dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab), L.blk,
                      X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
   SW_HIP(hipGetLastError());
   // the host vectors must outlive the copies
@@ -1382,7 +1759,13 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   // ---- Gram K_b = U_b U_b^T (lower tiles) ----
   float* K = X.p<float>(L.off_K);
   const int64_t sK = L.Cp * L.Cp;
-  const int64_t sKi = shared ? 0 : sK;  // the inverse applied for problem b
+  // (rho' I + K)^-1 applied to r for every problem: one S for all right-hand sides, or one per problem
+  auto apply_inverse = [&]() -> hipError_t {
+    return shared ? inv_apply_rhs(K, L.Cp, L.Cp, P, X.p<float>(L.off_r), X.p<float>(L.off_tmp),
+                                  X.p<float>(L.off_s), L.Cp, X.par + 5, kPar, X.st)
+                  : inv_apply(K, L.Cp, L.Cp, sK, P, X.p<float>(L.off_r), X.p<float>(L.off_tmp), X.p<float>(L.off_s),
+                              L.Cp, X.par + 5, kPar, X.st);
+  };
   SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
               L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st));
   SW_TRY(hipEventRecord(ev[2], X.st));
@@ -1482,7 +1865,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     hipError_t e;
     if ((e = colsum<float>(X, vf)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_ADMM, kyf, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = inv_apply(K, L.Cp, L.Cp, sKi, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
+    if ((e = apply_inverse()) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Ri = RA;
     Ri.op = ROW_ADMM;
@@ -1615,7 +1998,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
     if ((e = colsum<double>(X, rd)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = inv_apply(K, L.Cp, L.Cp, sKi, P, r, tmp, s, L.Cp, X.par + 5, kPar, X.st)) != hipSuccess) return e;
+    if ((e = apply_inverse()) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Rc = RA;
     Rc.op = ROW_CORR;

@@ -143,7 +143,7 @@ def test_tuning_knobs():
     # every knob: its default reads back, an out-of-range value is refused and leaves it unchanged
     for key, good, bad in [("integrate_waves_per_cu", 8, 65), ("integrate_lanes_per_orbit", 2, 3),
                            ("sparse_rows_per_wg", 64, 17), ("sparse_cols_per_wg", 512, 1024),
-                           ("sparse_lanes_per_row", 16, 32)]:
+                           ("sparse_lanes_per_row", 16, 32), ("rhs_per_group", 4, 3)]:
         old = P.get_tuning(key)
         assert old >= 0
         P.set_tuning(key, good)
