@@ -7,6 +7,7 @@ velocity bins = 48,000 constraints): integrate_and_bin -> solve_weights ->
 chi2, with every input already resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload barred|small]
+                  [--bootstrap B]   (also B bootstrap solves per build, Eq. 6)
 """
 import argparse
 import json
@@ -95,6 +96,9 @@ def main():
     ap.add_argument("--refine-iter", type=int, default=0, help="cap of the FP64 stage (0: library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch the solve iterations one by one")
     ap.add_argument("--no-accel", action="store_true", help="plain ADMM (no Anderson acceleration)")
+    ap.add_argument("--bootstrap", type=int, default=0,
+                    help="also solve this many bootstrap realisations of the data per build (shared matrix) "
+                         "and report chi2_model")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a 4 GiB device-to-device copy (scale for the HBM traffic counters)")
     args = ap.parse_args()
@@ -158,12 +162,23 @@ def main():
     log(f"workspaces: integrate {iws.numel() / 1e9:.1f} GB, solve {sws.numel() / 1e9:.1f} GB")
 
     reps, chis, t_int = [], [], []
+    boot = []  # per step: (status, reports, chi2_b, chi2_model, ms)
+    n_boot = args.bootstrap
+    kin0 = blocks[1][0]
+    if n_boot > 0:
+        # bootstrap realisations of the observed maps (Sec. 2.3): seeded normal deviates, resident in HBM
+        eps_t = torch.from_numpy(W.bootstrap_eps(n_boot, nc, seed=9)).to(dev)
+        D_t = torch.empty((n_boot, nc), dtype=torch.float64, device=dev)
+        w_b = torch.empty((n_boot, n), dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream()  # default priority; the solve captures its iterations into HIP graphs on it
     opts.use_graph = 0 if args.no_graph else 1
     opts.max_iter = args.max_iter
     opts.refine_iter = args.refine_iter
     if args.no_accel:
         opts.flags |= P.SW_SOLVE_NO_ACCEL
+    if n_boot > 0:
+        bws = torch.empty(P.solve_multi_workspace_bytes(n, nc, n_boot, opts), dtype=torch.uint8, device=dev)
+        log(f"bootstrap: {n_boot} realisations, workspace {bws.numel() / 1e9:.1f} GB")
 
     def step():
         with torch.cuda.stream(stream):
@@ -173,6 +188,12 @@ def main():
             e1.record()
             st, rep = P.solve_weights(A, d_t, s_t, w_tilde, -1.0, opts, w, sws)
             x = P.chi2(A, w, d_t, s_t, blocks[1][0], blocks[1][1], cws)
+            if n_boot > 0:
+                tb = time.perf_counter()
+                P.bootstrap_data(d_t, s_t, eps_t, kin0, nc, D_t)
+                stb, repb = P.solve_weights_multi(A, D_t, s_t, w_tilde, -1.0, opts, w_b, bws)
+                xb = [P.chi2(A, w_b[b], d_t, s_t, kin0, nc, cws) for b in range(n_boot)]
+                boot.append((stb, repb, xb, P.chi2_model(xb), 1e3 * (time.perf_counter() - tb)))
         torch.cuda.synchronize()
         t_int.append(e0.elapsed_time(e1))
         reps.append(rep.as_dict() | {"status": st})
@@ -181,12 +202,17 @@ def main():
     for i in range(args.warmup):
         step()
         log(f"warmup {i}: integrate {t_int[-1]:.1f} ms, solve {reps[-1]}")
-    reps.clear(); chis.clear(); t_int.clear()
+    reps.clear(); chis.clear(); t_int.clear(); boot.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
         log(f"step {i}: integrate {t_int[-1]:.1f} ms, chi2 {chis[-1]:.6g}, solve {reps[-1]}")
+        if n_boot > 0:
+            stb, repb, xb, xm, msb = boot[-1]
+            rit = [r.refine_iters for r in repb]
+            log(f"  bootstrap: {msb:.0f} ms, status {stb}, iterations max {max(rit)} median {int(np.median(rit))}, "
+                f"kkt max {max(r.kkt for r in repb):.2e}, chi2_b {min(xb):.6g}..{max(xb):.6g}, chi2_model {xm:.6g}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = 1e3 * el / args.steps
@@ -229,6 +255,23 @@ def main():
     }
     if it1 == 0:
         del rooflines["admm_fp32"], stages["admm_fp32"]  # the FP32 stage did not run (accelerated FP64 stage only)
+    if n_boot > 0:
+        # the bootstrap solves' FP64 stage: per iteration each group of rg data vectors streams the
+        # compressed copies four times (6 B per entry), the two triangles of the inverse are read once
+        # for all of them, and each data vector's Anderson mixing moves 91 N doubles; the iterations of
+        # a group are counted as (sum over data vectors of their iterations) / rg
+        repb = boot[-1][1]
+        rg = P.get_tuning("rhs_per_group") or 4
+        rg = 1 << max(0, math.ceil(math.log2(min(rg, n_boot))))
+        its_sum = float(sum(r.refine_iters for r in repb))
+        its_max = float(max(r.refine_iters for r in repb))
+        t_boot_ref = float(repb[0].t_refine_ms)
+        stages["bootstrap_refine_fp64"] = t_boot_ref
+        stages["bootstrap_rest"] = float(np.mean([b[4] for b in boot])) - t_boot_ref
+        rooflines["bootstrap_refine_fp64"] = {
+            "kernel": "k_csc_colsum_rhs + k_rowdot_csr_rhs + k_trmm_rhs (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
+            "peak": PEAK_HBM / 1e9, "ms": t_boot_ref,
+            "work": its_sum / rg * 4 * pass_bytes + its_max * tri_bytes + its_sum * aa_bytes}
     for k, r in rooflines.items():
         scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
         r["achieved"] = round(r["work"] / (r["ms"] * 1e-3) / scale, 3) if r["ms"] > 0 else None
@@ -244,7 +287,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "orbit-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if not f64 else "f64", "data": "synthetic",
-        "config": {"workload": cfg["name"], "n_orbits": n, "n_steps": n_steps, "n_constraints": nc,
+        "config": {"workload": cfg["name"] + (f"+{n_boot}_bootstraps" if n_boot else ""), "n_orbits": n,
+                   "n_steps": n_steps, "n_constraints": nc,
                    "gram": args.gram, "mock": cfg["mock"]},
         "model_builds_per_s": 1e3 / ms,
         "stage_ms": {k: round(v, 3) for k, v in stages.items()},
@@ -252,6 +296,13 @@ def main():
         "solve": {k: reps[-1][k] for k in ("iters", "refine_iters", "converged", "kkt", "mu", "rho", "status")},
         "chi2": chis[-1],
         "integrate_orbit_steps_per_s": orbit_steps / (t_i * 1e-3),
+        "bootstrap": None if n_boot == 0 else {
+            "n": n_boot, "ms": float(np.mean([b[4] for b in boot])), "status": boot[-1][0],
+            "solves_per_s": n_boot / (1e-3 * float(np.mean([b[4] for b in boot]))),
+            "refine_iters_max": int(max(r.refine_iters for r in boot[-1][1])),
+            "refine_iters_median": float(np.median([r.refine_iters for r in boot[-1][1]])),
+            "kkt_max": float(max(r.kkt for r in boot[-1][1])),
+            "chi2_b_range": [float(min(boot[-1][2])), float(max(boot[-1][2]))], "chi2_model": boot[-1][3]},
         "roofline": roof,
         "rooflines": rooflines,
     }
