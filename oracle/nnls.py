@@ -133,6 +133,28 @@ def relative_mu(U, nu):
     return nu * float(np.mean(np.sum(U * U, axis=0)))
 
 
+def _square(A):
+    return A.multiply(A) if hasattr(A, "multiply") else A * A
+
+
+def relative_mu_orbit_matrix(A, sigma, w_tilde, nu):
+    """relative_mu without forming U, for an orbit-major A[i][n] (dense, or a
+    scipy sparse matrix): ||U[:, i]||^2 = w_tilde^2 sum_n A[i][n]^2 / sigma_n^2."""
+    col = (w_tilde * w_tilde) * np.asarray(_square(A) @ (1.0 / (sigma * sigma))).ravel()
+    return nu * float(np.mean(col))
+
+
+def kkt_residual_orbit_matrix(A, d, sigma, w_tilde, mu, w):
+    """kkt_residual of Eq. 4 relative to ||U^T y||_inf, for the physical weights
+    w = w_tilde w' and an orbit-major A[i][n] (dense, or a scipy sparse matrix),
+    without forming U: U w' = (A^T w) / sigma and U^T e = w_tilde A (e / sigma)."""
+    wp = np.asarray(w, dtype=np.float64) / w_tilde
+    e = (np.asarray(A.T @ w).ravel() - d) / sigma
+    g = w_tilde * np.asarray(A @ (e / sigma)).ravel() + mu * wp
+    q = w_tilde * np.asarray(A @ (d / (sigma * sigma))).ravel()
+    return float(np.max(np.abs(np.minimum(wp, g)))) / float(np.max(np.abs(q)))
+
+
 def sigma_from_data(d, blocks, tol, floor=1e-3):
     """Per-constraint uncertainty: a relative tolerance (1% in Eq. 3) with a
     floor of `floor` times the block maximum for empty cells."""

@@ -354,3 +354,31 @@ def test_chi2_is_zero_at_truth_and_matches_direct_sum():
     d2 = d * (1 + 0.02 * rng.normal(size=30))
     direct = sum(((sum(w[i] * A[i, n] for i in range(50)) - d2[n]) / sig[n]) ** 2 for n in range(10, 30))
     assert N.chi2(A, w, d2, sig, 10, 30) == pytest.approx(direct, rel=1e-12)
+
+
+def test_matrix_free_kkt_and_mu_match_the_scaled_problem():
+    """The orbit-matrix forms used at full size (no U formed; dense or CSR A)
+    agree with kkt_residual / relative_mu on U = w~ A^T / sigma (pinned above by
+    brute force), vanish at the exact minimiser and see a one-weight
+    perturbation."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(9)
+    n, c = 120, 70
+    A = rng.random((n, c)) * (rng.random((n, c)) < 0.2)
+    d = A.T @ (rng.exponential(size=n) * (rng.random(n) < 0.2)) * (1 + 0.02 * rng.normal(size=c)) + 1e-3
+    sig = 0.02 * d
+    wt = 0.7
+    U, y = N.scale_problem(A, d, sig, wt)
+    mu = N.relative_mu(U, 1e-2)
+    qmax = np.abs(U.T @ y).max()
+    for Am in (A, sp.csr_matrix(A)):
+        assert N.relative_mu_orbit_matrix(Am, sig, wt, 1e-2) == pytest.approx(mu, rel=1e-12)
+    wp = N.nnls_oracle(U, y, mu)
+    for Am in (A, sp.csr_matrix(A)):
+        assert N.kkt_residual_orbit_matrix(Am, d, sig, wt, mu, wt * wp) < 1e-12
+    w_bad = 1.5 * wp
+    w_bad[int(np.argmin(wp))] = 0.5 * wp.max()
+    direct = N.kkt_residual(U, y, mu, w_bad) / qmax
+    assert direct > 1e3 * 1e-11  # well above the optimum's residual (min(w', g) is capped by the weights' scale)
+    for Am in (A, sp.csr_matrix(A)):
+        assert N.kkt_residual_orbit_matrix(Am, d, sig, wt, mu, wt * w_bad) == pytest.approx(direct, rel=1e-10)
