@@ -63,6 +63,12 @@ extern "C" {
                           Phi = -G M_DM ln(1 + m/R_s) / m,  m^2 = x^2 + y^2 + z^2/q^2 */
 #define SW_FERRERS2 6  /* Ferrers n = 2 bar, rho = rho_c (1 - m^2)^2:
                           p0 = M, p1 = a (along bar-frame x), p2 = b (y), p3 = c (z) */
+#define SW_DA_T3 7     /* Dehnen-Aly needle bar (Eq. 12, App. A) from the T3 parent:
+                          p0 = M, p1 = a >= 0, p2 = b > 0, p3 = L > 0 (needle half-length,
+                          along bar-frame x), p4 = eta in [-1, 1] (needle slope)          */
+#define SW_DA_V4 8     /* the same from the V4 parent; same slots.  Both are evaluated by
+                          Gauss-Legendre over each half of the needle after s = x + c sinh u;
+                          in single precision accurate to ~1e-6 for (a + b) / L >= 0.15    */
 
 #define SW_MAX_COMP 8
 

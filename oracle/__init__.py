@@ -17,7 +17,7 @@ import numpy as np
 
 from . import build as _build
 
-KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6}
+KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6, "da_t3": 7, "da_v4": 8}
 G = 4.300917270e-6
 
 _lib = None

@@ -12,6 +12,9 @@
  *                        are textbook pairs (Binney & Tremaine 2008, Sec. 2.2,
  *                        2.5); the Ferrers potential is the homoeoid-theorem
  *                        integral for rho = rho_c (1 - m^2)^2.
+ *   needle bars ........ Eq. 12 and App. A: the T3 and V4 parent pairs with
+ *                        each R^-n replaced by its convolution with the
+ *                        needle density f along the bar's x axis.
  *   integration ........ Sec. 2.2.2: fixed number of steps, corotating bar
  *                        frame, velocities kept inertial, Jacobi-energy cut.
  *   symmetrisation ..... Sec. 2.2.2, Table 1 (four mirror copies).
@@ -158,6 +161,169 @@ static void ferrers_integrals(double a, double b, double c, const double x[3], d
 static double ferrers_rho_c(const double* p) { return 105.0 * p[0] / (32.0 * M_PI * p[1] * p[2] * p[3]); }
 
 /* ------------------------------------------------------------------ */
+/* Dehnen-Aly needle bars (Eq. 12, App. A).  For the point (x, y, z),  */
+/* Z = a + zeta, zeta = sqrt(z^2 + b^2), and k = 0..6:                  */
+/*   J_k = int_{-L}^{L} f(s) D(s)^-(2k+1)/2 ds,                          */
+/*   X_k = int_{-L}^{L} f(s) (x - s) D(s)^-(2k+1)/2 ds,                  */
+/*   D(s) = (x - s)^2 + y^2 + Z^2,                                       */
+/*   f(s) = (1 + eta (1 - 2|s|/L)) / (2L) on |s| < L,                    */
+/* so J_k is Eq. 12's I_n for n = 2k + 1 (with x' = x - s).  Each half  */
+/* of the needle is integrated adaptively (f is linear there).          */
+/* ------------------------------------------------------------------ */
+#define DA_K 7
+
+typedef struct {
+  double x, y2Z2, L, eta;
+  double sgn; /* +1: s in [0, L]; -1: s in [-L, 0] (s = sgn * u, u in [0, L]) */
+} da_ctx;
+
+static void da_integrand(const da_ctx* C, double u, double f[2 * DA_K]) {
+  double s = C->sgn * u;
+  double fs = (1.0 + C->eta * (1.0 - 2.0 * u / C->L)) / (2.0 * C->L);
+  double dx = C->x - s;
+  double D = dx * dx + C->y2Z2;
+  double p = fs / sqrt(D);
+  for (int k = 0; k < DA_K; ++k) {
+    f[k] = p;
+    f[DA_K + k] = p * dx;
+    p = p / D;
+  }
+}
+
+static void da_gk15(const da_ctx* C, double lo, double hi, double res[2 * DA_K], double err[2 * DA_K]) {
+  double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+  double k[2 * DA_K], g[2 * DA_K], f1[2 * DA_K], f2[2 * DA_K];
+  da_integrand(C, mid, f1);
+  for (int j = 0; j < 2 * DA_K; ++j) { k[j] = WGK[7] * f1[j]; g[j] = WG[3] * f1[j]; }
+  for (int i = 0; i < 7; ++i) {
+    da_integrand(C, mid - half * XGK[i], f1);
+    da_integrand(C, mid + half * XGK[i], f2);
+    for (int j = 0; j < 2 * DA_K; ++j) {
+      k[j] += WGK[i] * (f1[j] + f2[j]);
+      if (i & 1) g[j] += WG[i / 2] * (f1[j] + f2[j]);
+    }
+  }
+  for (int j = 0; j < 2 * DA_K; ++j) {
+    res[j] = k[j] * half;
+    err[j] = fabs((k[j] - g[j]) * half);
+  }
+}
+
+/* absolute tolerance per entry: tol times the entry's size over the whole half */
+static void da_adapt(const da_ctx* C, double lo, double hi, const double scale[2 * DA_K], double tol, int depth,
+                     double out[2 * DA_K]) {
+  double r[2 * DA_K], e[2 * DA_K];
+  da_gk15(C, lo, hi, r, e);
+  int ok = 1;
+  for (int j = 0; j < 2 * DA_K; ++j)
+    if (e[j] > tol * scale[j] && e[j] > 1e-300) ok = 0;
+  if (ok || depth >= 40) {
+    for (int j = 0; j < 2 * DA_K; ++j) out[j] += r[j];
+    return;
+  }
+  double mid = 0.5 * (lo + hi);
+  da_adapt(C, lo, mid, scale, tol, depth + 1, out);
+  da_adapt(C, mid, hi, scale, tol, depth + 1, out);
+}
+
+/* J[k], X[k] of the needle bar with parameters p (M, a, b, L, eta) at x */
+static void da_integrals(const double* p, const double x[3], double J[DA_K], double X[DA_K], double* Z,
+                         double* zeta) {
+  double a = p[1], b = p[2];
+  *zeta = sqrt(x[2] * x[2] + b * b);
+  *Z = a + *zeta;
+  double out[2 * DA_K];
+  for (int j = 0; j < 2 * DA_K; ++j) out[j] = 0.0;
+  for (int h = 0; h < 2; ++h) {
+    da_ctx C;
+    C.x = x[0];
+    C.y2Z2 = x[1] * x[1] + (*Z) * (*Z);
+    C.L = p[3];
+    C.eta = p[4];
+    C.sgn = h == 0 ? 1.0 : -1.0;
+    double r[2 * DA_K], e[2 * DA_K], scale[2 * DA_K];
+    da_gk15(&C, 0.0, C.L, r, e);
+    for (int j = 0; j < 2 * DA_K; ++j) scale[j] = fabs(r[j]) + 1e-300;
+    da_adapt(&C, 0.0, C.L, scale, 1e-14, 0, out);
+  }
+  for (int k = 0; k < DA_K; ++k) {
+    J[k] = out[k];
+    X[k] = out[DA_K + k];
+  }
+}
+
+/* The parent potential -GM sum_n c_n R^-n written as coefficients c_n(Z, zeta)
+ * of n = 1, 3, 5, ... (index k = (n - 1) / 2) and their derivatives dc_n/dzeta
+ * (Z = a + zeta); returns the number of terms. */
+static int da_coeffs(int kind, double a, double b, double Z, double zeta, double c[5], double dc[5]) {
+  double b2 = b * b;
+  if (kind == ORC_DA_T3) {
+    /* App. A: Phi_T3 = -GM [1/R + a (Z - a/3)/R^3 + a^2 Z^2/R^5] */
+    c[0] = 1.0; dc[0] = 0.0;
+    c[1] = a * (Z - a / 3.0); dc[1] = a;
+    c[2] = a * a * Z * Z; dc[2] = 2.0 * a * a * Z;
+    return 3;
+  }
+  /* App. A: Phi_V4 = -GM [1/R + (a (Z - 2a/5) + b^2/2)/R^3
+   *   + 3a (a Z (2Z - a)/5 + (b^2/2)(Z - a/5))/R^5 + a^2 Z^2 (a Z + 3 b^2)/R^7
+   *   + 7 a^3 b^2 Z^4 / (2 zeta R^9)] */
+  c[0] = 1.0; dc[0] = 0.0;
+  c[1] = a * (Z - 2.0 * a / 5.0) + b2 / 2.0; dc[1] = a;
+  c[2] = 3.0 * a * (a * Z * (2.0 * Z - a) / 5.0 + (b2 / 2.0) * (Z - a / 5.0));
+  dc[2] = 3.0 * a * (a * (4.0 * Z - a) / 5.0 + b2 / 2.0);
+  c[3] = a * a * Z * Z * (a * Z + 3.0 * b2);
+  dc[3] = 3.0 * a * a * a * Z * Z + 6.0 * a * a * b2 * Z;
+  c[4] = 7.0 * a * a * a * b2 * Z * Z * Z * Z / (2.0 * zeta);
+  dc[4] = (7.0 * a * a * a * b2 / 2.0) * (4.0 * Z * Z * Z / zeta - Z * Z * Z * Z / (zeta * zeta));
+  return 5;
+}
+
+static double da_phi(int kind, const double* p, const double x[3]) {
+  double J[DA_K], X[DA_K], Z, zeta, c[5], dc[5];
+  da_integrals(p, x, J, X, &Z, &zeta);
+  int nt = da_coeffs(kind, p[1], p[2], Z, zeta, c, dc);
+  double s = 0.0;
+  for (int k = 0; k < nt; ++k) s = s + c[k] * J[k];
+  return -ORC_G * p[0] * s;
+}
+
+/* g = -grad Phi: with dI_n/dx = -n X_(n+2), dI_n/dy = -n y J_(n+2),
+ * dI_n/dZ = -n Z J_(n+2) and dZ/dz = z / zeta */
+static void da_accel_add(int kind, const double* p, const double x[3], double g[3]) {
+  double J[DA_K], X[DA_K], Z, zeta, c[5], dc[5];
+  da_integrals(p, x, J, X, &Z, &zeta);
+  int nt = da_coeffs(kind, p[1], p[2], Z, zeta, c, dc);
+  double GM = ORC_G * p[0];
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int k = 0; k < nt; ++k) {
+    double n = 2.0 * k + 1.0;
+    sx = sx + n * c[k] * X[k + 1];
+    sy = sy + n * c[k] * J[k + 1];
+    sz = sz + (dc[k] * J[k] - n * c[k] * Z * J[k + 1]);
+  }
+  g[0] = g[0] - GM * sx;
+  g[1] = g[1] - GM * x[1] * sy;
+  g[2] = g[2] + GM * sz * x[2] / zeta;
+}
+
+/* App. A densities with the same replacement (n = 5, 7, 9 for T3; 7..13 for V4) */
+static double da_density(int kind, const double* p, const double x[3]) {
+  double J[DA_K], X[DA_K], Z, zeta;
+  da_integrals(p, x, J, X, &Z, &zeta);
+  double M = p[0], a = p[1], b = p[2], e = zeta;
+  if (kind == ORC_DA_T3)
+    return (M * b * b / (4.0 * M_PI)) *
+           (3.0 * J[2] + 5.0 * a * Z * Z * (3.0 * e * e - 2.0 * a * e + a * a) / (e * e * e) * J[3] +
+            35.0 * a * a * Z * Z * Z * Z / (e * e) * J[4]);
+  return (3.0 * M * b * b * b * b / (8.0 * M_PI)) *
+         (5.0 * J[3] +
+          7.0 * a * Z * Z * (5.0 * e * e * e * e - 4.0 * a * e * e * e + 3.0 * a * a * e * e - 2.0 * a * a * a * e +
+                             a * a * a * a) / (e * e * e * e * e) * J[4] +
+          63.0 * a * a * Z * Z * Z * Z * (2.0 * e * e - 2.0 * a * e + a * a) / (e * e * e * e) * J[5] +
+          231.0 * a * a * a * Z * Z * Z * Z * Z * Z / (e * e * e) * J[6]);
+}
+
+/* ------------------------------------------------------------------ */
 /* Components.                                                          */
 /* ------------------------------------------------------------------ */
 static double comp_phi(const orc_comp* C, const double x[3]) {
@@ -196,6 +362,9 @@ static double comp_phi(const orc_comp* C, const double x[3]) {
       ferrers_integrals(p[1], p[2], p[3], x, I);
       return -(M_PI * ORC_G * p[1] * p[2] * p[3] * ferrers_rho_c(p) / 3.0) * I[0];
     }
+    case ORC_DA_T3:
+    case ORC_DA_V4:
+      return da_phi(C->kind, p, x);
   }
   return NAN;
 }
@@ -269,6 +438,10 @@ static void comp_accel_add(const orc_comp* C, const double x[3], double g[3]) {
       g[2] = g[2] - k * x[2] * I[3];
       return;
     }
+    case ORC_DA_T3:
+    case ORC_DA_V4:
+      da_accel_add(C->kind, p, x, g);
+      return;
   }
 }
 
@@ -310,6 +483,9 @@ static double comp_density(const orc_comp* C, const double x[3]) {
       if (m2 >= 1.0) return 0.0;
       return ferrers_rho_c(p) * (1.0 - m2) * (1.0 - m2);
     }
+    case ORC_DA_T3:
+    case ORC_DA_V4:
+      return da_density(C->kind, p, x);
   }
   return NAN;
 }

@@ -29,7 +29,9 @@ enum {
   ORC_PLUMMER = 3,    /* p0 = M, p1 = b                          */
   ORC_MN = 4,         /* p0 = M, p1 = a, p2 = b (Miyamoto-Nagai) */
   ORC_NFW_Q = 5,      /* p0 = M200, p1 = c, p2 = q, p3 = H0 [km/s/Mpc], 0 -> 70 */
-  ORC_FERRERS2 = 6    /* p0 = M, p1 = a (x), p2 = b (y), p3 = c (z) */
+  ORC_FERRERS2 = 6,   /* p0 = M, p1 = a (x), p2 = b (y), p3 = c (z) */
+  ORC_DA_T3 = 7,      /* Dehnen-Aly T3 needle bar: p0 = M, p1 = a, p2 = b, p3 = L, p4 = eta */
+  ORC_DA_V4 = 8       /* Dehnen-Aly V4 needle bar: same slots */
 };
 
 typedef struct {

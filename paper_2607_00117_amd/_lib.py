@@ -16,7 +16,7 @@ SW_GRAM_BF16, SW_GRAM_BF16X3, SW_GRAM_F32 = 0, 1, 2
 SW_SOLVE_DENSE = 1
 SW_SOLVE_NO_ACCEL = 2
 SW_FLAG_DRIFT, SW_FLAG_NONFINITE = 1, 2
-KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6}
+KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6, "da_t3": 7, "da_v4": 8}
 
 
 class SchwError(RuntimeError):

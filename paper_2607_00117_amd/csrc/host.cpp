@@ -172,6 +172,14 @@ extern "C" int build_potential(const sw_potential_desc* in, sw_potential* out) {
         k.c[6] = std::fmax(k.c[0], std::fmax(k.c[1], k.c[2]));
         break;
       }
+      case SW_DA_T3:
+      case SW_DA_V4:
+        SW_CHECK(std::isfinite(p[1]) && p[1] >= 0.0 && pos_finite(p[2]) && pos_finite(p[3]),
+                 "build_potential: needle bar needs a >= 0, b > 0, L > 0");
+        SW_CHECK(std::isfinite(p[4]) && p[4] >= -1.0 && p[4] <= 1.0, "build_potential: needle bar eta in [-1, 1]");
+        k.c[0] = GM; k.c[1] = p[1]; k.c[2] = p[2] * p[2]; k.c[3] = p[3]; k.c[4] = p[4];
+        k.c[5] = 1.0 / (2.0 * p[3]);
+        break;
       default:
         SW_CHECK(false, "build_potential: unknown component kind %d", c.kind);
     }

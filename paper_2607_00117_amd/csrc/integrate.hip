@@ -182,6 +182,15 @@ static int launch_hist(const uint64_t* ev, int64_t n_chunk, int32_t n_steps, int
   return SW_OK;
 }
 
+// whether a potential holds a needle bar (its kernels carry the bar's code)
+static bool has_needle(const sw_potential* p) {
+  PotK P;
+  std::memcpy(&P, p, sizeof P);
+  for (int i = 0; i < P.n_comp && i < SW_MAX_COMP; ++i)
+    if (P.comp[i].kind == SW_DA_T3 || P.comp[i].kind == SW_DA_V4) return true;
+  return false;
+}
+
 extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const int64_t* orbit_offsets,
                                  const void* ics, const void* dt, int64_t n_orb, int32_t n_steps, int32_t dtype,
                                  const sw_obs_spec* obs, void* A, double* overflow, double* drift, uint8_t* flags,
@@ -219,6 +228,7 @@ extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const 
   std::memset(&L, 0, sizeof L);
   std::memcpy(&L.p0, &pots[0], sizeof(PotK));
   L.n_pot = n_pot;
+  for (int b = 0; b < n_pot; ++b) L.needle = L.needle || has_needle(&pots[b]);
   if (n_pot > 1) {
     L.pots_dev = (const sw_potential*)ws;
     L.offsets_dev = (const int64_t*)(ws + align256((size_t)n_pot * sizeof(sw_potential)));
@@ -288,6 +298,7 @@ extern "C" int integrate_orbits(const sw_potential* pot, const void* ics, const 
   std::memset(&L, 0, sizeof L);
   std::memcpy(&L.p0, pot, sizeof(PotK));
   L.n_pot = 1;
+  L.needle = has_needle(pot);
   L.obs.drift_every = 0;
   L.ics = ics;
   L.dt = dt;

@@ -24,26 +24,30 @@ template <>
 struct Prec<float> {
   // LPO lanes per orbit: each lane's share, then the sum over the lane group
   // (the same sum in every lane of the group, so their states stay identical)
-  template <int LPO = 1>
+  template <int LPO = 1, bool NB = false>
   __device__ static void accel(const PotK& P, const float* s, float* g, float& lamw, int part = 0) {
     float gb[3];
-    accel_f32<LPO>(P, s[0], s[1], s[2], g[0], g[1], g[2], gb, lamw, part);
+    accel_f32<LPO, NB>(P, s[0], s[1], s[2], g[0], g[1], g[2], gb, lamw, part);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if constexpr (LPO == 2) gb[k] += __shfl_xor(gb[k], 1, 64);
       g[k] += gb[k];
     }
   }
-  __device__ static double jacobi(const PotK& P, const double* sd, float lamw) { return jacobi_f64_drift(P, sd, lamw); }
+  template <bool NB = false>
+  __device__ static double jacobi(const PotK& P, const double* sd, float lamw) {
+    return jacobi_f64_drift<NB>(P, sd, lamw);
+  }
 };
 template <>
 struct Prec<double> {
-  template <int LPO = 1>
+  template <int LPO = 1, bool NB = false>
   __device__ static void accel(const PotK& P, const double* s, double* g, float&, int = 0) {
     static_assert(LPO == 1, "the double-precision path runs one lane per orbit");
-    accel_f64(P, s, g);
+    accel_f64<NB>(P, s, g);
   }
-  __device__ static double jacobi(const PotK& P, const double* sd, float) { return jacobi_f64(P, sd); }
+  template <bool NB = false>
+  __device__ static double jacobi(const PotK& P, const double* sd, float) { return jacobi_f64<NB>(P, sd); }
 };
 
 __device__ __forceinline__ uint64_t pack4(const int* c) {
@@ -70,7 +74,7 @@ __device__ __forceinline__ int pot_index(const int64_t* offsets, int n_pot, int6
 // orbits; the lanes of a pair hold the same state, each evaluates its share of
 // the force and the pair adds the shares, so both advance identically; the
 // first lane of the pair writes the orbit's events and results.
-template <typename T, bool BATCHED, bool BIN, int LPO = 1>
+template <typename T, bool BATCHED, bool BIN, int LPO = 1, bool NB = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int64_t* __restrict__ offsets,
                  int32_t n_pot, ObsK O, const T* __restrict__ ics, const T* __restrict__ dts, int64_t n_orb,
@@ -107,11 +111,11 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
 
   float lamw = -1.0f;
   T g[3];
-  Prec<T>::template accel<LPO>(P, s, g, lamw, part);
+  Prec<T>::template accel<LPO, NB>(P, s, g, lamw, part);
   double sd[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
-  const double E0 = Prec<T>::jacobi(P, sd, lamw);
+  const double E0 = Prec<T>::template jacobi<NB>(P, sd, lamw);
   double dmax = 0.0;
   const int de = O.drift_every;
 
@@ -136,7 +140,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
       T py = s[4] + (cm1 * s[4] - sn * s[3]);
       s[0] = x; s[1] = y; s[3] = px; s[4] = py;
     }
-    Prec<T>::template accel<LPO>(P, s, g, lamw, part);
+    Prec<T>::template accel<LPO, NB>(P, s, g, lamw, part);
     s[3] = s[3] + h * g[0];
     s[4] = s[4] + h * g[1];
     s[5] = s[5] + h * g[2];
@@ -144,7 +148,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
     if (de > 0 && k % de == 0) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) sd[i] = (double)s[i];
-      double e = fabs(Prec<T>::jacobi(P, sd, lamw) / E0 - 1.0);
+      double e = fabs(Prec<T>::template jacobi<NB>(P, sd, lamw) / E0 - 1.0);
       if (!(e <= dmax)) dmax = e;
     }
     if constexpr (BIN) {
@@ -203,6 +207,7 @@ struct IntegrateLaunch {
   uint8_t* flags;
   void* final_state;
   bool bin;
+  bool needle;  // some potential holds a needle bar: the kernels built with its code
 };
 
 // Process-wide launch knobs (set through sw_set_tuning):
@@ -215,7 +220,8 @@ extern int g_num_cus;
 
 template <typename T>
 hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
-  const int lpo = (sizeof(T) == 4 && L.bin && g_lanes_per_orbit == 2) ? 2 : 1;
+  // potentials with needle bars run one lane per orbit
+  const int lpo = (sizeof(T) == 4 && L.bin && g_lanes_per_orbit == 2 && !L.needle) ? 2 : 1;
   int64_t tiles = (L.n_chunk + kWave / lpo - 1) / (kWave / lpo);
   if (g_waves_per_cu > 0) {
     const int64_t cap = (int64_t)g_waves_per_cu * g_num_cus;
@@ -225,6 +231,21 @@ hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
   const T* ics = (const T*)L.ics;
   const T* dt = (const T*)L.dt;
   T* fs = (T*)L.final_state;
+  if (L.needle) {
+    if (!L.bin)
+      hipLaunchKernelGGL((k_integrate<T, false, false, 1, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,
+                         L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift,
+                         L.flags, fs);
+    else if (L.n_pot > 1)
+      hipLaunchKernelGGL((k_integrate<T, true, true, 1, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,
+                         L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift,
+                         L.flags, fs);
+    else
+      hipLaunchKernelGGL((k_integrate<T, false, true, 1, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,
+                         L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m, L.ev_k, L.drift,
+                         L.flags, fs);
+    return hipGetLastError();
+  }
   if (L.bin) {
     if constexpr (sizeof(T) == 4) {
       if (lpo == 2) {

@@ -131,6 +131,140 @@ __device__ inline void ferrers_f64(const CompK& C, const double* gq, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// Dehnen-Aly needle bars (Eq. 12, App. A).  The T3 or V4 parent potential
+// -GM sum_n c_n(Z) R^-n (R^2 = x^2 + y^2 + Z^2, Z = a + zeta, zeta =
+// sqrt(z^2 + b^2)) with each R^-n replaced by its convolution along x with
+// the needle density f(s) = (1 + eta (1 - 2|s|/L)) / (2L):
+//   I_n = int_{-L}^{L} f(s) D^-n/2 ds,  D = (x - s)^2 + c^2,  c^2 = y^2 + Z^2.
+// Each half of the needle is integrated by Gauss-Legendre after
+// s = x + c sinh u: then ds = c cosh u du and D = (c cosh u)^2, so the
+// n = 2k + 1 integrand is f (c cosh u)^-2k, smooth where D^-n/2 is sharply
+// peaked at s = x.  The nodes t on (0, 1) and weights w come from the bar
+// rule (q = 1/t^2 - 1, W = 2 w / t^3).  Sums for k = 0 .. NK-1:
+//   J_k = int f D^-(2k+1)/2 ds,  X_k = int f (x - s) D^-(2k+1)/2 ds.
+// Derivatives: dI_n/dx = -n X_(n+2), dI_n/dy = -n y J_(n+2), dI_n/dZ = -n Z J_(n+2).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T asinh_(T v) {
+  const T av = v < T(0) ? -v : v;
+  const T r = log(av + sqrt(av * av + T(1)));
+  return v < T(0) ? -r : r;
+}
+template <>
+__device__ __forceinline__ float asinh_<float>(float v) {
+  const float av = fabsf(v), q = av * av + 1.0f;
+  const float r = __logf(av + q * rsqf_(q));
+  return v < 0.0f ? -r : r;
+}
+
+template <typename T, int NK, int NG>
+__device__ __forceinline__ void needle_sums(const T* gq, const T* gw, T x, T c, T L, T eta, T* J, T* X) {
+#pragma unroll
+  for (int k = 0; k < NK; ++k) { J[k] = T(0); X[k] = T(0); }
+  const T ic = T(1) / c, i2L = T(1) / (T(2) * L), iL2 = T(2) / L;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const T ua = asinh_<T>(((h ? -L : T(0)) - x) * ic), ub = asinh_<T>(((h ? T(0) : L) - x) * ic);
+    const T du = ub - ua;
+    for (int j = 0; j < NG; ++j) {
+      T t, w, e, ie;
+      if constexpr (sizeof(T) == 4) {
+        t = rsqf_(1.0f + gq[j]);
+        e = __expf(ua + du * t);
+        ie = rcpf_(e);
+      } else {
+        t = T(1) / sqrt(T(1) + gq[j]);
+        e = exp(ua + du * t);
+        ie = T(1) / e;
+      }
+      w = T(0.5) * gw[j] * (t * t * t);
+      const T sh = T(0.5) * (e - ie), ch = T(0.5) * (e + ie);
+      const T s = x + c * sh;
+      const T as = s < T(0) ? -s : s;
+      T p = du * w * ((T(1) + eta * (T(1) - as * iL2)) * i2L);
+      const T cc = c * ch;
+      T iD;
+      if constexpr (sizeof(T) == 4) iD = rcpf_(cc * cc);
+      else iD = T(1) / (cc * cc);
+      const T dx = -c * sh;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        J[k] += p;
+        X[k] += p * dx;
+        p *= iD;
+      }
+    }
+  }
+}
+
+// c_n and dc_n/dzeta (Z = a + zeta) of the parent, n = 2k + 1; NT terms
+// (T3: 3, V4: 5)
+template <typename T, int NT>
+__device__ __forceinline__ void needle_coeffs(T a, T b2, T Z, T zeta, T* c, T* dc) {
+  c[0] = T(1); dc[0] = T(0);
+  if constexpr (NT == 3) {
+    // T3: 1/R + a (Z - a/3)/R^3 + a^2 Z^2/R^5
+    c[1] = a * (Z - a / T(3)); dc[1] = a;
+    c[2] = a * a * Z * Z; dc[2] = T(2) * a * a * Z;
+  } else {
+    // V4: 1/R + (a (Z - 2a/5) + b^2/2)/R^3 + 3a (a Z (2Z - a)/5 + (b^2/2)(Z - a/5))/R^5
+    //     + a^2 Z^2 (a Z + 3 b^2)/R^7 + 7 a^3 b^2 Z^4 / (2 zeta R^9)
+    const T h = T(0.5) * b2;
+    c[1] = a * (Z - T(0.4) * a) + h; dc[1] = a;
+    c[2] = T(3) * a * (T(0.2) * a * Z * (T(2) * Z - a) + h * (Z - T(0.2) * a));
+    dc[2] = T(3) * a * (T(0.2) * a * (T(4) * Z - a) + h);
+    c[3] = a * a * Z * Z * (a * Z + T(3) * b2);
+    dc[3] = T(3) * a * a * a * Z * Z + T(6) * a * a * b2 * Z;
+    const T k9 = T(3.5) * a * a * a * b2, Z3 = Z * Z * Z, iz = T(1) / zeta;
+    c[4] = k9 * Z3 * Z * iz;
+    dc[4] = k9 * (T(4) * Z3 * iz - Z3 * Z * iz * iz);
+  }
+}
+
+// potential (phi != null) and acceleration added into g (g != null) of one needle bar;
+// K holds GM, a, b^2, L, eta (C.c or C.f)
+template <typename T, int NT, int NG>
+__device__ __forceinline__ void needle_bar(const T* K, const T* gq, const T* gw, T x, T y, T z, T* phi, T* g) {
+  const T GM = K[0], a = K[1], b2 = K[2], L = K[3], eta = K[4];
+  T zeta, c;
+  if constexpr (sizeof(T) == 4) {
+    const float izz = rsqf_(z * z + b2);
+    zeta = (z * z + b2) * izz;
+  } else {
+    zeta = sqrt(z * z + b2);
+  }
+  const T Z = a + zeta;
+  if constexpr (sizeof(T) == 4) {
+    const float q = y * y + Z * Z;
+    c = q * rsqf_(q);
+  } else {
+    c = sqrt(y * y + Z * Z);
+  }
+  T J[NT + 1], X[NT + 1], cf[NT], dcf[NT];
+  needle_sums<T, NT + 1, NG>(gq, gw, x, c, L, eta, J, X);
+  needle_coeffs<T, NT>(a, b2, Z, zeta, cf, dcf);
+  if (phi) {
+    T sp = T(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) sp += cf[k] * J[k];
+    *phi = -GM * sp;
+  }
+  if (g) {
+    T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const T n = T(2 * k + 1);
+      sx += n * cf[k] * X[k + 1];
+      sy += n * cf[k] * J[k + 1];
+      sz += dcf[k] * J[k] - n * cf[k] * Z * J[k + 1];
+    }
+    g[0] -= GM * sx;
+    g[1] -= GM * y * sy;
+    g[2] += GM * sz * z / zeta;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Single-precision acceleration (fast path).
 // ---------------------------------------------------------------------------
 // lamw: warm-start state of the first bar component (< 0: none yet); a
@@ -138,8 +272,10 @@ __device__ inline void ferrers_f64(const CompK& C, const double* gq, const doubl
 // With LPO lanes per orbit every lane evaluates the analytic components in
 // full (into g) and its share of every bar's quadrature nodes (into gb): the
 // force is g + the sum of gb over the lane group.  With LPO = 1, gb is the
-// whole bar force and the caller adds it.
-template <int LPO = 1>
+// whole bar force and the caller adds it.  NB: the potential may hold needle
+// bars (their code is compiled in only then, so that it does not weigh on the
+// registers of the kernels that integrate other potentials).
+template <int LPO = 1, bool NB = false>
 __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float z, float& gx, float& gy,
                                           float& gz, float* gb, float& lamw, int part = 0) {
   gx = 0.0f; gy = 0.0f; gz = 0.0f;
@@ -197,6 +333,15 @@ __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float
         gx -= f * x; gy -= f * y; gz -= f * z * C.f[2];
         break;
       }
+      case SW_DA_T3:
+      case SW_DA_V4:
+        if constexpr (NB) {
+          float gg[3] = {0.0f, 0.0f, 0.0f};
+          if (C.kind == SW_DA_T3) needle_bar<float, 3, kGL32>(C.f, P.gq32, P.gw32, x, y, z, nullptr, gg);
+          else needle_bar<float, 5, kGL32>(C.f, P.gq32, P.gw32, x, y, z, nullptr, gg);
+          gx += gg[0]; gy += gg[1]; gz += gg[2];
+        }
+        break;
       case SW_FERRERS2:
         if (first_bar) {
           ferrers_accel_f32<LPO>(C, P.gq32, P.gw32, x, y, z, gb[0], gb[1], gb[2], lamw, part);
@@ -216,6 +361,7 @@ __device__ __forceinline__ void accel_f32(const PotK& P, float x, float y, float
 // Double-precision acceleration and potential.  The analytic components use
 // exactly the operation order of their defining formulas.
 // ---------------------------------------------------------------------------
+template <bool NB = false>
 __device__ inline void accel_f64(const PotK& P, const double* xv, double* g) {
   const double x = xv[0], y = xv[1], z = xv[2];
   g[0] = 0.0; g[1] = 0.0; g[2] = 0.0;
@@ -267,10 +413,24 @@ __device__ inline void accel_f64(const PotK& P, const double* xv, double* g) {
       case SW_FERRERS2:
         ferrers_f64(C, P.gq64, P.gw64, x, y, z, nullptr, g);
         break;
+      case SW_DA_T3:
+        if constexpr (NB) needle_bar<double, 3, kGL64>(C.c, P.gq64, P.gw64, x, y, z, nullptr, g);
+        break;
+      case SW_DA_V4:
+        if constexpr (NB) needle_bar<double, 5, kGL64>(C.c, P.gq64, P.gw64, x, y, z, nullptr, g);
+        break;
       default:
         break;
     }
   }
+}
+
+// potential of a needle bar in double precision (32-node rule per half)
+__device__ inline double needle_phi_f64(const PotK& P, const CompK& C, double x, double y, double z) {
+  double v = 0.0;
+  if (C.kind == SW_DA_T3) needle_bar<double, 3, kGL64>(C.c, P.gq64, P.gw64, x, y, z, &v, nullptr);
+  else needle_bar<double, 5, kGL64>(C.c, P.gq64, P.gw64, x, y, z, &v, nullptr);
+  return v;
 }
 
 // Potential of one analytic (non-bar) component.
@@ -308,6 +468,7 @@ __device__ inline double phi_analytic_f64(const CompK& C, double x, double y, do
   return v;
 }
 
+template <bool NB = false>
 __device__ inline double phi_f64(const PotK& P, const double* xv) {
   const double x = xv[0], y = xv[1], z = xv[2];
   double s = 0.0;
@@ -315,17 +476,20 @@ __device__ inline double phi_f64(const PotK& P, const double* xv) {
     const CompK& C = P.comp[i];
     double v = 0.0;
     if (C.kind == SW_FERRERS2) ferrers_f64(C, P.gq64, P.gw64, x, y, z, &v, nullptr);
-    else v = phi_analytic_f64(C, x, y, z);
+    else if (C.kind == SW_DA_T3 || C.kind == SW_DA_V4) {
+      if constexpr (NB) v = needle_phi_f64(P, C, x, y, z);
+    } else v = phi_analytic_f64(C, x, y, z);
     s = s + v;
   }
   return s;
 }
 
 // E_J = |p|^2/2 + Phi(x) - Omega (x p_y - y p_x)
+template <bool NB = false>
 __device__ inline double jacobi_f64(const PotK& P, const double* s6) {
   double kin = 0.5 * (s6[3] * s6[3] + s6[4] * s6[4] + s6[5] * s6[5]);
   double Lz = s6[0] * s6[4] - s6[1] * s6[3];
-  return kin + phi_f64(P, s6) - P.omega * Lz;
+  return kin + phi_f64<NB>(P, s6) - P.omega * Lz;
 }
 
 // ---------------------------------------------------------------------------
@@ -370,6 +534,7 @@ __device__ inline double ferrers_phi_drift(const CompK& C, const float* gq, cons
   return -C.c[5] * Fp * rsq_f64(K);
 }
 
+template <bool NB = false>
 __device__ inline double jacobi_f64_drift(const PotK& P, const double* s6, float lamw) {
   const double x = s6[0], y = s6[1], z = s6[2];
   double phi = 0.0;
@@ -381,6 +546,9 @@ __device__ inline double jacobi_f64_drift(const PotK& P, const double* s6, float
       const double lam = (first_bar && lamw >= 0.0f) ? (double)lamw : ferrers_lambda_f64(C, x * x, y * y, z * z);
       first_bar = false;
       v = ferrers_phi_drift(C, P.gq32, P.gw32, x, y, z, lam);
+    } else if (C.kind == SW_DA_T3 || C.kind == SW_DA_V4) {
+      v = 0.0;
+      if constexpr (NB) v = needle_phi_f64(P, C, x, y, z);
     } else {
       v = phi_analytic_f64(C, x, y, z);
     }

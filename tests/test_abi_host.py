@@ -48,6 +48,7 @@ def test_struct_layouts_match(tmp_path):
 
 def test_build_potential_validation():
     P.build_potential([("plummer", (1e10, 0.5)), ("mn", (5e10, 3.0, 0.3))], 0.0, (0.1, 0.2, 0.3))
+    P.build_potential([("da_t3", (1e10, 1.5, 0.6, 3.5, 0.4)), ("da_v4", (3e9, 0.0, 0.8, 2.0, -1.0))], 40.0)
     bad = [
         [("plummer", (-1.0, 0.5))],
         [("plummer", (1e10, 0.0))],
@@ -56,6 +57,10 @@ def test_build_potential_validation():
         [("ferrers2", (1e10, 4.0, 0.0, 1.0))],
         [(99, (1.0,))],
         [("kepler", (float("nan"),))],
+        [("da_t3", (1e10, 1.0, 0.5, 3.0, 1.5))],   # eta outside [-1, 1]
+        [("da_v4", (1e10, 1.0, 0.5, 0.0, 0.0))],   # L = 0
+        [("da_t3", (1e10, 1.0, 0.0, 3.0, 0.0))],   # b = 0
+        [("da_v4", (1e10, -1.0, 0.5, 3.0, 0.0))],  # a < 0
     ]
     for comps in bad:
         with pytest.raises(P.SchwError) as e:

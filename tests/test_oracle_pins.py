@@ -47,6 +47,8 @@ COMPONENTS = [
     ("nfw_q", (1e12, 10.0, 1.0, 70.0)),
     ("nfw_q", (1e12, 10.0, 0.9, 70.0)),
     ("ferrers2", (1e10, 4.0, 1.5, 1.0)),
+    ("da_t3", (1e10, 1.5, 0.5, 3.0, 0.5)),
+    ("da_v4", (5e9, 1.0, 0.8, 2.0, -0.3)),
 ]
 POINTS = [np.array(p) for p in ([1.0, 2.0, 0.3], [0.2, -0.1, 0.05], [5.0, -1.0, 0.8], [3.9, 0.2, 0.1],
                                 [12.0, 7.0, -4.0], [0.5, 1.4, -0.2])]
