@@ -95,12 +95,26 @@ typedef struct {
 
 /* Observables (Sec. 2.2.4).  Column order of the orbit matrix:
  *   [ mass cells (ix*ny + iy)*nz + iz | kinematic cells aperture*nv + v_bin ].
+ * grid = SW_GRID_CARTESIAN: mass cells over bar-frame (x, y, z) boxes.
+ * grid = SW_GRID_CYLINDRICAL (Sec. 2.2.4's self-consistency grid): ix over
+ *   R = sqrt(x^2 + y^2) in [lo[0], hi[0]) (lo[0] >= 0), iy over ny <= 32
+ *   azimuthal sectors of the whole circle starting at phi = -pi (lo[1], hi[1]
+ *   unused), iz over z as before.  Decisions are exact: R bin k iff
+ *   e_k^2 <= x^2 + y^2 < e_(k+1)^2 with e_k = lo[0] + k w, w = (hi[0] - lo[0]) / nx
+ *   (every operation rounded in the integration precision); sector k iff
+ *   c_k y - s_k x >= 0 and c_(k+1) y - s_(k+1) x < 0, (c_k, s_k) = the cosine and
+ *   sine of -pi + 2 pi k / ny computed in double and rounded, the first such k
+ *   (k = 0, 1, ...) and the last sector when none passes (the axis x = y = 0,
+ *   points on the edge at phi = +-pi).
  * A coordinate v falls in bin floor(t), t = (v - lo) * (n / (hi - lo)) taken in
  * the integration precision with n / (hi - lo) rounded from double; it is
  * inside iff 0 <= t < n.  Mass cells use bar-frame (x, y, z); apertures use
  * sky pixels on (X, Y) = (x', y'); velocity bins use v_los = v_z'. */
+#define SW_GRID_CARTESIAN 0
+#define SW_GRID_CYLINDRICAL 1
+
 typedef struct {
-  int32_t nx, ny, nz, reserved0;
+  int32_t nx, ny, nz, grid;
   double lo[3], hi[3];
   int32_t npx, npy;
   double plo[2], phi[2];

@@ -50,7 +50,7 @@ class _Obs(C.Structure):
                 ("plo", C.c_double * 2), ("phi", C.c_double * 2),
                 ("pix2ap", C.POINTER(C.c_int32)), ("n_ap", C.c_int),
                 ("nv", C.c_int), ("vlo", C.c_double), ("vhi", C.c_double),
-                ("R", C.c_double * 9), ("symmetrize", C.c_int), ("drift_every", C.c_int)]
+                ("R", C.c_double * 9), ("symmetrize", C.c_int), ("drift_every", C.c_int), ("grid", C.c_int)]
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -124,6 +124,7 @@ def make_obs(spec, R):
         o.R[i] = R[i]
     o.symmetrize = int(spec.get("symmetrize", 1))
     o.drift_every = int(spec.get("drift_every", 1))
+    o.grid = 1 if spec.get("grid", "cartesian") == "cylindrical" else 0
     return o
 
 

@@ -590,12 +590,57 @@ static int bin_f(float v, float lo, float inv, int n) {
 
 static const double MIRROR[4][3] = {{1, 1, 1}, {1, 1, -1}, {-1, -1, 1}, {-1, -1, -1}};
 
+/* Cylindrical mass grid (Sec. 2.2.4: bins uniform in R, phi, z), decided
+ * exactly in the working precision: R bin k iff e_k^2 <= x^2 + y^2 < e_(k+1)^2,
+ * e_k = lo + k w; sector k iff the point is on or counterclockwise of the
+ * edge at phi_k = -pi + 2 pi k / n and clockwise of the edge at phi_(k+1)
+ * (cross products with the edge directions, cos and sin taken in double);
+ * a point that no sector's test takes (the axis, and the edge at phi = pi)
+ * goes to the last sector.  Scanned from k = 0: the first k whose test holds. */
+static int cyl_r_d(double R2, double lo, double w, int n) {
+  for (int k = 0; k < n; ++k) {
+    double e0 = lo + (double)k * w, e1 = lo + (double)(k + 1) * w;
+    if (R2 >= e0 * e0 && R2 < e1 * e1) return k;
+  }
+  return -1;
+}
+static int cyl_r_f(float R2, float lo, float w, int n) {
+  for (int k = 0; k < n; ++k) {
+    float e0 = lo + (float)k * w, e1 = lo + (float)(k + 1) * w;
+    if (R2 >= e0 * e0 && R2 < e1 * e1) return k;
+  }
+  return -1;
+}
+static int ccw_d(double x, double y, int k, int n) {
+  double ph = -M_PI + 2.0 * M_PI * k / n;
+  return cos(ph) * y - sin(ph) * x >= 0.0;
+}
+static int ccw_f(float x, float y, int k, int n) {
+  double ph = -M_PI + 2.0 * M_PI * k / n;
+  float c = (float)cos(ph), s = (float)sin(ph);
+  return c * y - s * x >= 0.0f;
+}
+static int cyl_sector_d(double x, double y, int n) {
+  for (int k = 0; k < n; ++k)
+    if (ccw_d(x, y, k, n) && !ccw_d(x, y, k + 1, n)) return k;
+  return n - 1;
+}
+static int cyl_sector_f(float x, float y, int n) {
+  for (int k = 0; k < n; ++k)
+    if (ccw_f(x, y, k, n) && !ccw_f(x, y, k + 1, n)) return k;
+  return n - 1;
+}
+
 static void cells_d(const orc_obs* O, const double s6[6], int copy, int* mcell, int* kcell) {
   double x = MIRROR[copy][0] * s6[0], y = MIRROR[copy][1] * s6[1], z = MIRROR[copy][2] * s6[2];
   double px = MIRROR[copy][0] * s6[3], py = MIRROR[copy][1] * s6[4], pz = MIRROR[copy][2] * s6[5];
   int ix = bin_d(x, O->lo[0], O->nx / (O->hi[0] - O->lo[0]), O->nx);
   int iy = bin_d(y, O->lo[1], O->ny / (O->hi[1] - O->lo[1]), O->ny);
   int iz = bin_d(z, O->lo[2], O->nz / (O->hi[2] - O->lo[2]), O->nz);
+  if (O->grid == 1) {
+    ix = cyl_r_d(x * x + y * y, O->lo[0], (O->hi[0] - O->lo[0]) / O->nx, O->nx);
+    iy = cyl_sector_d(x, y, O->ny);
+  }
   *mcell = (ix < 0 || iy < 0 || iz < 0) ? -1 : (ix * O->ny + iy) * O->nz + iz;
   const double* R = O->R;
   double X = R[0] * x + R[1] * y + R[2] * z;
@@ -619,6 +664,10 @@ static void cells_f(const orc_obs* O, const float s6[6], int copy, int* mcell, i
   int ix = bin_f(x, (float)O->lo[0], (float)(O->nx / (O->hi[0] - O->lo[0])), O->nx);
   int iy = bin_f(y, (float)O->lo[1], (float)(O->ny / (O->hi[1] - O->lo[1])), O->ny);
   int iz = bin_f(z, (float)O->lo[2], (float)(O->nz / (O->hi[2] - O->lo[2])), O->nz);
+  if (O->grid == 1) {
+    ix = cyl_r_f(x * x + y * y, (float)O->lo[0], (float)((O->hi[0] - O->lo[0]) / O->nx), O->nx);
+    iy = cyl_sector_f(x, y, O->ny);
+  }
   *mcell = (ix < 0 || iy < 0 || iz < 0) ? -1 : (ix * O->ny + iy) * O->nz + iz;
   float R[9];
   for (int i = 0; i < 9; ++i) R[i] = (float)O->R[i];

@@ -57,6 +57,8 @@ typedef struct {
   double R[9];           /* row-major projection matrix (x',y',z') = R (x,y,z) */
   int symmetrize;        /* 1: the four mirror copies, 0: the orbit alone */
   int drift_every;       /* Jacobi energy sampled every this many steps (0 = never) */
+  int grid;              /* 0: Cartesian mass grid; 1: cylindrical (R over [lo0, hi0), ny
+                            sectors of the whole circle from phi = -pi, z)            */
 } orc_obs;
 
 /* derived halo constants (Eq. 8-9): out[0] = R_s, out[1] = M_DM, out[2] = R200 */

@@ -39,7 +39,7 @@ class Potential(C.Structure):
 
 
 class ObsSpec(C.Structure):
-    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("grid", C.c_int32),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("npx", C.c_int32), ("npy", C.c_int32), ("plo", C.c_double * 2), ("phi", C.c_double * 2),
                 ("pix2ap", C.c_void_p), ("n_ap", C.c_int32), ("nv", C.c_int32),
@@ -174,6 +174,7 @@ def obs_spec(spec, pix2ap=None):
     n_ap); pix2ap: optional int32 device tensor."""
     o = ObsSpec()
     o.nx, o.ny, o.nz = spec["nx"], spec["ny"], spec["nz"]
+    o.grid = 1 if spec.get("grid", "cartesian") == "cylindrical" else 0
     for i in range(3):
         o.lo[i], o.hi[i] = spec["lo"][i], spec["hi"][i]
     o.npx, o.npy = spec["npx"], spec["npy"]

@@ -44,12 +44,20 @@ struct PotK {
 };
 static_assert(sizeof(PotK) <= sizeof(sw_potential), "PotK does not fit sw_potential");
 
+constexpr int kMaxSectors = 32;  // azimuthal sectors of the cylindrical mass grid
 struct ObsK {
   int32_t nx, ny, nz, npx, npy, nv, n_ap, ncopy, n_mass, n_kin;
   double lo[3], inv[3], plo[2], pinv[2], vlo, vinv;
   float lof[3], invf[3], plof[2], pinvf[2], vlof, vinvf;
   const int32_t* pix2ap;
   int32_t drift_every;
+  // cylindrical mass grid: R-edge spacing, sector edge directions (cos, sin) of
+  // -pi + 2 pi k / ny, k = 0..ny, in both precisions
+  int32_t cyl;
+  double rw;
+  float rwf;
+  double sc[kMaxSectors + 1], ss[kMaxSectors + 1];
+  float scf[kMaxSectors + 1], ssf[kMaxSectors + 1];
 };
 
 void set_error(const char* fmt, ...);

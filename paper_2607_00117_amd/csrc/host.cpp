@@ -75,6 +75,8 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k) {
     if (!(std::isfinite(o->plo[i]) && std::isfinite(o->phi[i]) && o->phi[i] > o->plo[i])) return false;
   if (!(std::isfinite(o->vlo) && std::isfinite(o->vhi) && o->vhi > o->vlo)) return false;
   if (o->drift_every < 0) return false;
+  if (o->grid != SW_GRID_CARTESIAN && o->grid != SW_GRID_CYLINDRICAL) return false;
+  if (o->grid == SW_GRID_CYLINDRICAL && (o->lo[0] < 0.0 || o->ny > kMaxSectors)) return false;
   int64_t n_ap = o->pix2ap ? o->n_ap : (int64_t)o->npx * o->npy;
   if (n_ap <= 0) return false;
   int64_t n_mass = (int64_t)o->nx * o->ny * o->nz, n_kin = n_ap * o->nv;
@@ -103,6 +105,16 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k) {
   k->vinvf = (float)k->vinv;
   k->pix2ap = o->pix2ap;
   k->drift_every = o->drift_every;
+  k->cyl = o->grid == SW_GRID_CYLINDRICAL ? 1 : 0;
+  k->rw = (o->hi[0] - o->lo[0]) / o->nx;
+  k->rwf = (float)k->rw;
+  for (int j = 0; j <= kMaxSectors; ++j) {
+    const double ph = -M_PI + 2.0 * M_PI * j / (k->cyl ? o->ny : 1);
+    k->sc[j] = j <= o->ny ? std::cos(ph) : 0.0;
+    k->ss[j] = j <= o->ny ? std::sin(ph) : 0.0;
+    k->scf[j] = (float)k->sc[j];
+    k->ssf[j] = (float)k->ss[j];
+  }
   return true;
 }
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restric
   }
 }
 
-template <typename T>
+template <typename T, bool CYL>
 __global__ void k_bin_points(const PotK P, ObsK O, const T* __restrict__ pts, int64_t n, int32_t* __restrict__ mass,
                              int32_t* __restrict__ kin) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,7 +81,7 @@ __global__ void k_bin_points(const PotK P, ObsK O, const T* __restrict__ pts, in
   T s[6];
   for (int k = 0; k < 6; ++k) s[k] = pts[(int64_t)k * n + i];
   int mc[4], kc[4];
-  cells4<T>(P, O, s, mc, kc);
+  cells4<T, CYL>(P, O, s, mc, kc);
   for (int c = 0; c < 4; ++c) {
     mass[4 * i + c] = mc[c];
     kin[4 * i + c] = kc[c];
@@ -266,6 +266,15 @@ extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const 
   return SW_OK;
 }
 
+template <typename T>
+static void launch_bin_points(bool cyl, dim3 grid, dim3 block, hipStream_t st, const PotK& P, const ObsK& O,
+                              const T* pts, int64_t n, int32_t* mass, int32_t* kin) {
+  if (cyl)
+    hipLaunchKernelGGL((k_bin_points<T, true>), grid, block, 0, st, P, O, pts, n, mass, kin);
+  else
+    hipLaunchKernelGGL((k_bin_points<T, false>), grid, block, 0, st, P, O, pts, n, mass, kin);
+}
+
 extern "C" int bin_points(const sw_potential* pot, const sw_obs_spec* obs, const void* pts, int64_t n, int32_t dtype,
                           int32_t* mass, int32_t* kin, void* stream) {
   SW_CHECK(pot && obs, "bin_points: null argument");
@@ -280,9 +289,9 @@ extern "C" int bin_points(const sw_potential* pot, const sw_obs_spec* obs, const
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   hipStream_t st = (hipStream_t)stream;
   if (dtype == SW_F32)
-    hipLaunchKernelGGL(k_bin_points<float>, grid, block, 0, st, P, O, (const float*)pts, n, mass, kin);
+    launch_bin_points<float>(O.cyl != 0, grid, block, st, P, O, (const float*)pts, n, mass, kin);
   else
-    hipLaunchKernelGGL(k_bin_points<double>, grid, block, 0, st, P, O, (const double*)pts, n, mass, kin);
+    launch_bin_points<double>(O.cyl != 0, grid, block, st, P, O, (const double*)pts, n, mass, kin);
   SW_HIP(hipGetLastError());
   return SW_OK;
 }

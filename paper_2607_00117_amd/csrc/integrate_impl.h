@@ -74,7 +74,7 @@ __device__ __forceinline__ int pot_index(const int64_t* offsets, int n_pot, int6
 // orbits; the lanes of a pair hold the same state, each evaluates its share of
 // the force and the pair adds the shares, so both advance identically; the
 // first lane of the pair writes the orbit's events and results.
-template <typename T, bool BATCHED, bool BIN, int LPO = 1, bool NB = false>
+template <typename T, bool BATCHED, bool BIN, int LPO = 1, bool NB = false, bool CYL = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int64_t* __restrict__ offsets,
                  int32_t n_pot, ObsK O, const T* __restrict__ ics, const T* __restrict__ dts, int64_t n_orb,
@@ -153,7 +153,7 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
     }
     if constexpr (BIN) {
       int mc[4], kc[4];
-      cells4<T>(P, O, s, mc, kc);
+      cells4<T, CYL>(P, O, s, mc, kc);
       if (part == 0) {
         stm[slot][lo] = pack4(mc);
         stk[slot][lo] = pack4(kc);
@@ -191,6 +191,9 @@ void k_integrate(const PotK p0, const sw_potential* __restrict__ pots, const int
   }  // tile loop
 }
 
+// the integration kernels take the potential and the observables by value
+static_assert(sizeof(PotK) + sizeof(ObsK) + 256 <= 4096, "kernel arguments exceed 4 KiB");
+
 struct IntegrateLaunch {
   PotK p0;                     // the potential when n_pot == 1
   const sw_potential* pots_dev;  // device copies when n_pot > 1
@@ -220,8 +223,8 @@ extern int g_num_cus;
 
 template <typename T>
 hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
-  // potentials with needle bars run one lane per orbit
-  const int lpo = (sizeof(T) == 4 && L.bin && g_lanes_per_orbit == 2 && !L.needle) ? 2 : 1;
+  // potentials with needle bars, and cylindrical grids, run one lane per orbit
+  const int lpo = (sizeof(T) == 4 && L.bin && g_lanes_per_orbit == 2 && !L.needle && !L.obs.cyl) ? 2 : 1;
   int64_t tiles = (L.n_chunk + kWave / lpo - 1) / (kWave / lpo);
   if (g_waves_per_cu > 0) {
     const int64_t cap = (int64_t)g_waves_per_cu * g_num_cus;
@@ -231,6 +234,29 @@ hipError_t launch_integrate_t(const IntegrateLaunch& L, hipStream_t st) {
   const T* ics = (const T*)L.ics;
   const T* dt = (const T*)L.dt;
   T* fs = (T*)L.final_state;
+  if (L.bin && L.obs.cyl) {
+    // cylindrical mass grid: one lane per orbit, needle bars compiled in when present
+    if (L.n_pot > 1) {
+      if (L.needle)
+        hipLaunchKernelGGL((k_integrate<T, true, true, 1, true, true>), grid, block, 0, st, L.p0, L.pots_dev,
+                           L.offsets_dev, L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m,
+                           L.ev_k, L.drift, L.flags, fs);
+      else
+        hipLaunchKernelGGL((k_integrate<T, true, true, 1, false, true>), grid, block, 0, st, L.p0, L.pots_dev,
+                           L.offsets_dev, L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m,
+                           L.ev_k, L.drift, L.flags, fs);
+    } else {
+      if (L.needle)
+        hipLaunchKernelGGL((k_integrate<T, false, true, 1, true, true>), grid, block, 0, st, L.p0, L.pots_dev,
+                           L.offsets_dev, L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m,
+                           L.ev_k, L.drift, L.flags, fs);
+      else
+        hipLaunchKernelGGL((k_integrate<T, false, true, 1, false, true>), grid, block, 0, st, L.p0, L.pots_dev,
+                           L.offsets_dev, L.n_pot, L.obs, ics, dt, L.n_orb, L.orb0, L.n_chunk, L.n_steps, L.ev_m,
+                           L.ev_k, L.drift, L.flags, fs);
+    }
+    return hipGetLastError();
+  }
   if (L.needle) {
     if (!L.bin)
       hipLaunchKernelGGL((k_integrate<T, false, false, 1, true>), grid, block, 0, st, L.p0, L.pots_dev, L.offsets_dev,

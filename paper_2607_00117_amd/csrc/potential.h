@@ -570,6 +570,59 @@ __device__ __forceinline__ int bin1(T v, T lo, T inv, int n) {
   return (t >= T(0) && t < T(n)) ? (int)t : -1;
 }
 
+// Cylindrical mass grid (exact decisions; see sw_obs_spec): R bin k iff
+// e_k^2 <= R^2 < e_(k+1)^2, e_k = lo + k w; sector k iff the point is on or
+// counterclockwise of its lower edge and clockwise of its upper edge, the
+// first such k, else the last sector.  A first guess from sqrt / atan2 is
+// corrected by walking to the neighbour whose test holds.  Helpers without
+// contraction of a*b+c.
+template <typename T>
+__device__ __forceinline__ T cyl_e2(T lo, T w, int k) {
+#pragma clang fp contract(off)
+  const T e = lo + (T)k * w;
+  return e * e;
+}
+template <typename T>
+__device__ __forceinline__ bool cyl_ccw(const T* c, const T* s, int k, T x, T y) {
+#pragma clang fp contract(off)
+  return c[k] * y - s[k] * x >= T(0);
+}
+template <typename T>
+__device__ __forceinline__ int cyl_rbin(T R2, T lo, T w, T inv, int n) {
+  if (R2 < cyl_e2<T>(lo, w, 0) || !(R2 < cyl_e2<T>(lo, w, n))) return -1;
+  int k = (int)((sqrt(R2) - lo) * inv);
+  k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+  while (k > 0 && R2 < cyl_e2<T>(lo, w, k)) --k;
+  while (k < n - 1 && !(R2 < cyl_e2<T>(lo, w, k + 1))) ++k;
+  return k;
+}
+template <typename T>
+__device__ __forceinline__ int cyl_sector(T x, T y, const T* c, const T* s, int n) {
+  // Away from underflow every cross product with an edge that is not nearly
+  // parallel to the point has its exact sign, so the edges counterclockwise
+  // of the point form one arc: among sectors 0..n-2 at most one passes the
+  // test, and the last sector competes with an earlier one only when edge 0
+  // (the same direction as edge n) also passes.  The guess is walked to the
+  // passing sector; tiny points, a failed test and that one case take the
+  // scan in sector order.
+  constexpr T kTiny = sizeof(T) == 8 ? T(0x1p-1000) : T(0x1p-100);
+  int k = (int)((atan2(y, x) + T(M_PI)) * (T(n) / T(2.0 * M_PI)));
+  k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+  while (k > 0 && !cyl_ccw<T>(c, s, k, x, y)) --k;
+  while (k < n - 1 && cyl_ccw<T>(c, s, k + 1, x, y)) ++k;
+  const T ax = fabs(x), ay = fabs(y);
+  if ((ax > ay ? ax : ay) < kTiny || !(cyl_ccw<T>(c, s, k, x, y) && !cyl_ccw<T>(c, s, k + 1, x, y)) ||
+      (k == n - 1 && cyl_ccw<T>(c, s, 0, x, y))) {
+    k = n - 1;
+    for (int j = 0; j < n - 1; ++j)
+      if (cyl_ccw<T>(c, s, j, x, y) && !cyl_ccw<T>(c, s, j + 1, x, y)) {
+        k = j;
+        break;
+      }
+  }
+  return k;
+}
+
 template <typename T>
 struct ObsT;
 template <>
@@ -581,6 +634,9 @@ struct ObsT<float> {
   __device__ static float vlo(const ObsK& O) { return O.vlof; }
   __device__ static float vinv(const ObsK& O) { return O.vinvf; }
   __device__ static float R(const PotK& P, int i) { return P.Rf[i]; }
+  __device__ static float rw(const ObsK& O) { return O.rwf; }
+  __device__ static const float* sc(const ObsK& O) { return O.scf; }
+  __device__ static const float* ss(const ObsK& O) { return O.ssf; }
 };
 template <>
 struct ObsT<double> {
@@ -591,6 +647,9 @@ struct ObsT<double> {
   __device__ static double vlo(const ObsK& O) { return O.vlo; }
   __device__ static double vinv(const ObsK& O) { return O.vinv; }
   __device__ static double R(const PotK& P, int i) { return P.R[i]; }
+  __device__ static double rw(const ObsK& O) { return O.rw; }
+  __device__ static const double* sc(const ObsK& O) { return O.sc; }
+  __device__ static const double* ss(const ObsK& O) { return O.ss; }
 };
 
 template <typename T>
@@ -604,14 +663,33 @@ __device__ __forceinline__ T proj3(T r0, T r1, T r2, T a, T b, T c) {
 // position and velocity alike.  Projections of copies 2 and 3 are exactly
 // the negations of copies 1 and 0 (IEEE rounding is sign-symmetric).
 // mcell/kcell: -1 when outside the block.
-template <typename T>
+// CYL: the mass grid is cylindrical (compiled in only for such grids: the
+// sector tables are indexed at run time, which would weigh on the registers of
+// the Cartesian kernels)
+template <typename T, bool CYL = false>
 __device__ __forceinline__ void cells4(const PotK& P, const ObsK& O, const T* s6, int* mcell, int* kcell) {
   using Q = ObsT<T>;
   const T x = s6[0], y = s6[1], z = s6[2], px = s6[3], py = s6[4], pz = s6[5];
   const int ixp = bin1<T>(x, Q::lo(O, 0), Q::inv(O, 0), O.nx), ixm = bin1<T>(-x, Q::lo(O, 0), Q::inv(O, 0), O.nx);
   const int iyp = bin1<T>(y, Q::lo(O, 1), Q::inv(O, 1), O.ny), iym = bin1<T>(-y, Q::lo(O, 1), Q::inv(O, 1), O.ny);
   const int izp = bin1<T>(z, Q::lo(O, 2), Q::inv(O, 2), O.nz), izm = bin1<T>(-z, Q::lo(O, 2), Q::inv(O, 2), O.nz);
-  const int ixs[4] = {ixp, ixp, ixm, ixm}, iys[4] = {iyp, iyp, iym, iym}, izs[4] = {izp, izm, izp, izm};
+  int ixs[4] = {ixp, ixp, ixm, ixm}, iys[4] = {iyp, iyp, iym, iym};
+  const int izs[4] = {izp, izm, izp, izm};
+  if constexpr (CYL) {
+    // (R, phi, z): R is the same for the four copies, the sector of (-x, -y) is that of the opposite point
+    T R2;
+    {
+#pragma clang fp contract(off)
+      R2 = x * x + y * y;
+    }
+    const int ir = cyl_rbin<T>(R2, Q::lo(O, 0), Q::rw(O), Q::inv(O, 0), O.nx);
+    const int sp = cyl_sector<T>(x, y, Q::sc(O), Q::ss(O), O.ny), sm = cyl_sector<T>(-x, -y, Q::sc(O), Q::ss(O), O.ny);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ixs[c] = ir;
+      iys[c] = c < 2 ? sp : sm;
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     mcell[c] = (ixs[c] < 0 || iys[c] < 0 || izs[c] < 0) ? -1 : (ixs[c] * O.ny + iys[c]) * O.nz + izs[c];

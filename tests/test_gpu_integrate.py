@@ -161,3 +161,60 @@ def test_barred_fp32_subsample_vs_fp64_oracle(gpu, lanes):
     assert np.median(l1) <= 2.0 * np.median(l1_ref) + 0.01
     assert np.percentile(l1, 90) <= 2.0 * np.percentile(l1_ref, 90) + 0.02
     assert abs(np.mean(fl & 1) - np.mean(fl_o & 1)) <= 0.01
+
+
+CYL = dict(nx=10, ny=6, nz=10, lo=(0.0, -math.pi, -3.0), hi=(10.0, math.pi, 3.0), npx=10, npy=5, plo=(-10, -5),
+           phi=(10, 5), nv=15, vlo=-450, vhi=450, symmetrize=1, drift_every=1, grid="cylindrical")
+
+
+def cyl_edge_points(rng, n, dtype):
+    """Random states plus states on, and one ulp either side of, the R edges
+    (on the x axis, where R^2 = x^2) and on the sector edge directions."""
+    pts = np.stack([rng.uniform(-12, 12, n), rng.uniform(-12, 12, n), rng.uniform(-4, 4, n),
+                    rng.normal(0, 200, n), rng.normal(0, 200, n), rng.normal(0, 200, n)]).astype(dtype)
+    k = n // 3
+    e = (CYL["lo"][0] + rng.integers(0, CYL["nx"] + 1, k) * ((CYL["hi"][0] - CYL["lo"][0]) / CYL["nx"])).astype(dtype)
+    jit = rng.integers(-1, 2, k)
+    e = np.where(jit < 0, np.nextafter(e, dtype(-np.inf)), np.where(jit > 0, np.nextafter(e, dtype(np.inf)), e))
+    sgn = np.where(rng.random(k) < 0.5, -1, 1).astype(dtype)
+    pts[0, :k] = sgn * e
+    pts[1, :k] = 0
+    ph = -math.pi + 2.0 * math.pi * rng.integers(0, CYL["ny"] + 1, k) / CYL["ny"]
+    r = rng.uniform(0.5, 9.5, k)
+    pts[0, k:2 * k] = (r * np.cos(ph).astype(dtype)).astype(dtype)
+    pts[1, k:2 * k] = (r * np.sin(ph).astype(dtype)).astype(dtype)
+    pts[:3, 2 * k] = 0  # the axis
+    return pts
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cylindrical_bin_points_bit_exact(gpu, dtype):
+    import torch
+    P = lib()
+    npd = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(12)
+    pts = cyl_edge_points(rng, 30000, npd)
+    euler = (0.7, 1.0, 0.0)
+    pot = P.build_potential(W.SMALL["components"], 0.0, euler)
+    o = P.obs_spec(CYL)
+    t = torch.from_numpy(pts).to(gpu)
+    mass = torch.empty((pts.shape[1], 4), dtype=torch.int32, device=gpu)
+    kin = torch.empty_like(mass)
+    P.bin_points(pot, o, t, mass, kin)
+    torch.cuda.synchronize()
+    om, ok = O.bin_points(O.make_obs(CYL, O.euler_matrix(*euler)), pts, dtype)
+    assert np.array_equal(mass.cpu().numpy(), om)
+    assert np.array_equal(kin.cpu().numpy(), ok)
+    assert (om < 0).any() and (om >= 0).any()
+
+
+def test_cylindrical_small_workload_fp64_counts_identical(gpu):
+    """The small model (2,000 orbits x 1,000 FP64 steps) on a 10 x 6 x 10 = 600-cell
+    cylindrical grid: counts, drifts and flags equal to the oracle's."""
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=1000)
+    A, ov, dr, fl = gpu_integrate(cfg, ics, dt, 1000, "f64", obs=CYL)
+    c_o, ov_o, dr_o, fl_o = oracle_integrate(cfg, ics, dt, 1000, obs=CYL)
+    assert np.array_equal(counts_from_fractions(A, 1000), c_o)
+    assert np.array_equal(dr, dr_o) and np.array_equal(fl, fl_o)
+    assert c_o[:, :600].sum() > 0
