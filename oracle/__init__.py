@@ -65,6 +65,7 @@ def _declare(L):
     L.orc_phi.argtypes = [P, _dp]; L.orc_phi.restype = C.c_double
     L.orc_accel.argtypes = [P, _dp, _dp]; L.orc_accel.restype = None
     L.orc_density.argtypes = [P, _dp]; L.orc_density.restype = C.c_double
+    L.orc_cell_mass.argtypes = [P, C.POINTER(_Obs), C.c_int, C.c_double, C.c_double]; L.orc_cell_mass.restype = C.c_double
     L.orc_jacobi.argtypes = [P, _dp]; L.orc_jacobi.restype = C.c_double
     L.orc_ferrers_lambda.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
     L.orc_ferrers_lambda.restype = C.c_double
@@ -140,6 +141,16 @@ def accel(pot, x):
 
 def density(pot, x):
     return lib().orc_density(C.byref(pot), np.ascontiguousarray(x, dtype=np.float64))
+
+
+def cell_masses(pot, obs, cells=None, rel_tol=1e-10, abs_tol=0.0):
+    """Target cell masses m*_n (Sec. 2.2.4): the mass of pot's density (every
+    component of pot) in each mass-grid cell of obs, by nested adaptive
+    Gauss-Kronrod to rel_tol of each piece or its share of abs_tol [M_sun]
+    per cell.  cells: indices to evaluate (default: all)."""
+    n = obs.nx * obs.ny * obs.nz
+    idx = range(n) if cells is None else cells
+    return np.array([lib().orc_cell_mass(C.byref(pot), C.byref(obs), int(c), rel_tol, abs_tol) for c in idx])
 
 
 def jacobi(pot, s):

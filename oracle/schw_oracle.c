@@ -767,3 +767,98 @@ void orc_integrate_and_bin_f32state(const orc_pot* P, const orc_obs* O, long n, 
                                     double* drift, uint8_t* flags, int nthreads) {
   integrate_and_bin_impl(P, O, n, ics, dt, nsteps, counts, overflow, drift, flags, nthreads, 1);
 }
+
+/* ------------------------------------------------------------------ */
+/* Target cell masses m*_n (Sec. 2.2.4): the mass of the potential's    */
+/* density (all of its components) in each cell of the mass grid,       */
+/*   Cartesian:   int dx int dy int dz rho(x, y, z),                    */
+/*   cylindrical: int R dR int dphi int dz rho(R cos phi, R sin phi, z),*/
+/* cell edges lo + k (hi - lo) / n (R, z) and -pi + 2 pi k / ny (phi).  */
+/* Each of the three nested integrals is adaptive Gauss-Kronrod (7/15   */
+/* points), bisecting until |K15 - G7| <= rel_tol |K15| on the piece.   */
+/* The densities are non-negative, so a relative test is meaningful.    */
+/* ------------------------------------------------------------------ */
+typedef double (*cm_fn)(void* ctx, double t);
+
+static double cm_gk15(cm_fn f, void* ctx, double lo, double hi, double* err) {
+  double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+  double fc = f(ctx, mid);
+  double k = WGK[7] * fc, g = WG[3] * fc;
+  for (int i = 0; i < 7; ++i) {
+    double s = f(ctx, mid - half * XGK[i]) + f(ctx, mid + half * XGK[i]);
+    k += WGK[i] * s;
+    if (i & 1) g += WG[i / 2] * s;
+  }
+  *err = fabs((k - g) * half);
+  return k * half;
+}
+
+/* accepts a piece when |K15 - G7| <= max(rel_tol |K15|, abs_tol); the halves
+ * of a bisected piece share its absolute tolerance */
+static double cm_adapt(cm_fn f, void* ctx, double lo, double hi, double rel_tol, double abs_tol, int depth) {
+  double err, r = cm_gk15(f, ctx, lo, hi, &err);
+  if (!isfinite(r) || err <= fmax(rel_tol * fabs(r), abs_tol) || depth >= 30) return r;
+  double mid = 0.5 * (lo + hi);
+  return cm_adapt(f, ctx, lo, mid, rel_tol, 0.5 * abs_tol, depth + 1) +
+         cm_adapt(f, ctx, mid, hi, rel_tol, 0.5 * abs_tol, depth + 1);
+}
+
+typedef struct {
+  const orc_pot* P;
+  int cyl;
+  double u, v;        /* outer coordinates: (x, y) or (R, phi) */
+  double lo[3], hi[3]; /* the cell */
+  double tol, atol[3]; /* relative tolerance; absolute one of each level's integral */
+} cm_ctx;
+
+static double cm_f3(void* c, double z) {
+  cm_ctx* C = (cm_ctx*)c;
+  double x[3];
+  if (C->cyl) {
+    x[0] = C->u * cos(C->v);
+    x[1] = C->u * sin(C->v);
+  } else {
+    x[0] = C->u;
+    x[1] = C->v;
+  }
+  x[2] = z;
+  return orc_density(C->P, x);
+}
+
+static double cm_f2(void* c, double v) {
+  cm_ctx* C = (cm_ctx*)c;
+  C->v = v;
+  return cm_adapt(cm_f3, c, C->lo[2], C->hi[2], C->tol, C->atol[2], 0);
+}
+
+static double cm_f1(void* c, double u) {
+  cm_ctx* C = (cm_ctx*)c;
+  C->u = u;
+  double s = cm_adapt(cm_f2, c, C->lo[1], C->hi[1], C->tol, C->atol[1], 0);
+  return C->cyl ? u * s : s;
+}
+
+double orc_cell_mass(const orc_pot* P, const orc_obs* O, int cell, double rel_tol, double abs_tol) {
+  int ix = cell / (O->ny * O->nz), iy = (cell / O->nz) % O->ny, iz = cell % O->nz;
+  cm_ctx C;
+  C.P = P;
+  C.cyl = O->grid == 1;
+  C.tol = rel_tol;
+  int idx[3] = {ix, iy, iz}, n[3] = {O->nx, O->ny, O->nz};
+  for (int d = 0; d < 3; ++d) {
+    double w = (O->hi[d] - O->lo[d]) / n[d];
+    C.lo[d] = O->lo[d] + idx[d] * w;
+    C.hi[d] = O->lo[d] + (idx[d] + 1) * w;
+  }
+  if (C.cyl) {
+    C.lo[1] = -M_PI + 2.0 * M_PI * iy / O->ny;
+    C.hi[1] = -M_PI + 2.0 * M_PI * (iy + 1) / O->ny;
+  }
+  /* an error e in an inner integral adds at most e times the outer extent
+   * (times R, cylindrical) to the cell's mass */
+  double l0 = C.hi[0] - C.lo[0], l1 = C.hi[1] - C.lo[1], rmax = C.cyl ? C.hi[0] : 1.0;
+  C.atol[0] = abs_tol;
+  C.atol[1] = abs_tol / (l0 * rmax);
+  C.atol[2] = abs_tol / (l0 * rmax * l1);
+  return cm_adapt(cm_f1, &C, C.lo[0], C.hi[0], rel_tol, abs_tol, 0);
+}

@@ -100,6 +100,11 @@ void orc_integrate_and_bin_f32state(const orc_pot* P, const orc_obs* O, long n, 
 void orc_bin_points_f64(const orc_obs* O, long n, const double* pts, int32_t* mass, int32_t* kin);
 void orc_bin_points_f32(const orc_obs* O, long n, const float* pts, int32_t* mass, int32_t* kin);
 
+/* Mass of P's density in mass-grid cell `cell` ((ix*ny + iy)*nz + iz), in M_sun,
+ * by nested adaptive Gauss-Kronrod: a piece is accepted when its error
+ * estimate is below rel_tol times its value or its share of abs_tol [M_sun]. */
+double orc_cell_mass(const orc_pot* P, const orc_obs* O, int cell, double rel_tol, double abs_tol);
+
 #ifdef __cplusplus
 }
 #endif
