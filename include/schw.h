@@ -15,6 +15,7 @@
  *   solve_weights      Sec. 2.3, Eq. 3-4: regularised non-negative least squares for
  *                      the orbit weights by ADMM (linear solve + clip + dual update).
  *   chi2               Sec. 2.4, Eq. 5: chi^2 over a constraint range.
+ *   cell_masses        Sec. 2.2.4: target masses m*_n of the density grid.
  *
  * Conventions shared by every entry point
  *  - Units: kpc, km/s, Msun; G = 4.300917270e-6 kpc (km/s)^2 / Msun; time in
@@ -308,6 +309,25 @@ size_t chi2_workspace_bytes(int64_t n_con);
  *   A device [n_orb][n_con] (dtype), w device [n_orb] double, out device [n_con] double. */
 int model_observables(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, double* out,
                       void* stream);
+
+/* ---------------------------------------------------------------------------
+ * cell_masses (Sec. 2.2.4): the target masses m*_n of the self-consistency
+ * constraint, out[n] = the mass [Msun] of the selected components' density in
+ * mass cell n of obs (Cartesian boxes, or the cylindrical cells (R, phi, z)
+ * with volume element R dR dphi dz; cell order as in the orbit matrix).
+ *   comp_mask  bit i selects component i of pot (the stellar components, e.g.
+ *              disc and bar); each must have a density: SW_PLUMMER,
+ *              SW_ISOCHRONE, SW_MN (Eq. 11), SW_FERRERS2, SW_DA_T3 / SW_DA_V4
+ *              (App. A with Eq. 12).  Kepler and NFW components are refused.
+ *   n_sub      1..16: each cell is cut into n_sub^3 boxes, each integrated by
+ *              an 8 x 8 x 8 Gauss-Legendre rule in FP64.  Smooth densities
+ *              converge fast (MN to ~1e-11 relative at n_sub = 2); the
+ *              Ferrers bar's edge (density ~ (1 - m^2)^2) converges slowly:
+ *              n_sub = 8 keeps the error below 1e-9 of the bar's mass.
+ *   out        device [nx*ny*nz] double.
+ * Only the mass-grid fields of obs are read (nx, ny, nz, lo, hi, grid). */
+int cell_masses(const sw_potential* pot, const sw_obs_spec* obs, uint32_t comp_mask, int32_t n_sub, double* out,
+                void* stream);
 
 /* ---------------------------------------------------------------------------
  * Test and inspection entry points.

@@ -16,6 +16,7 @@ SW_GRAM_BF16, SW_GRAM_BF16X3, SW_GRAM_F32 = 0, 1, 2
 SW_SOLVE_DENSE = 1
 SW_SOLVE_NO_ACCEL = 2
 SW_FLAG_DRIFT, SW_FLAG_NONFINITE = 1, 2
+SW_GRID_CARTESIAN, SW_GRID_CYLINDRICAL = 0, 1
 KINDS = {"kepler": 1, "isochrone": 2, "plummer": 3, "mn": 4, "nfw_q": 5, "ferrers2": 6, "da_t3": 7, "da_v4": 8}
 
 
@@ -107,6 +108,7 @@ def load():
     L.chi2_workspace_bytes.restype = sz
     L.model_observables.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     L.bin_points.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), vp, i64, i32, vp, vp, vp]
+    L.cell_masses.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), C.c_uint32, i32, vp, vp]
     L.integrate_orbits.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, i32, vp, vp]
     L.mlp_param_count.restype = i64
     L.mlp_workspace_bytes.argtypes = [i64]
@@ -318,6 +320,11 @@ def model_observables(A, w, out):
 def bin_points(pot, obs, pts, mass, kin):
     _check(load().bin_points(C.byref(pot), C.byref(obs), _ptr(pts), pts.shape[1], _dtype_code(pts), _ptr(mass),
                              _ptr(kin), _stream()))
+
+
+def cell_masses(pot, obs, comp_mask, n_sub, out):
+    """m*_n of the components selected by comp_mask into out (device double [n_mass])."""
+    _check(load().cell_masses(C.byref(pot), C.byref(obs), int(comp_mask), int(n_sub), _ptr(out), _stream()))
 
 
 def integrate_orbits(pot, ics, dt, n_steps, out):

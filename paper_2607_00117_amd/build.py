@@ -27,6 +27,7 @@ SOURCES = {
     "mlp.hip": [],
     "gh.hip": [],
     "bootstrap.hip": [],
+    "cellmass.hip": [],
 }
 
 

@@ -103,6 +103,30 @@ def test_integrate_and_bin_validation_before_launch():
     assert b"workspace" in L.sw_last_error()
 
 
+def test_cell_masses_validation_before_launch():
+    L = P.load()
+    pot = P.build_potential([("mn", (5e10, 3.0, 0.3)), ("ferrers2", (1e10, 4.0, 1.5, 1.0)),
+                             ("nfw_q", (1e12, 10.0, 0.9, 70.0)), ("kepler", (1e8,))])
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def call(mask=0b11, n_sub=4, obs_=None, out=fake):
+        return L.cell_masses(C.byref(pot), C.byref(obs_ or _obs()), mask, n_sub, out, None)
+    assert call(mask=0) == -1                 # nothing selected
+    assert call(mask=0b10000) == -1           # component 4 does not exist
+    assert call(mask=0b111) == -1             # the NFW halo has no stellar density
+    assert call(mask=0b1001) == -1            # nor has a point mass
+    assert b"no stellar density" in L.sw_last_error()
+    assert call(n_sub=0) == -1 and call(n_sub=17) == -1
+    assert call(out=None) == -1
+    bad = _obs()
+    bad.nz = 0
+    assert call(obs_=bad) == -1
+    cyl = _obs()
+    cyl.grid = P.SW_GRID_CYLINDRICAL
+    cyl.lo[0] = -1.0                          # R must start at >= 0
+    assert call(obs_=cyl) == -1
+
+
 def test_solve_and_chi2_validation_before_launch():
     L = P.load()
     opts = _lib.SolveOpts()
