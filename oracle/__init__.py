@@ -50,7 +50,8 @@ class _Obs(C.Structure):
                 ("plo", C.c_double * 2), ("phi", C.c_double * 2),
                 ("pix2ap", C.POINTER(C.c_int32)), ("n_ap", C.c_int),
                 ("nv", C.c_int), ("vlo", C.c_double), ("vhi", C.c_double),
-                ("R", C.c_double * 9), ("symmetrize", C.c_int), ("drift_every", C.c_int), ("grid", C.c_int)]
+                ("R", C.c_double * 9), ("symmetrize", C.c_int), ("drift_every", C.c_int), ("grid", C.c_int),
+                ("surface", C.c_int), ("upsilon", C.c_double)]
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -126,6 +127,8 @@ def make_obs(spec, R):
     o.symmetrize = int(spec.get("symmetrize", 1))
     o.drift_every = int(spec.get("drift_every", 1))
     o.grid = 1 if spec.get("grid", "cartesian") == "cylindrical" else 0
+    o.surface = int(spec.get("surface", 0))
+    o.upsilon = float(spec.get("upsilon", 1.0))
     return o
 
 
@@ -206,7 +209,12 @@ def bin_points(obs, pts, precision="f64"):
     return mass, kin
 
 
-def time_fractions(counts, nsteps, symmetrize=True):
+def time_fractions(counts, nsteps, symmetrize=True, obs=None):
     """Sec. 2.2.4: each sample carries weight dt / t_total = 1 / nsteps, split
-    over the mirror copies."""
-    return counts / float((4 if symmetrize else 1) * nsteps)
+    over the mirror copies.  With obs's surface block on, that block (the last
+    n_ap columns) is the surface luminosity, the mass fraction divided by the
+    mass-to-light ratio upsilon."""
+    A = counts / float((4 if symmetrize else 1) * nsteps)
+    if obs is not None and obs.surface:
+        A[:, A.shape[1] - obs.n_ap:] /= obs.upsilon
+    return A

@@ -570,7 +570,7 @@ void orc_orbit(const orc_pot* P, const double ic[6], double dt, int nsteps, doub
   }
 }
 
-int orc_ncon(const orc_obs* O) { return O->nx * O->ny * O->nz + O->n_ap * O->nv; }
+int orc_ncon(const orc_obs* O) { return O->nx * O->ny * O->nz + O->n_ap * O->nv + (O->surface ? O->n_ap : 0); }
 
 /* ------------------------------------------------------------------ */
 /* Binning (Sec. 2.2.4).  A coordinate v falls in bin floor(t) with      */
@@ -631,7 +631,7 @@ static int cyl_sector_f(float x, float y, int n) {
   return n - 1;
 }
 
-static void cells_d(const orc_obs* O, const double s6[6], int copy, int* mcell, int* kcell) {
+static void cells_d(const orc_obs* O, const double s6[6], int copy, int* mcell, int* kcell, int* acell) {
   double x = MIRROR[copy][0] * s6[0], y = MIRROR[copy][1] * s6[1], z = MIRROR[copy][2] * s6[2];
   double px = MIRROR[copy][0] * s6[3], py = MIRROR[copy][1] * s6[4], pz = MIRROR[copy][2] * s6[5];
   int ix = bin_d(x, O->lo[0], O->nx / (O->hi[0] - O->lo[0]), O->nx);
@@ -655,9 +655,10 @@ static void cells_d(const orc_obs* O, const double s6[6], int copy, int* mcell, 
     ap = O->pix2ap ? O->pix2ap[pix] : pix;
   }
   *kcell = (ap < 0 || kv < 0) ? -1 : ap * O->nv + kv;
+  *acell = ap;
 }
 
-static void cells_f(const orc_obs* O, const float s6[6], int copy, int* mcell, int* kcell) {
+static void cells_f(const orc_obs* O, const float s6[6], int copy, int* mcell, int* kcell, int* acell) {
   float sx = (float)MIRROR[copy][0], sy = (float)MIRROR[copy][1], sz = (float)MIRROR[copy][2];
   float x = sx * s6[0], y = sy * s6[1], z = sz * s6[2];
   float px = sx * s6[3], py = sy * s6[4], pz = sz * s6[5];
@@ -683,6 +684,14 @@ static void cells_f(const orc_obs* O, const float s6[6], int copy, int* mcell, i
     ap = O->pix2ap ? O->pix2ap[pix] : pix;
   }
   *kcell = (ap < 0 || kv < 0) ? -1 : ap * O->nv + kv;
+  *acell = ap;
+}
+
+/* kinematic cell as bin_points reports it: with the surface block on, an
+ * event in aperture a whose velocity is outside the range reports n_ap*nv + a */
+static int kin_code(const orc_obs* O, int k, int a) {
+  if (k >= 0) return k;
+  return (O->surface && a >= 0) ? O->n_ap * O->nv + a : -1;
 }
 
 void orc_bin_points_f64(const orc_obs* O, long n, const double* pts, int32_t* mass, int32_t* kin) {
@@ -690,10 +699,10 @@ void orc_bin_points_f64(const orc_obs* O, long n, const double* pts, int32_t* ma
     double s6[6];
     for (int j = 0; j < 6; ++j) s6[j] = pts[j * n + i];
     for (int c = 0; c < 4; ++c) {
-      int m, k;
-      cells_d(O, s6, c, &m, &k);
+      int m, k, a;
+      cells_d(O, s6, c, &m, &k, &a);
       mass[4 * i + c] = m;
-      kin[4 * i + c] = k;
+      kin[4 * i + c] = kin_code(O, k, a);
     }
   }
 }
@@ -703,10 +712,10 @@ void orc_bin_points_f32(const orc_obs* O, long n, const float* pts, int32_t* mas
     float s6[6];
     for (int j = 0; j < 6; ++j) s6[j] = pts[j * n + i];
     for (int c = 0; c < 4; ++c) {
-      int m, k;
-      cells_f(O, s6, c, &m, &k);
+      int m, k, a;
+      cells_f(O, s6, c, &m, &k, &a);
       mass[4 * i + c] = m;
-      kin[4 * i + c] = k;
+      kin[4 * i + c] = kin_code(O, k, a);
     }
   }
 }
@@ -715,7 +724,7 @@ static void integrate_and_bin_impl(const orc_pot* P, const orc_obs* O, long n, c
                                    const double* dt, int nsteps, int32_t* counts, int64_t* overflow,
                                    double* drift, uint8_t* flags, int nthreads, int round_state) {
   int ncon = orc_ncon(O);
-  int nmass = O->nx * O->ny * O->nz;
+  int nmass = O->nx * O->ny * O->nz, nkin = O->n_ap * O->nv;
   int ncopy = O->symmetrize ? 4 : 1;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -736,10 +745,11 @@ static void integrate_and_bin_impl(const orc_pot* P, const orc_obs* O, long n, c
       for (int j = 0; j < 6; ++j)
         if (!isfinite(s[j])) nonfinite = 1;
       for (int c = 0; c < ncopy; ++c) {
-        int m, kc;
-        cells_d(O, s, c, &m, &kc);
+        int m, kc, a;
+        cells_d(O, s, c, &m, &kc, &a);
         if (m >= 0) row[m] += 1; else ovm += 1;
         if (kc >= 0) row[nmass + kc] += 1; else ovk += 1;
+        if (O->surface && a >= 0) row[nmass + nkin + a] += 1;
       }
       if (O->drift_every > 0 && k % O->drift_every == 0) {
         double e = fabs(orc_jacobi(P, s) / E0 - 1.0);

@@ -59,6 +59,9 @@ typedef struct {
   int drift_every;       /* Jacobi energy sampled every this many steps (0 = never) */
   int grid;              /* 0: Cartesian mass grid; 1: cylindrical (R over [lo0, hi0), ny
                             sectors of the whole circle from phi = -pi, z)            */
+  int surface;           /* 1: a surface-density column per aperture after the kinematic
+                            block, every event in the aperture whatever its velocity  */
+  double upsilon;        /* mass-to-light ratio dividing that block (Sec. 2.2.4)        */
 } orc_obs;
 
 /* derived halo constants (Eq. 8-9): out[0] = R_s, out[1] = M_DM, out[2] = R200 */
