@@ -95,7 +95,8 @@ typedef struct {
 } sw_potential;
 
 /* Observables (Sec. 2.2.4).  Column order of the orbit matrix:
- *   [ mass cells (ix*ny + iy)*nz + iz | kinematic cells aperture*nv + v_bin ].
+ *   [ mass cells (ix*ny + iy)*nz + iz | kinematic cells aperture*nv + v_bin
+ *     | surface density per aperture (only with surface = 1) ].
  * grid = SW_GRID_CARTESIAN: mass cells over bar-frame (x, y, z) boxes.
  * grid = SW_GRID_CYLINDRICAL (Sec. 2.2.4's self-consistency grid): ix over
  *   R = sqrt(x^2 + y^2) in [lo[0], hi[0]) (lo[0] >= 0), iy over ny <= 32
@@ -107,6 +108,12 @@ typedef struct {
  *   sine of -pi + 2 pi k / ny computed in double and rounded, the first such k
  *   (k = 0, 1, ...) and the last sector when none passes (the axis x = y = 0,
  *   points on the edge at phi = +-pi).
+ * surface = 1 appends n_ap columns after the kinematic block: the surface
+ *   luminosity of each aperture, every event whose sky position falls in it
+ *   (whatever its velocity) as a time fraction divided by upsilon, computed as
+ *   (count / (copies * steps)) / upsilon in double.  It needs
+ *   n_ap * nv + n_ap < 65535.  bin_points then reports an event in aperture a
+ *   whose velocity is outside [vlo, vhi) as kin = n_ap * nv + a (else -1).
  * A coordinate v falls in bin floor(t), t = (v - lo) * (n / (hi - lo)) taken in
  * the integration precision with n / (hi - lo) rounded from double; it is
  * inside iff 0 <= t < n.  Mass cells use bar-frame (x, y, z); apertures use
@@ -125,6 +132,9 @@ typedef struct {
   double vlo, vhi;
   int32_t symmetrize;  /* 1: co-add the four mirror copies of Table 1; 0: orbit alone */
   int32_t drift_every; /* Jacobi energy sampled every this many steps (0: never) */
+  int32_t surface;     /* 1: append the surface-density block (Sec. 2.2.4), 0: none */
+  int32_t pad;
+  double upsilon;      /* stellar mass-to-light ratio > 0 dividing that block */
 } sw_obs_spec;
 
 /* flags per orbit */

@@ -45,7 +45,8 @@ class ObsSpec(C.Structure):
                 ("npx", C.c_int32), ("npy", C.c_int32), ("plo", C.c_double * 2), ("phi", C.c_double * 2),
                 ("pix2ap", C.c_void_p), ("n_ap", C.c_int32), ("nv", C.c_int32),
                 ("vlo", C.c_double), ("vhi", C.c_double),
-                ("symmetrize", C.c_int32), ("drift_every", C.c_int32)]
+                ("symmetrize", C.c_int32), ("drift_every", C.c_int32),
+                ("surface", C.c_int32), ("pad", C.c_int32), ("upsilon", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -173,7 +174,7 @@ def build_potential(components, omega=0.0, euler=(0.0, 0.0, 0.0)):
 
 def obs_spec(spec, pix2ap=None):
     """spec: dict (nx, ny, nz, lo, hi, npx, npy, plo, phi, nv, vlo, vhi, symmetrize, drift_every,
-    n_ap); pix2ap: optional int32 device tensor."""
+    n_ap, optional grid, surface, upsilon); pix2ap: optional int32 device tensor."""
     o = ObsSpec()
     o.nx, o.ny, o.nz = spec["nx"], spec["ny"], spec["nz"]
     o.grid = 1 if spec.get("grid", "cartesian") == "cylindrical" else 0
@@ -191,11 +192,13 @@ def obs_spec(spec, pix2ap=None):
     o.nv, o.vlo, o.vhi = spec["nv"], spec["vlo"], spec["vhi"]
     o.symmetrize = int(spec.get("symmetrize", 1))
     o.drift_every = int(spec.get("drift_every", 1))
+    o.surface = int(spec.get("surface", 0))
+    o.upsilon = float(spec.get("upsilon", 1.0))
     return o
 
 
 def ncon(obs):
-    return obs.nx * obs.ny * obs.nz + obs.n_ap * obs.nv
+    return obs.nx * obs.ny * obs.nz + obs.n_ap * obs.nv + (obs.n_ap if obs.surface else 0)
 
 
 def _pots_array(pots):

@@ -54,6 +54,7 @@ struct ObsK {
   // cylindrical mass grid: R-edge spacing, sector edge directions (cos, sin) of
   // -pi + 2 pi k / ny, k = 0..ny, in both precisions
   int32_t cyl;
+  int32_t surface;  // surface-density block on: out-of-range velocities keep their aperture
   double rw;
   float rwf;
   double sc[kMaxSectors + 1], ss[kMaxSectors + 1];

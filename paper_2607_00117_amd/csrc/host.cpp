@@ -81,6 +81,9 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k) {
   if (n_ap <= 0) return false;
   int64_t n_mass = (int64_t)o->nx * o->ny * o->nz, n_kin = n_ap * o->nv;
   if (n_mass >= 65535 || n_kin >= 65535) return false;
+  if (o->surface != 0 && o->surface != 1) return false;
+  if (o->surface && (!(std::isfinite(o->upsilon) && o->upsilon > 0.0) || n_kin + n_ap >= 65535)) return false;
+  k->surface = o->surface;
   k->nx = o->nx; k->ny = o->ny; k->nz = o->nz;
   k->npx = o->npx; k->npy = o->npy; k->nv = o->nv;
   k->n_ap = (int32_t)n_ap;

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restric
                                                        int32_t n_steps, int32_t ncopy, int32_t ncell, int32_t opw,
                                                        int32_t wide, int64_t row0, int64_t n_con, int32_t col_off,
                                                        T* __restrict__ A, double* __restrict__ overflow,
-                                                       int32_t slot) {
+                                                       int32_t slot, int32_t fold_nv, int32_t fold_nkin,
+                                                       double div) {
   extern __shared__ uint32_t hist[];
   __shared__ uint32_t ovc[32];
   const int tid = threadIdx.x;
@@ -44,8 +45,11 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restric
     for (int s = tid; s < n_steps; s += kHistThreads) {
       const uint64_t v = e[s];
       for (int c = 0; c < ncopy; ++c) {
-        const uint32_t idx = (uint32_t)(v >> (16 * c)) & 0xFFFFu;
-        if (idx == 0xFFFFu) {
+        uint32_t idx = (uint32_t)(v >> (16 * c)) & 0xFFFFu;
+        // surface pass: kinematic codes ap*nv + v_bin and n_kin + ap fold to ap
+        if (fold_nv > 0 && idx != 0xFFFFu)
+          idx = idx < (uint32_t)fold_nkin ? idx / (uint32_t)fold_nv : idx - (uint32_t)fold_nkin;
+        if (idx >= (uint32_t)ncell) {  // 0xFFFF, or a surface-only code in the kinematic pass
           ++ov;
         } else if (wide) {
           atomicAdd(&hg[idx], 1u);
@@ -67,9 +71,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const uint64_t* __restric
     T* row = A + (row0 + j) * n_con + col_off;
     for (int c = tid; c < ncell; c += kHistThreads) {
       const uint32_t cnt = wide ? hg[c] : (hg[c >> 1] >> ((c & 1) * 16)) & 0xFFFFu;
-      row[c] = (T)((double)cnt / denom);
+      row[c] = (T)((double)cnt / denom / div);
     }
-    if (tid == 0) overflow[(row0 + j) * 2 + slot] = (double)ovc[g] / denom;
+    if (tid == 0 && slot >= 0) overflow[(row0 + j) * 2 + slot] = (double)ovc[g] / denom;
   }
 }
 
@@ -164,7 +168,7 @@ extern "C" size_t integrate_workspace_bytes(const sw_obs_spec* obs, int32_t n_po
 template <typename T>
 static int launch_hist(const uint64_t* ev, int64_t n_chunk, int32_t n_steps, int32_t ncopy, int32_t ncell,
                        int64_t row0, int64_t n_con, int32_t col_off, void* A, double* overflow, int32_t slot,
-                       hipStream_t st) {
+                       hipStream_t st, int32_t fold_nv = 0, int32_t fold_nkin = 0, double div = 1.0) {
   const int wide = (int64_t)ncopy * n_steps > 65535 ? 1 : 0;
   const int nw = wide ? ncell : (ncell + 1) / 2;
   int opw = (g_hist_lds_kb * 1024) / (4 * nw);
@@ -177,7 +181,7 @@ static int launch_hist(const uint64_t* ev, int64_t n_chunk, int32_t n_steps, int
   }
   dim3 grid((unsigned)((n_chunk + opw - 1) / opw)), block(kHistThreads);
   hipLaunchKernelGGL(k_hist<T>, grid, block, lds, st, ev, n_chunk, n_steps, ncopy, ncell, opw, wide, row0, n_con,
-                     col_off, (T*)A, overflow, slot);
+                     col_off, (T*)A, overflow, slot, fold_nv, fold_nkin, div);
   SW_HIP(hipGetLastError());
   return SW_OK;
 }
@@ -205,6 +209,7 @@ extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const 
     SW_CHECK(orbit_offsets[k + 1] >= orbit_offsets[k], "integrate_and_bin: orbit_offsets must be non-decreasing");
   ObsK O;
   SW_CHECK(obs_to_k(obs, &O), "integrate_and_bin: invalid observable specification");
+  const double upsilon = obs->upsilon;
   if (n_orb == 0) return SW_OK;
   SW_CHECK(ics && dt && A && overflow && drift && flags, "integrate_and_bin: null device buffer");
   const size_t hdr = header_bytes(n_pot);
@@ -246,7 +251,7 @@ extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const 
   L.drift = drift;
   L.flags = flags;
   L.bin = true;
-  const int64_t n_con = (int64_t)O.n_mass + O.n_kin;
+  const int64_t n_con = (int64_t)O.n_mass + O.n_kin + (O.surface ? O.n_ap : 0);
   for (int64_t orb0 = 0; orb0 < n_orb; orb0 += chunk) {
     L.orb0 = orb0;
     L.n_chunk = (n_orb - orb0 < chunk) ? n_orb - orb0 : chunk;
@@ -256,10 +261,16 @@ extern "C" int integrate_and_bin(const sw_potential* pots, int32_t n_pot, const 
       rc = launch_hist<float>(L.ev_m, L.n_chunk, n_steps, O.ncopy, O.n_mass, orb0, n_con, 0, A, overflow, 0, st);
       if (rc == SW_OK)
         rc = launch_hist<float>(L.ev_k, L.n_chunk, n_steps, O.ncopy, O.n_kin, orb0, n_con, O.n_mass, A, overflow, 1, st);
+      if (rc == SW_OK && O.surface)
+        rc = launch_hist<float>(L.ev_k, L.n_chunk, n_steps, O.ncopy, O.n_ap, orb0, n_con, O.n_mass + O.n_kin, A,
+                                overflow, -1, st, O.nv, O.n_kin, upsilon);
     } else {
       rc = launch_hist<double>(L.ev_m, L.n_chunk, n_steps, O.ncopy, O.n_mass, orb0, n_con, 0, A, overflow, 0, st);
       if (rc == SW_OK)
         rc = launch_hist<double>(L.ev_k, L.n_chunk, n_steps, O.ncopy, O.n_kin, orb0, n_con, O.n_mass, A, overflow, 1, st);
+      if (rc == SW_OK && O.surface)
+        rc = launch_hist<double>(L.ev_k, L.n_chunk, n_steps, O.ncopy, O.n_ap, orb0, n_con, O.n_mass + O.n_kin, A,
+                                 overflow, -1, st, O.nv, O.n_kin, upsilon);
     }
     if (rc != SW_OK) return rc;
   }

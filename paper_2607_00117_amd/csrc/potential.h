@@ -710,7 +710,9 @@ __device__ __forceinline__ void cells4(const PotK& P, const ObsK& O, const T* s6
       int pix = jx * O.npy + jy;
       ap = O.pix2ap ? O.pix2ap[pix] : pix;
     }
-    kcell[c] = (ap < 0 || kv < 0) ? -1 : ap * O.nv + kv;
+    // with the surface block on, an event in an aperture outside the velocity
+    // range keeps its aperture as code n_kin + ap (counted by that block only)
+    kcell[c] = ap < 0 ? -1 : (kv >= 0 ? ap * O.nv + kv : (O.surface ? O.n_kin + ap : -1));
   }
 }
 
