@@ -66,6 +66,7 @@ def _declare(L):
     L.orc_phi.argtypes = [P, _dp]; L.orc_phi.restype = C.c_double
     L.orc_accel.argtypes = [P, _dp, _dp]; L.orc_accel.restype = None
     L.orc_density.argtypes = [P, _dp]; L.orc_density.restype = C.c_double
+    L.orc_jeans.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, _dp]; L.orc_jeans.restype = None
     L.orc_cell_mass.argtypes = [P, C.POINTER(_Obs), C.c_int, C.c_double, C.c_double]; L.orc_cell_mass.restype = C.c_double
     L.orc_jacobi.argtypes = [P, _dp]; L.orc_jacobi.restype = C.c_double
     L.orc_ferrers_lambda.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
@@ -154,6 +155,18 @@ def cell_masses(pot, obs, cells=None, rel_tol=1e-10, abs_tol=0.0):
     n = obs.nx * obs.ny * obs.nz
     idx = range(n) if cells is None else cells
     return np.array([lib().orc_cell_mass(C.byref(pot), C.byref(obs), int(c), rel_tol, abs_tol) for c in idx])
+
+
+def jeans_ics(pot, pos, eps, h_R, h_z, b=1.0):
+    """Jeans-equation initial conditions (Sec. 2.2.1) at positions pos [3][n]:
+    returns (moments [4][n] = sigma_R, sigma_phi, sigma_z, mean v_phi; ics [6][n])."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    n = pos.shape[1]
+    mom = np.zeros((4, n))
+    ics = np.zeros((6, n))
+    lib().orc_jeans(C.byref(pot), h_R, h_z, b, n, pos, eps, mom, ics)
+    return mom, ics
 
 
 def jacobi(pot, s):

@@ -872,3 +872,83 @@ double orc_cell_mass(const orc_pot* P, const orc_obs* O, int cell, double rel_to
   C.atol[2] = abs_tol / (l0 * rmax * l1);
   return cm_adapt(cm_f1, &C, C.lo[0], C.hi[0], rel_tol, abs_tol, 0);
 }
+
+/* ------------------------------------------------------------------ */
+/* Initial velocities from the anisotropic Jeans equations in the       */
+/* axisymmetrised potential (Sec. 2.2.1).  Tracer density: the fiducial */
+/* nu(R, z) ~ exp(-R/hR - |z|/hz) the positions are drawn from; the      */
+/* velocity ellipsoid is aligned with (R, phi, z), sigma_R^2 = b         */
+/* sigma_z^2.  With F the azimuth-averaged force:                        */
+/*   sigma_z^2(R, z) = (1/nu) int_|z|^inf nu(R, z') (-F_z(R, z')) dz'    */
+/*                   = hz int_0^inf e^-s (-F_z(R, |z| + hz s)) ds,      */
+/*   <v_phi^2> = b sigma_z^2 + (R/nu) d(b nu sigma_z^2)/dR - R F_R(R, z) */
+/*             = b [sigma_z^2 (1 - R/hR) + R d sigma_z^2/dR] - R F_R,    */
+/*   sigma_phi = sigma_R (isotropic in the plane), and the mean          */
+/*   azimuthal velocity sqrt(max(<v_phi^2> - sigma_phi^2, 0)) (the        */
+/*   rotation curve less the asymmetric drift).                          */
+/* Every integral is adaptive Gauss-Kronrod; d/dR is a Richardson-        */
+/* extrapolated central difference.                                      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  const orc_pot* P;
+  double R, z, tol;
+  int comp; /* 0: F_R, 1: F_z */
+  double hz, zabs;
+} jn_ctx;
+
+static double jn_fphi(void* c, double ph) {
+  jn_ctx* C = (jn_ctx*)c;
+  double x[3] = {C->R * cos(ph), C->R * sin(ph), C->z}, g[3];
+  orc_accel(C->P, x, g);
+  return C->comp == 0 ? g[0] * cos(ph) + g[1] * sin(ph) : g[2];
+}
+
+/* azimuth average of F_R (comp 0) or F_z (comp 1) at (R, z) */
+static double jn_favg(const orc_pot* P, double R, double z, int comp, double tol) {
+  jn_ctx C = {P, R, z, tol, comp, 0.0, 0.0};
+  return cm_adapt(jn_fphi, &C, 0.0, 2.0 * M_PI, tol, 1e-300, 0) / (2.0 * M_PI);
+}
+
+static double jn_fs(void* c, double s) {
+  jn_ctx* C = (jn_ctx*)c;
+  return exp(-s) * -jn_favg(C->P, C->R, C->zabs + C->hz * s, 1, C->tol);
+}
+
+static double jn_sigz2(const orc_pot* P, double R, double z, double hz, double tol) {
+  jn_ctx C = {P, R, 0.0, tol, 1, hz, fabs(z)};
+  /* e^-s below 1e-30 of its start beyond s = 70 */
+  double a = 0.0, s = 0.0;
+  for (double b = 0.5; b <= 70.0; b *= 2.0) { /* panels [0,.5], [.5,1], [1,2], ... */
+    a += cm_adapt(jn_fs, &C, s, b, tol, 1e-300, 0);
+    s = b;
+  }
+  return hz * a;
+}
+
+void orc_jeans(const orc_pot* P, double hR, double hz, double b, long n, const double* pos, const double* eps,
+               double* mom, double* ics) {
+  const double tol = 1e-11;
+  for (long i = 0; i < n; ++i) {
+    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    double R = sqrt(x * x + y * y), ph = atan2(y, x);
+    double s0 = jn_sigz2(P, R, z, hz, tol);
+    double h = 2e-3 * fmax(R, hz);
+    double d1 = (jn_sigz2(P, R + h, z, hz, tol) - jn_sigz2(P, R - h, z, hz, tol)) / (2.0 * h);
+    double d2 = (jn_sigz2(P, R + 0.5 * h, z, hz, tol) - jn_sigz2(P, R - 0.5 * h, z, hz, tol)) / h;
+    double dsig = (4.0 * d2 - d1) / 3.0;
+    double vphi2 = b * (s0 * (1.0 - R / hR) + R * dsig) - R * jn_favg(P, R, z, 0, tol);
+    double sz = sqrt(fmax(s0, 0.0)), sR = sqrt(b) * sz, sp = sR;
+    double vc = sqrt(fmax(vphi2 - b * s0, 0.0));
+    mom[i] = sR;
+    mom[n + i] = sp;
+    mom[2 * n + i] = sz;
+    mom[3 * n + i] = vc;
+    double vR = sR * eps[i], vp = vc + sp * eps[n + i], vz = sz * eps[2 * n + i];
+    ics[i] = x;
+    ics[n + i] = y;
+    ics[2 * n + i] = z;
+    ics[3 * n + i] = vR * cos(ph) - vp * sin(ph);
+    ics[4 * n + i] = vR * sin(ph) + vp * cos(ph);
+    ics[5 * n + i] = vz;
+  }
+}

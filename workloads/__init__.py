@@ -138,6 +138,24 @@ def disc_ics(table, n, seed=3, n_steps=10000, periods=50.0, h_R=3.5, h_z=1.2, R_
     return ics, dt
 
 
+def disc_positions(n, seed=3, h_R=3.5, h_z=1.2, R_max=15.0, z_max=5.0):
+    """Starting positions [3][n] from the fiducial p(R, z) ~ R exp(-R/h_R)
+    exp(-|z|/h_z) truncated at R_max, z_max, uniform azimuth, and the standard
+    normal deviates [3][n] of their velocity draws (v_R, v_phi, v_z)."""
+    rng = np.random.default_rng(seed + 500)
+    Rs = np.empty(0)
+    while Rs.size < n:
+        r = rng.gamma(2.0, h_R, size=2 * n)
+        Rs = np.concatenate([Rs, r[(r < R_max) & (r > 1e-3)]])
+    zs = np.empty(0)
+    while zs.size < n:
+        z = rng.laplace(0.0, h_z, size=2 * n)
+        zs = np.concatenate([zs, z[np.abs(z) < z_max]])
+    Rs, zs = Rs[:n], zs[:n]
+    ph = rng.uniform(0.0, 2 * math.pi, size=n)
+    return np.stack([Rs * np.cos(ph), Rs * np.sin(ph), zs]), rng.standard_normal((3, n))
+
+
 def mock_draw(n_orb, seed, frac=0.1):
     """Seeded subset of round(frac N) orbits with weights ~ Exp(1)."""
     rng = np.random.default_rng(seed)
