@@ -16,6 +16,7 @@
  *                      the orbit weights by ADMM (linear solve + clip + dual update).
  *   chi2               Sec. 2.4, Eq. 5: chi^2 over a constraint range.
  *   cell_masses        Sec. 2.2.4: target masses m*_n of the density grid.
+ *   jeans_ics          Sec. 2.2.1: Jeans-equation velocities of the initial conditions.
  *
  * Conventions shared by every entry point
  *  - Units: kpc, km/s, Msun; G = 4.300917270e-6 kpc (km/s)^2 / Msun; time in
@@ -338,6 +339,28 @@ int model_observables(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con
  * Only the mass-grid fields of obs are read (nx, ny, nz, lo, hi, grid). */
 int cell_masses(const sw_potential* pot, const sw_obs_spec* obs, uint32_t comp_mask, int32_t n_sub, double* out,
                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * jeans_ics (Sec. 2.2.1): initial conditions of the orbit library from the
+ * anisotropic Jeans equations in the azimuth-averaged potential pot (all
+ * components, bar frame, no rotation terms).  The tracer has the fiducial
+ * density nu ~ exp(-R/h_R - |z|/h_z) the positions are drawn from; the velocity
+ * ellipsoid is aligned with (R, phi, z) with sigma_R^2 = b sigma_z^2 and
+ * sigma_phi = sigma_R:
+ *   sigma_z^2 = h_z int_0^inf e^-s (-F_z(R, |z| + h_z s)) ds,
+ *   <v_phi^2> = b [sigma_z^2 (1 - R/h_R) + R d sigma_z^2/dR] - R F_R(R, z),
+ *   mean v_phi = sqrt(max(<v_phi^2> - sigma_phi^2, 0)),
+ * F the azimuth average of the force (128-point trapezoid rule), the s-integral
+ * by 13 graded panels of 8-point Gauss-Legendre, d/dR by Richardson-combined
+ * central differences (steps h, h/2; h = 2e-3 max(R, h_z)).  FP64.
+ *   pos       device [3][n] double: starting positions (bar frame, kpc)
+ *   eps       device [3][n] double: standard normal deviates for v_R, v_phi, v_z
+ *   moments   device [4][n] double out: sigma_R, sigma_phi, sigma_z, mean v_phi
+ *   ics       device [6][n] double out: positions and velocities
+ *             v_R = sigma_R eps0, v_phi = mean + sigma_phi eps1, v_z = sigma_z eps2
+ *             (prograde about +z), as integrate_and_bin takes them. */
+int jeans_ics(const sw_potential* pot, const double* pos, const double* eps, int64_t n, double h_R, double h_z,
+              double b, double* moments, double* ics, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Test and inspection entry points.

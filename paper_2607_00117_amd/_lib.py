@@ -110,6 +110,7 @@ def load():
     L.model_observables.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     L.bin_points.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), vp, i64, i32, vp, vp, vp]
     L.cell_masses.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), C.c_uint32, i32, vp, vp]
+    L.jeans_ics.argtypes = [C.POINTER(Potential), vp, vp, i64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
     L.integrate_orbits.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, i32, vp, vp]
     L.mlp_param_count.restype = i64
     L.mlp_workspace_bytes.argtypes = [i64]
@@ -328,6 +329,12 @@ def bin_points(pot, obs, pts, mass, kin):
 def cell_masses(pot, obs, comp_mask, n_sub, out):
     """m*_n of the components selected by comp_mask into out (device double [n_mass])."""
     _check(load().cell_masses(C.byref(pot), C.byref(obs), int(comp_mask), int(n_sub), _ptr(out), _stream()))
+
+
+def jeans_ics(pot, pos, eps, h_R, h_z, b, moments, ics):
+    """Jeans-equation initial conditions at pos (device double [3][n])."""
+    _check(load().jeans_ics(C.byref(pot), _ptr(pos), _ptr(eps), pos.shape[1], float(h_R), float(h_z), float(b),
+                            _ptr(moments), _ptr(ics), _stream()))
 
 
 def integrate_orbits(pot, ics, dt, n_steps, out):

@@ -28,6 +28,7 @@ SOURCES = {
     "gh.hip": [],
     "bootstrap.hip": [],
     "cellmass.hip": [],
+    "jeans.hip": [],
 }
 
 

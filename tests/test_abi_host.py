@@ -127,6 +127,20 @@ def test_cell_masses_validation_before_launch():
     assert call(obs_=cyl) == -1
 
 
+def test_jeans_ics_validation_before_launch():
+    L = P.load()
+    pot = P.build_potential([("mn", (5e10, 3.0, 0.3))])
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def call(n=4, hR=3.5, hz=1.2, b=1.0, out=fake):
+        return L.jeans_ics(C.byref(pot), fake, fake, n, hR, hz, b, fake, out, None)
+    assert call(n=-1) == -1
+    assert call(hR=0.0) == -1 and call(hz=float("nan")) == -1
+    assert call(b=0.0) == -1
+    assert call(out=None) == -1
+    assert call(n=0, out=None) == 0          # nothing to do
+
+
 def test_solve_and_chi2_validation_before_launch():
     L = P.load()
     opts = _lib.SolveOpts()
