@@ -159,11 +159,11 @@ def cell_masses(pot, obs, cells=None, rel_tol=1e-10, abs_tol=0.0):
 
 def jeans_ics(pot, pos, eps, h_R, h_z, b=1.0):
     """Jeans-equation initial conditions (Sec. 2.2.1) at positions pos [3][n]:
-    returns (moments [4][n] = sigma_R, sigma_phi, sigma_z, mean v_phi; ics [6][n])."""
+    returns (moments [5][n] = sigma_R, sigma_phi, sigma_z, mean v_phi, v_c; ics [6][n])."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     n = pos.shape[1]
-    mom = np.zeros((4, n))
+    mom = np.zeros((5, n))
     ics = np.zeros((6, n))
     lib().orc_jeans(C.byref(pot), h_R, h_z, b, n, pos, eps, mom, ics)
     return mom, ics

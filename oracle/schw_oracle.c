@@ -936,13 +936,15 @@ void orc_jeans(const orc_pot* P, double hR, double hz, double b, long n, const d
     double d1 = (jn_sigz2(P, R + h, z, hz, tol) - jn_sigz2(P, R - h, z, hz, tol)) / (2.0 * h);
     double d2 = (jn_sigz2(P, R + 0.5 * h, z, hz, tol) - jn_sigz2(P, R - 0.5 * h, z, hz, tol)) / h;
     double dsig = (4.0 * d2 - d1) / 3.0;
-    double vphi2 = b * (s0 * (1.0 - R / hR) + R * dsig) - R * jn_favg(P, R, z, 0, tol);
+    double vcz2 = -R * jn_favg(P, R, z, 0, tol); /* circular speed^2 at the star's (R, z) */
+    double vphi2 = b * (s0 * (1.0 - R / hR) + R * dsig) + vcz2;
     double sz = sqrt(fmax(s0, 0.0)), sR = sqrt(b) * sz, sp = sR;
     double vc = sqrt(fmax(vphi2 - b * s0, 0.0));
     mom[i] = sR;
     mom[n + i] = sp;
     mom[2 * n + i] = sz;
     mom[3 * n + i] = vc;
+    mom[4 * n + i] = sqrt(fmax(vcz2, 0.0));
     double vR = sR * eps[i], vp = vc + sp * eps[n + i], vz = sz * eps[2 * n + i];
     ics[i] = x;
     ics[n + i] = y;

@@ -109,7 +109,8 @@ void orc_bin_points_f32(const orc_obs* O, long n, const float* pts, int32_t* mas
 double orc_cell_mass(const orc_pot* P, const orc_obs* O, int cell, double rel_tol, double abs_tol);
 
 /* Jeans-equation initial velocities (Sec. 2.2.1) at n positions pos [3][n]
- * (bar frame): mom [4][n] = sigma_R, sigma_phi, sigma_z, mean v_phi; ics [6][n] =
+ * (bar frame): mom [5][n] = sigma_R, sigma_phi, sigma_z, mean v_phi, v_c
+ * (circular speed sqrt(-R F_R) at the star's (R, z)); ics [6][n] =
  * positions and velocities v_R = sigma_R eps0, v_phi = mean + sigma_phi eps1,
  * v_z = sigma_z eps2 (eps [3][n] standard normal deviates). */
 void orc_jeans(const orc_pot* P, double hR, double hz, double b, long n, const double* pos, const double* eps,

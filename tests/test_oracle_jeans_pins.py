@@ -56,6 +56,7 @@ def test_point_mass_radial_jeans_equation(R, z, b):
     assert mom[2, 0] ** 2 == pytest.approx(s2, rel=1e-9)
     assert mom[0, 0] ** 2 == pytest.approx(b * s2, rel=1e-9)
     assert mom[3, 0] == pytest.approx(mean, rel=1e-7)
+    assert mom[4, 0] == pytest.approx(math.sqrt(GM * R * R / (R * R + z * z) ** 1.5), rel=1e-10)
 
 
 def test_barred_azimuth_average_matches_trapezoid():

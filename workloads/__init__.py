@@ -156,6 +156,12 @@ def disc_positions(n, seed=3, h_R=3.5, h_z=1.2, R_max=15.0, z_max=5.0):
     return np.stack([Rs * np.cos(ph), Rs * np.sin(ph), zs]), rng.standard_normal((3, n))
 
 
+def dither_deviates(n_dither, n, seed=5):
+    """Uniform deviates on [-1/2, 1/2) [n_dither][6][n] placing each initial
+    condition's realisations in the box around it."""
+    return np.random.default_rng(seed + 700).uniform(-0.5, 0.5, size=(n_dither, 6, n))
+
+
 def mock_draw(n_orb, seed, frac=0.1):
     """Seeded subset of round(frac N) orbits with weights ~ Exp(1)."""
     rng = np.random.default_rng(seed)
