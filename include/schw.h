@@ -16,7 +16,8 @@
  *                      the orbit weights by ADMM (linear solve + clip + dual update).
  *   chi2               Sec. 2.4, Eq. 5: chi^2 over a constraint range.
  *   cell_masses        Sec. 2.2.4: target masses m*_n of the density grid.
- *   jeans_ics          Sec. 2.2.1: Jeans-equation velocities of the initial conditions.
+ *   jeans_ics          Sec. 2.2.1: Jeans-equation velocities of the initial conditions;
+ *   dither_ics, bundle_rows   dithered realisations and their bundle means.
  *
  * Conventions shared by every entry point
  *  - Units: kpc, km/s, Msun; G = 4.300917270e-6 kpc (km/s)^2 / Msun; time in
@@ -355,12 +356,30 @@ int cell_masses(const sw_potential* pot, const sw_obs_spec* obs, uint32_t comp_m
  * central differences (steps h, h/2; h = 2e-3 max(R, h_z)).  FP64.
  *   pos       device [3][n] double: starting positions (bar frame, kpc)
  *   eps       device [3][n] double: standard normal deviates for v_R, v_phi, v_z
- *   moments   device [4][n] double out: sigma_R, sigma_phi, sigma_z, mean v_phi
+ *   moments   device [5][n] double out: sigma_R, sigma_phi, sigma_z, mean v_phi and
+ *             v_c = sqrt(-R F_R(R, z)), the circular speed at the position
  *   ics       device [6][n] double out: positions and velocities
  *             v_R = sigma_R eps0, v_phi = mean + sigma_phi eps1, v_z = sigma_z eps2
  *             (prograde about +z), as integrate_and_bin takes them. */
 int jeans_ics(const sw_potential* pot, const double* pos, const double* eps, int64_t n, double h_R, double h_z,
               double b, double* moments, double* ics, void* stream);
+
+/* dither_ics (Sec. 2.2.1): n_dither (1..64) realisations of each initial
+ * condition on a box around it: out[c][i*n_dither + k] = ics[c][i] +
+ * u[k][c][i] * (dx for positions, fv * vc[i] for velocities), each product and
+ * sum rounded in FP64 (the paper: dx = 0.1 kpc, fv = 0.05, n_dither = 4).
+ *   ics device [6][n], vc device [n] (jeans_ics' moment 4), u device
+ *   [n_dither][6][n] deviates (uniform on [-1/2, 1/2) for the paper's box),
+ *   out device [6][n*n_dither] double.  The realisations of one initial
+ *   condition are consecutive, so each bundle is a run of rows of A.
+ * bundle_rows: out[b][c] = (sum_k A[b*n_dither + k][c]) / n_dither, summed in
+ *   row order in FP64 and rounded to dtype: the orbit matrix of the bundles,
+ *   each entering the fit as one orbit.  A device [n_bundle*n_dither][n_con],
+ *   out device [n_bundle][n_con] (dtype), not aliased. */
+int dither_ics(const double* ics, const double* vc, const double* u, int64_t n, int32_t n_dither, double dx, double fv,
+               double* out, void* stream);
+int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, int32_t n_dither, void* out,
+                void* stream);
 
 /* ---------------------------------------------------------------------------
  * Test and inspection entry points.

@@ -111,6 +111,8 @@ def load():
     L.bin_points.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), vp, i64, i32, vp, vp, vp]
     L.cell_masses.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), C.c_uint32, i32, vp, vp]
     L.jeans_ics.argtypes = [C.POINTER(Potential), vp, vp, i64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
+    L.dither_ics.argtypes = [vp, vp, vp, i64, i32, C.c_double, C.c_double, vp, vp]
+    L.bundle_rows.argtypes = [vp, i32, i64, i64, i32, vp, vp]
     L.integrate_orbits.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, i32, vp, vp]
     L.mlp_param_count.restype = i64
     L.mlp_workspace_bytes.argtypes = [i64]
@@ -332,9 +334,20 @@ def cell_masses(pot, obs, comp_mask, n_sub, out):
 
 
 def jeans_ics(pot, pos, eps, h_R, h_z, b, moments, ics):
-    """Jeans-equation initial conditions at pos (device double [3][n])."""
+    """Jeans-equation initial conditions at pos (device double [3][n]); moments [5][n], ics [6][n]."""
     _check(load().jeans_ics(C.byref(pot), _ptr(pos), _ptr(eps), pos.shape[1], float(h_R), float(h_z), float(b),
                             _ptr(moments), _ptr(ics), _stream()))
+
+
+def dither_ics(ics, vc, u, dx, fv, out):
+    """n_dither = u.shape[0] realisations of each initial condition into out [6][n*n_dither]."""
+    _check(load().dither_ics(_ptr(ics), _ptr(vc), _ptr(u), ics.shape[1], u.shape[0], float(dx), float(fv), _ptr(out),
+                             _stream()))
+
+
+def bundle_rows(A, n_dither, out):
+    """out[b] = mean of rows b*n_dither .. (b+1)*n_dither - 1 of A."""
+    _check(load().bundle_rows(_ptr(A), _dtype_code(A), out.shape[0], A.shape[1], int(n_dither), _ptr(out), _stream()))
 
 
 def integrate_orbits(pot, ics, dt, n_steps, out):

@@ -1,5 +1,8 @@
-// Initial conditions of the orbit library from the anisotropic Jeans equations
-// (Sec. 2.2.1): at each starting position, the velocity dispersions and the
+// Initial conditions of the orbit library (Sec. 2.2.1): velocities from the
+// anisotropic Jeans equations, dithered realisations, and the bundle means of
+// the orbit matrix.
+//
+// jeans_ics: at each starting position, the velocity dispersions and the
 // mean rotation of a tracer with the fiducial density
 // nu(R, z) ~ exp(-R/h_R - |z|/h_z) in the azimuth-averaged potential, then one
 // Gaussian draw per velocity component.
@@ -108,6 +111,7 @@ __global__ __launch_bounds__(kJnThreads) void k_jeans(PotK P, JeansK K, const do
     mom[n + i] = sR;
     mom[2 * n + i] = sz;
     mom[3 * n + i] = mean;
+    mom[4 * n + i] = sqrt(fmax(-R * FR, 0.0));
     const double ph = atan2(y, x), c = cos(ph), sn = sin(ph);
     const double vR = sR * eps[i], vp = mean + sR * eps[n + i], vz = sz * eps[2 * n + i];
     ics[i] = x;
@@ -117,6 +121,33 @@ __global__ __launch_bounds__(kJnThreads) void k_jeans(PotK P, JeansK K, const do
     ics[4 * n + i] = vR * sn + vp * c;
     ics[5 * n + i] = vz;
   }
+}
+
+// realisation k of initial condition i -> column i nd + k: each coordinate
+// moved by its deviate times dx (positions) or fv v_c (velocities); products
+// and sums rounded separately
+__global__ void k_dither(const double* __restrict__ ics, const double* __restrict__ vc, const double* __restrict__ u,
+                         int64_t n, int32_t nd, double dx, double fv, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, m = n * nd;
+  if (j >= m) return;
+  const int64_t i = j / nd, k = j % nd;
+  for (int c = 0; c < 6; ++c) {
+    const double scale = c < 3 ? dx : fv * vc[i];
+    out[c * m + j] = ics[c * n + i] + u[(k * 6 + c) * n + i] * scale;
+  }
+}
+
+// bundle row b = mean of rows b nd .. b nd + nd - 1, summed in row order in FP64
+template <typename T>
+__global__ void k_bundle(const T* __restrict__ A, int64_t nb, int64_t C, int32_t nd, T* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * C) return;
+  const int64_t b = idx / C, c = idx % C;
+  const T* a = A + (b * nd) * C + c;
+  double s = (double)a[0];
+  for (int k = 1; k < nd; ++k) s = s + (double)a[(int64_t)k * C];
+  out[idx] = (T)(s / nd);
 }
 
 // n-point Gauss-Legendre rule on [-1, 1] by Newton's iteration on P_n
@@ -170,6 +201,40 @@ extern "C" int jeans_ics(const sw_potential* pot, const double* pos, const doubl
     hipLaunchKernelGGL(k_jeans<true>, dim3((unsigned)n), dim3(kJnThreads), 0, st, P, K, pos, eps, n, moments, ics);
   else
     hipLaunchKernelGGL(k_jeans<false>, dim3((unsigned)n), dim3(kJnThreads), 0, st, P, K, pos, eps, n, moments, ics);
+  SW_HIP(hipGetLastError());
+  return SW_OK;
+}
+
+extern "C" int dither_ics(const double* ics, const double* vc, const double* u, int64_t n, int32_t n_dither, double dx,
+                          double fv, double* out, void* stream) {
+  SW_CHECK(n >= 0 && n_dither >= 1 && n_dither <= 64, "dither_ics: need n >= 0 and 1 <= n_dither <= 64");
+  SW_CHECK(std::isfinite(dx) && dx >= 0.0 && std::isfinite(fv) && fv >= 0.0, "dither_ics: box sizes must be >= 0");
+  if (n == 0) return SW_OK;
+  SW_CHECK(ics && vc && u && out, "dither_ics: null device buffer");
+  const int64_t m = n * n_dither;
+  SW_CHECK((m + 255) / 256 <= 0x7fffffff, "dither_ics: too many realisations for one launch");
+  hipLaunchKernelGGL(k_dither, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, (hipStream_t)stream, ics, vc, u, n,
+                     n_dither, dx, fv, out);
+  SW_HIP(hipGetLastError());
+  return SW_OK;
+}
+
+extern "C" int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, int32_t n_dither, void* out,
+                           void* stream) {
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "bundle_rows: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_bundle >= 0 && n_con >= 0 && n_dither >= 1, "bundle_rows: need n_bundle, n_con >= 0, n_dither >= 1");
+  const int64_t m = n_bundle * n_con;
+  if (m == 0) return SW_OK;
+  SW_CHECK(A && out && A != out, "bundle_rows: null or aliased device buffer");
+  SW_CHECK((m + 255) / 256 <= 0x7fffffff, "bundle_rows: too many entries for one launch");
+  const dim3 grid((unsigned)((m + 255) / 256));
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SW_F32)
+    hipLaunchKernelGGL(k_bundle<float>, grid, dim3(256), 0, st, (const float*)A, n_bundle, n_con, n_dither,
+                       (float*)out);
+  else
+    hipLaunchKernelGGL(k_bundle<double>, grid, dim3(256), 0, st, (const double*)A, n_bundle, n_con, n_dither,
+                       (double*)out);
   SW_HIP(hipGetLastError());
   return SW_OK;
 }

@@ -139,6 +139,11 @@ def test_jeans_ics_validation_before_launch():
     assert call(b=0.0) == -1
     assert call(out=None) == -1
     assert call(n=0, out=None) == 0          # nothing to do
+    assert L.dither_ics(fake, fake, fake, 4, 0, 0.1, 0.05, fake, None) == -1   # no realisations
+    assert L.dither_ics(fake, fake, fake, 4, 4, -0.1, 0.05, fake, None) == -1  # negative box
+    assert L.bundle_rows(fake, 3, 2, 5, 4, fake, None) == -1                   # dtype
+    assert L.bundle_rows(fake, 1, 2, 5, 4, fake, None) == -1                   # aliased
+    assert L.bundle_rows(fake, 1, 2, 5, 0, C.c_void_p(0x2000), None) == -1     # n_dither = 0
 
 
 def test_solve_and_chi2_validation_before_launch():
