@@ -67,6 +67,11 @@ def _declare(L):
     L.orc_accel.argtypes = [P, _dp, _dp]; L.orc_accel.restype = None
     L.orc_density.argtypes = [P, _dp]; L.orc_density.restype = C.c_double
     L.orc_jeans.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_long, _dp, _dp, _dp, _dp]; L.orc_jeans.restype = None
+    L.orc_orbit_bs23.argtypes = [P, _dp, C.c_double, C.c_int, C.c_double, C.c_double, _dp, _dp]
+    L.orc_orbit_bs23.restype = None
+    L.orc_integrate_bs23_and_bin.argtypes = [P, C.POINTER(_Obs), C.c_long, _dp, _dp, C.c_int, C.c_double, C.c_double,
+                                             _dp, _dp, _dp, _u8, C.c_int]
+    L.orc_integrate_bs23_and_bin.restype = None
     L.orc_cell_mass.argtypes = [P, C.POINTER(_Obs), C.c_int, C.c_double, C.c_double]; L.orc_cell_mass.restype = C.c_double
     L.orc_jacobi.argtypes = [P, _dp]; L.orc_jacobi.restype = C.c_double
     L.orc_ferrers_lambda.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
@@ -208,6 +213,29 @@ def integrate_and_bin(pot, obs, ics, dt, nsteps, nthreads=0, f32_state=False):
     fn = lib().orc_integrate_and_bin_f32state if f32_state else lib().orc_integrate_and_bin
     fn(C.byref(pot), C.byref(obs), n, ics, dt, nsteps, counts, ov, drift, flags, nthreads)
     return counts, ov, drift, flags
+
+
+def orbit_bs23(pot, ic, h0, nsteps, rtol, atol):
+    """Adaptive BS23 orbit: (traj [nsteps+1][6], dts [nsteps])."""
+    traj = np.zeros((nsteps + 1, 6))
+    dts = np.zeros(nsteps)
+    lib().orc_orbit_bs23(C.byref(pot), np.ascontiguousarray(ic, dtype=np.float64), float(h0), int(nsteps),
+                         float(rtol), float(atol), traj, dts)
+    return traj, dts
+
+
+def integrate_bs23_and_bin(pot, obs, ics, h0, nsteps, rtol, atol, nthreads=0):
+    """Adaptive BS23 with time-weighted binning: (A [n][ncon] fractions,
+    overflow [n][2] fractions, drift [n], flags [n])."""
+    ics = np.ascontiguousarray(ics, dtype=np.float64)
+    n = ics.shape[1]
+    A = np.zeros((n, ncon(obs)))
+    ov = np.zeros((n, 2))
+    drift = np.zeros(n)
+    flags = np.zeros(n, dtype=np.uint8)
+    lib().orc_integrate_bs23_and_bin(C.byref(pot), C.byref(obs), n, ics, np.ascontiguousarray(h0, dtype=np.float64),
+                                     int(nsteps), float(rtol), float(atol), A, ov, drift, flags, nthreads)
+    return A, ov, drift, flags
 
 
 def bin_points(obs, pts, precision="f64"):

@@ -954,3 +954,116 @@ void orc_jeans(const orc_pot* P, double hR, double hz, double b, long n, const d
     ics[5 * n + i] = vz;
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* Adaptive Bogacki-Shampine 3(2) integration (Sec. 2.2.2) with a fixed */
+/* number of accepted steps, and the time-weighted binning of Sec.      */
+/* 2.2.4: the state after accepted step k is a sample of weight         */
+/* dt_k / t_total, t_total the sum of the accepted steps.               */
+/* Equations of motion in the bar frame, (x, p) with p the inertial     */
+/* velocity on the rotating axes:                                       */
+/*   dx/dt = p + Omega (y, -x, 0),  dp/dt = -grad Phi + Omega (p_y, -p_x, 0). */
+/* Error per step: max_i |y3_i - y2_i| / (atol + rtol max(|y_i|, |y3_i|)); */
+/* accepted when <= 1; next step h min(5, max(0.2, 0.9 err^(-1/3))).     */
+/* ------------------------------------------------------------------ */
+static void bs_rhs(const orc_pot* P, const double* y, double* f) {
+  double g[3];
+  orc_accel(P, y, g);
+  double W = P->omega;
+  f[0] = y[3] + W * y[1];
+  f[1] = y[4] - W * y[0];
+  f[2] = y[5];
+  f[3] = g[0] + W * y[4];
+  f[4] = g[1] - W * y[3];
+  f[5] = g[2];
+}
+
+/* one accepted step from y (k1 = f(y) on entry, f(y_new) on return); h is the
+ * step tried first and, on return, the next one; returns the step taken, or 0
+ * after 100 rejections in a row */
+static double bs_step(const orc_pot* P, double* y, double* k1, double* h, double rtol, double atol) {
+  for (int tries = 0; tries < 100; ++tries) {
+    double hh = *h, t[6], k2[6], k3[6], y3[6], k4[6];
+    for (int i = 0; i < 6; ++i) t[i] = y[i] + 0.5 * hh * k1[i];
+    bs_rhs(P, t, k2);
+    for (int i = 0; i < 6; ++i) t[i] = y[i] + 0.75 * hh * k2[i];
+    bs_rhs(P, t, k3);
+    for (int i = 0; i < 6; ++i) y3[i] = y[i] + hh * (2.0 / 9.0 * k1[i] + 1.0 / 3.0 * k2[i] + 4.0 / 9.0 * k3[i]);
+    bs_rhs(P, y3, k4);
+    double err = 0.0;
+    for (int i = 0; i < 6; ++i) {
+      double y2 = y[i] + hh * (7.0 / 24.0 * k1[i] + 0.25 * k2[i] + 1.0 / 3.0 * k3[i] + 0.125 * k4[i]);
+      double sc = atol + rtol * fmax(fabs(y[i]), fabs(y3[i]));
+      err = fmax(err, fabs(y3[i] - y2) / sc);
+    }
+    double fac = err > 0.0 ? 0.9 * pow(err, -1.0 / 3.0) : 5.0;
+    fac = fmin(5.0, fmax(0.2, fac));
+    if (err <= 1.0) {
+      for (int i = 0; i < 6; ++i) { y[i] = y3[i]; k1[i] = k4[i]; }
+      *h = hh * fac;
+      return hh;
+    }
+    *h = hh * fac;
+  }
+  return 0.0;
+}
+
+void orc_orbit_bs23(const orc_pot* P, const double ic[6], double h0, int nsteps, double rtol, double atol,
+                    double* traj, double* dts) {
+  double y[6], k1[6], h = h0;
+  for (int i = 0; i < 6; ++i) { y[i] = ic[i]; traj[i] = ic[i]; }
+  bs_rhs(P, y, k1);
+  for (int k = 1; k <= nsteps; ++k) {
+    dts[k - 1] = bs_step(P, y, k1, &h, rtol, atol);
+    for (int i = 0; i < 6; ++i) traj[6 * k + i] = y[i];
+  }
+}
+
+void orc_integrate_bs23_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics, const double* h0,
+                                int nsteps, double rtol, double atol, double* A, double* overflow, double* drift,
+                                uint8_t* flags, int nthreads) {
+  int ncon = orc_ncon(O), nmass = O->nx * O->ny * O->nz, nkin = O->n_ap * O->nv;
+  int ncopy = O->symmetrize ? 4 : 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (long i = 0; i < n; ++i) {
+    double y[6], k1[6], h = h0[i];
+    for (int j = 0; j < 6; ++j) y[j] = ics[j * n + i];
+    double* row = A + i * (long)ncon;
+    for (int c = 0; c < ncon; ++c) row[c] = 0.0;
+    double ovm = 0.0, ovk = 0.0, ttot = 0.0, E0 = orc_jacobi(P, y), dmax = 0.0;
+    int bad = 0;
+    bs_rhs(P, y, k1);
+    for (int k = 1; k <= nsteps; ++k) {
+      double dt = bs_step(P, y, k1, &h, rtol, atol);
+      if (dt == 0.0) bad = 1;
+      for (int j = 0; j < 6; ++j)
+        if (!isfinite(y[j])) bad = 1;
+      ttot += dt;
+      for (int c = 0; c < ncopy; ++c) {
+        int m, kc, a;
+        cells_d(O, y, c, &m, &kc, &a);
+        if (m >= 0) row[m] += dt; else ovm += dt;
+        if (kc >= 0) row[nmass + kc] += dt; else ovk += dt;
+        if (O->surface && a >= 0) row[nmass + nkin + a] += dt;
+      }
+      if (O->drift_every > 0 && k % O->drift_every == 0) {
+        double e = fabs(orc_jacobi(P, y) / E0 - 1.0);
+        if (!(e <= dmax)) dmax = e;
+      }
+    }
+    double den = (double)ncopy * ttot;
+    for (int c = 0; c < ncon; ++c) row[c] /= den;
+    if (O->surface)
+      for (int c = nmass + nkin; c < ncon; ++c) row[c] /= O->upsilon;
+    overflow[2 * i] = ovm / den;
+    overflow[2 * i + 1] = ovk / den;
+    drift[i] = dmax;
+    uint8_t f = 0;
+    if (!(dmax <= 0.1)) f |= 1;
+    if (bad) f |= 2;
+    flags[i] = f;
+  }
+}

@@ -116,6 +116,19 @@ double orc_cell_mass(const orc_pot* P, const orc_obs* O, int cell, double rel_to
 void orc_jeans(const orc_pot* P, double hR, double hz, double b, long n, const double* pos, const double* eps,
                double* mom, double* ics);
 
+/* Adaptive Bogacki-Shampine 3(2) orbits (Sec. 2.2.2) with nsteps accepted
+ * steps from the trial step h0: traj [(nsteps+1)][6], dts [nsteps] the steps
+ * taken (0 after 100 rejections in a row). */
+void orc_orbit_bs23(const orc_pot* P, const double ic[6], double h0, int nsteps, double rtol, double atol,
+                    double* traj, double* dts);
+/* The same for n orbits with time-weighted binning (Sec. 2.2.4): A [n][ncon]
+ * time fractions (sample k weighted dt_k / t_total, over the copies),
+ * overflow [n][2] the fractions outside each block, drift, flags as
+ * orc_integrate_and_bin (flag 2 also for a step that was never accepted). */
+void orc_integrate_bs23_and_bin(const orc_pot* P, const orc_obs* O, long n, const double* ics, const double* h0,
+                                int nsteps, double rtol, double atol, double* A, double* overflow, double* drift,
+                                uint8_t* flags, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
