@@ -18,6 +18,7 @@
  *   cell_masses        Sec. 2.2.4: target masses m*_n of the density grid.
  *   jeans_ics          Sec. 2.2.1: Jeans-equation velocities of the initial conditions;
  *   dither_ics, bundle_rows   dithered realisations and their bundle means.
+ *   integrate_bs23_and_bin    Sec. 2.2.2: adaptive BS23 orbits, time-weighted binning.
  *
  * Conventions shared by every entry point
  *  - Units: kpc, km/s, Msun; G = 4.300917270e-6 kpc (km/s)^2 / Msun; time in
@@ -380,6 +381,29 @@ int dither_ics(const double* ics, const double* vc, const double* u, int64_t n, 
                double* out, void* stream);
 int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, int32_t n_dither, void* out,
                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * integrate_bs23_and_bin (Sec. 2.2.2, Sec. 2.2.4): the orbit library by
+ * adaptive Bogacki-Shampine 3(2) steps in FP64 instead of the leapfrog: n_steps
+ * accepted steps per orbit from the trial step h0[i]; error of a step
+ * max_i |y3_i - y2_i| / (atol + rtol max(|y_i|, |y3_i|)) over the six
+ * coordinates, accepted when <= 1, next step h min(5, max(0.2, 0.9 err^(-1/3))).
+ * The state after accepted step k is a sample of weight dt_k / t_total
+ * (t_total the sum of the accepted steps), split over the mirror copies, so
+ * A holds time fractions in the layout of integrate_and_bin (surface block
+ * included); the weights are added in no fixed order (last-bit differences
+ * between runs).  Drift and flags as integrate_and_bin; 100 rejections in a
+ * row set SW_FLAG_NONFINITE.
+ *   ics device [6][n_orb] double, h0 device [n_orb] double (> 0),
+ *   A device [n_orb][ncon] double, overflow device [n_orb][2] double,
+ *   drift device [n_orb] double, flags device [n_orb] uint8,
+ *   workspace of integrate_bs23_workspace_bytes(n_orb, n_steps) bytes
+ *   (24 B per orbit-step: packed cells of both blocks and the step). */
+int integrate_bs23_and_bin(const sw_potential* pot, const double* ics, const double* h0, int64_t n_orb,
+                           int32_t n_steps, double rtol, double atol, const sw_obs_spec* obs, double* A,
+                           double* overflow, double* drift, uint8_t* flags, void* workspace, size_t ws_bytes,
+                           void* stream);
+size_t integrate_bs23_workspace_bytes(int64_t n_orb, int32_t n_steps);
 
 /* ---------------------------------------------------------------------------
  * Test and inspection entry points.

@@ -113,6 +113,10 @@ def load():
     L.jeans_ics.argtypes = [C.POINTER(Potential), vp, vp, i64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
     L.dither_ics.argtypes = [vp, vp, vp, i64, i32, C.c_double, C.c_double, vp, vp]
     L.bundle_rows.argtypes = [vp, i32, i64, i64, i32, vp, vp]
+    L.integrate_bs23_and_bin.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, C.c_double, C.c_double,
+                                         C.POINTER(ObsSpec), vp, vp, vp, vp, vp, sz, vp]
+    L.integrate_bs23_workspace_bytes.argtypes = [i64, i32]
+    L.integrate_bs23_workspace_bytes.restype = sz
     L.integrate_orbits.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, i32, vp, vp]
     L.mlp_param_count.restype = i64
     L.mlp_workspace_bytes.argtypes = [i64]
@@ -348,6 +352,17 @@ def dither_ics(ics, vc, u, dx, fv, out):
 def bundle_rows(A, n_dither, out):
     """out[b] = mean of rows b*n_dither .. (b+1)*n_dither - 1 of A."""
     _check(load().bundle_rows(_ptr(A), _dtype_code(A), out.shape[0], A.shape[1], int(n_dither), _ptr(out), _stream()))
+
+
+def integrate_bs23_workspace_bytes(n_orb, n_steps):
+    return load().integrate_bs23_workspace_bytes(int(n_orb), int(n_steps))
+
+
+def integrate_bs23_and_bin(pot, ics, h0, n_steps, rtol, atol, obs, A, overflow, drift, flags, workspace):
+    """Adaptive BS23 orbits with time-weighted binning (FP64 tensors)."""
+    _check(load().integrate_bs23_and_bin(C.byref(pot), _ptr(ics), _ptr(h0), ics.shape[1], int(n_steps), float(rtol),
+                                         float(atol), C.byref(obs), _ptr(A), _ptr(overflow), _ptr(drift), _ptr(flags),
+                                         _ptr(workspace), workspace.numel() * workspace.element_size(), _stream()))
 
 
 def integrate_orbits(pot, ics, dt, n_steps, out):

@@ -29,6 +29,7 @@ SOURCES = {
     "bootstrap.hip": [],
     "cellmass.hip": [],
     "jeans.hip": [],
+    "bs23.hip": ["-ffp-contract=off"],
 }
 
 

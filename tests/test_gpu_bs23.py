@@ -1,0 +1,81 @@
+"""GPU parity of the adaptive Bogacki-Shampine 3(2) path (Sec. 2.2.2) with
+time-weighted binning (Sec. 2.2.4) against the oracle.
+
+Both sides take the same FP64 operations in the same order (no fused
+multiply-adds); the step-size factor's cube root (pow) and the order in which
+the weights are added into the histogram differ in the last bit.  The step
+control amplifies such differences: the error estimate is a difference of the
+two embedded solutions, of relative size ~rtol, so a last-bit change of the
+state moves it, and the next step, by ~u / rtol = 1e-16 / 1e-8 = 1e-8
+relative; the sample weights dt_k / t_total (each ~1e-3 for 1,000 steps) and
+sample positions move accordingly.  Bar: every matrix entry and overflow
+fraction within 1e-8, drift within 1e-9, flags equal on the small model
+(regular orbits); on the rotating barred model (chaotic orbits) rows within
+1e-6 in L1 over short runs, on the barred grid whose blocks need several
+histogram windows.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_common import lib
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_bs23(cfg, obs, ics, h0, n_steps, rtol, atol):
+    import torch
+    P = lib()
+    dev = torch.device("cuda:0")
+    pot = P.build_potential(cfg["components"], cfg["omega"], cfg["euler"])
+    o = P.obs_spec(obs)
+    n = ics.shape[1]
+    A = torch.empty((n, P.ncon(o)), dtype=torch.float64, device=dev)
+    ov = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(n, dtype=torch.float64, device=dev)
+    fl = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.integrate_bs23_workspace_bytes(n, n_steps), dtype=torch.uint8, device=dev)
+    ic_t = torch.from_numpy(np.ascontiguousarray(ics)).to(dev)
+    h_t = torch.from_numpy(np.ascontiguousarray(h0)).to(dev)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    P.integrate_bs23_and_bin(pot, ic_t, h_t, n_steps, rtol, atol, o, A, ov, dr, fl, ws)
+    t1.record()
+    torch.cuda.synchronize()
+    print(f"{n} orbits x {n_steps} accepted steps: {t0.elapsed_time(t1):.1f} ms")
+    return A.cpu().numpy(), ov.cpu().numpy(), dr.cpu().numpy(), fl.cpu().numpy()
+
+
+def oracle_bs23(cfg, obs, ics, h0, n_steps, rtol, atol):
+    pot = O.make_pot(cfg["components"], cfg["omega"])
+    ob = O.make_obs(obs, O.euler_matrix(*cfg["euler"]))
+    return O.integrate_bs23_and_bin(pot, ob, ics, h0, n_steps, rtol, atol)
+
+
+def test_small_model_matches_oracle(gpu):
+    cfg = W.SMALL
+    obs = dict(cfg["obs"], surface=1, upsilon=2.0)
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=1000)
+    A, ov, dr, fl = gpu_bs23(cfg, obs, ics, dt, 1000, 1e-8, 1e-10)
+    A_o, ov_o, dr_o, fl_o = oracle_bs23(cfg, obs, ics, dt, 1000, 1e-8, 1e-10)
+    print("max |dA|", np.abs(A - A_o).max(), "max |d overflow|", np.abs(ov - ov_o).max(), "max |d drift|",
+          np.abs(dr - dr_o).max())
+    assert np.array_equal(fl, fl_o) and np.all(fl == 0)
+    assert np.abs(A - A_o).max() <= 1e-8 and np.abs(ov - ov_o).max() <= 1e-8
+    assert np.abs(dr - dr_o).max() <= 1e-9
+    assert np.allclose(A[:, :1000].sum(1) + ov[:, 0], 1.0, rtol=0, atol=1e-12)
+
+
+def test_barred_model_windows(gpu):
+    """Rotating Ferrers bar, 64 orbits x 300 steps on the barred model's grid
+    (18,000 mass and 30,000 kinematic cells: 3 and 4 histogram windows)."""
+    cfg = W.BARRED
+    ics, dt = W.disc_ics(W.load_table(cfg["table"]), 64, seed=11, n_steps=2000)
+    A, ov, dr, fl = gpu_bs23(cfg, cfg["obs"], ics, dt, 300, 1e-7, 1e-9)
+    A_o, ov_o, dr_o, fl_o = oracle_bs23(cfg, cfg["obs"], ics, dt, 300, 1e-7, 1e-9)
+    l1 = np.abs(A - A_o).sum(1)
+    print("max row L1", l1.max())
+    assert np.array_equal(fl, fl_o)
+    assert l1.max() <= 1e-6 and np.abs(ov - ov_o).max() <= 1e-6
+    assert A.shape[1] == 48000 and (A[:, 18000:] > 0).any()
