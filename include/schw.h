@@ -317,6 +317,22 @@ int chi2(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const doubl
 size_t chi2_workspace_bytes(int64_t n_con);
 
 /* ---------------------------------------------------------------------------
+ * chi2_noalloc: chi2 for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and result as chi2 without the workspace: the
+ * scratch (partial column sums, the model values and the result, 16.5 MiB) is a
+ * static device array of the library that each GPU holds until the process
+ * ends.  No device memory is allocated or freed.  The sums are split over 32
+ * orbit slabs instead of chi2's 256, so the two agree to rounding, not bit for
+ * bit.  Limit: n_con <= chi2_noalloc_max_con() (65,536); larger problems return
+ * SW_EINVAL.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (several streams or threads) race and must be serialised by the
+ * caller.  Synchronises the stream (the result is a host value). */
+int chi2_noalloc(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, const double* d,
+                 const double* sigma, int64_t col_begin, int64_t col_end, double* out, void* stream);
+int64_t chi2_noalloc_max_con(void);
+
+/* ---------------------------------------------------------------------------
  * model_observables: out[n] = sum_i w_i A[i][n] in double precision (the
  * superposition of Sec. 2.3 for given weights; used to form mock data).
  *   A device [n_orb][n_con] (dtype), w device [n_orb] double, out device [n_con] double. */

@@ -106,6 +106,9 @@ def load():
     L.chi2_model.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double)]
     L.chi2.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp, sz, vp]
     L.chi2_workspace_bytes.argtypes = [i64]
+    L.chi2_noalloc.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp]
+    L.chi2_noalloc_max_con.argtypes = []
+    L.chi2_noalloc_max_con.restype = i64
     L.chi2_workspace_bytes.restype = sz
     L.model_observables.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     L.bin_points.argtypes = [C.POINTER(Potential), C.POINTER(ObsSpec), vp, i64, i32, vp, vp, vp]
@@ -306,6 +309,18 @@ def chi2(A, w, d, sigma, col_begin, col_end, workspace):
                        int(col_end), C.byref(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                        _stream()))
     return out.value
+
+
+def chi2_noalloc(A, w, d, sigma, col_begin, col_end):
+    out = C.c_double(0.0)
+    n_orb, n_con = A.shape
+    _check(load().chi2_noalloc(_ptr(A), _dtype_code(A), n_orb, n_con, _ptr(w), _ptr(d), _ptr(sigma), int(col_begin),
+                               int(col_end), C.byref(out), _stream()))
+    return out.value
+
+
+def chi2_noalloc_max_con():
+    return int(load().chi2_noalloc_max_con())
 
 
 def gh_workspace_bytes(n_ap, nv, n_gh=4):

@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gemm.h"
@@ -2153,12 +2154,36 @@ __global__ __launch_bounds__(kColThreads) void k_colsum1(const TA* __restrict__ 
   }
 }
 
-__global__ void k_sum_slabs(const double* __restrict__ part, int64_t C, double* __restrict__ m) {
+__global__ void k_sum_slabs(const double* __restrict__ part, int64_t C, int slabs, double* __restrict__ m) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= C) return;
   double t = 0.0;
-  for (int s = 0; s < kSlabs; ++s) t += part[(int64_t)s * C + n];
+  for (int s = 0; s < slabs; ++s) t += part[(int64_t)s * C + n];
   m[n] = t;
+}
+
+// chi^2 of Eq. 5 over [cb, ce) with its scratch at `ws` (slabs x C partial
+// column sums, then C model values, then the result): every slab writes every
+// column of its partials and the sums overwrite m, so nothing needs clearing.
+static int chi2_launch(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, const double* d,
+                       const double* sigma, int64_t cb, int64_t ce, int slabs, char* ws, double* out,
+                       hipStream_t st) {
+  double* part = (double*)ws;
+  double* m = (double*)(ws + a256((size_t)slabs * n_con * 8));
+  double* res = (double*)(ws + a256((size_t)slabs * n_con * 8) + a256((size_t)n_con * 8));
+  const int64_t rps = (n_orb + slabs - 1) / slabs;
+  dim3 grid((unsigned)((n_con + kColTile - 1) / kColTile), (unsigned)slabs);
+  if (dtype == SW_F32)
+    hipLaunchKernelGGL(k_colsum1<float>, grid, dim3(kColThreads), 0, st, (const float*)A, n_orb, n_con, w, rps, part, 0);
+  else
+    hipLaunchKernelGGL(k_colsum1<double>, grid, dim3(kColThreads), 0, st, (const double*)A, n_orb, n_con, w, rps, part,
+                       0);
+  hipLaunchKernelGGL(k_sum_slabs, dim3(blocks_for(n_con)), dim3(256), 0, st, part, n_con, slabs, m);
+  hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st, m, d, sigma, cb, ce, res);
+  SW_HIP(hipGetLastError());
+  SW_HIP(hipMemcpyAsync(out, res, 8, hipMemcpyDeviceToHost, st));
+  SW_HIP(hipStreamSynchronize(st));
+  return SW_OK;
 }
 
 extern "C" int chi2(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w, const double* d,
@@ -2172,24 +2197,58 @@ extern "C" int chi2(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, 
     set_error("chi2: workspace too small");
     return SW_ENOMEM;
   }
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  double* part = (double*)ws;
-  double* m = (double*)(ws + a256((size_t)kSlabs * n_con * 8));
-  double* res = (double*)(ws + a256((size_t)kSlabs * n_con * 8) + a256((size_t)n_con * 8));
-  const int64_t rps = (n_orb + kSlabs - 1) / kSlabs;
-  dim3 grid((unsigned)((n_con + kColTile - 1) / kColTile), (unsigned)kSlabs);
-  if (dtype == SW_F32)
-    hipLaunchKernelGGL(k_colsum1<float>, grid, dim3(kColThreads), 0, st, (const float*)A, n_orb, n_con, w, rps, part, 0);
-  else
-    hipLaunchKernelGGL(k_colsum1<double>, grid, dim3(kColThreads), 0, st, (const double*)A, n_orb, n_con, w, rps, part,
-                       0);
-  hipLaunchKernelGGL(k_sum_slabs, dim3(blocks_for(n_con)), dim3(256), 0, st, part, n_con, m);
-  hipLaunchKernelGGL(k_chi2_final, dim3(1), dim3(1024), 0, st, m, d, sigma, col_begin, col_end, res);
-  SW_HIP(hipGetLastError());
-  SW_HIP(hipMemcpyAsync(out, res, 8, hipMemcpyDeviceToHost, st));
-  SW_HIP(hipStreamSynchronize(st));
+  return chi2_launch(A, dtype, n_orb, n_con, w, d, sigma, col_begin, col_end, kSlabs, (char*)workspace, out,
+                     (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// chi2_noalloc: chi2 with its scratch in a file-scope device array instead of
+// a caller workspace.  The array is held by each device for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocSlabs = 32;
+constexpr int64_t kNoAllocMaxCon = (int64_t)1 << 16;
+constexpr size_t kNoAllocBytes =
+    ((size_t)kNoAllocSlabs * kNoAllocMaxCon * 8 + 255) / 256 * 256 + (size_t)kNoAllocMaxCon * 8 + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// the device address of `scratch` on the current device, looked up once per device
+static int scratch_address(void** ptr) {
+  int dev = 0;
+  SW_HIP(hipGetDevice(&dev));
+  SW_CHECK(dev >= 0 && dev < kMaxDevices, "chi2_noalloc: device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    SW_CHECK(p != nullptr, "chi2_noalloc: no device address for the scratch array on device %d", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
   return SW_OK;
+}
+
+extern "C" int64_t chi2_noalloc_max_con(void) { return kNoAllocMaxCon; }
+
+extern "C" int chi2_noalloc(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w,
+                            const double* d, const double* sigma, int64_t col_begin, int64_t col_end, double* out,
+                            void* stream) {
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "chi2_noalloc: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_orb > 0 && n_con > 0, "chi2_noalloc: need n_orb > 0 and n_con > 0");
+  SW_CHECK(n_con <= kNoAllocMaxCon, "chi2_noalloc: n_con = %lld exceeds the static scratch limit of %lld constraints",
+           (long long)n_con, (long long)kNoAllocMaxCon);
+  SW_CHECK(col_begin >= 0 && col_end <= n_con && col_begin <= col_end, "chi2_noalloc: bad column range");
+  SW_CHECK(A && w && d && sigma && out, "chi2_noalloc: null argument");
+  void* ptr = nullptr;
+  const int rc = scratch_address(&ptr);
+  if (rc != SW_OK) return rc;
+  return chi2_launch(A, dtype, n_orb, n_con, w, d, sigma, col_begin, col_end, kNoAllocSlabs, (char*)ptr, out,
+                     (hipStream_t)stream);
 }
 
 extern "C" int model_observables(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* w,

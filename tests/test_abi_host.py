@@ -165,6 +165,21 @@ def test_solve_and_chi2_validation_before_launch():
     assert P.chi2_workspace_bytes(100) > 0
 
 
+def test_chi2_noalloc_validation_before_launch():
+    """The no-allocation chi2 rejects sizes beyond its static scratch and bad
+    arguments on the host, before touching the device."""
+    L = P.load()
+    fake = C.c_void_p(0x1000)
+    out = C.c_double()
+    lim = P.chi2_noalloc_max_con()
+    assert lim == 65536
+    assert L.chi2_noalloc(fake, 1, 10, lim + 1, fake, fake, fake, 0, 5, C.byref(out), None) == -1
+    assert "static scratch limit" in L.sw_last_error().decode()
+    assert L.chi2_noalloc(fake, 1, 10, 5, fake, fake, fake, 3, 9, C.byref(out), None) == -1  # range > n_con
+    assert L.chi2_noalloc(fake, 3, 10, 5, fake, fake, fake, 0, 5, C.byref(out), None) == -1  # dtype
+    assert L.chi2_noalloc(None, 1, 10, 5, fake, fake, fake, 0, 5, C.byref(out), None) == -1  # null matrix
+
+
 def test_workspace_queries_scale():
     obs = _obs()
     a = P.integrate_workspace_bytes(obs, 1, 1000, 100, 1)
