@@ -76,6 +76,8 @@ def _declare(L):
     L.orc_jacobi.argtypes = [P, _dp]; L.orc_jacobi.restype = C.c_double
     L.orc_ferrers_lambda.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
     L.orc_ferrers_lambda.restype = C.c_double
+    L.orc_set_ferrers_rule.argtypes = [C.c_int]
+    L.orc_set_ferrers_rule.restype = C.c_int
     L.orc_nfw_derived.argtypes = [C.c_double, C.c_double, C.c_double, _dp]; L.orc_nfw_derived.restype = None
     L.orc_euler_matrix.argtypes = [C.c_double, C.c_double, C.c_double, _dp]; L.orc_euler_matrix.restype = None
     L.orc_step.argtypes = [P, _dp, C.c_double]; L.orc_step.restype = None
@@ -180,6 +182,13 @@ def jacobi(pot, s):
 
 def ferrers_lambda(a, b, c, x):
     return lib().orc_ferrers_lambda(a, b, c, np.ascontiguousarray(x, dtype=np.float64))
+
+
+def set_ferrers_rule(n):
+    """Timing mode of the Ferrers integrals: a fixed n-point Gauss-Legendre rule
+    (n <= 128) instead of the adaptive one (n = 0, the default)."""
+    if lib().orc_set_ferrers_rule(int(n)) != 0:
+        raise ValueError(f"bad Ferrers rule {n}")
 
 
 def nfw_derived(M200, c, H0=70.0):

@@ -65,3 +65,20 @@ def orbit_moments(A_kin, n_ap, nv, vlo, vhi, v0, s, n_gh=4):
         G = bin_kernel(vlo, vhi, nv, v0[a], s[a], n_gh)
         out[:, a, :] = A_kin[:, a, :] @ G.T
     return out
+
+
+def fit_matrix(A, n_mass, kin0, surf0, n_ap, nv, vlo, vhi, v0, s, gamma, n_gh=4):
+    """The stacked orbit matrix of Eq. 3 with Gauss-Hermite kinematics: the
+    density block, the surface-density columns (when surf0 is not None) and the
+    matrices h_{m,i,n} = g_m(i, n) / gamma_n, m = 1..n_gh (m-major), gamma_n the
+    observed luminosity of aperture n (the per-orbit h_m are linear only for a
+    fixed normalisation)."""
+    A = np.asarray(A, dtype=np.float64)
+    g = orbit_moments(A[:, kin0:kin0 + n_ap * nv], n_ap, nv, vlo, vhi, v0, s, n_gh)  # [N][n_ap][n_gh + 1]
+    parts = [A[:, :n_mass]]
+    if surf0 is not None:
+        parts.append(A[:, surf0:surf0 + n_ap])
+    gamma = np.asarray(gamma, dtype=np.float64)
+    for m in range(1, n_gh + 1):
+        parts.append(g[:, :, m] / gamma[None, :])
+    return np.hstack(parts)

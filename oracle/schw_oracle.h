@@ -73,6 +73,8 @@ double orc_density(const orc_pot* P, const double x[3]);
 double orc_jacobi(const orc_pot* P, const double s[6]);
 /* root of m^2(lambda) = 1 of a Ferrers ellipsoid (0 inside) */
 double orc_ferrers_lambda(double a, double b, double c, const double x[3]);
+/* Ferrers integrals by a fixed n-point Gauss-Legendre rule (timing mode, n <= 128); 0 = adaptive (default) */
+int orc_set_ferrers_rule(int n);
 
 void orc_euler_matrix(double alpha, double beta, double gamma, double R[9]);
 

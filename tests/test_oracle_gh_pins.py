@@ -83,3 +83,36 @@ def test_moments_are_linear_in_the_histogram():
     b = 2.0 * gh.moments_from_histogram(h1, -450, 450, 12.0, 90.0) + 3.0 * gh.moments_from_histogram(
         h2, -450, 450, 12.0, 90.0)
     assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+
+
+def test_fit_matrix_blocks_and_linearity():
+    """The fit matrix of Eq. 3: the density and surface columns are copies of
+    the orbit matrix's; the h-block summed over orbits with their weights is the
+    h_m of the summed histogram for the observed luminosity: a Gaussian LOSVD
+    shifted by d = 0.4 s from the reference, split at random over three orbits,
+    gives h_m = exp(-d^2/4) (d/sqrt(2))^m / sqrt(m!) (to the binning error)."""
+    from scipy.stats import norm
+    n_mass, n_ap, nv = 3, 2, 300
+    vlo, vhi, v0, s, d = -600.0, 600.0, 10.0, 80.0, 0.4
+    edges = np.linspace(vlo, vhi, nv + 1)
+    hist = np.diff(norm.cdf((edges - (v0 + d * s)) / s))  # unit luminosity
+    rng = np.random.default_rng(3)
+    split = rng.dirichlet(np.ones(3), size=nv).T  # [3 orbits][nv], columns sum to 1
+    lum = np.array([2.0, 0.5])
+    A = np.zeros((3, n_mass + n_ap * nv + n_ap))
+    A[:, :n_mass] = rng.uniform(size=(3, n_mass))
+    for a in range(n_ap):
+        A[:, n_mass + a * nv:n_mass + (a + 1) * nv] = lum[a] * split * hist
+    surf0 = n_mass + n_ap * nv
+    A[:, surf0:] = rng.uniform(size=(3, n_ap))
+    F = gh.fit_matrix(A, n_mass, n_mass, surf0, n_ap, nv, vlo, vhi, [v0] * n_ap, [s] * n_ap, lum, n_gh=4)
+    assert F.shape == (3, n_mass + n_ap + 4 * n_ap)
+    np.testing.assert_array_equal(F[:, :n_mass], A[:, :n_mass])
+    np.testing.assert_array_equal(F[:, n_mass:n_mass + n_ap], A[:, surf0:])
+    h = F[:, n_mass + n_ap:].sum(0).reshape(4, n_ap)
+    for m in range(1, 5):
+        ref = math.exp(-d * d / 4) * (d / math.sqrt(2)) ** m / math.sqrt(math.factorial(m))
+        np.testing.assert_allclose(h[m - 1], ref, atol=2e-4)
+    F2 = gh.fit_matrix(A, n_mass, n_mass, None, n_ap, nv, vlo, vhi, [v0] * n_ap, [s] * n_ap, lum, n_gh=2)
+    assert F2.shape == (3, n_mass + 2 * n_ap)
+    np.testing.assert_allclose(F2[:, n_mass:], F[:, n_mass + n_ap:n_mass + 3 * n_ap], rtol=1e-13)

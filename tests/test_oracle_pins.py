@@ -87,6 +87,24 @@ def test_flattened_nfw_density_positive():
         assert fd_laplacian(pot, x, 1e-3) > 0
 
 
+@pytest.mark.parametrize("q", [0.6, 0.9, 1.4])
+def test_nfw_flattening_direction(q):
+    """Potential flattening m^2 = x^2 + y^2 + z^2/q^2: the flattened potential at
+    height q r on the symmetry axis is the spherical one at r, the midplane is
+    unchanged, and the vertical force there is the spherical one divided by q
+    (chain rule through m = z/q).  Writing z^2 q^2 instead fails all three."""
+    pq = O.make_pot([("nfw_q", (1e12, 10.0, q, 70.0))])
+    p1 = O.make_pot([("nfw_q", (1e12, 10.0, 1.0, 70.0))])
+    for r in (0.4, 3.0, 25.0, 180.0):
+        assert O.phi(pq, np.array([0.0, 0.0, q * r])) == pytest.approx(O.phi(p1, np.array([0.0, 0.0, r])), rel=1e-13)
+        gz_q = O.accel(pq, np.array([0.0, 0.0, q * r]))[2]
+        gz_1 = O.accel(p1, np.array([0.0, 0.0, r]))[2]
+        assert gz_q == pytest.approx(gz_1 / q, rel=1e-12)
+        xm = np.array([0.6 * r, -0.8 * r, 0.0])
+        assert O.phi(pq, xm) == pytest.approx(O.phi(p1, xm), rel=1e-14)
+        np.testing.assert_allclose(O.accel(pq, xm), O.accel(p1, xm), rtol=1e-13, atol=0.0)
+
+
 def test_ferrers_sphere_matches_gauss_theorem():
     a, M = 2.0, 3e9
     pot = O.make_pot([("ferrers2", (M, a, a, a))])
@@ -384,3 +402,20 @@ def test_matrix_free_kkt_and_mu_match_the_scaled_problem():
     assert direct > 1e3 * 1e-11  # well above the optimum's residual (min(w', g) is capped by the weights' scale)
     for Am in (A, sp.csr_matrix(A)):
         assert N.kkt_residual_orbit_matrix(Am, d, sig, wt, mu, wt * w_bad) == pytest.approx(direct, rel=1e-10)
+
+
+def test_ferrers_fixed_rule_timing_mode_matches_adaptive():
+    """The oracle's fixed 64-point Gauss-Legendre timing mode of the Ferrers
+    integrals reproduces the adaptive rule to 1e-12 inside, on and outside the bar."""
+    pot = O.make_pot([("ferrers2", (1e10, 4.0, 1.5, 1.0))])
+    rng = np.random.default_rng(8)
+    pts = np.concatenate([rng.uniform(-1, 1, (60, 3)) * [4, 1.5, 1], rng.uniform(-30, 30, (60, 3)),
+                          [[4.0, 0.0, 0.0], [0.0, 1.5, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 0.0]]])
+    ref = [(O.phi(pot, x), O.accel(pot, x)) for x in pts]
+    O.set_ferrers_rule(64)
+    try:
+        for x, (p, g) in zip(pts, ref):
+            assert O.phi(pot, x) == pytest.approx(p, rel=1e-12)
+            np.testing.assert_allclose(O.accel(pot, x), g, rtol=0, atol=1e-12 * max(np.max(np.abs(g)), 1e-300))
+    finally:
+        O.set_ferrers_rule(0)
