@@ -106,6 +106,10 @@ def load():
     L.chi2_model.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double)]
     L.chi2.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp, sz, vp]
     L.chi2_workspace_bytes.argtypes = [i64]
+    L.gh_fit_workspace_bytes.argtypes = [i32, i32, i32]
+    L.gh_fit_workspace_bytes.restype = sz
+    L.gh_fit_matrix.argtypes = [vp, i32, i64, i64, i64, i64, i64, i32, i32, C.c_double, C.c_double,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double), i32, vp, vp, sz, vp]
     L.chi2_noalloc.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, i64, C.POINTER(C.c_double), vp]
     L.chi2_noalloc_max_con.argtypes = []
     L.chi2_noalloc_max_con.restype = i64
@@ -195,6 +199,7 @@ def obs_spec(spec, pix2ap=None):
         o.plo[i], o.phi[i] = spec["plo"][i], spec["phi"][i]
     if pix2ap is not None:
         o.pix2ap = pix2ap.data_ptr()
+        o._pix2ap = pix2ap  # the spec keeps the device map alive as long as it is used
         o.n_ap = int(spec["n_ap"])
     else:
         o.pix2ap = None
@@ -321,6 +326,20 @@ def chi2_noalloc(A, w, d, sigma, col_begin, col_end):
 
 def chi2_noalloc_max_con():
     return int(load().chi2_noalloc_max_con())
+
+
+def gh_fit_workspace_bytes(n_ap, nv, n_gh=4):
+    return load().gh_fit_workspace_bytes(int(n_ap), int(nv), int(n_gh))
+
+
+def gh_fit_matrix(A, n_mass, kin0, surf0, n_ap, nv, vlo, vhi, v0, s, gamma, out, workspace, n_gh=4):
+    """out: device [n_orb][n_mass (+ n_ap) + n_gh * n_ap] of A's dtype; surf0 < 0: no surface block;
+    v0, s, gamma: sequences of n_ap floats."""
+    n_orb, n_con = A.shape
+    arr = lambda v: (C.c_double * n_ap)(*[float(x) for x in v])  # noqa: E731
+    _check(load().gh_fit_matrix(_ptr(A), _dtype_code(A), n_orb, n_con, int(n_mass), int(kin0), int(surf0), int(n_ap),
+                                int(nv), float(vlo), float(vhi), arr(v0), arr(s), arr(gamma), int(n_gh), _ptr(out),
+                                _ptr(workspace), workspace.numel() * workspace.element_size(), _stream()))
 
 
 def gh_workspace_bytes(n_ap, nv, n_gh=4):

@@ -24,6 +24,7 @@ import time
 import numpy as np
 
 from . import _lib as P
+from . import jackknife
 
 
 class ModelBuilder:
@@ -71,46 +72,43 @@ class ModelBuilder:
         self.w = torch.empty(n_tot, dtype=torch.float64, device=self.dev)
         self.cws = torch.empty(P.chi2_workspace_bytes(self.nc), dtype=torch.uint8, device=self.dev)
         self.n_built = 0
+        self.n_resolved = 0
+        self.n_unconverged = 0
+        self.last_converged = np.zeros(0, dtype=bool)
+        self._sws1 = None
+        self._jk_work = {}
 
     def chi2(self, thetas):
-        """chi^2 of each parameter vector (rows of thetas); batches of max_batch."""
-        out = []
+        """chi^2 of each parameter vector (rows of thetas); batches of max_batch.
+        self.last_converged holds, per row, whether its weight solve met the
+        KKT tolerance (a solve that reaches the batch's cap is repeated alone
+        with a 4x higher cap first); self.n_unconverged counts the builds that
+        never did."""
+        out, conv = [], []
         for k0 in range(0, len(thetas), self.max_batch):
-            out.extend(self._chi2_batch(thetas[k0:k0 + self.max_batch]))
+            r, c = self._chi2_batch(thetas[k0:k0 + self.max_batch])
+            out.extend(r)
+            conv.extend(c.tolist())
+        self.last_converged = np.array(conv, dtype=bool)
+        self.n_unconverged += int((~self.last_converged).sum())
         return np.array(out)
 
     def jackknife_dchi2(self, theta, n_ap, nv):
-        """Sec. 2.4: one build at theta, then n_ap weight solves of the same
-        matrix, solve a without aperture a's nv kinematic constraints (their
-        sigma set so large that they carry no weight), all in one batched
-        call; chi^2_a is taken over the kinematic constraints that solve a
-        kept.  Returns (dchi2, chi2 values)."""
-        torch = self.torch
-        if n_ap > self.max_batch:
-            raise ValueError("jackknife needs n_ap <= max_batch")
+        """Sec. 2.4: one build at theta, then the aperture jackknife of its
+        chi^2 (`jackknife.jackknife_dchi2`: n_ap weight solves of the same
+        matrix, each without one aperture's data, the full problem's
+        regularisation held fixed).  Returns (dchi2, chi^2 values)."""
         self._chi2_batch(np.asarray(theta, dtype=np.float64)[None, :])
-        n, k0 = self.n, self.kin[0]
-        for a in range(1, n_ap):
-            self.A[a * n:(a + 1) * n].copy_(self.A[:n])
-            self.fl[a * n:(a + 1) * n].copy_(self.fl[:n])
-        sig = self.sig[:n_ap].clone()
-        for a in range(n_ap):
-            sig[a, k0 + a * nv:k0 + (a + 1) * nv] = 1e30 * float(self.s1.max())
-        offs = [n * j for j in range(n_ap + 1)]
-        A = self.A[:n * n_ap]
-        self.opts.mask = self.fl.data_ptr() if self.drift_mask else None
-        P.solve_weights_batched(A, offs, self.d[:n_ap], sig, [self.w_tilde] * n_ap, -1.0, self.opts,
-                                self.w[:n * n_ap], self.sws)
-        cb, ce = self.kin
-        chi = []
-        for a in range(n_ap):
-            Aa, wa = A[offs[a]:offs[a + 1]], self.w[offs[a]:offs[a + 1]]
-            full = P.chi2(Aa, wa, self.d1, self.s1, cb, ce, self.cws)
-            held = P.chi2(Aa, wa, self.d1, self.s1, k0 + a * nv, k0 + (a + 1) * nv, self.cws)
-            chi.append(full - held)
-        chi = np.array(chi)
-        dchi2 = math.sqrt((n_ap - 1) / n_ap * float(np.sum((chi - chi.mean()) ** 2)))
-        return dchi2, chi
+        n = self.n
+        mu = self.last_reports[0].mu
+        o = self.obs
+        surf0 = o.nx * o.ny * o.nz + o.n_ap * o.nv if o.surface else None
+        mask = self.fl[:n] if self.drift_mask else None
+        opts = type(self.opts).from_buffer_copy(self.opts)
+        dchi2, chis, _, _ = jackknife.jackknife_dchi2(self.A[:n], self.d1, self.s1, self.w_tilde, mu, self.kin[0],
+                                                      n_ap, nv, surf0=surf0, mask=mask, opts=opts,
+                                                      work=self._jk_work)
+        return dchi2, chis
 
     def _chi2_batch(self, thetas):
         k = len(thetas)
@@ -126,6 +124,11 @@ class ModelBuilder:
         self.opts.mask = self.fl.data_ptr() if self.drift_mask else None
         st, reps = P.solve_weights_batched(A, offs, self.d[:k], self.sig[:k], [self.w_tilde] * k, -1.0, self.opts,
                                            self.w[:n_tot], self.sws)
+        conv = np.array([bool(r.converged) for r in reps])
+        for j in np.flatnonzero(~conv):
+            # a problem that reached the batch's iteration cap is solved again on its own with a higher cap;
+            # if it still does not converge it is reported as such
+            conv[j], reps[j] = self._resolve(A[offs[j]:offs[j + 1]], offs[j])
         cb, ce = self.kin if self.kin else (0, self.nc)
         res = []
         for j in range(k):
@@ -133,7 +136,19 @@ class ModelBuilder:
                               self.cws))
         self.n_built += k
         self.last_reports = reps
-        return res
+        return res, conv
+
+    def _resolve(self, A1, i0):
+        n = self.n
+        opts = type(self.opts).from_buffer_copy(self.opts)
+        opts.refine_iter = 4 * (self.opts.refine_iter if self.opts.refine_iter > 0 else 2000)
+        opts.mask = self.fl[i0:i0 + n].data_ptr() if self.drift_mask else None
+        need = P.solve_workspace_bytes(n, self.nc, opts)
+        if self._sws1 is None or self._sws1.numel() < need:
+            self._sws1 = self.torch.empty(need, dtype=self.torch.uint8, device=self.dev)
+        st, rep = P.solve_weights(A1, self.d1, self.s1, self.w_tilde, -1.0, opts, self.w[i0:i0 + n], self._sws1)
+        self.n_resolved += 1
+        return bool(rep.converged), rep
 
 
 class Surrogate:
@@ -206,23 +221,27 @@ class Surrogate:
 
 
 def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, seed=8, use_surrogate=True,
-            log=None):
+            log=None, normals=None, uniforms=None):
     """Delayed-acceptance random-walk Metropolis over a uniform prior box,
     many walkers advanced together: each step proposes for every walker,
     screens with the surrogate, and builds the survivors' models in one batch.
-    Returns the chains and counters."""
+    The random numbers are drawn from `seed` (per step: normals [n_w, d], then
+    uniforms [n_w, 2]) unless given as normals [n_steps][n_w][d] and uniforms
+    [n_steps][n_w][2].  Returns the chains and counters."""
     rng = np.random.default_rng(seed)
     th = np.array(theta0, dtype=np.float64)
     n_w, d = th.shape
     scale = step_frac * (np.asarray(hi) - np.asarray(lo))
     chi = builder.chi2(th)
+    n_unconv = int((~getattr(builder, "last_converged", np.ones(n_w, dtype=bool))).sum())
     chi_s = surrogate.predict(th) if use_surrogate else chi.copy()
     chains = np.empty((n_steps, n_w, d))
     n_full, n_s1, n_acc = len(th), 0, 0
     t0 = time.perf_counter()
     for k in range(n_steps):
-        prop = th + scale * rng.normal(size=(n_w, d))
-        u = rng.uniform(size=(n_w, 2))
+        z = rng.normal(size=(n_w, d)) if normals is None else np.asarray(normals[k])
+        u = rng.uniform(size=(n_w, 2)) if uniforms is None else np.asarray(uniforms[k])
+        prop = th + scale * z
         inside = np.all((prop >= lo) & (prop <= hi), axis=1)
         if use_surrogate:
             cs = surrogate.predict(prop)
@@ -235,6 +254,7 @@ def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, 
         n_s1 += len(idx)
         if len(idx):
             cf = builder.chi2(prop[idx])
+            n_unconv += int((~getattr(builder, "last_converged", np.ones(len(idx), dtype=bool))).sum())
             n_full += len(idx)
             for j, i in enumerate(idx):
                 if use_surrogate:
@@ -251,4 +271,4 @@ def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, 
             log(f"mcmc step {k + 1}/{n_steps}: full builds {n_full}, accepted {n_acc}")
     el = time.perf_counter() - t0
     return {"chains": chains, "n_full_builds": n_full, "n_stage1": n_s1, "n_accepted": n_acc, "seconds": el,
-            "proposals": n_steps * n_w, "models_per_s": n_steps * n_w / el}
+            "proposals": n_steps * n_w, "models_per_s": n_steps * n_w / el, "n_unconverged_builds": n_unconv}

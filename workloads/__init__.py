@@ -33,6 +33,7 @@ SMALL = dict(
              nv=15, vlo=-450.0, vhi=450.0, symmetrize=1, drift_every=1),
     ic_seed=1, mock=dict(seed=2, frac=0.1, noise=0.0, tol=0.01),
     table="plummer_mn",
+    subsample=dict(seed=9, n=2000),
 )
 
 # Barred model: MN disc + rotating Ferrers n=2 bar + flattened NFW halo,
