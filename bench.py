@@ -56,30 +56,158 @@ def mock_sigma(d, blocks, tol, floor=1e-3):
     return s
 
 
-def cpu_baseline(cfg, seconds_target=20.0):
-    """The FP64 oracle's integrate-and-bin on a bounded sample of the same
-    workload (same potential, grid, step size), timed on the host cores."""
+def host_threads():
+    """Threads the oracle runs on: the CPUs this process may use, capped by
+    OMP_NUM_THREADS when it is set; and the physical cores lscpu reports."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(avail, omp) if omp > 0 else avail
+    phys = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu", "-p=Core,Socket"], capture_output=True, text=True, timeout=10).stdout
+        phys = len({ln for ln in out.splitlines() if ln and not ln.startswith("#")})
+    except Exception:
+        pass
+    return threads, phys
+
+
+def _csr_copy(A):
+    """Host FP64 CSR copy of a device orbit matrix (row chunks converted on the GPU)."""
+    import scipy.sparse as sp
+    n, c = A.shape
+    parts = []
+    for r0 in range(0, n, 10000):
+        csr = A[r0:r0 + 10000].to_sparse_csr()
+        parts.append(sp.csr_matrix((csr.values().cpu().numpy().astype(np.float64),
+                                    csr.col_indices().cpu().numpy().astype(np.int32),
+                                    csr.crow_indices().cpu().numpy().astype(np.int64)), shape=(min(10000, n - r0), c)))
+        del csr
+    return sp.vstack(parts, format="csr")
+
+
+def cpu_baseline_leg(cfg, run):
+    """The oracle leg: times the FP64 oracle's whole model build (integrate+bin
+    with its fixed 64-point Gauss-Legendre Ferrers timing mode, exact NNLS,
+    chi^2) on the seeded 1,000-orbit subsample of the workload, and states the
+    GPU's errors against the oracle on that subsample and on the headline solve:
+      * integration: per-orbit row L1 between the GPU's FP32 rows and the
+        oracle's FP64 rows (the floor: the oracle whose state is rounded to
+        binary32 every step), |drift difference|;
+      * weight solve on one matrix (the oracle's FP64 subsample matrix in FP32,
+        its own mock, the oracle's drift mask): weights L1, chi^2;
+      * headline solve: the oracle's FP64 KKT residual and chi^2 of the GPU's
+        weights from a CSR copy of the GPU's matrix.
+    `run` holds the GPU objects of the timed build."""
     import oracle as O
-    table = W.load_table(cfg["table"])
+    from oracle import nnls as N
+    P, torch, dev = run["P"], run["torch"], run["dev"]
+    threads, phys = host_threads()
     n_steps = cfg["n_steps"]
-    ics, dt = W.disc_ics(table, cfg["n_orb"], seed=cfg["ic_seed"], n_steps=n_steps) if cfg is W.BARRED else \
-        W.grid_ics(table, seed=cfg["ic_seed"], n_steps=n_steps)
+    blocks = W.blocks(cfg["obs"])
+    kin0, kin1 = blocks[1]
+    sub = W.subsample_draw(cfg["n_orb"], cfg["subsample"]["n"], cfg["subsample"]["seed"])
+    ns = len(sub)
+    f64 = cfg["dtype"] == "f64"
+    npd = np.float64 if f64 else np.float32
+    ic = np.ascontiguousarray(run["ics"][:, sub].astype(npd))
+    dt = np.ascontiguousarray(run["dt"][sub].astype(npd))
+    ic64, dt64 = ic.astype(np.float64), dt.astype(np.float64)
     pot = O.make_pot(cfg["components"], cfg["omega"])
     ob = O.make_obs(cfg["obs"], O.euler_matrix(*cfg["euler"]))
-    threads = os.cpu_count() or 1
-    # calibrate on a short run, then size the sample to ~seconds_target
-    n_cal = min(64, ics.shape[1])
-    t0 = time.perf_counter()
-    O.integrate_and_bin(pot, ob, ics[:, :n_cal], dt[:n_cal], min(n_steps, 1000), nthreads=threads)
-    rate = n_cal * min(n_steps, 1000) / max(time.perf_counter() - t0, 1e-6)
-    n_s = int(max(threads, min(ics.shape[1], seconds_target * rate / n_steps)))
-    idx = W.subsample_draw(ics.shape[1], n_s, 17)
-    t0 = time.perf_counter()
-    O.integrate_and_bin(pot, ob, ics[:, idx], dt[idx], n_steps, nthreads=threads)
-    el = time.perf_counter() - t0
-    return {"value": n_s * n_steps / el, "unit": "orbit-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"integrate+bin of {n_s} seeded orbits x {n_steps} steps of the same workload "
-                      f"({el:.1f} s); the weight solve is not in the sample"}
+    O.set_ferrers_rule(64)
+    try:
+        t0 = time.perf_counter()
+        c_o, _, dr_o, fl_o = O.integrate_and_bin(pot, ob, ic64, dt64, n_steps, nthreads=threads)
+        A_o = O.time_fractions(c_o, n_steps)
+        w_mock = W.mock_draw(ns, cfg["mock"]["seed"])
+        nc = A_o.shape[1]
+        d_s = A_o.T @ w_mock
+        if cfg["mock"]["noise"] > 0:
+            d_s = d_s * (1 + cfg["mock"]["noise"] * W.noise_draw(nc, cfg["mock"]["seed"]))
+        sig_s = N.sigma_from_data(d_s, blocks, cfg["mock"]["tol"])
+        wt_s = N.w_tilde_from_data(d_s, blocks[0], ns)
+        mask_o = ((fl_o & 1) != 0) | ((fl_o & 2) != 0)
+        keep = np.flatnonzero(~mask_o)
+        U, y = N.scale_problem(A_o[keep], d_s, sig_s, wt_s)
+        mu_s = N.relative_mu(U, 1e-2)
+        wp = N.nnls_oracle(U, y, mu_s)
+        w_o = np.zeros(ns)
+        w_o[keep] = wp * wt_s
+        x_o = N.chi2(A_o, w_o, d_s, sig_s, kin0, kin1)
+        el = time.perf_counter() - t0
+        f32_floor = None
+        if not f64:
+            c_p, *_ = O.integrate_and_bin(pot, ob, ic64, dt64, n_steps, nthreads=threads, f32_state=True)
+            f32_floor = O.time_fractions(c_p, n_steps)
+    finally:
+        O.set_ferrers_rule(0)
+    errors = {}
+    # GPU integration of the same subsample, same launch configuration
+    td = torch.float64 if f64 else torch.float32
+    code = P.SW_F64 if f64 else P.SW_F32
+    obs = run["obs"]
+    A_g = torch.empty((ns, nc), dtype=td, device=dev)
+    ov = torch.empty((ns, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(ns, dtype=torch.float64, device=dev)
+    fl = torch.empty(ns, dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.integrate_workspace_bytes(obs, 1, ns, n_steps, code), dtype=torch.uint8, device=dev)
+    P.integrate_and_bin(run["pot"], [0, ns], torch.from_numpy(ic).to(dev), torch.from_numpy(dt).to(dev), n_steps, obs,
+                        A_g, ov, dr, fl, ws)
+    torch.cuda.synchronize()
+    Ag = A_g.cpu().numpy().astype(np.float64)
+    l1 = np.abs(Ag - A_o).sum(1) / 2
+    ddr = np.abs(dr.cpu().numpy() - dr_o)
+    errors["integrate_subsample"] = {
+        "orbits": ns, "row_l1_median": float(np.median(l1)), "row_l1_p90": float(np.percentile(l1, 90)),
+        "drift_absdiff_median": float(np.median(ddr)), "drift_absdiff_p99": float(np.percentile(ddr, 99)),
+        "flagged_frac_gpu": float(np.mean(fl.cpu().numpy() & 1)), "flagged_frac_oracle": float(np.mean(fl_o & 1))}
+    if f32_floor is not None:
+        l1p = np.abs(f32_floor - A_o).sum(1) / 2
+        errors["integrate_subsample"].update(row_l1_floor_median=float(np.median(l1p)),
+                                             row_l1_floor_p90=float(np.percentile(l1p, 90)))
+    else:
+        errors["integrate_subsample"]["bit_exact"] = bool(np.array_equal(Ag, A_o))
+    # the weight solve on one matrix: the oracle's subsample matrix and mock
+    A_s = torch.from_numpy(A_o.astype(npd)).to(dev)
+    mk = torch.from_numpy(mask_o.astype(np.uint8)).to(dev)
+    opts = type(run["opts"]).from_buffer_copy(run["opts"])
+    opts.mask = mk.data_ptr()
+    w_s = torch.empty(ns, dtype=torch.float64, device=dev)
+    sws = torch.empty(P.solve_workspace_bytes(ns, nc, opts), dtype=torch.uint8, device=dev)
+    d_t, s_t = torch.from_numpy(d_s).to(dev), torch.from_numpy(sig_s).to(dev)
+    cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(run["stream"]):
+        st, rep = P.solve_weights(A_s, d_t, s_t, wt_s, -1.0, opts, w_s, sws)
+        x_g = P.chi2(A_s, w_s, d_t, s_t, kin0, kin1, cws)
+    torch.cuda.synchronize()
+    wg = w_s.cpu().numpy()
+    # the GPU solved the FP32-rounded matrix: the oracle's chi^2 of the GPU's weights is taken on that same matrix
+    A_s64 = A_o.astype(npd).astype(np.float64)
+    errors["solve_subsample"] = {
+        "orbits": ns, "status": st, "weights_l1_rel": float(np.abs(wg - w_o).sum() / np.abs(w_o).sum()),
+        "chi2_rel": float(abs(x_g / x_o - 1)), "chi2_rel_same_matrix": float(abs(x_g / N.chi2(A_s64, wg, d_s, sig_s,
+                                                                                               kin0, kin1) - 1)),
+        "kkt_gpu": rep.kkt}
+    del A_s, sws, ws, A_g
+    # the headline solve: the oracle's certificate from a CSR copy of the GPU's own matrix
+    A_csr = _csr_copy(run["A"])
+    w = run["w"].cpu().numpy()
+    d, sig, wt = run["d"], run["sig"], run["w_tilde"]
+    keep_h = np.flatnonzero(run["fl"].cpu().numpy() == 0)
+    kkt_o = N.kkt_residual_orbit_matrix(A_csr[keep_h], d, sig, wt, run["mu"], w[keep_h])
+    x_h = N.chi2(A_csr, w, d, sig, kin0, kin1)
+    errors["headline_solve"] = {"kkt_oracle": kkt_o, "kkt_gpu": run["kkt"], "chi2_rel": float(abs(run["chi2"] / x_h - 1)),
+                                "mu_rel": float(abs(run["mu"] / N.relative_mu_orbit_matrix(A_csr[keep_h], sig, wt, 1e-2)
+                                                    - 1))}
+    del A_csr
+    base = {"value": ns * n_steps / el, "unit": "orbit-steps/s", "cores": threads, "physical_cores": phys,
+            "kind": "oracle",
+            "sample": f"whole model build by the FP64 oracle (integrate+bin with its 64-point Gauss-Legendre "
+                      f"Ferrers timing mode, exact NNLS by active set, chi^2) of the seeded {ns}-orbit subsample x "
+                      f"{n_steps} steps with the workload's {nc} constraints and a mock of that subsample "
+                      f"({el:.1f} s on {threads} threads); its solve is smaller than the full library's"}
+    return base, errors
 
 
 def main():
@@ -99,6 +227,8 @@ def main():
     ap.add_argument("--bootstrap", type=int, default=0,
                     help="also solve this many bootstrap realisations of the data per build (shared matrix) "
                          "and report chi2_model")
+    ap.add_argument("--factor-gemm", type=int, choices=[0, 1], default=None,
+                    help="factorisation products on fp32 MFMA (0) or bf16x3 MFMA (1); default: the library's")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a 4 GiB device-to-device copy (scale for the HBM traffic counters)")
     args = ap.parse_args()
@@ -110,6 +240,8 @@ def main():
     import torch
     import paper_2607_00117_amd as P
 
+    if args.factor_gemm is not None:
+        P.set_tuning("factor_gemm", args.factor_gemm)
     if args.workload == "walkers":
         return bench_walkers(args)
     if args.workload == "surrogate":
@@ -219,7 +351,10 @@ def main():
     orbit_steps = n * n_steps
     value = orbit_steps * args.steps / el
 
-    # rooflines per stage (algorithmic work per build / the stage's HIP-event time on the solve stream)
+    # rooflines per stage: the algorithmic work of the method per build (the unit of
+    # `achieved`), over the stage's HIP-event time on the solve stream; the work the
+    # kernels issue (extra MFMA passes of the bf16x3 split, the explicit inverse,
+    # residual-correction passes, Anderson mixing) is reported beside it as `issued`
     t_gram = float(np.mean([r["t_gram_ms"] for r in reps]))
     t_factor = float(np.mean([r["t_factor_ms"] for r in reps]))
     t_admm = float(np.mean([r["t_admm_ms"] for r in reps]))
@@ -232,34 +367,42 @@ def main():
     passes = {"bf16": 1, "bf16x3": 3, "f32": 1}[args.gram]
     stages = {"integrate_and_bin": t_i, "gram": t_gram, "factorise": t_factor, "admm_fp32": t_admm,
               "refine_fp64": t_ref}
-    # bytes of one compressed pass (fp32 value + 16-bit index per entry) or of a dense pass over A
-    pass_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
-    tri_bytes = 4.0 * C * (C + 1)  # both triangles of the fp32 inverse factor
-    # Anderson mixing per FP64 iteration: 91 vectors of N doubles read or written (the
-    # history of 10 three-part entries read twice, iterates, residuals, newest entries)
+    # |U|: one pass over the orbit matrix as stored for the iterations (fp32 value + 16-bit
+    # index per nonzero, or the dense matrix); |L|: one triangle of the fp32 inverse factor
+    u_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
+    l_bytes = 4.0 * C * (C + 1) / 2.0
+    per_iter = 2 * u_bytes + 2 * l_bytes
+    # Anderson mixing per FP64 iteration: 91 vectors of N doubles read or written
     aa_bytes = 0.0 if args.no_accel else 91.0 * N * 8.0
+    refine_passes = float(reps[-1].get("u_passes_per_iter", 4.0))
     rooflines = {
         "integrate_and_bin": {"kernel": "k_integrate + k_hist", "bound": "alu", "unit": "TFLOP/s",
                               "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
-                              "work": FLOP_PER_ORBIT_STEP[cfg["name"]] * N * n_steps, "ms": t_i},
+                              "work": FLOP_PER_ORBIT_STEP[cfg["name"]] * N * n_steps, "ms": t_i,
+                              "work_rule": "flop per orbit-step counted from the formulas x orbit-steps"},
         "gram": {"kernel": f"k_gram_bf16 ({args.gram})" if args.gram != "f32" else "k_gemm_nt_f32 (Gram)",
                  "bound": "mfma", "unit": "TFLOP/s",
                  "peak": (PEAK_BF16 if args.gram != "f32" else PEAK_F32_MFMA) / 1e12,
-                 "work": passes * C * (C + 1) * N, "ms": t_gram},
+                 "work": C * (C + 1) * N, "issued": passes * C * (C + 1) * N, "ms": t_gram,
+                 "work_rule": "SYRK C(C+1)N"},
         "factorise": {"kernel": "k_potrf_diag + k_gemm_nt_f32 (Cholesky, inverse factor)", "bound": "mfma",
-                      "unit": "TFLOP/s", "peak": PEAK_F32_MFMA / 1e12, "work": 2.0 * C ** 3 / 3.0, "ms": t_factor},
+                      "unit": "TFLOP/s", "peak": PEAK_F32_MFMA / 1e12, "work": C ** 3 / 3.0,
+                      "issued": 2.0 * C ** 3 / 3.0, "ms": t_factor, "work_rule": "Cholesky C^3/3"},
         "admm_fp32": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
-                      "peak": PEAK_HBM / 1e9, "work": it1 * (2 * pass_bytes + tri_bytes), "ms": t_admm},
+                      "peak": PEAK_HBM / 1e9, "work": it1 * per_iter, "issued": it1 * per_iter, "ms": t_admm,
+                      "work_rule": "2|U| + 2|L| per iteration"},
         "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
-                        "peak": PEAK_HBM / 1e9, "work": it2 * (4 * pass_bytes + tri_bytes + aa_bytes), "ms": t_ref},
+                        "peak": PEAK_HBM / 1e9, "work": it2 * per_iter,
+                        "issued": it2 * (refine_passes * u_bytes + 2 * l_bytes + aa_bytes), "ms": t_ref,
+                        "work_rule": "2|U| + 2|L| per iteration"},
     }
     if it1 == 0:
         del rooflines["admm_fp32"], stages["admm_fp32"]  # the FP32 stage did not run (accelerated FP64 stage only)
     if n_boot > 0:
-        # the bootstrap solves' FP64 stage: per iteration each group of rg data vectors streams the
-        # compressed copies four times (6 B per entry), the two triangles of the inverse are read once
-        # for all of them, and each data vector's Anderson mixing moves 91 N doubles; the iterations of
-        # a group are counted as (sum over data vectors of their iterations) / rg
+        # the bootstrap solves' FP64 stage: per iteration each data vector needs 2|U| + 2|L| of
+        # algorithmic traffic; issued: each group of rg vectors streams the compressed copies four
+        # times, the two triangles are read once for all vectors, and each vector's Anderson mixing
+        # moves 91 N doubles
         repb = boot[-1][1]
         rg = P.get_tuning("rhs_per_group") or 4
         rg = 1 << max(0, math.ceil(math.log2(min(rg, n_boot))))
@@ -270,12 +413,16 @@ def main():
         stages["bootstrap_rest"] = float(np.mean([b[4] for b in boot])) - t_boot_ref
         rooflines["bootstrap_refine_fp64"] = {
             "kernel": "k_csc_colsum_rhs + k_rowdot_csr_rhs + k_trmm_rhs (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
-            "peak": PEAK_HBM / 1e9, "ms": t_boot_ref,
-            "work": its_sum / rg * 4 * pass_bytes + its_max * tri_bytes + its_sum * aa_bytes}
+            "peak": PEAK_HBM / 1e9, "ms": t_boot_ref, "work": its_sum * per_iter,
+            "issued": its_sum / rg * 4 * u_bytes + its_max * 2 * l_bytes + its_sum * aa_bytes,
+            "work_rule": "2|U| + 2|L| per iteration and data vector"}
     for k, r in rooflines.items():
         scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
         r["achieved"] = round(r["work"] / (r["ms"] * 1e-3) / scale, 3) if r["ms"] > 0 else None
         r["frac"] = round(r["achieved"] / r["peak"], 4) if r["achieved"] is not None else None
+        if "issued" in r and r["ms"] > 0:
+            r["issued_rate"] = round(r["issued"] / (r["ms"] * 1e-3) / scale, 3)
+            r["issued"] = float(r["issued"])
         r["traffic"] = TRAFFIC.get((cfg["name"], k))
         if (cfg["name"], k) in TRAFFIC_PER_ITER:
             r["traffic"] = TRAFFIC_PER_ITER[(cfg["name"], k)] * (it1 if k == "admm_fp32" else it2)
@@ -294,6 +441,10 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in stages.items()},
         "dominant_stage": dominant,
         "solve": {k: reps[-1][k] for k in ("iters", "refine_iters", "converged", "kkt", "mu", "rho", "status")},
+        "precision": {"integrate": "fp32 (Jacobi drift in fp64)", "gram": args.gram + " MFMA, fp32 accumulate",
+                      "factorise": "fp32", "iterations": f"{int(it1)} fp32 ADMM + {int(it2)} fp64 "
+                      "(the accelerated solve runs its ADMM iterations in fp64 from the start)",
+                      "chi2": "fp64"},
         "chi2": chis[-1],
         "integrate_orbit_steps_per_s": orbit_steps / (t_i * 1e-3),
         "bootstrap": None if n_boot == 0 else {
@@ -306,8 +457,10 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_cpu_baseline and "subsample" in cfg:
+        run = dict(P=P, torch=torch, dev=dev, ics=ics, dt=dt, obs=obs, pot=pot, opts=opts, stream=stream, A=A, w=w,
+                   fl=fl, d=d, sig=sig, w_tilde=w_tilde, mu=reps[-1]["mu"], kkt=reps[-1]["kkt"], chi2=chis[-1])
+        out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline_leg(cfg, run)
     if args.calibration_copy:
         src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -407,8 +407,9 @@ int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, i
  * The state after accepted step k is a sample of weight dt_k / t_total
  * (t_total the sum of the accepted steps), split over the mirror copies, so
  * A holds time fractions in the layout of integrate_and_bin (surface block
- * included); the weights are added in no fixed order (last-bit differences
- * between runs).  Drift and flags as integrate_and_bin; 100 rejections in a
+ * included); each weight is rounded to a 64-bit fixed-point integer in units
+ * of 2^-52 (at most 2^-53 from its value) and the integers are summed, so the
+ * result does not depend on summation order and repeated runs are identical.  Drift and flags as integrate_and_bin; 100 rejections in a
  * row set SW_FLAG_NONFINITE.
  *   ics device [6][n_orb] double, h0 device [n_orb] double (> 0),
  *   A device [n_orb][ncon] double, overflow device [n_orb][2] double,
@@ -481,6 +482,28 @@ int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64
                double* out, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * gh_fit_matrix (Sec. 2.2.4, Eq. 2-3): the orbit matrix of the weight problem
+ * with Gauss-Hermite kinematics, the stacked matrices m_{i,n}, Sigma_{i,n} and
+ * h_{m,i,n} of Eq. 3:
+ *   out[i][n]                         = A[i][n],               n < n_mass (density block)
+ *   out[i][n_mass + a]                = A[i][surf0 + a],        a < n_ap (surface block; absent if surf0 < 0)
+ *   out[i][h0 + (m - 1) n_ap + a]     = g_m(i, a) / gamma[a],   m = 1..n_gh, h0 = n_mass (+ n_ap)
+ * with g_m(i, a) the linear moment of gh_moments (orbit i's velocity histogram
+ * in aperture a, bins of [vlo, vhi) read as uniform) about the reference
+ * Gaussian (v0[a], s[a]), divided by the aperture's observed luminosity
+ * gamma[a] > 0 so that sum_i w_i out[i][h0 + (m - 1) n_ap + a] is the model's
+ * h_m when its luminosity matches the data's (the linearity of Eq. 2).
+ *   A       device [n_orb][n_con] (dtype); kinematic block at kin0 (n_ap * nv cells)
+ *   v0, s, gamma  host [n_ap]
+ *   out     device [n_orb][h0 + n_gh * n_ap] of dtype (not aliased with A)
+ *   workspace >= gh_fit_workspace_bytes(n_ap, nv, n_gh)
+ * Synchronises the stream.  Returns SW_OK, SW_EINVAL, SW_ENOMEM or SW_EHIP. */
+size_t gh_fit_workspace_bytes(int32_t n_ap, int32_t nv, int32_t n_gh);
+int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64_t n_mass, int64_t kin0,
+                  int64_t surf0, int32_t n_ap, int32_t nv, double vlo, double vhi, const double* v0, const double* s,
+                  const double* gamma, int32_t n_gh, void* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning (process-wide, not thread-safe; set before launching work):
  *   "integrate_waves_per_cu"  0: one 64-orbit wave per workgroup over the whole
  *                             library; k in [1, 64]: persistent grid of k waves
@@ -501,6 +524,17 @@ int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64
  *                             (0: automatic = up to 4; 1, 2, 4 or 8; it sets
  *                             the block sizes of the compressed copies, so
  *                             query solve_multi_workspace_bytes after it)
+ *   "gram_skip"               weight solve: 1 (default) skips the 32-orbit
+ *                             stages of the Gram whose row or column panel of
+ *                             the scaled matrix is zero (the result is the same
+ *                             to the bit), 0 streams every stage
+ *   "factor_gemm"             weight solve: the large products of the Cholesky
+ *                             factorisation and of the inversion of its factor
+ *                             on fp32 MFMA (0) or on bf16 MFMA with each fp32
+ *                             operand split into a bf16 pair, three products
+ *                             per pair (1, the default); the factor only
+ *                             preconditions the FP64 iteration, so this moves
+ *                             the iteration count, not the solution
  * sw_get_tuning returns the current value (-1 for an unknown key).           */
 int sw_set_tuning(const char* key, int32_t value);
 int32_t sw_get_tuning(const char* key);

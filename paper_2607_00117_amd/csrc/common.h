@@ -71,6 +71,10 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 //  g_sparse_cols   constraints per column-sum workgroup
 //  g_sparse_lanes  lanes per row in the row dots (16 or 64)
 //  g_rhs_group     right-hand sides of one shared matrix per workgroup (1, 2, 4, 8)
+//  g_factor_x3     1: the factorisation's large products on bf16x3 MFMA, 0: fp32 MFMA
+extern int g_factor_x3;
+//  g_gram_dense    1: the Gram streams every 32-orbit stage (no zero-panel skipping)
+extern int g_gram_dense;
 extern int g_sparse_rows;
 extern int g_sparse_cols;
 extern int g_sparse_lanes;

@@ -18,16 +18,21 @@ constexpr int kNB = 128;  // Cholesky / triangular-solve block size, also the GE
 // a multiple of 256, rows past M zero), ld = row stride of X; xoff/xlen given
 // on the device (bf16 modes) and on the host (fp32 mode); K_b = K + b * sK.
 inline int64_t gram_rows(int mode, int64_t M) { return mode == SW_GRAM_F32 ? M : (M + 255) / 256 * 256; }
+// nz (bf16 modes, may be null): bit g of nz[t * nzw + g / 64] is set when rows
+// [256 t, 256 t + 256) of X hold a nonzero in columns [32 g, 32 g + 32); the
+// 32-column stages whose row or column panel is zero are skipped.
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
                 const int64_t* xlen_d, const int64_t* xoff_h, const int64_t* xlen_h, int nb, float* K, int64_t ldk,
-                int64_t sK, hipStream_t st);
+                int64_t sK, hipStream_t st, const uint64_t* nz = nullptr, int64_t nzw = 0);
 
 // C = beta C + alpha A B^T per problem (fp32 MFMA, fp32 accumulate).
 // M, N, K multiples of 128 (K multiple of 32).  lower: only tiles with tile_m >= tile_n.
 // a_lower: A is lower triangular in 128-tiles (row tile m reads k < 128 (m + 1) only).
+// x3: the same product with the operands split into bf16 pairs (hi + lo) on
+// bf16 MFMA, three products per pair (~2^-16 of each product dropped).
 hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, int64_t sA,
                        const float* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
-                       bool lower, int nb, hipStream_t st, bool a_lower = false);
+                       bool lower, int nb, hipStream_t st, bool a_lower = false, bool x3 = false);
 
 // Cholesky factor L_b of each n x n (n multiple of 128) SPD matrix held in
 // the lower triangle of S_b (row-major, ld): blocked right-looking, 128 x 128

@@ -79,10 +79,15 @@ static int64_t super_grid(int64_t nt) {
 // A 512-thread workgroup owns a 256 x 256 tile of K; its 8 waves form a
 // 2 x 4 grid of 128 x 64 blocks (4 x 2 MFMA 32x32 outputs each), so a wave
 // issues 24 (X3: hi.hi + hi.lo + lo.hi) MFMAs per 12 operand reads from LDS.
-// Operands stream through LDS in k-stages of 32 (rows padded to 80 bytes so
-// the 16-byte reads of a half-wave hit distinct banks); the next stage is
-// fetched into registers while the current one is consumed.  On diagonal
-// tiles the row and column panels coincide and are staged once.
+// Operands stream through two LDS buffers in k-stages of 32 (rows padded to
+// 80 bytes so the 16-byte reads of a half-wave hit distinct banks): while a
+// stage is consumed from one buffer the next is fetched into registers and
+// then written to the other, one barrier per stage.  On diagonal tiles the
+// row and column panels coincide and are staged once.
+// Stage skipping: when `nz` is given, bit g of nz[t * nzw + g / 64] says
+// whether rows [256 t, 256 t + 256) of X have a nonzero in columns
+// [32 g, 32 g + 32) (global stage g); a stage whose row panel or column panel
+// is zero adds nothing and is skipped.
 // X has Mx rows (a multiple of 256, zero past the constraints); entries of K
 // are stored for rows and columns below M only.
 // ---------------------------------------------------------------------------
@@ -96,15 +101,13 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
                                                          const int64_t* __restrict__ xoff,
                                                          const int64_t* __restrict__ xlen, int64_t ld,
                                                          float* __restrict__ Kall, int64_t ldk, int64_t sK, int64_t M,
-                                                         int64_t nt) {
+                                                         int64_t nt, const uint64_t* __restrict__ nz, int64_t nzw) {
   constexpr int NM = X3 ? 4 : 2;  // staged panels: A hi, B hi (, A lo, B lo)
-  __shared__ __attribute__((aligned(16))) __bf16 sm[NM][kGT][kGPad];
+  __shared__ __attribute__((aligned(16))) __bf16 sm[2][NM][kGT][kGPad];
   const int64_t bp = blockIdx.y;
   int64_t tm, tn;
   if (!super_tile(blockIdx.x, nt, tm, tn)) return;
-  const int64_t Kd = xlen[bp];
-  hi += xoff[bp];
-  lo += xoff[bp];
+  const int64_t g0 = xoff[bp] / kGBK, g1 = (xoff[bp] + xlen[bp]) / kGBK;  // global stages of problem bp
   float* __restrict__ K = Kall + bp * sK;
   const bool diag = tm == tn;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -117,6 +120,23 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
+  // the next stage >= g whose row and column panels both hold a nonzero (g1: none)
+  const uint64_t* nzA = nz ? nz + tm * nzw : nullptr;
+  const uint64_t* nzB = nz ? nz + tn * nzw : nullptr;
+  auto next = [&](int64_t g) -> int64_t {
+    if (!nzA) return g;
+    while (g < g1) {
+      const int64_t wd = g >> 6;
+      const uint64_t m = (nzA[wd] & nzB[wd]) & (~0ull << (g & 63));
+      if (m) {
+        const int64_t c = (wd << 6) + __builtin_ctzll(m);
+        return c < g1 ? c : g1;
+      }
+      g = (wd + 1) << 6;
+    }
+    return g1;
+  };
+
   // a panel stage is 256 rows x 32 k = 1024 chunks of 16 B, 2 per thread:
   // chunk q = tid + 512 j is row q / 4, k offset 8 (q % 4)
   const int r0 = tid >> 2, r1 = r0 + kGThreads / 4, cc = (tid & 3) * 8;
@@ -125,7 +145,8 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
   const __bf16* pAl = lo + tm * kGT * ld + cc;
   const __bf16* pBl = lo + tn * kGT * ld + cc;
   uint4 gAh0, gAh1, gBh0, gBh1, gAl0, gAl1, gBl0, gBl1;
-  auto gload = [&](int64_t k0) {
+  auto gload = [&](int64_t g) {
+    const int64_t k0 = g * kGBK;
     gAh0 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r0 * ld + k0);
     gAh1 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r1 * ld + k0);
     if (!diag) {
@@ -141,40 +162,50 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
       }
     }
   };
-  gload(0);
-  const int bA = 0, bB = diag ? 0 : 1;  // LDS panels read as A and as B
-  for (int64_t k0 = 0; k0 < Kd; k0 += kGBK) {
-    *reinterpret_cast<uint4*>(&sm[0][r0][cc]) = gAh0;
-    *reinterpret_cast<uint4*>(&sm[0][r1][cc]) = gAh1;
+  auto stage = [&](int buf) {
+    *reinterpret_cast<uint4*>(&sm[buf][0][r0][cc]) = gAh0;
+    *reinterpret_cast<uint4*>(&sm[buf][0][r1][cc]) = gAh1;
     if (!diag) {
-      *reinterpret_cast<uint4*>(&sm[1][r0][cc]) = gBh0;
-      *reinterpret_cast<uint4*>(&sm[1][r1][cc]) = gBh1;
+      *reinterpret_cast<uint4*>(&sm[buf][1][r0][cc]) = gBh0;
+      *reinterpret_cast<uint4*>(&sm[buf][1][r1][cc]) = gBh1;
     }
     if constexpr (X3) {
-      *reinterpret_cast<uint4*>(&sm[2][r0][cc]) = gAl0;
-      *reinterpret_cast<uint4*>(&sm[2][r1][cc]) = gAl1;
+      *reinterpret_cast<uint4*>(&sm[buf][2][r0][cc]) = gAl0;
+      *reinterpret_cast<uint4*>(&sm[buf][2][r1][cc]) = gAl1;
       if (!diag) {
-        *reinterpret_cast<uint4*>(&sm[3][r0][cc]) = gBl0;
-        *reinterpret_cast<uint4*>(&sm[3][r1][cc]) = gBl1;
+        *reinterpret_cast<uint4*>(&sm[buf][3][r0][cc]) = gBl0;
+        *reinterpret_cast<uint4*>(&sm[buf][3][r1][cc]) = gBl1;
       }
     }
-    __syncthreads();
-    if (k0 + kGBK < Kd) gload(k0 + kGBK);
+  };
+  const int bA = 0, bB = diag ? 0 : 1;  // LDS panels read as A and as B
+  int64_t g = next(g0);
+  int buf = 0;
+  if (g < g1) {
+    gload(g);
+    stage(0);
+  }
+  __syncthreads();
+  while (g < g1) {
+    const int64_t gn = next(g + 1);
+    if (gn < g1) gload(gn);
 #pragma unroll
     for (int ks = 0; ks < kGBK / 16; ++ks) {
       const int kc = ks * 16 + 8 * (lane >> 5);
       bf16x8 bn[2], bnl[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        bn[b] = *reinterpret_cast<const bf16x8*>(&sm[bB][wn * 64 + b * 32 + (lane & 31)][kc]);
-        if constexpr (X3) bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
+        bn[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB][wn * 64 + b * 32 + (lane & 31)][kc]);
+        if constexpr (X3)
+          bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
       }
       // one row block's operands at a time keeps the live fragments few
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm[bA][wm * 128 + a * 32 + (lane & 31)][kc]);
+        const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm[buf][bA][wm * 128 + a * 32 + (lane & 31)][kc]);
         bf16x8 aml;
-        if constexpr (X3) aml = *reinterpret_cast<const bf16x8*>(&sm[bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
+        if constexpr (X3)
+          aml = *reinterpret_cast<const bf16x8*>(&sm[buf][bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bn[b], acc[a][b], 0, 0, 0);
@@ -185,7 +216,11 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
         }
       }
     }
+    // the other buffer was last read before the previous barrier
+    if (gn < g1) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
+    g = gn;
   }
   const bool edge = (tm + 1) * kGT > M;  // only the last tile row/column can cross M
 #pragma unroll
@@ -198,6 +233,31 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
         const int64_t col = tn * kGT + wn * 64 + b * 32 + (lane & 31);
         if (!edge || (row < M && col < M)) K[row * ldk + col] = acc[a][b][i];
       }
+}
+
+// Tile of a 128-tiled GEMM workgroup (false: none).  With a lower-triangular
+// A (a_lower) and a full output, row tile tm has (tm + 1) * 128 inner terms;
+// row tiles are then dealt to the XCDs round-robin from the longest down (XCD
+// x gets the k-th longest for k = x mod 8), each XCD taking all column tiles
+// of its row tiles: every XCD gets an equal share of long and short tiles, and
+// an A row panel is read by one XCD only.  Otherwise XCD x takes a contiguous
+// run of tiles (row-major, or the lower triangle when `lower`).
+__device__ __forceinline__ bool gemm_tile(int64_t ntn, int lower, int a_lower, int64_t n_tiles, int64_t& tm,
+                                          int64_t& tn) {
+  if (a_lower && !lower) {
+    const int64_t ntm = n_tiles / ntn;
+    const int64_t x = blockIdx.x % kXcd, r = blockIdx.x / kXcd, i = r / ntn;
+    const int64_t k = i * kXcd + x;
+    if (k >= ntm) return false;
+    tm = ntm - 1 - k;
+    tn = r - i * ntn;
+    return true;
+  }
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return false;
+  if (lower) tri_tile(t, tm, tn);
+  else { tm = t / ntn; tn = t - tm * ntn; }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -219,24 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
   __shared__ float As[kT][kPadF];
   __shared__ float Bs[kT][kPadF];
   int64_t tm, tn;
-  if (a_lower && !lower) {
-    // lower-triangular A: row tile tm has (tm + 1) * 128 inner terms.  Row tiles
-    // are dealt to the XCDs round-robin from the longest down (XCD x gets the
-    // k-th longest for k = x mod 8), each XCD taking all column tiles of its
-    // row tiles: every XCD gets an equal share of long and short tiles, and
-    // an A row panel is read by one XCD only.
-    const int64_t ntm = n_tiles / ntn;
-    const int64_t x = blockIdx.x % kXcd, r = blockIdx.x / kXcd, i = r / ntn;
-    const int64_t k = i * kXcd + x;
-    if (k >= ntm) return;
-    tm = ntm - 1 - k;
-    tn = r - i * ntn;
-  } else {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= n_tiles) return;
-    if (lower) tri_tile(t, tm, tn);
-    else { tm = t / ntn; tn = t - tm * ntn; }
-  }
+  if (!gemm_tile(ntn, lower, a_lower, n_tiles, tm, tn)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   floatx16 acc[2][2];
@@ -292,6 +335,121 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(am[a], bn[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t row = tm * kT + wm * 64 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int64_t col = tn * kT + wn * 64 + b * 32 + (lane & 31);
+        float* cp = C + row * ldc + col;
+        const float v = alpha * acc[a][b][i];
+        *cp = (beta == 0.0f) ? v : beta * (*cp) + v;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// The same product with each fp32 operand split on the fly into a bf16 pair,
+// x = hi + lo (hi = x rounded to bf16, lo = the remainder rounded to bf16), and
+// C = beta C + alpha (A_hi B_hi^T + A_hi B_lo^T + A_lo B_hi^T) on bf16 MFMA
+// (32x32x16) with fp32 accumulation: the dropped terms are ~2^-16 of each
+// product.  Same tiles, schedule and split-K as k_gemm_nt_f32; operands are
+// staged as hi/lo planes in LDS (rows padded to 80 bytes).
+// ---------------------------------------------------------------------------
+constexpr int kX3Pad = kBKf + 8;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K, float alpha,
+                                                         const float* __restrict__ A, int64_t lda, int64_t sA,
+                                                         const float* __restrict__ B, int64_t ldb, int64_t sB,
+                                                         float beta, float* __restrict__ C, int64_t ldc, int64_t sC,
+                                                         int lower, int a_lower, int64_t n_tiles, int64_t kc,
+                                                         int64_t sPart) {
+  A += blockIdx.y * sA;
+  B += blockIdx.y * sB;
+  C += blockIdx.y * sC;
+  __shared__ __attribute__((aligned(16))) __bf16 sm[4][kT][kX3Pad];  // A hi, B hi, A lo, B lo
+  int64_t tm, tn;
+  if (!gemm_tile(ntn, lower, a_lower, n_tiles, tm, tn)) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+  const float* Ab = A + tm * kT * lda;
+  const float* Bb = B + tn * kT * ldb;
+  // a stage is 128 rows x 32 k of each operand: thread t loads rows t/8 + 32 i,
+  // k offset 4 (t % 8), as four float4 per operand
+  float4 ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + kThreads * i;
+      const int r = idx >> 3, c = (idx & 7) * 4;
+      ra[i] = *reinterpret_cast<const float4*>(Ab + (int64_t)r * lda + k0 + c);
+      rb[i] = *reinterpret_cast<const float4*>(Bb + (int64_t)r * ldb + k0 + c);
+    }
+  };
+  auto split4 = [](const float4 v, __bf16* hi, __bf16* lo) {
+    const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const __bf16 h = (__bf16)x[j];
+      hi[j] = h;
+      lo[j] = (__bf16)(x[j] - (float)h);
+    }
+  };
+  int64_t Kend = (a_lower && (tm + 1) * kT < K) ? (tm + 1) * kT : K;
+  int64_t kbeg = 0;
+  if (kc > 0) {
+    kbeg = (int64_t)blockIdx.z * kc;
+    if (kbeg >= Kend) return;
+    Kend = kbeg + kc < Kend ? kbeg + kc : Kend;
+    C += (int64_t)blockIdx.z * sPart;
+  }
+  gload(kbeg);
+  for (int64_t k0 = kbeg; k0 < Kend; k0 += kBKf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + kThreads * i;
+      const int r = idx >> 3, c = (idx & 7) * 4;
+      __bf16 h[4], l[4];
+      split4(ra[i], h, l);
+      *reinterpret_cast<uint2*>(&sm[0][r][c]) = *reinterpret_cast<const uint2*>(h);
+      *reinterpret_cast<uint2*>(&sm[2][r][c]) = *reinterpret_cast<const uint2*>(l);
+      split4(rb[i], h, l);
+      *reinterpret_cast<uint2*>(&sm[1][r][c]) = *reinterpret_cast<const uint2*>(h);
+      *reinterpret_cast<uint2*>(&sm[3][r][c]) = *reinterpret_cast<const uint2*>(l);
+    }
+    __syncthreads();
+    if (k0 + kBKf < Kend) gload(k0 + kBKf);
+#pragma unroll
+    for (int ks = 0; ks < kBKf / 16; ++ks) {
+      const int kcol = ks * 16 + 8 * (lane >> 5);
+      bf16x8 bh[2], bl[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bh[b] = *reinterpret_cast<const bf16x8*>(&sm[1][wn * 64 + b * 32 + (lane & 31)][kcol]);
+        bl[b] = *reinterpret_cast<const bf16x8*>(&sm[3][wn * 64 + b * 32 + (lane & 31)][kcol]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm[0][wm * 64 + a * 32 + (lane & 31)][kcol]);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm[2][wm * 64 + a * 32 + (lane & 31)][kcol]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
@@ -654,7 +812,7 @@ __global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__
 // ---------------------------------------------------------------------------
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
                 const int64_t* xlen_d, const int64_t* xoff_h, const int64_t* xlen_h, int nb, float* K, int64_t ldk,
-                int64_t sK, hipStream_t st) {
+                int64_t sK, hipStream_t st, const uint64_t* nz, int64_t nzw) {
   if (mode == SW_GRAM_F32) {
     for (int b = 0; b < nb; ++b) {
       hipError_t e = gemm_nt_f32(M, M, xlen_h[b], 1.0f, xf + xoff_h[b], ld, 0, xf + xoff_h[b], ld, 0, 0.0f, K + b * sK,
@@ -667,24 +825,26 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
   const int64_t grid = super_grid(nt);
   if (mode == SW_GRAM_BF16X3)
     hipLaunchKernelGGL(k_gram_bf16<true>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt);
+                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
   else
     hipLaunchKernelGGL(k_gram_bf16<false>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt);
+                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
   return hipGetLastError();
 }
 
+int g_factor_x3 = 1;
+
 hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, int64_t sA,
                        const float* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
-                       bool lower, int nb, hipStream_t st, bool a_lower) {
+                       bool lower, int nb, hipStream_t st, bool a_lower, bool x3) {
   const int64_t ntm = M / kT, ntn = N / kT;
   const int64_t n_tiles = lower ? ntm * (ntm + 1) / 2 : ntm * ntn;
   if (n_tiles == 0) return hipSuccess;
   const int64_t grid = (a_lower && !lower) ? kXcd * ((ntm + kXcd - 1) / kXcd) * ntn
                                            : ((n_tiles + kXcd - 1) / kXcd) * kXcd;
-  hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st, ntn, K, alpha, A, lda,
-                     sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles, (int64_t)0,
-                     (int64_t)0);
+  hipLaunchKernelGGL(x3 ? k_gemm_nt_x3 : k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb), dim3(kThreads), 0, st, ntn,
+                     K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles,
+                     (int64_t)0, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -712,11 +872,13 @@ static hipError_t gemm_lower_split(int64_t M, int64_t N, const float* W, int64_t
                                    int64_t sParts, int nb, hipStream_t st) {
   const int64_t ntn = N / kT;
   const int64_t kc = split_kc(M, ntn, nb);
-  if (kc >= M) return gemm_nt_f32(M, N, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, ldx, sX, false, nb, st, true);
+  const bool x3 = g_factor_x3 != 0;
+  if (kc >= M) return gemm_nt_f32(M, N, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, ldx, sX, false, nb, st, true, x3);
   const int64_t ntm = M / kT, n_tiles = ntm * ntn, nchunk = (M + kc - 1) / kc;
   const int64_t grid = kXcd * ((ntm + kXcd - 1) / kXcd) * ntn;
-  hipLaunchKernelGGL(k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kThreads), 0, st, ntn,
-                     M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles, kc, M * N);
+  hipLaunchKernelGGL(x3 ? k_gemm_nt_x3 : k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk),
+                     dim3(kThreads), 0, st, ntn, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles,
+                     kc, M * N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nq = M * (N / 4);
@@ -745,7 +907,7 @@ static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* d
         // block column j (rows from its diagonal down) -= its rows of the group's panels times theirs
         const float* Pg = K + j * kNB * ld + j0 * kNB;
         e = gemm_nt_f32(n - j * kNB, kNB, (j - j0) * kNB, -1.0f, Pg, ld, sK, Pg, ld, sK, 1.0f, Kjj, ld, sK, false,
-                        nb_prob, st);
+                        nb_prob, st, false, g_factor_x3 != 0);
         if (e != hipSuccess) return e;
       }
       hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)nb_prob), dim3(kPotrfThreads), 0, st, Kjj, ld, sK,
@@ -764,7 +926,7 @@ static hipError_t cholesky(float* K, int64_t n, int64_t ld, int64_t sK, float* d
     // trailing update K_22 -= L_g L_g^T over the group's panels (lower tiles)
     const float* Pg = K + j1 * kNB * ld + j0 * kNB;
     e = gemm_nt_f32(rest, rest, (j1 - j0) * kNB, -1.0f, Pg, ld, sK, Pg, ld, sK, 1.0f, K + j1 * kNB * ld + j1 * kNB, ld,
-                    sK, true, nb_prob, st);
+                    sK, true, nb_prob, st, false, g_factor_x3 != 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -835,7 +997,7 @@ static hipError_t invert_factor(float* K, int64_t n, int64_t ld, int64_t sK, con
                            0, st, K + r1 * ld + j * kNB, ld, sK, Lt, kin, sT, (int64_t)(kNB / kTT));
         if ((e = hipGetLastError()) != hipSuccess) return e;
         e = gemm_nt_f32(rest, kNB, kin, 1.0f, K + r1 * ld + r1, ld, sK, Lt, kin, sT, 1.0f, C, w, sT, false, nb_prob, st,
-                        true);
+                        true, g_factor_x3 != 0);
         if (e != hipSuccess) return e;
       }
       hipLaunchKernelGGL(k_transpose, dim3((unsigned)((kNB / kTT) * (kNB / kTT)), (unsigned)nb_prob), dim3(kThreads),

@@ -90,6 +90,50 @@ __global__ __launch_bounds__(256) void k_gh_moments(const TA* __restrict__ A, in
     if (m <= n_gh) o[m] = acc[m];
 }
 
+// Rows of the fit matrix (Eq. 3): the mass block and the surface-density
+// columns copied, out[i][0, n_mass) = A[i][0, n_mass), out[i][n_mass + a] =
+// A[i][surf0 + a] (surf0 >= 0).  One thread per output entry.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_fit_copy(const TA* __restrict__ A, int64_t n_orb, int64_t n_con,
+                                                  int64_t n_mass, int64_t surf0, int32_t n_sigma, int64_t n_out,
+                                                  TA* __restrict__ out) {
+  const int64_t w = n_mass + n_sigma;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_orb * w) return;
+  const int64_t i = t / w, c = t - i * w;
+  out[i * n_out + c] = c < n_mass ? A[i * n_con + c] : A[i * n_con + surf0 + (c - n_mass)];
+}
+
+// The Gauss-Hermite block of the fit matrix: out[i][h0 + (m - 1) n_ap + a] =
+// g_m(i, a) / gamma[a], m = 1..n_gh, one thread per (orbit, aperture).
+template <typename TA>
+__global__ __launch_bounds__(256) void k_fit_gh(const TA* __restrict__ A, int64_t n_orb, int64_t n_con, int64_t kin0,
+                                                int32_t n_ap, int32_t nv, int32_t n_gh, const double* __restrict__ G,
+                                                const double* __restrict__ inv_gamma, int64_t h0, int64_t n_out,
+                                                TA* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_orb * n_ap) return;
+  const int64_t i = t / n_ap;
+  const int a = (int)(t - i * n_ap);
+  const TA* row = A + i * n_con + kin0 + (int64_t)a * nv;
+  const double* Ga = G + (size_t)a * (n_gh + 1) * nv;
+  double acc[kMaxGH + 1];
+#pragma unroll
+  for (int m = 0; m <= kMaxGH; ++m) acc[m] = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double v = (double)row[k];
+    if (v == 0.0) continue;
+#pragma unroll
+    for (int m = 1; m <= kMaxGH; ++m)
+      if (m <= n_gh) acc[m] += Ga[(size_t)m * nv + k] * v;
+  }
+  TA* o = out + i * n_out + h0 + a;
+  const double ig = inv_gamma[a];
+#pragma unroll
+  for (int m = 1; m <= kMaxGH; ++m)
+    if (m <= n_gh) o[(int64_t)(m - 1) * n_ap] = (TA)(acc[m] * ig);
+}
+
 }  // namespace sw
 
 using namespace sw;
@@ -134,5 +178,63 @@ extern "C" int gh_moments(const void* A, int32_t dtype, int64_t n_orb, int64_t n
   SW_HIP(hipGetLastError());
   // the host copy of G must outlive the transfer
   SW_HIP(hipStreamSynchronize(st));
+  return SW_OK;
+}
+
+extern "C" size_t gh_fit_workspace_bytes(int32_t n_ap, int32_t nv, int32_t n_gh) {
+  const size_t g = gh_workspace_bytes(n_ap, nv, n_gh);
+  return g ? g + (size_t)n_ap * sizeof(double) : 0;
+}
+
+extern "C" int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, int64_t n_mass, int64_t kin0,
+                             int64_t surf0, int32_t n_ap, int32_t nv, double vlo, double vhi, const double* v0,
+                             const double* s, const double* gamma, int32_t n_gh, void* out, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  SW_CHECK(dtype == SW_F32 || dtype == SW_F64, "gh_fit_matrix: dtype must be SW_F32 or SW_F64");
+  SW_CHECK(n_orb >= 0 && n_ap >= 1 && nv >= 1, "gh_fit_matrix: need n_orb >= 0, n_ap >= 1, nv >= 1");
+  SW_CHECK(n_gh >= 1 && n_gh <= kMaxGH, "gh_fit_matrix: n_gh in [1, %d]", kMaxGH);
+  SW_CHECK(n_mass >= 0 && n_mass <= n_con, "gh_fit_matrix: mass block beyond n_con");
+  SW_CHECK(kin0 >= 0 && kin0 + (int64_t)n_ap * nv <= n_con, "gh_fit_matrix: kinematic block beyond n_con");
+  SW_CHECK(surf0 < 0 || surf0 + n_ap <= n_con, "gh_fit_matrix: surface block beyond n_con");
+  SW_CHECK(std::isfinite(vlo) && std::isfinite(vhi) && vhi > vlo, "gh_fit_matrix: need vhi > vlo");
+  SW_CHECK(v0 && s && gamma, "gh_fit_matrix: null v0 / s / gamma");
+  for (int a = 0; a < n_ap; ++a) {
+    SW_CHECK(std::isfinite(v0[a]) && std::isfinite(s[a]) && s[a] > 0.0, "gh_fit_matrix: aperture %d needs s > 0", a);
+    SW_CHECK(std::isfinite(gamma[a]) && gamma[a] > 0.0, "gh_fit_matrix: aperture %d needs gamma > 0", a);
+  }
+  const size_t gbytes = gh_workspace_bytes(n_ap, nv, n_gh), need = gh_fit_workspace_bytes(n_ap, nv, n_gh);
+  if (ws_bytes < need || !workspace) {
+    set_error("gh_fit_matrix: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return SW_ENOMEM;
+  }
+  if (n_orb == 0) return SW_OK;
+  SW_CHECK(A && out, "gh_fit_matrix: null device buffer");
+  double c[kMaxGH + 1][kMaxGH + 1];
+  hermite_coefficients(n_gh, c);
+  std::vector<double> G(gbytes / sizeof(double) + n_ap);
+  for (int a = 0; a < n_ap; ++a) bin_kernel(vlo, vhi, nv, v0[a], s[a], n_gh, c, G.data() + (size_t)a * (n_gh + 1) * nv);
+  for (int a = 0; a < n_ap; ++a) G[gbytes / sizeof(double) + a] = 1.0 / gamma[a];
+  hipStream_t st = (hipStream_t)stream;
+  SW_HIP(hipMemcpyAsync(workspace, G.data(), need, hipMemcpyHostToDevice, st));
+  const double* Gd = (const double*)workspace;
+  const double* ig = Gd + gbytes / sizeof(double);
+  const int32_t n_sig = surf0 >= 0 ? n_ap : 0;
+  const int64_t h0 = n_mass + n_sig, n_out = h0 + (int64_t)n_gh * n_ap;
+  const int64_t nc = n_orb * (n_mass + n_sig), ng = n_orb * n_ap;
+  if (dtype == SW_F32) {
+    if (nc > 0)
+      hipLaunchKernelGGL(k_fit_copy<float>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const float*)A, n_orb,
+                         n_con, n_mass, surf0, n_sig, n_out, (float*)out);
+    hipLaunchKernelGGL(k_fit_gh<float>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, (const float*)A, n_orb,
+                       n_con, kin0, n_ap, nv, n_gh, Gd, ig, h0, n_out, (float*)out);
+  } else {
+    if (nc > 0)
+      hipLaunchKernelGGL(k_fit_copy<double>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const double*)A,
+                         n_orb, n_con, n_mass, surf0, n_sig, n_out, (double*)out);
+    hipLaunchKernelGGL(k_fit_gh<double>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, (const double*)A, n_orb,
+                       n_con, kin0, n_ap, nv, n_gh, Gd, ig, h0, n_out, (double*)out);
+  }
+  SW_HIP(hipGetLastError());
+  SW_HIP(hipStreamSynchronize(st));  // the host copy of the maps must outlive the transfer
   return SW_OK;
 }

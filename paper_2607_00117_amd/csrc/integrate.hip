@@ -135,6 +135,16 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_sparse_lanes = value;
     return SW_OK;
   }
+  if (k == "gram_skip") {
+    SW_CHECK(value == 0 || value == 1, "sw_set_tuning: gram_skip: 1 (skip zero panels) or 0 (stream every stage)");
+    g_gram_dense = value ? 0 : 1;
+    return SW_OK;
+  }
+  if (k == "factor_gemm") {
+    SW_CHECK(value == 0 || value == 1, "sw_set_tuning: factor_gemm: 0 (fp32 MFMA) or 1 (bf16x3 MFMA)");
+    g_factor_x3 = value;
+    return SW_OK;
+  }
   if (k == "rhs_per_group") {
     SW_CHECK(value == 0 || value == 1 || value == 2 || value == 4 || value == 8,
              "sw_set_tuning: rhs_per_group: 0 (automatic), 1, 2, 4 or 8");
@@ -154,6 +164,8 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "sparse_cols_per_wg") return g_sparse_cols;
   if (k == "sparse_lanes_per_row") return g_sparse_lanes;
   if (k == "rhs_per_group") return g_rhs_group;
+  if (k == "factor_gemm") return g_factor_x3;
+  if (k == "gram_skip") return g_gram_dense ? 0 : 1;
   return -1;
 }
 

@@ -56,6 +56,7 @@ constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) res
 constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
 
 int g_sparse_rows = 0;
+int g_gram_dense = 0;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
 int g_rhs_group = 0;
@@ -78,8 +79,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// X[n][xoff_b + j] = w~_b A[off_b + j][n] / sigma_b,n (zero-padded, masked
-// orbits zero): constraint-major operand of the Gram.  64 x 64 LDS tiles.
+// X[n][xoff_b + j] = w~_b A[off_b + p_j][n] / sigma_b,n (zero-padded, masked
+// orbits zero): constraint-major operand of the Gram, its columns in the orbit
+// order p = perm[off_b ..] (the rows' order when perm is null).  64 x 64 LDS tiles.
 // ---------------------------------------------------------------------------
 template <typename TA>
 __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_t C, int64_t Npt,
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
                                                 int nprob, const double* __restrict__ sigma,
                                                 const double* __restrict__ par, const uint8_t* __restrict__ mask,
                                                 int mode, __bf16* __restrict__ hi, __bf16* __restrict__ lo,
-                                                float* __restrict__ xf) {
+                                                float* __restrict__ xf, const int32_t* __restrict__ perm) {
   __shared__ float tile[64][65];
   const int64_t n0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
   const int b = find_problem(xoff, nprob, c0);
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
     const int64_t j = c0 - xoff[b] + r, n = n0 + tx;
     float v = 0.0f;
     if (j < nb && n < C) {
-      const int64_t i = off[b] + j;
+      const int64_t i = off[b] + (perm ? perm[off[b] + j] : j);
       if (!(mask && mask[i])) v = (float)((double)A[i * C + n] * (wt / sg[n]));
     }
     tile[r][tx] = v;
@@ -117,6 +119,38 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
       if (mode == SW_GRAM_BF16X3) lo[at] = (__bf16)(v - (float)h);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Zero-panel bits of the Gram operand: bit g of nz[t * nzw + g / 64] is set when
+// rows [256 t, 256 t + 256) of X (the hi plane) hold a nonzero in columns
+// [32 g, 32 g + 32).  Workgroup (word, tile): 256 threads each scan 8 columns of
+// every row of the tile; four threads make a 32-column stage.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nz_bits(const __bf16* __restrict__ hi, int64_t Npt, int64_t nzw,
+                                                 uint64_t* __restrict__ nz) {
+  __shared__ uint32_t part[4];
+  const int64_t wd = blockIdx.x, t = blockIdx.y;
+  const int64_t col = wd * 2048 + 8 * (int64_t)threadIdx.x;
+  uint32_t any = 0;
+  if (col < Npt) {
+    const __bf16* p = hi + t * 256 * Npt + col;
+    for (int r = 0; r < 256; ++r) {
+      const uint4 v = *reinterpret_cast<const uint4*>(p + (int64_t)r * Npt);
+      any |= (v.x | v.y | v.z | v.w) & 0x7fff7fffu;
+    }
+  }
+  uint32_t f = any != 0 ? 1u : 0u;
+  f |= __shfl_xor(f, 1);
+  f |= __shfl_xor(f, 2);
+  const uint64_t bal = __ballot(f != 0 && (threadIdx.x & 3) == 0);
+  uint32_t bits = 0;
+  for (int i = 0; i < 16; ++i) bits |= (uint32_t)((bal >> (4 * i)) & 1u) << i;
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    nz[t * nzw + wd] = (uint64_t)part[0] | ((uint64_t)part[1] << 16) | ((uint64_t)part[2] << 32) |
+                       ((uint64_t)part[3] << 48);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,21 +223,33 @@ __host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps, int64_t
   return rps >= blk ? 1 : blk / rps;
 }
 
-// cnt[i][cb] = nonzeros of row i in column block cb (one wave per row)
+// cnt[i][cb] = nonzeros of row i in column block cb (one wave per row);
+// tiles[i] = number of 256-column tiles of row i holding a nonzero (the row's
+// footprint on the Gram's panels; blk is a multiple of 256)
 template <typename TA>
 __global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C, int ncb, int64_t blk,
-                                                 int64_t* __restrict__ cnt) {
+                                                 int64_t* __restrict__ cnt, int32_t* __restrict__ tiles) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const TA* row = A + i * C;
+  int32_t nt = 0;
+  int64_t last = -1;
   for (int cb = 0; cb < ncb; ++cb) {
     const int64_t c1 = (int64_t)(cb + 1) * blk < C ? (int64_t)(cb + 1) * blk : C;
     int64_t k = 0;
-    for (int64_t c = (int64_t)cb * blk + lane; c < c1; c += 64) k += row[c] != TA(0);
+    for (int64_t c0 = (int64_t)cb * blk; c0 < c1; c0 += 64) {
+      const bool v = c0 + lane < c1 && row[c0 + lane] != TA(0);
+      k += v;
+      if (__ballot(v) != 0 && (c0 >> 8) != last) {
+        last = c0 >> 8;
+        ++nt;
+      }
+    }
     for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
     if (lane == 0) cnt[i * ncb + cb] = k;
   }
+  if (lane == 0 && tiles) tiles[i] = nt;
 }
 
 // cpart[b][s][c] = number of nonzeros of column c in slab s of problem b
@@ -1300,6 +1346,9 @@ struct SolveLayout {
   int nrb_a;    // rg > 1: row blocks that hold orbits (partials per column)
   size_t off_pd;  // rg > 1: partial row dots [P][ncb][NA]
   size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_crow, off_cval;
+  int64_t nzw;    // 64-bit words of zero-panel bits per 256-row tile of X
+  size_t off_nz;  // zero-panel bits of the Gram operand [Cx / 256][nzw]
+  size_t off_tiles, off_perm;  // per orbit: nonzero 256-constraint tiles; the orbit order of X's columns
   size_t total;
 };
 
@@ -1332,6 +1381,8 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_hi = take(gram_mode == SW_GRAM_F32 ? 0 : xe * 2);
   L.off_lo = take(gram_mode == SW_GRAM_BF16X3 ? xe * 2 : 0);
   L.off_xf = take(gram_mode == SW_GRAM_F32 ? xe * 4 : 0);
+  L.nzw = (L.Npt + 2047) / 2048;
+  L.off_nz = take(gram_mode == SW_GRAM_F32 ? 0 : (size_t)(gram_rows(gram_mode, L.Cp) / 256) * L.nzw * 8);
   L.off_K = take(PA * L.Cp * L.Cp * 4);
   L.off_dinv = take(PA * L.Cp * kNB * 4);
   L.off_part = take((size_t)P * kSlabs * L.C * 8);
@@ -1389,6 +1440,8 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
   L.off_pd = take(L.rg > 1 ? (size_t)P * L.ncb * NA * 8 : 0);
+  L.off_tiles = take(NA * 4);
+  L.off_perm = take(NA * 4);
   L.total = o;
   return L;
 }
@@ -1396,6 +1449,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
 struct Ctx {
   SolveLayout L;
   bool sparse = false;
+  const int32_t* perm = nullptr;  // orbit order of the Gram operand's columns (null: the rows' order)
   int64_t nnz = 0;
   char* ws;
   hipStream_t st;
@@ -1543,8 +1597,9 @@ static int build_sparse(Ctx& X) {
     if (L.rps[b] > L.blk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
   int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
   int32_t* cpart = X.p<int32_t>(L.off_cpart);
+  int32_t* tiles = X.p<int32_t>(L.off_tiles);
   hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
-                     rcnt);
+                     rcnt, tiles);
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
                      dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
@@ -1552,7 +1607,29 @@ static int build_sparse(Ctx& X) {
   std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
   SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
+  std::vector<int32_t> ht((size_t)NA);
+  SW_HIP(hipMemcpyAsync(ht.data(), tiles, ht.size() * 4, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipStreamSynchronize(X.st));
+  if (!g_gram_dense) {
+    // The Gram is a sum over orbits, so its operand may take the orbits in any
+    // order.  Ordered by footprint (number of nonzero 256-constraint tiles, a
+    // stable counting sort within each matrix) the orbits of one 32-orbit stage
+    // cover similar parts of the grid and the sky, and more stages of a panel
+    // are all zero.  perm[aoff_b + j] = row (within matrix b) of column j.
+    const int64_t nkey = (L.C + 255) / 256 + 1;
+    std::vector<int32_t> perm((size_t)NA);
+    std::vector<int64_t> start((size_t)nkey + 1);
+    for (int b = 0; b < P; ++b) {
+      const int64_t a0 = L.aoff[b], a1 = L.aoff[b + 1];
+      std::fill(start.begin(), start.end(), 0);
+      for (int64_t i = a0; i < a1; ++i) ++start[(size_t)std::min<int64_t>(ht[i], nkey - 1) + 1];
+      for (int64_t k = 0; k < nkey; ++k) start[k + 1] += start[k];
+      for (int64_t i = a0; i < a1; ++i) perm[a0 + start[(size_t)std::min<int64_t>(ht[i], nkey - 1)]++] = (int32_t)(i - a0);
+    }
+    SW_HIP(hipMemcpyAsync(X.p<int32_t>(L.off_perm), perm.data(), perm.size() * 4, hipMemcpyHostToDevice, X.st));
+    SW_HIP(hipStreamSynchronize(X.st));  // perm's host copy is freed on return
+    X.perm = X.p<int32_t>(L.off_perm);
+  }
   // segments are padded to whole quads (4 entries)
   auto quad = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
   int64_t nnz = 0, at = 0;
@@ -1739,21 +1816,28 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   // ---- scaled data and the transposed operand of the Gram ----
   hipLaunchKernelGGL(k_scaled_data, dim3(blocks_for(L.Cp), (unsigned)P), dim3(256), 0, X.st, d, sigma, X.sS, L.C,
                      L.Cp, X.p<double>(L.off_ys));
+  if (!(opt->flags & SW_SOLVE_DENSE)) {
+    const int rs = dtype == SW_F32 ? build_sparse<float>(X) : build_sparse<double>(X);
+    if (rs != SW_OK) return rs;
+  }
   {
     dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
     if (dtype == SW_F32)
       hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d, X.xoff_d,
                          PA, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
-                         X.p<float>(L.off_xf));
+                         X.p<float>(L.off_xf), X.perm);
     else
       hipLaunchKernelGGL(k_prep_x<double>, grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt, X.aoff_d,
                          X.xoff_d, PA, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
-                         X.p<float>(L.off_xf));
+                         X.p<float>(L.off_xf), X.perm);
     SW_TRY(hipGetLastError());
   }
-  if (!(opt->flags & SW_SOLVE_DENSE)) {
-    const int rs = dtype == SW_F32 ? build_sparse<float>(X) : build_sparse<double>(X);
-    if (rs != SW_OK) return rs;
+  const uint64_t* nzbits = nullptr;
+  if (opt->gram != SW_GRAM_F32 && !g_gram_dense) {
+    hipLaunchKernelGGL(k_nz_bits, dim3((unsigned)L.nzw, (unsigned)(gram_rows(opt->gram, L.Cp) / 256)), dim3(256), 0,
+                       X.st, X.p<__bf16>(L.off_hi), L.Npt, L.nzw, X.p<uint64_t>(L.off_nz));
+    SW_TRY(hipGetLastError());
+    nzbits = X.p<uint64_t>(L.off_nz);
   }
   SW_TRY(hipEventRecord(ev[1], X.st));
 
@@ -1768,7 +1852,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
                               L.Cp, X.par + 5, kPar, X.st);
   };
   SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
-              L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st));
+              L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st, nzbits, L.nzw));
   SW_TRY(hipEventRecord(ev[2], X.st));
   double* acc = X.p<double>(L.off_acc);
   SW_TRY(zero_acc(X));

@@ -79,3 +79,53 @@ def test_barred_model_windows(gpu):
     assert np.array_equal(fl, fl_o)
     assert l1.max() <= 1e-6 and np.abs(ov - ov_o).max() <= 1e-6
     assert A.shape[1] == 48000 and (A[:, 18000:] > 0).any()
+
+
+def test_repeated_runs_are_identical(gpu):
+    """The time-weighted histograms sum fixed-point integers, so two runs give
+    the same matrix to the bit (rotating barred model, several windows)."""
+    cfg = W.BARRED
+    ics, dt = W.disc_ics(W.load_table(cfg["table"]), 200, seed=12, n_steps=2000)
+    r1 = gpu_bs23(cfg, cfg["obs"], ics, dt, 400, 1e-4, 1e-6)
+    r2 = gpu_bs23(cfg, cfg["obs"], ics, dt, 400, 1e-4, 1e-6)
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+def test_paper_tolerance_small_model(gpu):
+    """The paper's settings (Sec. 2.2.2): rtol 1e-4 and 5,000 accepted steps per
+    orbit, on the small model's 2,000 orbits (regular orbits, static potential):
+    the step control now amplifies last-bit state differences by only
+    ~u / rtol = 1e-12, so entries agree to 1e-8 except where a sample sits on a
+    bin edge; flags equal, drift within 1e-9, every row's blocks normalised."""
+    cfg = W.SMALL
+    obs = dict(cfg["obs"], surface=1, upsilon=1.0)
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=5000)
+    A, ov, dr, fl = gpu_bs23(cfg, obs, ics, dt, 5000, 1e-4, 1e-6)
+    A_o, ov_o, dr_o, fl_o = oracle_bs23(cfg, obs, ics, dt, 5000, 1e-4, 1e-6)
+    l1 = np.abs(A - A_o).sum(1)
+    print(f"row L1 median {np.median(l1):.3g} p99 {np.percentile(l1, 99):.3g} max {l1.max():.3g}; "
+          f"max |d drift| {np.abs(dr - dr_o).max():.3g}; drift median {np.median(dr_o):.3g}")
+    assert np.array_equal(fl, fl_o)
+    assert np.abs(dr - dr_o).max() <= 1e-9
+    assert np.median(l1) <= 1e-8 and np.percentile(l1, 99) <= 1e-3
+    assert np.allclose(A[:, :1000].sum(1) + ov[:, 0], 1.0, rtol=0, atol=1e-11)
+    assert np.allclose(A[:, 1000:1750].sum(1) + ov[:, 1], 1.0, rtol=0, atol=1e-11)
+
+
+def test_paper_tolerance_barred_model(gpu):
+    """rtol 1e-4 on the rotating barred model (chaotic orbits: the paper's
+    Sec. 2.4 notes that chi^2 moves with the integration tolerance), 128 orbits
+    x 1,000 steps: flags equal, drift within 1e-6, most rows close and every
+    row's blocks normalised."""
+    cfg = W.BARRED
+    ics, dt = W.disc_ics(W.load_table(cfg["table"]), 128, seed=13, n_steps=2000)
+    A, ov, dr, fl = gpu_bs23(cfg, cfg["obs"], ics, dt, 1000, 1e-4, 1e-6)
+    A_o, ov_o, dr_o, fl_o = oracle_bs23(cfg, cfg["obs"], ics, dt, 1000, 1e-4, 1e-6)
+    l1 = np.abs(A - A_o).sum(1)
+    print(f"row L1 median {np.median(l1):.3g} p90 {np.percentile(l1, 90):.3g} max {l1.max():.3g}; "
+          f"max |d drift| {np.abs(dr - dr_o).max():.3g}")
+    assert np.array_equal(fl, fl_o)
+    assert np.median(np.abs(dr - dr_o)) <= 1e-6
+    assert np.median(l1) <= 1e-3
+    assert np.allclose(A[:, :18000].sum(1) + ov[:, 0], 1.0, rtol=0, atol=1e-11)

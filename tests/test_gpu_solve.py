@@ -101,7 +101,17 @@ def test_workspace_contents_do_not_matter(gpu):
         assert np.abs(w1 - w0).sum() <= 1e-9 * np.abs(w0).sum()
 
 
-def test_solve_ragged_larger(gpu):
+@pytest.fixture(params=[0, 1], ids=["factor_fp32", "factor_bf16x3"])
+def factor_gemm(request):
+    """The factorisation's large products on fp32 MFMA or on bf16x3 MFMA."""
+    P = lib()
+    old = P.get_tuning("factor_gemm")
+    P.set_tuning("factor_gemm", request.param)
+    yield request.param
+    P.set_tuning("factor_gemm", old)
+
+
+def test_solve_ragged_larger(gpu, factor_gemm):
     n, c = 3001, 1003
     blocks = [(0, 300), (300, c)]
     A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=7)
@@ -115,7 +125,7 @@ def test_solve_ragged_larger(gpu):
     assert abs(chi2_gpu(h, 300, c) / x_o - 1) < CHI2_TOL
 
 
-def test_small_workload_end_to_end(gpu):
+def test_small_workload_end_to_end(gpu, factor_gemm):
     """Plummer + MN workload, FP64 on both sides: the GPU builds the orbit matrix,
     solves and evaluates chi^2; the oracle does all three on its own matrix."""
     import oracle as O
@@ -316,3 +326,31 @@ def test_gh_moments_match_oracle(gpu, dtype):
     err = np.abs(g - ref).max() / scale
     print("gh max rel err", err)
     assert err < 1e-12
+
+
+def test_gram_panel_skipping_matches_dense_gram(gpu):
+    """The Gram takes the orbits in footprint order and skips the 32-orbit stages
+    whose panels are zero (a skipped stage adds exactly zero; only the fp32
+    summation order of the Gram changes); the solve lands on the weights of
+    the Gram that streams every stage in the rows' order, within the KKT
+    tolerance, and within the oracle's bar."""
+    P = lib()
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, *_ = gpu_integrate(cfg, ics, dt, 400, "f64")
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A, blocks, cfg["mock"]["seed"], 0.02, 0.02)
+    w_o, _ = oracle_solve(A, d, sig, wt, 1e-2)
+    out = {}
+    old = P.get_tuning("gram_skip")
+    try:
+        for skip in (0, 1):
+            P.set_tuning("gram_skip", skip)
+            w, status, rep, _ = gpu_solve(A, d, sig, wt, 1e-2, 1)
+            out[skip] = (w, status, rep.refine_iters)
+    finally:
+        P.set_tuning("gram_skip", old)
+    print({k: (v[1], v[2]) for k, v in out.items()})
+    assert out[0][1] == 0 and out[1][1] == 0
+    assert np.abs(out[1][0] - out[0][0]).sum() <= 1e-5 * np.abs(out[0][0]).sum()
+    assert np.abs(out[1][0] - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
