@@ -8,6 +8,15 @@ chi2, with every input already resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload barred|small]
                   [--bootstrap B]   (also B bootstrap solves per build, Eq. 6)
+  python bench.py --workload paper  (the paper's own pipeline: Jeans initial conditions
+                  x 4 dithers, BS23 at rtol 1e-4 for 5,000 steps, cylindrical grid,
+                  ~600 apertures, Gauss-Hermite fit, 100 bootstrap solves, chi^2_model)
+  python bench.py --workload walkers | surrogate   (batched walkers; DA-MCMC)
+
+The default line's `roofline` is the dominant stage's, its `achieved` the
+method's algorithmic work over the stage time; `cpu_baseline` is the FP64
+oracle's whole build of a seeded orbit subsample, and `errors_vs_oracle` the
+GPU's errors against the oracle on that subsample and on the headline solve.
 """
 import argparse
 import json
@@ -215,7 +224,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate"])
+    ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate", "paper"])
+    ap.add_argument("--bs23-steps", type=int, default=0, help="paper: accepted BS23 steps (0: the paper's 5,000)")
     ap.add_argument("--n-train", type=int, default=20000, help="surrogate: training builds")
     ap.add_argument("--mcmc-steps", type=int, default=200, help="surrogate: DA-MCMC steps per walker")
     ap.add_argument("--gram", default="bf16x3", choices=["bf16", "bf16x3", "f32"])
@@ -227,6 +237,8 @@ def main():
     ap.add_argument("--bootstrap", type=int, default=0,
                     help="also solve this many bootstrap realisations of the data per build (shared matrix) "
                          "and report chi2_model")
+    ap.add_argument("--refine-passes", type=int, choices=[2, 4], default=None,
+                    help="passes over A per FP64 iteration (2: U^T U x carried, 4: residual from A)")
     ap.add_argument("--factor-gemm", type=int, choices=[0, 1], default=None,
                     help="factorisation products on fp32 MFMA (0) or bf16x3 MFMA (1); default: the library's")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -242,8 +254,12 @@ def main():
 
     if args.factor_gemm is not None:
         P.set_tuning("factor_gemm", args.factor_gemm)
+    if args.refine_passes is not None:
+        P.set_tuning("refine_passes", args.refine_passes)
     if args.workload == "walkers":
         return bench_walkers(args)
+    if args.workload == "paper":
+        return bench_paper(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
     cfg = W.BARRED if args.workload == "barred" else W.SMALL
@@ -374,7 +390,10 @@ def main():
     per_iter = 2 * u_bytes + 2 * l_bytes
     # Anderson mixing per FP64 iteration: 91 vectors of N doubles read or written
     aa_bytes = 0.0 if args.no_accel else 91.0 * N * 8.0
-    refine_passes = float(reps[-1].get("u_passes_per_iter", 4.0))
+    # passes over A per FP64 iteration: 2 with U^T U x carried (plus 2 per batch of
+    # iterations between checks to recompute it), 4 with the residual from A
+    check = 10.0
+    refine_passes = 2.0 + 2.0 / check if P.get_tuning("refine_passes") == 2 else 4.0
     rooflines = {
         "integrate_and_bin": {"kernel": "k_integrate + k_hist", "bound": "alu", "unit": "TFLOP/s",
                               "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
@@ -558,7 +577,7 @@ def bench_walkers(args):
     sws = torch.empty(P.solve_batched_workspace_bytes(offs, nc, opts), dtype=torch.uint8, device=dev)
     cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream()
-    chis, t_int, t_solve = [], [], []
+    chis, t_int, t_solve, n_conv = [], [], [], []
 
     def step():
         with torch.cuda.stream(stream):
@@ -572,11 +591,12 @@ def bench_walkers(args):
             torch.cuda.synchronize()
             t2 = time.perf_counter()
         t_int.append(1e3 * (t1 - t0)); t_solve.append(1e3 * (t2 - t1)); chis.append(x)
+        n_conv.append(sum(int(r.converged) for r in reps))
         return reps
 
     for _ in range(args.warmup):
         step()
-    t_int.clear(); t_solve.clear(); chis.clear()
+    t_int.clear(); t_solve.clear(); chis.clear(); n_conv.clear()
     t0 = time.perf_counter()
     for i in range(args.steps):
         reps = step()
@@ -596,7 +616,189 @@ def bench_walkers(args):
                       "n_constraints": nc, "autotune": best},
            "orbit_steps_per_s": n_tot * n_steps * args.steps / el,
            "integrate_ms": float(np.mean(t_int)), "solve_chi2_ms": float(np.mean(t_solve)),
-           "chi2_range": [float(np.min(chis[-1])), float(np.max(chis[-1]))]}
+           "chi2_range": [float(np.min(chis[-1])), float(np.max(chis[-1]))],
+           "converged": f"{min(n_conv)}/{n_w}",
+           "converged_builds_per_s": min(n_conv) * args.steps / el}
+    print(json.dumps(out))
+
+
+# FP64 flop per force evaluation of the barred potential (32-point Gauss-Legendre
+# Ferrers bar: 3 warm Newton steps x 21, setup 14, 32 nodes x 28, scaling 12;
+# MN 22; NFW_q 27) and per attempted BS23 step (three force evaluations with
+# FSAL, the stage combinations and the error norm, 6 x 27 + 30)
+FLOP_PER_FORCE_F64 = 63 + 14 + 32 * 28 + 12 + 22 + 27
+FLOP_PER_BS23_STEP = 3 * FLOP_PER_FORCE_F64 + 6 * 27 + 30
+
+
+def paper_mock(P, torch, dev, cfg, pot, obs, pix2ap, n_ap, A_b, m_star, n_mass, kin0, surf0):
+    """The observed maps (a stand-in for the paper's IFU data): a seeded 10% subset of
+    the bundles with Exp(1) weights scaled to the stellar mass of the density grid;
+    Sigma* its surface block (+1% noise), the reference Gaussian of each aperture its
+    LOSVD's mean and dispersion (at least 20 km/s), h* its h_m for the observed
+    luminosity gamma* = Sigma* (+ noise of Delta h*); the density data are m*_n."""
+    o = cfg["obs"]
+    nb = A_b.shape[0]
+    w = torch.from_numpy(W.mock_draw(nb, cfg["mock"]["seed"])).to(dev)
+    full = torch.empty(A_b.shape[1], dtype=torch.float64, device=dev)
+    P.model_observables(A_b, w, full)
+    torch.cuda.synchronize()
+    raw = full.cpu().numpy()
+    ms = m_star.cpu().numpy()
+    scale = float(ms.sum()) / float(raw[:n_mass].sum())
+    raw = raw * scale
+    nv, vlo, vhi = o["nv"], o["vlo"], o["vhi"]
+    sig_obs = raw[surf0:surf0 + n_ap]
+    gamma = np.maximum(sig_obs, 1e-3 * sig_obs.max())
+    hist = raw[kin0:kin0 + n_ap * nv].reshape(n_ap, nv)
+    vc = vlo + (np.arange(nv) + 0.5) * (vhi - vlo) / nv
+    tot = np.maximum(hist.sum(1), 1e-300)
+    v0 = (hist * vc).sum(1) / tot
+    s = np.sqrt(np.maximum((hist * (vc - v0[:, None]) ** 2).sum(1) / tot, 20.0 ** 2))
+    n_gh = cfg["n_gh"]
+    nf = n_mass + n_ap + n_gh * n_ap
+    F = torch.empty((nb, nf), dtype=torch.float64, device=dev)
+    gws = torch.empty(P.gh_fit_workspace_bytes(n_ap, nv, n_gh), dtype=torch.uint8, device=dev)
+    P.gh_fit_matrix(A_b, n_mass, kin0, surf0, n_ap, nv, vlo, vhi, v0, s, gamma, F, gws, n_gh=n_gh)
+    model = torch.empty(nf, dtype=torch.float64, device=dev)
+    P.model_observables(F, w * scale, model)
+    torch.cuda.synchronize()
+    d = model.cpu().numpy()
+    rng = np.random.default_rng(cfg["mock"]["seed"] + 4000)
+    d[:n_mass] = ms
+    d[n_mass:n_mass + n_ap] *= 1 + cfg["mock"]["noise"] * rng.standard_normal(n_ap)
+    d[n_mass + n_ap:] += cfg["dh"] * rng.standard_normal(nf - n_mass - n_ap)
+    sig = np.empty(nf)
+    for b0, b1 in ((0, n_mass), (n_mass, n_mass + n_ap)):
+        top = float(np.max(np.abs(d[b0:b1])))
+        sig[b0:b1] = cfg["mock"]["tol"] * np.maximum(np.abs(d[b0:b1]), 1e-3 * top)
+    sig[n_mass + n_ap:] = cfg["dh"]
+    return d, sig, v0, s, gamma, float(ms.sum()) / nb
+
+
+def bench_paper(args):
+    """The paper's pipeline for one trial potential of the barred model, every
+    step in the library's kernels: Jeans initial velocities at 7,500 seeded
+    positions, 4 dithered realisations each (Sec. 2.2.1), BS23 orbits in FP64
+    at rtol 1e-4 for 5,000 accepted steps with time-weighted binning into a
+    600-cell cylindrical grid, ~600 irregular apertures x 30 velocity bins and
+    the surface block (Sec. 2.2.2-2.2.4), bundle means, the target cell masses,
+    the Gauss-Hermite fit matrix (Eq. 2-3), 100 bootstrap realisations of the
+    maps solved on the shared matrix, chi^2_b and chi^2_model (Eq. 5-6).
+    A step = one model."""
+    import torch
+    import paper_2607_00117_amd as P
+    cfg = W.PAPER
+    o = cfg["obs"]
+    dev = torch.device("cuda:0")
+    n_ic, nd, S = cfg["n_ic"], cfg["n_dither"], args.bs23_steps or cfg["n_steps"]
+    n = n_ic * nd
+    comps, omega, euler = W.BARRED["components"], W.BARRED["omega"], W.BARRED["euler"]
+    pot = P.build_potential(comps, omega, euler)
+    pmap, n_ap = W.voronoi_map(o["npx"], o["npy"], o["plo"], o["phi"], cfg["n_gen"], cfg["ap_seed"], cfg["ap_scale"])
+    pix_t = torch.from_numpy(pmap).to(dev)
+    obs = P.obs_spec(dict(o, n_ap=n_ap), pix_t)
+    nc = P.ncon(obs)
+    n_mass = o["nx"] * o["ny"] * o["nz"]
+    kin0, surf0 = n_mass, n_mass + n_ap * o["nv"]
+    n_gh = cfg["n_gh"]
+    nf = n_mass + n_ap + n_gh * n_ap
+    pos, eps = W.disc_positions(n_ic, seed=cfg["ic_seed"], h_R=cfg["h_R"], h_z=cfg["h_z"])
+    pos_t, eps_t = torch.from_numpy(pos).to(dev), torch.from_numpy(eps).to(dev)
+    u_t = torch.from_numpy(W.dither_deviates(nd, n_ic, seed=cfg["ic_seed"])).to(dev)
+    mom = torch.empty((5, n_ic), dtype=torch.float64, device=dev)
+    ic1 = torch.empty((6, n_ic), dtype=torch.float64, device=dev)
+    ics = torch.empty((6, n), dtype=torch.float64, device=dev)
+    h0 = torch.full((n,), cfg["h0"], dtype=torch.float64, device=dev)
+    A = torch.empty((n, nc), dtype=torch.float64, device=dev)
+    ov = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(n, dtype=torch.float64, device=dev)
+    fl = torch.empty(n, dtype=torch.uint8, device=dev)
+    bws = torch.empty(P.integrate_bs23_workspace_bytes(n, S), dtype=torch.uint8, device=dev)
+    A_b = torch.empty((n_ic, nc), dtype=torch.float64, device=dev)
+    m_star = torch.empty(n_mass, dtype=torch.float64, device=dev)
+    F = torch.empty((n_ic, nf), dtype=torch.float64, device=dev)
+    gws = torch.empty(P.gh_fit_workspace_bytes(n_ap, o["nv"], n_gh), dtype=torch.uint8, device=dev)
+    log(f"paper pipeline: {n_ic} x {nd} orbits, BS23 rtol {cfg['rtol']} x {S} steps, {nc} binned constraints, "
+        f"{n_ap} apertures, fit matrix {n_ic} x {nf}, {cfg['n_boot']} bootstraps")
+    stream = torch.cuda.Stream()
+    B = cfg["n_boot"]
+    opts = P._lib.SolveOpts()
+    opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
+
+    def build():
+        """The orbit library's part of a model: returns the stage events."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record()
+        P.jeans_ics(pot, pos_t, eps_t, cfg["h_R"], cfg["h_z"], cfg["jeans_b"], mom, ic1)
+        P.dither_ics(ic1, mom[4].contiguous(), u_t, cfg["dx"], cfg["fv"], ics)
+        ev[1].record()
+        P.integrate_bs23_and_bin(pot, ics, h0, S, cfg["rtol"], cfg["atol"], obs, A, ov, dr, fl, bws)
+        ev[2].record()
+        P.bundle_rows(A, nd, A_b)
+        P.cell_masses(pot, obs, cfg["stellar_mask"], cfg["n_sub"], m_star)
+        ev[3].record()
+        return ev
+
+    # the observed maps, from one build at the same parameters (untimed)
+    with torch.cuda.stream(stream):
+        build()
+    torch.cuda.synchronize()
+    d, sig, v0, s, gamma, w_tilde = paper_mock(P, torch, dev, cfg, pot, obs, pix_t, n_ap, A_b, m_star, n_mass, kin0,
+                                               surf0)
+    d_t, s_t = torch.from_numpy(d).to(dev), torch.from_numpy(sig).to(dev)
+    e_t = torch.from_numpy(W.bootstrap_eps(B, nf, seed=cfg["mock"]["seed"])).to(dev)
+    D_t = torch.empty((B, nf), dtype=torch.float64, device=dev)
+    Wb = torch.empty((B, n_ic), dtype=torch.float64, device=dev)
+    sws = torch.empty(P.solve_multi_workspace_bytes(n_ic, nf, B, opts), dtype=torch.uint8, device=dev)
+    cws = torch.empty(P.chi2_workspace_bytes(nf), dtype=torch.uint8, device=dev)
+    res = []
+
+    def step():
+        with torch.cuda.stream(stream):
+            ev = build()
+            P.gh_fit_matrix(A_b, n_mass, kin0, surf0, n_ap, o["nv"], o["vlo"], o["vhi"], v0, s, gamma, F, gws,
+                            n_gh=n_gh)
+            P.bootstrap_data(d_t, s_t, e_t, n_mass, nf, D_t)
+            ev[4].record()
+            st, reps = P.solve_weights_multi(F, D_t, s_t, w_tilde, -1.0, opts, Wb, sws)
+            chis = [P.chi2(F, Wb[b], d_t, s_t, n_mass, nf, cws) for b in range(B)]
+            xm = P.chi2_model(chis)
+            ev[5].record()
+        torch.cuda.synchronize()
+        res.append({"ms": {"ics": ev[0].elapsed_time(ev[1]), "bs23": ev[1].elapsed_time(ev[2]),
+                           "bundle_cellmass": ev[2].elapsed_time(ev[3]), "fit_matrix": ev[3].elapsed_time(ev[4]),
+                           "bootstrap_solve_chi2": ev[4].elapsed_time(ev[5])},
+                    "status": st, "iters_max": max(r.refine_iters for r in reps),
+                    "kkt_max": max(r.kkt for r in reps), "chi2_range": [min(chis), max(chis)], "chi2_model": xm,
+                    "flagged_orbits": int((fl != 0).sum().item())})
+
+    for _ in range(args.warmup):
+        step()
+    res.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"step {i}: {res[-1]}")
+    el = time.perf_counter() - t0
+    ms = 1e3 * el / args.steps
+    st_ms = {k: float(np.mean([r["ms"][k] for r in res])) for k in res[0]["ms"]}
+    t_b = st_ms["bs23"]
+    work = FLOP_PER_BS23_STEP * n * S
+    roof = {"kernel": "k_bs23 + k_hist_w", "bound": "alu", "unit": "TFLOP/s", "peak": PEAK_F64_VALU / 1e12,
+            "work": float(work), "ms": t_b, "achieved": round(work / (t_b * 1e-3) / 1e12, 3),
+            "work_rule": f"{FLOP_PER_BS23_STEP} FP64 flop per accepted step (three force evaluations) x orbit-steps",
+            "traffic": None, "stage": "bs23"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    out = {"metric": METRIC, "value": n * S * args.steps / el, "unit": "orbit-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": cfg["name"] if S == cfg["n_steps"] else cfg["name"].replace("5k", f"{S}"),
+                      "n_orbits": n, "n_bundles": n_ic, "n_steps": S, "rtol": cfg["rtol"], "n_apertures": n_ap,
+                      "n_binned_constraints": nc, "n_fit_constraints": nf, "n_bootstraps": B},
+           "model_builds_per_s": 1e3 / ms, "stage_ms": {k: round(v, 2) for k, v in st_ms.items()},
+           "dominant_stage": max(st_ms, key=st_ms.get), "last": res[-1], "roofline": roof,
+           "context": "the paper quotes about 1.3 s per model (build + 100 bootstrap solves + chi^2) on one A100"}
     print(json.dumps(out))
 
 
@@ -645,7 +847,10 @@ def bench_surrogate(args):
         chi = builder.chi2(thetas)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
-        log(f"{args.n_train} training builds in {t_build:.1f} s ({args.n_train / t_build:.1f} builds/s)")
+        conv = builder.last_converged
+        log(f"{args.n_train} training builds in {t_build:.1f} s ({args.n_train / t_build:.1f} builds/s), "
+            f"{int((~conv).sum())} weight solves not converged (left out of the training set)")
+        thetas, chi = thetas[conv], chi[conv]
         n_tr = int(0.9 * len(thetas))
         sur = S.Surrogate(lo, hi)
         t0 = time.perf_counter()
@@ -656,8 +861,29 @@ def bench_surrogate(args):
         log(f"surrogate fit {t_fit:.1f} s; held-out |chi2_s - chi2|/dchi2 median {np.median(err):.3g}, "
             f"frac<1 {np.mean(err < 1):.3f}")
         theta0 = W.walker_thetas(32, seed=8, spread=0.05)
-        res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log)
-        res_mh = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=False, log=log)
+        adapt = args.mcmc_steps // 2
+
+        def refit(th_b, chi_b):
+            # the chains' neighbourhood: every full build so far, weighted like the whole training set
+            rep = max(1, n_tr // max(1, len(chi_b)))
+            sur.fit(np.concatenate([thetas[:n_tr], np.repeat(th_b, rep, axis=0)]),
+                    np.concatenate([chi[:n_tr], np.repeat(chi_b, rep)]), epochs=8, batch=512, keep_scaling=True,
+                    seed=len(chi_b))
+
+        res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log,
+                           refit=refit, refit_every=max(10, adapt // 5), adapt_steps=adapt)
+        res_mh = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=False, log=log,
+                           adapt_steps=adapt)
+        # the screen's error where the chains walk: full builds made after adaptation
+        bt, bc = res_da["built"]
+        n_late = res_da["n_full_builds_after_adapt"]
+        loc_err = np.abs(sur.predict(bt[-n_late:]) - bc[-n_late:]) / dchi2 if n_late > 0 else np.zeros(1)
+        # chain moments after adaptation, DA against plain Metropolis (same random numbers)
+        cd, cm = res_da["chains"][adapt:].reshape(-1, 12), res_mh["chains"][adapt:].reshape(-1, 12)
+        moment_diff = float(np.max(np.abs(cd.mean(0) - cm.mean(0)) / np.maximum(cm.std(0), 1e-300)))
+        log(f"after adaptation: DA full builds {res_da['n_full_builds_after_adapt']} vs plain MH "
+            f"{res_mh['n_full_builds_after_adapt']}; screen error near the chains median "
+            f"{np.median(loc_err):.3g} dchi2; max |mean difference| / std {moment_diff:.3g}")
         # the plain single-model path: one trial potential per build, no batching, no surrogate
         single = S.ModelBuilder(W.theta_to_model, ics, dt, n_steps, obs_d, d, sig, wt, 1, kin_block=blocks[1],
                                 solve_opts=opts)
@@ -677,12 +903,20 @@ def bench_surrogate(args):
            "config": {"workload": "surrogate_da_mcmc_32_walkers_small_model_barred_family", "n_train": args.n_train,
                       "mcmc_steps": args.mcmc_steps},
            "dchi2": dchi2, "dchi2_rule": "aperture jackknife", "chi2_seed_spread": seed_spread,
-           "train_builds_per_s": args.n_train / t_build,
+           "train_builds_per_s": args.n_train / t_build, "train_builds_unconverged": int((~conv).sum()),
            "heldout_err_over_dchi2_median": float(np.median(err)), "heldout_frac_err_below_dchi2": float(np.mean(err < 1)),
            "plain_mh_models_per_s": res_mh["models_per_s"], "single_model_path_per_s": single_per_s,
            "speedup_vs_single_model_path": res_da["models_per_s"] / single_per_s,
-           "da": {k: res_da[k] for k in ("n_full_builds", "n_stage1", "n_accepted", "seconds", "proposals")},
-           "mh": {k: res_mh[k] for k in ("n_full_builds", "n_accepted", "seconds", "proposals")}}
+           "da": {k: res_da[k] for k in ("n_full_builds", "n_stage1", "n_accepted", "seconds", "proposals",
+                                          "n_full_builds_after_adapt", "n_stage1_after_adapt",
+                                          "n_unconverged_builds")},
+           "mh": {k: res_mh[k] for k in ("n_full_builds", "n_accepted", "seconds", "proposals",
+                                          "n_full_builds_after_adapt", "n_unconverged_builds")},
+           "adapt_steps": adapt,
+           "full_builds_ratio_after_adapt": res_da["n_full_builds_after_adapt"] / max(1, res_mh[
+               "n_full_builds_after_adapt"]),
+           "local_err_over_dchi2_median": float(np.median(loc_err)),
+           "chain_mean_diff_over_std_max": moment_diff}
     print(json.dumps(out))
 
 

@@ -524,6 +524,13 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             (0: automatic = up to 4; 1, 2, 4 or 8; it sets
  *                             the block sizes of the compressed copies, so
  *                             query solve_multi_workspace_bytes after it)
+ *   "refine_passes"           weight solve, FP64 stage: 2 (default) passes over
+ *                             the orbit matrix per iteration, with U^T U x carried
+ *                             alongside the iterate (updated by each correction,
+ *                             mixed with it by the Anderson step, recomputed from
+ *                             the matrix at the start of every batch of
+ *                             iterations between convergence checks), or 4 (the
+ *                             residual recomputed from the matrix every iteration)
  *   "gram_skip"               weight solve: 1 (default) skips the 32-orbit
  *                             stages of the Gram whose row or column panel of
  *                             the scaled matrix is zero (the result is the same

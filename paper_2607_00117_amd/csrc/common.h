@@ -74,7 +74,9 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 //  g_factor_x3     1: the factorisation's large products on bf16x3 MFMA, 0: fp32 MFMA
 extern int g_factor_x3;
 //  g_gram_dense    1: the Gram streams every 32-orbit stage (no zero-panel skipping)
+//  g_refine_two    1: two passes over A per FP64 iteration (U^T U x carried), 0: four
 extern int g_gram_dense;
+extern int g_refine_two;
 extern int g_sparse_rows;
 extern int g_sparse_cols;
 extern int g_sparse_lanes;

@@ -51,12 +51,14 @@ constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
 constexpr int kAAMem = 10;          // Anderson acceleration: iterations kept in the history
 constexpr int kAAThreads = 256, kAAPer = 4, kAAChunk = kAAThreads * kAAPer;  // AA passes: orbits per workgroup
 constexpr int kAADots = 2 * kAAMem + 1;
+constexpr int kAAComp = 4;  // history components: x, z, u (mixed and fitted) and h = U^T U x (mixed only)
 constexpr double kAARestart = 10.0;  // history cleared when the residual exceeds this many times its minimum
 constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) residual has not
 constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
 
 int g_sparse_rows = 0;
 int g_gram_dense = 0;
+int g_refine_two = 1;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
 int g_rhs_group = 0;
@@ -224,16 +226,18 @@ __host__ __device__ __forceinline__ int64_t slabs_per_block(int64_t rps, int64_t
 }
 
 // cnt[i][cb] = nonzeros of row i in column block cb (one wave per row);
-// tiles[i] = number of 256-column tiles of row i holding a nonzero (the row's
-// footprint on the Gram's panels; blk is a multiple of 256)
+// foot[i] = the row's footprint on the Gram's panels: word 0 the number of
+// 256-column tiles holding a nonzero, words 1-4 the bitmap of those tiles
+// (tile t at bit t % 64 of word 1 + t / 64, tiles past 255 folded onto
+// t % 256); blk is a multiple of 256
 template <typename TA>
 __global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64_t N, int64_t C, int ncb, int64_t blk,
-                                                 int64_t* __restrict__ cnt, int32_t* __restrict__ tiles) {
+                                                 int64_t* __restrict__ cnt, uint64_t* __restrict__ foot) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
   const TA* row = A + i * C;
-  int32_t nt = 0;
+  uint64_t nt = 0, bits[4] = {0, 0, 0, 0};
   int64_t last = -1;
   for (int cb = 0; cb < ncb; ++cb) {
     const int64_t c1 = (int64_t)(cb + 1) * blk < C ? (int64_t)(cb + 1) * blk : C;
@@ -244,12 +248,14 @@ __global__ __launch_bounds__(256) void k_row_nnz(const TA* __restrict__ A, int64
       if (__ballot(v) != 0 && (c0 >> 8) != last) {
         last = c0 >> 8;
         ++nt;
+        const int t = (int)(last & 255);
+        bits[t >> 6] |= 1ull << (t & 63);
       }
     }
     for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
     if (lane == 0) cnt[i * ncb + cb] = k;
   }
-  if (lane == 0 && tiles) tiles[i] = nt;
+  if (lane < 5 && foot) foot[i * 5 + lane] = lane == 0 ? nt : bits[lane - 1];
 }
 
 // cpart[b][s][c] = number of nonzeros of column c in slab s of problem b
@@ -743,7 +749,7 @@ __global__ void k_scaled_data(const double* __restrict__ d, const double* __rest
   if (n < Cp) y[(int64_t)b * Cp + n] = n < C ? d[(int64_t)b * C + n] / sigma[b * sS + n] : 0.0;
 }
 
-enum RowOp { ROW_Q = 0, ROW_ADMM = 1, ROW_H = 2, ROW_CORR = 3, ROW_KKT = 4 };
+enum RowOp { ROW_Q = 0, ROW_ADMM = 1, ROW_H = 2, ROW_CORR = 3, ROW_KKT = 4, ROW_CORR2 = 5 };
 
 struct RowArgs {
   int op;
@@ -757,6 +763,7 @@ struct RowArgs {
   float* qf; float* zf; float* uf; float* vf;
   // fp64 stage
   double* qd; double* xd; double* zd; double* ud; double* vd; double* rd;
+  double* hd;   // fp64 stage, two passes per iteration: h = U^T U x carried with the iterate (null: not carried)
   double* acc;  // per problem [kAcc]: 0 |x-z|^2, 1 |z-zold|^2, 2 |x|^2, 3 |z|^2, 4 |u|^2, 5 max|q|, 6 kkt max, 7 |z|^2, 9 |e|^2
   // orbit-major compressed rows of A (used when A is stored sparse)
   const int64_t* csr_ptr;
@@ -811,6 +818,25 @@ __device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, d
     case ROW_H: {
       const double bb = R.qd[i] + rho * R.vd[i];
       R.rd[i] = masked ? 0.0 : bb - dot - rhop * R.xd[i];
+      if (R.hd) R.hd[i] = masked ? 0.0 : dot;
+      break;
+    }
+    case ROW_CORR2: {
+      // the correction of ROW_CORR, carrying h = U^T U x along: the Woodbury step
+      // moves U x by U M r = s (exactly for the exact inverse), so U^T U x moves by
+      // U^T s = dot, and the next iteration's residual needs no pass over A
+      const double z0 = R.zd[i], u0 = R.ud[i];
+      const double x = masked ? 0.0 : R.xd[i] + (R.rd[i] - dot) / rhop;
+      const double xh = alpha * x + (1.0 - alpha) * z0;
+      const double z = masked ? 0.0 : fmax(0.0, xh + u0);
+      const double u = masked ? 0.0 : u0 + xh - z;
+      const double h = masked ? 0.0 : R.hd[i] + dot;
+      R.xd[i] = x;
+      R.zd[i] = z;
+      R.ud[i] = u;
+      R.vd[i] = z - u;
+      R.hd[i] = h;
+      R.rd[i] = masked ? 0.0 : R.qd[i] + rho * (z - u) - h - rhop * x;
       break;
     }
     case ROW_CORR: {
@@ -1102,14 +1128,20 @@ static unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 
 //   w+ = g(w) - sum_j gamma_j (dW_j + dF_j),  gamma = argmin |f - dF gamma|,
 // from the normal equations (regularised by 1e-10 of their trace).  The
 // history is cleared when |f| exceeds kAARestart times its smallest value
-// since the last clearing.  Vectors are [3][N] (x, z, u), problem b owns
+// since the last clearing.  Vectors are [4][N] (x, z, u, h): gamma is fitted on
+// (x, z, u) only and h = U^T U x, which is linear in x, is mixed with the same
+// gamma so that it stays U^T U of the mixed x; problem b owns
 // indices off[b]..off[b+1]-1 of each; per-problem state (iteration, history
 // length, smallest |f|) lives on the device so the steps can be captured.
 // ---------------------------------------------------------------------------
 struct AAArgs {
   double *x, *z, *u, *v;  // the iterate of the FP64 stage
-  double *w, *wp, *fp;    // [3][N] current iterate, previous iterate, previous residual
-  double *df, *y;         // [kAAMem][3][N] history: dF_j and dW_j + dF_j
+  double *h, *r;          // h = U^T U x carried with the iterate, and the residual r (null: not carried)
+  const double* q;        // U^T y
+  const uint8_t* mask;
+  int shared;             // mask indexed by orbit within the problem
+  double *w, *wp, *fp;    // [kAAComp][N] current iterate, previous iterate, previous residual
+  double *df, *y;         // [kAAMem][kAAComp][N] history: dF_j and dW_j + dF_j
   double *G, *gam, *st;   // per problem: [kAAMem][kAAMem] dF_i . dF_j, [kAAMem] gamma, {it, count, min |f|}
   double* part;           // [P][nbx][kAADots] block partials of the dot products
   const int64_t* off;
@@ -1126,7 +1158,8 @@ __global__ __launch_bounds__(256) void k_aa_init(AAArgs a) {
     a.w[i] = a.x[i];
     a.w[a.N + i] = a.z[i];
     a.w[2 * a.N + i] = a.u[i];
-    for (int64_t k = 0; k < 3 * (int64_t)kAAMem; ++k) {  // unused history slots must hold finite values
+    a.w[3 * a.N + i] = a.h ? a.h[i] : 0.0;
+    for (int64_t k = 0; k < kAAComp * (int64_t)kAAMem; ++k) {  // unused history slots must hold finite values
       a.df[k * a.N + i] = 0.0;
       a.y[k * a.N + i] = 0.0;
     }
@@ -1148,7 +1181,8 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_dots(AAArgs a) {
   const int64_t it = (int64_t)a.st[b * 4 + 0];
   const bool hist = it >= 1;
   const int s = hist ? (int)((it - 1) % kAAMem) : 0;
-  const int64_t V = 3 * a.N;
+  const int64_t V = kAAComp * a.N;
+  const int nc = a.h ? 4 : 3;
   double dots[kAADots];
 #pragma unroll
   for (int k = 0; k < kAADots; ++k) dots[k] = 0.0;
@@ -1156,25 +1190,26 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_dots(AAArgs a) {
     const int64_t j = (int64_t)blockIdx.x * kAAChunk + q * kAAThreads + threadIdx.x;
     if (j >= nb) break;
     const int64_t i = n0 + j;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double g = c == 0 ? a.x[i] : (c == 1 ? a.z[i] : a.u[i]);
+    for (int c = 0; c < nc; ++c) {
+      const double g = c == 0 ? a.x[i] : (c == 1 ? a.z[i] : (c == 2 ? a.u[i] : a.h[i]));
       const int64_t e = c * a.N + i;
       const double wv = a.w[e], f = g - wv;
       if (hist) {
         const double d = f - a.fp[e];
         a.df[s * V + e] = d;
         a.y[s * V + e] = (wv - a.wp[e]) + d;
+        if (c < 3) {
 #pragma unroll
-        for (int k = 0; k < kAAMem; ++k) {
-          const double dk = k == s ? d : a.df[k * V + e];
-          dots[k] += d * dk;
-          dots[kAAMem + k] += dk * f;
+          for (int k = 0; k < kAAMem; ++k) {
+            const double dk = k == s ? d : a.df[k * V + e];
+            dots[k] += d * dk;
+            dots[kAAMem + k] += dk * f;
+          }
         }
       }
       a.fp[e] = f;
       a.wp[e] = wv;
-      dots[2 * kAAMem] += f * f;
+      if (c < 3) dots[2 * kAAMem] += f * f;
     }
   }
   __shared__ double red[kAAThreads / 64][kAADots];
@@ -1287,7 +1322,8 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_mix(AAArgs a) {
   const int b = blockIdx.y;
   if (a.par[b * kPar + 5] == 0.0) return;
   const int64_t n0 = a.off[b], nb = a.off[b + 1] - n0;
-  const int64_t V = 3 * a.N;
+  const int64_t V = kAAComp * a.N;
+  const double rho = a.par[b * kPar + 1], rhop = a.par[b * kPar + 2];
   double gm[kAAMem];
   bool any = false;
 #pragma unroll
@@ -1299,7 +1335,7 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_mix(AAArgs a) {
     const int64_t j = (int64_t)blockIdx.x * kAAChunk + q * kAAThreads + threadIdx.x;
     if (j >= nb) break;
     const int64_t i = n0 + j;
-    double x = a.x[i], z = a.z[i], u = a.u[i];
+    double x = a.x[i], z = a.z[i], u = a.u[i], h = a.h ? a.h[i] : 0.0;
     if (any) {
 #pragma unroll
       for (int k = 0; k < kAAMem; ++k) {
@@ -1307,15 +1343,22 @@ __global__ __launch_bounds__(kAAThreads) void k_aa_mix(AAArgs a) {
         x -= gm[k] * a.y[k * V + i];
         z -= gm[k] * a.y[k * V + a.N + i];
         u -= gm[k] * a.y[k * V + 2 * a.N + i];
+        if (a.h) h -= gm[k] * a.y[k * V + 3 * a.N + i];
       }
       a.x[i] = x;
       a.z[i] = z;
       a.u[i] = u;
       a.v[i] = z - u;
+      if (a.h) {
+        const bool masked = a.mask && a.mask[a.shared ? j : i];
+        a.h[i] = h;
+        a.r[i] = masked ? 0.0 : a.q[i] + rho * (z - u) - h - rhop * x;
+      }
     }
     a.w[i] = x;
     a.w[a.N + i] = z;
     a.w[2 * a.N + i] = u;
+    a.w[3 * a.N + i] = h;
   }
 }
 
@@ -1331,7 +1374,7 @@ struct SolveLayout {
   std::vector<int64_t> aoff;
   size_t off_hi, off_lo, off_xf, off_K, off_dinv, off_part;
   size_t off_qf, off_zf, off_uf, off_vf;
-  size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd;
+  size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd, off_hd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
   size_t off_par, off_acc, off_idx, off_bad, off_ftmp;
   // Anderson acceleration of the FP64 stage (aa = history length, 0 = off)
@@ -1348,7 +1391,7 @@ struct SolveLayout {
   size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_crow, off_cval;
   int64_t nzw;    // 64-bit words of zero-panel bits per 256-row tile of X
   size_t off_nz;  // zero-panel bits of the Gram operand [Cx / 256][nzw]
-  size_t off_tiles, off_perm;  // per orbit: nonzero 256-constraint tiles; the orbit order of X's columns
+  size_t off_tiles, off_perm;  // per orbit: footprint (count + bitmap of nonzero 256-constraint tiles); X's orbit order
   size_t total;
 };
 
@@ -1388,7 +1431,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_part = take((size_t)P * kSlabs * L.C * 8);
   L.off_qf = take(N * 4); L.off_zf = take(N * 4); L.off_uf = take(N * 4); L.off_vf = take(N * 4);
   L.off_qd = take(N * 8); L.off_xd = take(N * 8); L.off_zd = take(N * 8); L.off_ud = take(N * 8);
-  L.off_vd = take(N * 8); L.off_rd = take(N * 8);
+  L.off_vd = take(N * 8); L.off_rd = take(N * 8); L.off_hd = take(N * 8);
   L.off_kyf = take(VP * 4); L.off_r = take(VP * 4); L.off_tmp = take(VP * 4); L.off_s = take(VP * 4);
   L.off_sc = take(VP * 8); L.off_td = take(VP * 8); L.off_ys = take(VP * 8);
   L.off_par = take((size_t)P * kPar * 8);
@@ -1401,7 +1444,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
     for (int b = 0; b < P; ++b) nmax = std::max<int64_t>(nmax, off[b + 1] - off[b]);
     L.aa = aa;
     L.aa_nbx = (int)((nmax + kAAChunk - 1) / kAAChunk);
-    const size_t v3 = aa ? 3 * N * 8 : 0;
+    const size_t v3 = aa ? (size_t)kAAComp * N * 8 : 0;
     L.off_aw = take(v3); L.off_awp = take(v3); L.off_afp = take(v3);
     L.off_adf = take(v3 * aa); L.off_ay = take(v3 * aa);
     L.off_ag = take((size_t)P * kAAMem * kAAMem * 8);
@@ -1440,7 +1483,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
   L.off_pd = take(L.rg > 1 ? (size_t)P * L.ncb * NA * 8 : 0);
-  L.off_tiles = take(NA * 4);
+  L.off_tiles = take(NA * 5 * 8);
   L.off_perm = take(NA * 4);
   L.total = o;
   return L;
@@ -1597,9 +1640,9 @@ static int build_sparse(Ctx& X) {
     if (L.rps[b] > L.blk) return SW_OK;  // a slab longer than an LDS block: keep the dense passes
   int64_t* rcnt = X.p<int64_t>(L.off_rcnt);
   int32_t* cpart = X.p<int32_t>(L.off_cpart);
-  int32_t* tiles = X.p<int32_t>(L.off_tiles);
+  uint64_t* foot = X.p<uint64_t>(L.off_tiles);
   hipLaunchKernelGGL(k_row_nnz<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
-                     rcnt, tiles);
+                     rcnt, foot);
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
                      dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
@@ -1607,24 +1650,29 @@ static int build_sparse(Ctx& X) {
   std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
   SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
-  std::vector<int32_t> ht((size_t)NA);
-  SW_HIP(hipMemcpyAsync(ht.data(), tiles, ht.size() * 4, hipMemcpyDeviceToHost, X.st));
+  std::vector<uint64_t> hf((size_t)NA * 5);
+  SW_HIP(hipMemcpyAsync(hf.data(), foot, hf.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipStreamSynchronize(X.st));
   if (!g_gram_dense) {
     // The Gram is a sum over orbits, so its operand may take the orbits in any
-    // order.  Ordered by footprint (number of nonzero 256-constraint tiles, a
-    // stable counting sort within each matrix) the orbits of one 32-orbit stage
-    // cover similar parts of the grid and the sky, and more stages of a panel
-    // are all zero.  perm[aoff_b + j] = row (within matrix b) of column j.
-    const int64_t nkey = (L.C + 255) / 256 + 1;
+    // order.  Ordered by footprint (the number of nonzero 256-constraint tiles,
+    // then the bitmap of those tiles, lexicographically, within each matrix)
+    // the orbits of one 32-orbit stage cover the same parts of the grid and the
+    // sky, and more stages of a panel are all zero.  perm[aoff_b + j] = row
+    // (within matrix b) of column j.
     std::vector<int32_t> perm((size_t)NA);
-    std::vector<int64_t> start((size_t)nkey + 1);
     for (int b = 0; b < P; ++b) {
       const int64_t a0 = L.aoff[b], a1 = L.aoff[b + 1];
-      std::fill(start.begin(), start.end(), 0);
-      for (int64_t i = a0; i < a1; ++i) ++start[(size_t)std::min<int64_t>(ht[i], nkey - 1) + 1];
-      for (int64_t k = 0; k < nkey; ++k) start[k + 1] += start[k];
-      for (int64_t i = a0; i < a1; ++i) perm[a0 + start[(size_t)std::min<int64_t>(ht[i], nkey - 1)]++] = (int32_t)(i - a0);
+      int32_t* pb = perm.data() + a0;
+      for (int64_t i = a0; i < a1; ++i) pb[i - a0] = (int32_t)(i - a0);
+      const uint64_t* fb = hf.data() + a0 * 5;
+      std::stable_sort(pb, pb + (a1 - a0), [fb](int32_t x, int32_t y) {
+        const uint64_t* fx = fb + (int64_t)x * 5;
+        const uint64_t* fy = fb + (int64_t)y * 5;
+        for (int k = 0; k < 5; ++k)
+          if (fx[k] != fy[k]) return fx[k] < fy[k];
+        return false;
+      });
     }
     SW_HIP(hipMemcpyAsync(X.p<int32_t>(L.off_perm), perm.data(), perm.size() * 4, hipMemcpyHostToDevice, X.st));
     SW_HIP(hipStreamSynchronize(X.st));  // perm's host copy is freed on return
@@ -2031,16 +2079,15 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, vf, vd, L.N);
   SW_TRY(hipGetLastError());
   AAArgs AA;
+  const bool two = g_refine_two != 0;  // two passes over A per FP64 iteration, h carried
+  double* hd = X.p<double>(L.off_hd);
   AA.x = xd; AA.z = zd; AA.u = ud; AA.v = vd;
+  AA.h = two ? hd : nullptr; AA.r = rd; AA.q = qd; AA.mask = mask; AA.shared = shared ? 1 : 0;
   AA.w = X.p<double>(L.off_aw); AA.wp = X.p<double>(L.off_awp); AA.fp = X.p<double>(L.off_afp);
   AA.df = X.p<double>(L.off_adf); AA.y = X.p<double>(L.off_ay);
   AA.G = X.p<double>(L.off_ag); AA.gam = X.p<double>(L.off_agam); AA.st = X.p<double>(L.off_ast);
   AA.part = X.p<double>(L.off_apart);
   AA.off = X.off_d; AA.par = X.par; AA.N = L.N; AA.nbx = L.aa_nbx; AA.P = P;
-  if (aa) {
-    hipLaunchKernelGGL(k_aa_init, dim3(blocks_for(std::max<int64_t>(L.N, P))), dim3(256), 0, X.st, AA);
-    SW_TRY(hipGetLastError());
-  }
   std::vector<double> kkt(P, 0.0), obj(P, 0.0);
   std::vector<int> support(P, 0);
   // the KKT evaluation covers the active problems; a frozen problem keeps its last values
@@ -2070,25 +2117,41 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   n_active = 0;
   for (int b = 0; b < P; ++b) n_active += active[b];
   SW_TRY(set_active(active));
-  auto refine_iter_body = [&]() -> hipError_t {
+  // residual of the ridge system at x: r = q + rho v - (U^T U + rho' I) x, and
+  // (two passes per iteration) h = U^T U x, exactly: two passes over A
+  auto refresh = [&]() -> hipError_t {
     hipError_t e;
-    // residual of the ridge system at x_old: r = q + rho v - (U^T U + rho' I) x_old
     if ((e = colsum<double>(X, xd)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_PLAIN, nullptr, nullptr, td, nullptr)) != hipSuccess) return e;
     if ((e = colscale<double>(X, td)) != hipSuccess) return e;
     RowArgs Rh = RA;
     Rh.op = ROW_H;
     Rh.acc = nullptr;
-    if ((e = rowdot(X, Rh)) != hipSuccess) return e;
-    // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U)
+    Rh.hd = two ? hd : nullptr;
+    return rowdot(X, Rh);
+  };
+  // correction: x = x_old + M r, M = (1/rho')(I - U^T (rho' I + K)^-1 U): two passes over A
+  auto correct = [&]() -> hipError_t {
+    hipError_t e;
     if ((e = colsum<double>(X, rd)) != hipSuccess) return e;
     if ((e = colreduce(X, COL_PLAIN, nullptr, r, nullptr, nullptr)) != hipSuccess) return e;
     if ((e = apply_inverse()) != hipSuccess) return e;
     if ((e = colscale<float>(X, s)) != hipSuccess) return e;
     RowArgs Rc = RA;
-    Rc.op = ROW_CORR;
+    Rc.op = two ? ROW_CORR2 : ROW_CORR;
     Rc.acc = nullptr;
+    Rc.hd = two ? hd : nullptr;
     return rowdot(X, Rc);
+  };
+  // one iteration: with h carried, the correction alone (the next residual comes
+  // from h, which every batch of iterations starts by recomputing exactly);
+  // otherwise the residual from A, then the correction
+  auto refine_iter_body = [&]() -> hipError_t {
+    if (!two) {
+      hipError_t e = refresh();
+      if (e != hipSuccess) return e;
+    }
+    return correct();
   };
   // one step: the refinement iteration, then (accelerated) the Anderson
   // mixing; the step before a convergence check is the plain one, so the
@@ -2102,12 +2165,21 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     return hipGetLastError();
   };
   auto refine_batch = [&](int run) -> hipError_t {
+    if (two) {
+      hipError_t e = refresh();
+      if (e != hipSuccess) return e;
+    }
     for (int k = 0; k < run; ++k) {
       hipError_t e = refine_step(k == run - 1);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
+  if (two) SW_TRY(refresh());  // h of the iterate entering the stage, before the history takes it
+  if (aa) {
+    hipLaunchKernelGGL(k_aa_init, dim3(blocks_for(std::max<int64_t>(L.N, P))), dim3(256), 0, X.st, AA);
+    SW_TRY(hipGetLastError());
+  }
   if (use_graph && n_active > 0) SW_TRY(capture([&]() { return refine_batch(check_every); }, 1, &g2.e));
   std::vector<int> rit(P, 0);
   int k_done = 0;

@@ -180,10 +180,14 @@ class Surrogate:
         x = 2.0 * (np.asarray(thetas, dtype=np.float64) - self.lo) / (self.hi - self.lo) - 1.0
         return self.torch.from_numpy(x.astype(np.float32)).cuda()
 
-    def fit(self, thetas, chi2, epochs=200, batch=512, lr=1e-3, seed=1):
+    def fit(self, thetas, chi2, epochs=200, batch=512, lr=1e-3, seed=1, keep_scaling=False):
+        """Mini-batch Adam on (theta, log chi^2); keep_scaling: continue from the
+        current weights with the current target standardisation (a refit)."""
         torch = self.torch
         t = np.log(np.asarray(chi2, dtype=np.float64))
-        self.mu_t, self.sd_t = float(t.mean()), float(t.std() + 1e-12)
+        if not keep_scaling:
+            self.mu_t, self.sd_t = float(t.mean()), float(t.std() + 1e-12)
+        batch = min(batch, len(t))
         tt = torch.from_numpy(((t - self.mu_t) / self.sd_t).astype(np.float32)).cuda()
         x = self._x(thetas)
         n = x.shape[0]
@@ -221,13 +225,20 @@ class Surrogate:
 
 
 def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, seed=8, use_surrogate=True,
-            log=None, normals=None, uniforms=None):
+            log=None, normals=None, uniforms=None, refit=None, refit_every=50, adapt_steps=0):
     """Delayed-acceptance random-walk Metropolis over a uniform prior box,
     many walkers advanced together: each step proposes for every walker,
     screens with the surrogate, and builds the survivors' models in one batch.
     The random numbers are drawn from `seed` (per step: normals [n_w, d], then
     uniforms [n_w, 2]) unless given as normals [n_steps][n_w][d] and uniforms
-    [n_steps][n_w][2].  Returns the chains and counters."""
+    [n_steps][n_w][2].
+    refit(thetas, chi2s): optional, called every refit_every steps during the
+    first adapt_steps steps with every full build made so far (the chains'
+    neighbourhood); it retrains the surrogate, whose values at the current
+    states are then recomputed.  The screen is fixed after adapt_steps (the
+    chain after that point leaves the posterior invariant whatever the screen).
+    Returns the chains and counters; n_full_builds_after_adapt and
+    n_stage1_after_adapt count the steps after adaptation."""
     rng = np.random.default_rng(seed)
     th = np.array(theta0, dtype=np.float64)
     n_w, d = th.shape
@@ -237,8 +248,15 @@ def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, 
     chi_s = surrogate.predict(th) if use_surrogate else chi.copy()
     chains = np.empty((n_steps, n_w, d))
     n_full, n_s1, n_acc = len(th), 0, 0
+    built_th, built_chi = [th.copy()], [chi.copy()]
+    full_at_adapt = s1_at_adapt = None
     t0 = time.perf_counter()
     for k in range(n_steps):
+        if k == adapt_steps:
+            full_at_adapt, s1_at_adapt = n_full, n_s1
+        if refit is not None and use_surrogate and 0 < k < adapt_steps and k % refit_every == 0:
+            refit(np.concatenate(built_th), np.concatenate(built_chi))
+            chi_s = surrogate.predict(th)
         z = rng.normal(size=(n_w, d)) if normals is None else np.asarray(normals[k])
         u = rng.uniform(size=(n_w, 2)) if uniforms is None else np.asarray(uniforms[k])
         prop = th + scale * z
@@ -256,6 +274,8 @@ def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, 
             cf = builder.chi2(prop[idx])
             n_unconv += int((~getattr(builder, "last_converged", np.ones(len(idx), dtype=bool))).sum())
             n_full += len(idx)
+            built_th.append(prop[idx].copy())
+            built_chi.append(np.asarray(cf, dtype=np.float64).copy())
             for j, i in enumerate(idx):
                 if use_surrogate:
                     a2 = -(cf[j] - chi[i]) / dchi2 + (cs[i] - chi_s[i]) / dchi2
@@ -270,5 +290,9 @@ def da_mcmc(builder, surrogate, theta0, lo, hi, n_steps, dchi2, step_frac=0.05, 
         if log and (k + 1) % max(1, n_steps // 10) == 0:
             log(f"mcmc step {k + 1}/{n_steps}: full builds {n_full}, accepted {n_acc}")
     el = time.perf_counter() - t0
+    if full_at_adapt is None:
+        full_at_adapt, s1_at_adapt = n_full, n_s1
     return {"chains": chains, "n_full_builds": n_full, "n_stage1": n_s1, "n_accepted": n_acc, "seconds": el,
-            "proposals": n_steps * n_w, "models_per_s": n_steps * n_w / el, "n_unconverged_builds": n_unconv}
+            "proposals": n_steps * n_w, "models_per_s": n_steps * n_w / el, "n_unconverged_builds": n_unconv,
+            "n_full_builds_after_adapt": n_full - full_at_adapt, "n_stage1_after_adapt": n_s1 - s1_at_adapt,
+            "built": (np.concatenate(built_th), np.concatenate(built_chi))}

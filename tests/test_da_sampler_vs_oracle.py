@@ -98,3 +98,45 @@ def test_exact_screen_passes_every_inside_proposal_to_the_full_build():
     res = S.da_mcmc(b, Exact(), theta0, LO, HI, n_steps, dchi2, step_frac=step_frac, use_surrogate=True,
                     normals=normals, uniforms=uniforms)
     assert res["n_accepted"] == res["n_stage1"]
+
+
+def test_adapted_screen_then_exact_delayed_acceptance():
+    """With the screen refitted during the first adapt_steps steps (here a toy
+    refit that changes its bias), the chain after adaptation is the oracle's
+    delayed-acceptance chain with the final screen, started from the state
+    reached at adapt_steps, on the same random numbers."""
+    n_w, n_steps, adapt, step_frac, dchi2 = 4, 300, 100, 0.08, 10.0
+    rng = np.random.default_rng(9)
+    normals = rng.normal(size=(n_steps, n_w, D))
+    uniforms = rng.uniform(size=(n_steps, n_w, 2))
+    theta0 = CENTRE + rng.normal(scale=0.2, size=(n_w, D))
+    b = ToyBuilder()
+
+    class Adaptive:
+        bias = 0.0
+
+        def predict(self, t):
+            t = np.atleast_2d(t)
+            return 30.0 * np.sum((t - CENTRE - self.bias) ** 2, axis=1) + 90.0
+
+    s = Adaptive()
+    calls = []
+
+    def refit(th, chi):
+        calls.append(len(chi))
+        s.bias = 0.1 / len(calls)
+
+    res = S.da_mcmc(b, s, theta0, LO, HI, n_steps, dchi2, step_frac=step_frac, use_surrogate=True,
+                    normals=normals, uniforms=uniforms, refit=refit, refit_every=25, adapt_steps=adapt)
+    assert len(calls) == 3 and calls == sorted(calls)
+    chol = np.diag(step_frac * (HI - LO))
+    start = res["chains"][adapt - 1]
+    n_eval, n_s1 = 0, 0
+    for i in range(n_w):
+        chain, ne, ns = mcmc.da_mh(_logp(dchi2, b.chi2), _logp(dchi2, s.predict), start[i], chol,
+                                   normals[adapt:, i], uniforms[adapt:, i])
+        np.testing.assert_array_equal(res["chains"][adapt:, i], chain)
+        n_eval += ne - 1
+        n_s1 += ns
+    assert res["n_full_builds_after_adapt"] == n_eval
+    assert res["n_stage1_after_adapt"] == n_s1

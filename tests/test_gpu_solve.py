@@ -354,3 +354,36 @@ def test_gram_panel_skipping_matches_dense_gram(gpu):
     assert out[0][1] == 0 and out[1][1] == 0
     assert np.abs(out[1][0] - out[0][0]).sum() <= 1e-5 * np.abs(out[0][0]).sum()
     assert np.abs(out[1][0] - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
+
+
+@pytest.mark.parametrize("flags", [0, 2], ids=["anderson", "plain_admm"])
+def test_two_pass_iterations_match_four(gpu, flags):
+    """The FP64 stage with U^T U x carried along (two passes over A per
+    iteration, the default) and with the residual recomputed from A every
+    iteration (four passes) reach the same weights, both within the oracle's
+    bar, with and without the Anderson acceleration."""
+    import oracle as O
+    from tests.gpu_common import oracle_integrate
+    P = lib()
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, *_ = gpu_integrate(cfg, ics, dt, cfg["n_steps"], "f64")
+    c_o, *_ = oracle_integrate(cfg, ics, dt, cfg["n_steps"])
+    A_o = O.time_fractions(c_o, cfg["n_steps"])
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A_o, blocks, cfg["mock"]["seed"], 0.02, cfg["mock"]["tol"])
+    w_o, _ = oracle_solve(A_o, d, sig, wt, 1e-2)
+    out = {}
+    old = P.get_tuning("refine_passes")
+    try:
+        for passes in (2, 4):
+            P.set_tuning("refine_passes", passes)
+            w, status, rep, _ = gpu_solve(A, d, sig, wt, 1e-2, 1, flags=flags)
+            out[passes] = (w, status, rep.iters, rep.refine_iters, rep.kkt)
+    finally:
+        P.set_tuning("refine_passes", old)
+    print({k: v[1:] for k, v in out.items()})
+    for passes, (w, status, _, _, kkt) in out.items():
+        assert status == 0, passes
+        assert np.abs(w - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL, passes
+    assert np.abs(out[2][0] - out[4][0]).sum() <= 1e-4 * np.abs(out[4][0]).sum()

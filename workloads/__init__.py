@@ -227,3 +227,43 @@ def ncon(obs):
 def blocks(obs):
     nm = obs["nx"] * obs["ny"] * obs["nz"]
     return [(0, nm), (nm, ncon(obs))]
+
+
+# The paper's own pipeline (Sec. 2.2-2.4, Sec. 3.2.3) on the barred model: 7,500
+# Jeans initial conditions x 4 dithers, BS23 (rtol 1e-4) for 5,000 accepted
+# steps, a 600-cell cylindrical density grid, ~600 irregular apertures of a
+# 60 x 40 pixel grid with 30 velocity bins, the surface-density block, and
+# 100 bootstrap realisations of the maps.
+PAPER = dict(
+    name="paper_pipeline_barred_7500x4_bs23_5k_steps_f64",
+    n_ic=7500, n_dither=4, n_steps=5000, rtol=1e-4, atol=1e-6, h0=2e-3, dx=0.1, fv=0.05, h_R=3.5, h_z=1.2,
+    jeans_b=1.0, n_boot=100, n_gh=4, dh=0.02, stellar_mask=0b011, n_sub=4,
+    obs=dict(nx=10, ny=6, nz=10, lo=(0.0, -math.pi, -3.0), hi=(10.0, math.pi, 3.0), grid="cylindrical",
+             npx=60, npy=40, plo=(-10.0, -20.0 / 3.0), phi=(10.0, 20.0 / 3.0),
+             nv=30, vlo=-450.0, vhi=450.0, symmetrize=1, drift_every=1, surface=1, upsilon=1.0),
+    n_gen=880, ap_scale=6.0, ap_seed=23, ic_seed=21, mock=dict(seed=22, frac=0.1, tol=0.01, noise=0.01),
+)
+
+
+def voronoi_map(npx, npy, plo, phi, n_gen, seed, scale=3.0):
+    """A stand-in for the paper's Voronoi apertures (its PowerBin binning of an
+    IFU field is not available): n_gen seeded generators, denser towards the
+    centre (exponential in radius with the given scale, uniform angle), each
+    pixel of the npx x npy grid assigned to its nearest generator; generators
+    with no pixel are dropped and the rest renumbered in order.  Returns
+    (map [npx * npy] int32, pixel (jX, jY) at jX * npy + jY; number of apertures)."""
+    rng = np.random.default_rng(seed + 3000)
+    r = rng.exponential(scale, size=4 * n_gen)
+    t = rng.uniform(0.0, 2 * math.pi, size=4 * n_gen)
+    gx, gy = r * np.cos(t), r * np.sin(t)
+    keep = (gx >= plo[0]) & (gx < phi[0]) & (gy >= plo[1]) & (gy < phi[1])
+    gx, gy = gx[keep][:n_gen], gy[keep][:n_gen]
+    px = plo[0] + (np.arange(npx) + 0.5) * (phi[0] - plo[0]) / npx
+    py = plo[1] + (np.arange(npy) + 0.5) * (phi[1] - plo[1]) / npy
+    X, Y = np.meshgrid(px, py, indexing="ij")
+    d2 = (X.reshape(-1, 1) - gx[None, :]) ** 2 + (Y.reshape(-1, 1) - gy[None, :]) ** 2
+    near = np.argmin(d2, axis=1)
+    used = np.unique(near)
+    remap = np.full(gx.size, -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return remap[near].astype(np.int32), int(used.size)
