@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--refine-iter", type=int, default=0, help="cap of the FP64 stage (0: library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch the solve iterations one by one")
     ap.add_argument("--no-accel", action="store_true", help="plain ADMM (no Anderson acceleration)")
+    ap.add_argument("--rho", type=float, default=None,
+                    help="ADMM penalty as a multiple of trace(U U^T)/N (default: the library's, 1)")
     ap.add_argument("--bootstrap", type=int, default=0,
                     help="also solve this many bootstrap realisations of the data per build (shared matrix) "
                          "and report chi2_model")
@@ -304,6 +306,8 @@ def main():
     opts.gram = {"bf16": P.SW_GRAM_BF16, "bf16x3": P.SW_GRAM_BF16X3, "f32": P.SW_GRAM_F32}[args.gram]
     opts.nu = 1e-2
     opts.mask = mask.data_ptr()
+    if args.rho is not None:
+        opts.rho = -args.rho
     w = torch.empty(n, dtype=torch.float64, device=dev)
     sws = torch.empty(P.solve_workspace_bytes(n, nc, opts), dtype=torch.uint8, device=dev)
     cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
@@ -430,11 +434,21 @@ def main():
         t_boot_ref = float(repb[0].t_refine_ms)
         stages["bootstrap_refine_fp64"] = t_boot_ref
         stages["bootstrap_rest"] = float(np.mean([b[4] for b in boot])) - t_boot_ref
+        # the shared matrix's passes: compressed per group of rg vectors, or (reported nnz 0)
+        # dense FP64 MFMA products that read A once per pass for all vectors; the multi-vector
+        # inverse products read the fp32 factor
+        l32 = 4.0 * C * (C + 1) / 2.0
+        if repb[0].nnz > 0:
+            kern, a_issued = "k_csc_colsum_rhs + k_rowdot_csr_rhs + k_trmm_rhs (+ k_aa_*)", its_sum / rg * 4 * u_bytes
+        else:
+            kern = "k_dgemm_rhs + k_trmm_rhs (+ k_aa_*)"
+            a_issued = its_max * refine_passes * N * C * (8.0 if f64 else 4.0)
         rooflines["bootstrap_refine_fp64"] = {
-            "kernel": "k_csc_colsum_rhs + k_rowdot_csr_rhs + k_trmm_rhs (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
-            "peak": PEAK_HBM / 1e9, "ms": t_boot_ref, "work": its_sum * per_iter,
-            "issued": its_sum / rg * 4 * u_bytes + its_max * 2 * l_bytes + its_sum * aa_bytes,
-            "work_rule": "2|U| + 2|L| per iteration and data vector"}
+            "kernel": kern, "bound": "hbm", "unit": "GB/s",
+            "peak": PEAK_HBM / 1e9, "ms": t_boot_ref, "work": its_max * (2 * u_bytes + 2 * l32),
+            "issued": a_issued + its_max * 2 * l32 + its_sum * aa_bytes,
+            "work_rule": "2|U| + 2|L| per iteration of the batch (A and the factor read once for all "
+                         "data vectors)"}
     for k, r in rooflines.items():
         scale = 1e12 if r["unit"] == "TFLOP/s" else 1e9
         r["achieved"] = round(r["work"] / (r["ms"] * 1e-3) / scale, 3) if r["ms"] > 0 else None
@@ -630,6 +644,41 @@ FLOP_PER_FORCE_F64 = 63 + 14 + 32 * 28 + 12 + 22 + 27
 FLOP_PER_BS23_STEP = 3 * FLOP_PER_FORCE_F64 + 6 * 27 + 30
 
 
+def paper_maps(raw, cfg, n_ap, kin0, surf0):
+    """The observed luminosity gamma* (Sigma*, floored at 1e-3 of its maximum) and the
+    reference Gaussian (v0, s) of each aperture: the mean and dispersion of the
+    binned LOSVD (at least 20 km/s), from the binned maps `raw` of a mock."""
+    o = cfg["obs"]
+    nv, vlo, vhi = o["nv"], o["vlo"], o["vhi"]
+    sig_obs = raw[surf0:surf0 + n_ap]
+    gamma = np.maximum(sig_obs, 1e-3 * sig_obs.max())
+    hist = raw[kin0:kin0 + n_ap * nv].reshape(n_ap, nv)
+    vc = vlo + (np.arange(nv) + 0.5) * (vhi - vlo) / nv
+    tot = np.maximum(hist.sum(1), 1e-300)
+    v0 = (hist * vc).sum(1) / tot
+    s = np.sqrt(np.maximum((hist * (vc - v0[:, None]) ** 2).sum(1) / tot, 20.0 ** 2))
+    return gamma, v0, s
+
+
+def paper_data(model, cfg, n_mass, n_ap, m_star=None):
+    """The observed data vector and its uncertainties from the fit-matrix
+    observables `model` of a mock: the density block (m*_n when given), Sigma*
+    with 1% noise and h* with noise of Delta h*, seeded; sigma 1% of the density
+    and Sigma (floored at 1e-3 of their maxima), Delta h* on the h-blocks."""
+    d = np.array(model, dtype=np.float64)
+    rng = np.random.default_rng(cfg["mock"]["seed"] + 4000)
+    if m_star is not None:
+        d[:n_mass] = m_star
+    d[n_mass:n_mass + n_ap] *= 1 + cfg["mock"]["noise"] * rng.standard_normal(n_ap)
+    d[n_mass + n_ap:] += cfg["dh"] * rng.standard_normal(d.size - n_mass - n_ap)
+    sig = np.empty(d.size)
+    for b0, b1 in ((0, n_mass), (n_mass, n_mass + n_ap)):
+        top = float(np.max(np.abs(d[b0:b1])))
+        sig[b0:b1] = cfg["mock"]["tol"] * np.maximum(np.abs(d[b0:b1]), 1e-3 * top)
+    sig[n_mass + n_ap:] = cfg["dh"]
+    return d, sig
+
+
 def paper_mock(P, torch, dev, cfg, pot, obs, pix2ap, n_ap, A_b, m_star, n_mass, kin0, surf0):
     """The observed maps (a stand-in for the paper's IFU data): a seeded 10% subset of
     the bundles with Exp(1) weights scaled to the stellar mass of the density grid;
@@ -647,13 +696,7 @@ def paper_mock(P, torch, dev, cfg, pot, obs, pix2ap, n_ap, A_b, m_star, n_mass, 
     scale = float(ms.sum()) / float(raw[:n_mass].sum())
     raw = raw * scale
     nv, vlo, vhi = o["nv"], o["vlo"], o["vhi"]
-    sig_obs = raw[surf0:surf0 + n_ap]
-    gamma = np.maximum(sig_obs, 1e-3 * sig_obs.max())
-    hist = raw[kin0:kin0 + n_ap * nv].reshape(n_ap, nv)
-    vc = vlo + (np.arange(nv) + 0.5) * (vhi - vlo) / nv
-    tot = np.maximum(hist.sum(1), 1e-300)
-    v0 = (hist * vc).sum(1) / tot
-    s = np.sqrt(np.maximum((hist * (vc - v0[:, None]) ** 2).sum(1) / tot, 20.0 ** 2))
+    gamma, v0, s = paper_maps(raw, cfg, n_ap, kin0, surf0)
     n_gh = cfg["n_gh"]
     nf = n_mass + n_ap + n_gh * n_ap
     F = torch.empty((nb, nf), dtype=torch.float64, device=dev)
@@ -662,17 +705,106 @@ def paper_mock(P, torch, dev, cfg, pot, obs, pix2ap, n_ap, A_b, m_star, n_mass, 
     model = torch.empty(nf, dtype=torch.float64, device=dev)
     P.model_observables(F, w * scale, model)
     torch.cuda.synchronize()
-    d = model.cpu().numpy()
-    rng = np.random.default_rng(cfg["mock"]["seed"] + 4000)
-    d[:n_mass] = ms
-    d[n_mass:n_mass + n_ap] *= 1 + cfg["mock"]["noise"] * rng.standard_normal(n_ap)
-    d[n_mass + n_ap:] += cfg["dh"] * rng.standard_normal(nf - n_mass - n_ap)
-    sig = np.empty(nf)
-    for b0, b1 in ((0, n_mass), (n_mass, n_mass + n_ap)):
-        top = float(np.max(np.abs(d[b0:b1])))
-        sig[b0:b1] = cfg["mock"]["tol"] * np.maximum(np.abs(d[b0:b1]), 1e-3 * top)
-    sig[n_mass + n_ap:] = cfg["dh"]
+    d, sig = paper_data(model.cpu().numpy(), cfg, n_mass, n_ap, m_star=ms)
     return d, sig, v0, s, gamma, float(ms.sum()) / nb
+
+
+def paper_oracle_leg(cfg, run, n_bundles=16):
+    """The oracle leg of the paper pipeline: the FP64 oracle's whole model
+    (Jeans initial conditions, dithers, BS23 with time-weighted binning, bundle
+    means, the Gauss-Hermite fit matrix, the exact NNLS of the observed maps and
+    chi^2) for the first n_bundles of the seeded initial conditions, timed on the
+    host; and the GPU's errors against the oracle on that sample: the Jeans
+    moments, the BS23 rows (from the oracle's initial conditions), the fit
+    matrix (from the oracle's bundle rows) and the weight solve on the oracle's
+    fit matrix."""
+    import oracle as O
+    from oracle import gh as GH
+    from oracle import ics as OI
+    from oracle import nnls as N
+    P, torch, dev = run["P"], run["torch"], run["dev"]
+    threads, phys = host_threads()
+    o = cfg["obs"]
+    nd, S = cfg["n_dither"], run["S"]
+    pos, eps, u = run["pos"][:, :n_bundles], run["eps"][:, :n_bundles], run["u"][:, :, :n_bundles]
+    comps, omega, euler = W.BARRED["components"], W.BARRED["omega"], W.BARRED["euler"]
+    pot = O.make_pot(comps, omega)
+    ob = O.make_obs(dict(o, pix2ap=run["pmap"], n_ap=run["n_ap"]), O.euler_matrix(*euler))
+    n_mass, kin0, surf0, n_ap, n_gh = run["n_mass"], run["kin0"], run["surf0"], run["n_ap"], cfg["n_gh"]
+    O.set_ferrers_rule(64)
+    try:
+        t0 = time.perf_counter()
+        mom_o, ic_o = O.jeans_ics(pot, pos, eps, cfg["h_R"], cfg["h_z"], cfg["jeans_b"])
+        ics_o = OI.dither(ic_o, mom_o[4], u, cfg["dx"], cfg["fv"])
+        h0 = np.full(ics_o.shape[1], cfg["h0"])
+        A_o, _, _, _ = O.integrate_bs23_and_bin(pot, ob, ics_o, h0, S, cfg["rtol"], cfg["atol"], nthreads=threads)
+        Ab_o = OI.bundle_rows(A_o, nd)
+        # the sample's own mock (the same recipe: a 10% subset with Exp(1) weights)
+        w_s = W.mock_draw(n_bundles, cfg["mock"]["seed"])
+        gamma, v0, sw = paper_maps(Ab_o.T @ w_s, cfg, n_ap, kin0, surf0)
+        F_o = GH.fit_matrix(Ab_o, n_mass, kin0, surf0, n_ap, o["nv"], o["vlo"], o["vhi"], v0, sw, gamma, n_gh)
+        d, sig = paper_data(F_o.T @ w_s, cfg, n_mass, n_ap)
+        wt = float(d[:n_mass].sum()) / n_bundles
+        U, y = N.scale_problem(F_o, d, sig, wt)
+        mu = N.relative_mu(U, 1e-2)
+        w_o = N.nnls_oracle(U, y, mu) * wt
+        x_o = N.chi2(F_o, w_o, d, sig, n_mass, F_o.shape[1])
+        el = time.perf_counter() - t0
+    finally:
+        O.set_ferrers_rule(0)
+    errors = {}
+    # Jeans moments on the same positions
+    mom = torch.empty((5, n_bundles), dtype=torch.float64, device=dev)
+    ic1 = torch.empty((6, n_bundles), dtype=torch.float64, device=dev)
+    P.jeans_ics(run["pot"], torch.from_numpy(np.ascontiguousarray(pos)).to(dev),
+                torch.from_numpy(np.ascontiguousarray(eps)).to(dev), cfg["h_R"], cfg["h_z"], cfg["jeans_b"], mom, ic1)
+    torch.cuda.synchronize()
+    # each moment's largest error relative to its largest magnitude (a moment can vanish at
+    # a position, e.g. the mean rotation on the minor axis)
+    mg = mom.cpu().numpy()
+    scale = np.maximum(np.abs(mom_o).max(axis=1, keepdims=True), 1e-300)
+    errors["jeans_moments_max_rel"] = float(np.max(np.abs(mg - mom_o) / scale))
+    # BS23 from the oracle's initial conditions
+    n = ics_o.shape[1]
+    A = torch.empty((n, A_o.shape[1]), dtype=torch.float64, device=dev)
+    ov = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    dr = torch.empty(n, dtype=torch.float64, device=dev)
+    fl = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = torch.empty(P.integrate_bs23_workspace_bytes(n, S), dtype=torch.uint8, device=dev)
+    P.integrate_bs23_and_bin(run["pot"], torch.from_numpy(ics_o).to(dev), torch.from_numpy(h0).to(dev), S,
+                             cfg["rtol"], cfg["atol"], run["obs"], A, ov, dr, fl, ws)
+    torch.cuda.synchronize()
+    l1 = np.abs(A.cpu().numpy() - A_o).sum(1) / 2
+    errors["bs23_rows"] = {"orbits": n, "row_l1_median": float(np.median(l1)), "row_l1_p90": float(np.percentile(l1, 90)),
+                           "rows_above_1e-6": float(np.mean(l1 > 1e-6))}
+    # the fit matrix from the oracle's bundle rows
+    Ab = torch.from_numpy(Ab_o).to(dev)
+    F = torch.empty(F_o.shape, dtype=torch.float64, device=dev)
+    gws = torch.empty(P.gh_fit_workspace_bytes(n_ap, o["nv"], n_gh), dtype=torch.uint8, device=dev)
+    P.gh_fit_matrix(Ab, n_mass, kin0, surf0, n_ap, o["nv"], o["vlo"], o["vhi"], v0, sw, gamma, F, gws, n_gh=n_gh)
+    torch.cuda.synchronize()
+    Fg = F.cpu().numpy()
+    errors["fit_matrix_max_abs"] = float(np.max(np.abs(Fg - F_o)))
+    # the weight solve on the oracle's fit matrix
+    opts = P._lib.SolveOpts()
+    opts.gram, opts.nu = P.SW_GRAM_BF16X3, 1e-2
+    Ft = torch.from_numpy(F_o).to(dev)
+    w = torch.empty(n_bundles, dtype=torch.float64, device=dev)
+    sws = torch.empty(P.solve_workspace_bytes(n_bundles, F_o.shape[1], opts), dtype=torch.uint8, device=dev)
+    d_t, s_t = torch.from_numpy(d).to(dev), torch.from_numpy(sig).to(dev)
+    st, rep = P.solve_weights(Ft, d_t, s_t, wt, -1.0, opts, w, sws)
+    cws = torch.empty(P.chi2_workspace_bytes(F_o.shape[1]), dtype=torch.uint8, device=dev)
+    x_g = P.chi2(Ft, w, d_t, s_t, n_mass, F_o.shape[1], cws)
+    wg = w.cpu().numpy()
+    errors["solve_sample"] = {"bundles": n_bundles, "status": st, "kkt_gpu": rep.kkt,
+                              "weights_l1_rel": float(np.abs(wg - w_o).sum() / max(np.abs(w_o).sum(), 1e-300)),
+                              "chi2_rel": float(abs(x_g / x_o - 1))}
+    base = {"value": n * S / el, "unit": "orbit-steps/s", "cores": threads, "physical_cores": phys, "kind": "oracle",
+            "sample": f"the FP64 oracle's model (Jeans initial conditions, {nd} dithers, BS23 at rtol {cfg['rtol']} "
+                      f"for {S} steps with time-weighted binning, bundle means, the Gauss-Hermite fit matrix, one "
+                      f"exact NNLS of the observed maps, chi^2) for the first {n_bundles} of the {cfg['n_ic']} "
+                      f"seeded initial conditions ({el:.1f} s on {threads} threads; no bootstrap solves)"}
+    return base, errors
 
 
 def bench_paper(args):
@@ -799,6 +931,10 @@ def bench_paper(args):
            "model_builds_per_s": 1e3 / ms, "stage_ms": {k: round(v, 2) for k, v in st_ms.items()},
            "dominant_stage": max(st_ms, key=st_ms.get), "last": res[-1], "roofline": roof,
            "context": "the paper quotes about 1.3 s per model (build + 100 bootstrap solves + chi^2) on one A100"}
+    if not args.no_cpu_baseline:
+        run = dict(P=P, torch=torch, dev=dev, S=S, pos=pos, eps=eps, u=W.dither_deviates(nd, n_ic, seed=cfg["ic_seed"]),
+                   pmap=pmap, n_ap=n_ap, n_mass=n_mass, kin0=kin0, surf0=surf0, pot=pot, obs=obs)
+        out["cpu_baseline"], out["errors_vs_oracle"] = paper_oracle_leg(cfg, run)
     print(json.dumps(out))
 
 

@@ -243,7 +243,8 @@ typedef struct {
      factor = rho' I + blocked Cholesky, admm = q, Ky and the fp32 iterations,
      refine = fp64 refinement, KKT evaluations and output */
   double t_prep_ms, t_gram_ms, t_factor_ms, t_admm_ms, t_refine_ms;
-  double nnz; /* nonzeros of A when the ADMM passes used the compressed copies, else 0 */
+  double nnz; /* nonzeros of A when the ADMM passes used the compressed copies, else 0
+                 (dense passes over A, among them the FP64 MFMA passes of a shared matrix) */
 } sw_solve_report;
 
 int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,
@@ -524,6 +525,11 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             (0: automatic = up to 4; 1, 2, 4 or 8; it sets
  *                             the block sizes of the compressed copies, so
  *                             query solve_multi_workspace_bytes after it)
+ *   "multi_dense"             solve_weights_multi: the passes over the shared
+ *                             matrix as dense FP64 MFMA products over all data
+ *                             vectors (1), as compressed passes per group of
+ *                             rhs_per_group vectors (2), or whichever the cost
+ *                             model (density, vector count) finds faster (0)
  *   "refine_passes"           weight solve, FP64 stage: 2 (default) passes over
  *                             the orbit matrix per iteration, with U^T U x carried
  *                             alongside the iterate (updated by each correction,

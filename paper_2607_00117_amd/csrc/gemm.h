@@ -15,9 +15,16 @@ constexpr int kNB = 128;  // Cholesky / triangular-solve block size, also the GE
 //  mode SW_GRAM_BF16X3: X = hi + lo (bf16 pair), K ~ hi hi^T + hi lo^T + lo hi^T
 //  mode SW_GRAM_F32:    X = xf (fp32)
 // M = rows of K (multiple of 128); X has gram_rows(mode, M) rows (bf16 modes:
-// a multiple of 256, rows past M zero), ld = row stride of X; xoff/xlen given
-// on the device (bf16 modes) and on the host (fp32 mode); K_b = K + b * sK.
+// a multiple of 256, rows past M zero) and ld columns (a multiple of 32);
+// xoff/xlen given on the device (bf16 modes) and on the host (fp32 mode);
+// K_b = K + b * sK.  fp32 mode: X row-major, entry (m, k) at m * ld + k.
+// bf16 modes: X stage-blocked, entry (m, k) at gram_at(m, k, ld): the rows of a
+// 256-row panel and the 32 columns of a stage form one contiguous 256 x 32
+// row-major block, blocks in stage order within a panel, panels in row order.
 inline int64_t gram_rows(int mode, int64_t M) { return mode == SW_GRAM_F32 ? M : (M + 255) / 256 * 256; }
+__host__ __device__ inline int64_t gram_at(int64_t m, int64_t k, int64_t ld) {
+  return (m >> 8) * 256 * ld + (k >> 5) * 8192 + (m & 255) * 32 + (k & 31);
+}
 // nz (bf16 modes, may be null): bit g of nz[t * nzw + g / 64] is set when rows
 // [256 t, 256 t + 256) of X hold a nonzero in columns [32 g, 32 g + 32); the
 // 32-column stages whose row or column panel is zero are skipped.

@@ -84,6 +84,10 @@ static int64_t super_grid(int64_t nt) {
 // stage is consumed from one buffer the next is fetched into registers and
 // then written to the other, one barrier per stage.  On diagonal tiles the
 // row and column panels coincide and are staged once.
+// X is stored stage-blocked (gram_at): the 256 x 32 block of a row panel and a
+// stage is 16 KB of contiguous memory, so a stage's fetch is two fully
+// coalesced 8 KB sweeps of the workgroup instead of 256 row pieces of 64 bytes
+// spread over the whole panel.
 // Stage skipping: when `nz` is given, bit g of nz[t * nzw + g / 64] says
 // whether rows [256 t, 256 t + 256) of X have a nonzero in columns
 // [32 g, 32 g + 32) (global stage g); a stage whose row panel or column panel
@@ -139,26 +143,29 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
 
   // a panel stage is 256 rows x 32 k = 1024 chunks of 16 B, 2 per thread:
   // chunk q = tid + 512 j is row q / 4, k offset 8 (q % 4)
+  // (in the stage block, chunk q sits at element 8 q: the workgroup reads the
+  // block's two halves front to back)
   const int r0 = tid >> 2, r1 = r0 + kGThreads / 4, cc = (tid & 3) * 8;
-  const __bf16* pAh = hi + tm * kGT * ld + cc;
-  const __bf16* pBh = hi + tn * kGT * ld + cc;
-  const __bf16* pAl = lo + tm * kGT * ld + cc;
-  const __bf16* pBl = lo + tn * kGT * ld + cc;
+  const __bf16* pAh = hi + tm * kGT * ld + tid * 8;
+  const __bf16* pBh = hi + tn * kGT * ld + tid * 8;
+  const __bf16* pAl = lo + tm * kGT * ld + tid * 8;
+  const __bf16* pBl = lo + tn * kGT * ld + tid * 8;
+  constexpr int64_t kHalf = kGThreads * 8;  // elements in half a stage block
   uint4 gAh0, gAh1, gBh0, gBh1, gAl0, gAl1, gBl0, gBl1;
   auto gload = [&](int64_t g) {
-    const int64_t k0 = g * kGBK;
-    gAh0 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r0 * ld + k0);
-    gAh1 = *reinterpret_cast<const uint4*>(pAh + (int64_t)r1 * ld + k0);
+    const int64_t k0 = g * (kGT * kGBK);
+    gAh0 = *reinterpret_cast<const uint4*>(pAh + k0);
+    gAh1 = *reinterpret_cast<const uint4*>(pAh + k0 + kHalf);
     if (!diag) {
-      gBh0 = *reinterpret_cast<const uint4*>(pBh + (int64_t)r0 * ld + k0);
-      gBh1 = *reinterpret_cast<const uint4*>(pBh + (int64_t)r1 * ld + k0);
+      gBh0 = *reinterpret_cast<const uint4*>(pBh + k0);
+      gBh1 = *reinterpret_cast<const uint4*>(pBh + k0 + kHalf);
     }
     if constexpr (X3) {
-      gAl0 = *reinterpret_cast<const uint4*>(pAl + (int64_t)r0 * ld + k0);
-      gAl1 = *reinterpret_cast<const uint4*>(pAl + (int64_t)r1 * ld + k0);
+      gAl0 = *reinterpret_cast<const uint4*>(pAl + k0);
+      gAl1 = *reinterpret_cast<const uint4*>(pAl + k0 + kHalf);
       if (!diag) {
-        gBl0 = *reinterpret_cast<const uint4*>(pBl + (int64_t)r0 * ld + k0);
-        gBl1 = *reinterpret_cast<const uint4*>(pBl + (int64_t)r1 * ld + k0);
+        gBl0 = *reinterpret_cast<const uint4*>(pBl + k0);
+        gBl1 = *reinterpret_cast<const uint4*>(pBl + k0 + kHalf);
       }
     }
   };
@@ -192,28 +199,36 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
 #pragma unroll
     for (int ks = 0; ks < kGBK / 16; ++ks) {
       const int kc = ks * 16 + 8 * (lane >> 5);
-      bf16x8 bn[2], bnl[2];
+      bf16x8 bn[2], bnl[2], am[4], aml[4];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         bn[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB][wn * 64 + b * 32 + (lane & 31)][kc]);
         if constexpr (X3)
           bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
       }
-      // one row block's operands at a time keeps the live fragments few
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm[buf][bA][wm * 128 + a * 32 + (lane & 31)][kc]);
-        bf16x8 aml;
+        am[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][bA][wm * 128 + a * 32 + (lane & 31)][kc]);
         if constexpr (X3)
-          aml = *reinterpret_cast<const bf16x8*>(&sm[buf][bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
+          aml[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
+      }
+      // each sweep issues 8 MFMAs on 8 different accumulators, so no MFMA waits
+      // for the one before it
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bn[b], acc[a][b], 0, 0, 0);
-          if constexpr (X3) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bnl[b], acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml, bn[b], acc[a][b], 0, 0, 0);
-          }
-        }
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bn[b], acc[a][b], 0, 0, 0);
+      if constexpr (X3) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bnl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml[a], bn[b], acc[a][b], 0, 0, 0);
       }
     }
     // the other buffer was last read before the previous barrier
@@ -439,17 +454,25 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K,
         bh[b] = *reinterpret_cast<const bf16x8*>(&sm[1][wn * 64 + b * 32 + (lane & 31)][kcol]);
         bl[b] = *reinterpret_cast<const bf16x8*>(&sm[3][wn * 64 + b * 32 + (lane & 31)][kcol]);
       }
+      bf16x8 ah[2], al[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm[0][wm * 64 + a * 32 + (lane & 31)][kcol]);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm[2][wm * 64 + a * 32 + (lane & 31)][kcol]);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
-        }
+        ah[a] = *reinterpret_cast<const bf16x8*>(&sm[0][wm * 64 + a * 32 + (lane & 31)][kcol]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&sm[2][wm * 64 + a * 32 + (lane & 31)][kcol]);
       }
+      // sweeps over the 4 accumulators: no MFMA waits for the one before it
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -823,12 +846,13 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
   }
   const int64_t nt = (M + kGT - 1) / kGT;
   const int64_t grid = super_grid(nt);
-  if (mode == SW_GRAM_BF16X3)
+  if (mode == SW_GRAM_BF16X3) {
     hipLaunchKernelGGL(k_gram_bf16<true>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
                        (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
-  else
+  } else {
     hipLaunchKernelGGL(k_gram_bf16<false>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
                        (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
+  }
   return hipGetLastError();
 }
 

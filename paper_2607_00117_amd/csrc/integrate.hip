@@ -135,6 +135,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_sparse_lanes = value;
     return SW_OK;
   }
+  if (k == "multi_dense") {
+    SW_CHECK(value >= 0 && value <= 2, "sw_set_tuning: multi_dense: 0 (by cost), 1 (dense MFMA), 2 (compressed)");
+    g_multi_dense = value;
+    return SW_OK;
+  }
   if (k == "refine_passes") {
     SW_CHECK(value == 2 || value == 4, "sw_set_tuning: refine_passes: 2 (h carried) or 4 (residual from A)");
     g_refine_two = value == 2 ? 1 : 0;
@@ -172,6 +177,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "factor_gemm") return g_factor_x3;
   if (k == "gram_skip") return g_gram_dense ? 0 : 1;
   if (k == "refine_passes") return g_refine_two ? 2 : 4;
+  if (k == "multi_dense") return g_multi_dense;
   return -1;
 }
 

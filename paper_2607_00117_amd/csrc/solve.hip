@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "gemm.h"
@@ -51,7 +52,8 @@ constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
 constexpr int kAAMem = 10;          // Anderson acceleration: iterations kept in the history
 constexpr int kAAThreads = 256, kAAPer = 4, kAAChunk = kAAThreads * kAAPer;  // AA passes: orbits per workgroup
 constexpr int kAADots = 2 * kAAMem + 1;
-constexpr int kAAComp = 4;  // history components: x, z, u (mixed and fitted) and h = U^T U x (mixed only)
+constexpr int kAAComp = 4;
+constexpr int kDenseChunks = 16;  // dense passes of a shared matrix: at most this many K chunks  // history components: x, z, u (mixed and fitted) and h = U^T U x (mixed only)
 constexpr double kAARestart = 10.0;  // history cleared when the residual exceeds this many times its minimum
 constexpr int kStallChecks = 10;    // stage 1 stalls when max(primal, dual) residual has not
 constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChecks checks earlier
@@ -59,6 +61,7 @@ constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChe
 int g_sparse_rows = 0;
 int g_gram_dense = 0;
 int g_refine_two = 1;
+int g_multi_dense = 0;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
 int g_rhs_group = 0;
@@ -83,7 +86,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // X[n][xoff_b + j] = w~_b A[off_b + p_j][n] / sigma_b,n (zero-padded, masked
 // orbits zero): constraint-major operand of the Gram, its columns in the orbit
-// order p = perm[off_b ..] (the rows' order when perm is null).  64 x 64 LDS tiles.
+// order p = perm[off_b ..] (the rows' order when perm is null), row-major (fp32)
+// or stage-blocked (bf16 pair, gram_at).  64 x 64 LDS tiles.
 // ---------------------------------------------------------------------------
 template <typename TA>
 __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_t C, int64_t Npt,
@@ -112,10 +116,10 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
   for (int r = ty; r < 64; r += 4) {
     const int64_t n = n0 + r, col = c0 + tx;
     const float v = tile[tx][r];
-    const int64_t at = n * Npt + col;
     if (mode == SW_GRAM_F32) {
-      xf[at] = v;
+      xf[n * Npt + col] = v;
     } else {
+      const int64_t at = gram_at(n, col, Npt);
       const __bf16 h = (__bf16)v;
       hi[at] = h;
       if (mode == SW_GRAM_BF16X3) lo[at] = (__bf16)(v - (float)h);
@@ -124,31 +128,109 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
 }
 
 // ---------------------------------------------------------------------------
+// Dense passes of one shared matrix over all right-hand sides on FP64 MFMA
+// (v_mfma_f64_16x16x4): out[m][z][n] = sum over k in chunk z of V[m][k] B(k, n),
+//   column sums  V = the orbit vectors [P][n_a] (k = orbit), B(k, n) = A[k][n];
+//   row dots     V = the scaled constraint vectors [P][Cp] (k = constraint),
+//                B(k, n) = A[n][k] (TRANSB).
+// Used when the matrix is dense enough that streaming it once per pass for all
+// right-hand sides beats the compressed passes, which read it once per group of
+// a few (the fit matrices with Gauss-Hermite blocks).  A 256-thread workgroup
+// owns a 64 x 64 output tile (four waves of 32 x 32 = 2 x 2 MFMA blocks) and one
+// chunk of K, staged through LDS 32 at a time; the chunks' partials are summed
+// in order by the reductions of the compressed passes.
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kDT = 64, kDK = 32;
+
+template <typename TV, typename TA, bool TRANSB>
+__global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_t K, const TV* __restrict__ V,
+                                                   int64_t ldv, const TA* __restrict__ A, int64_t lda, int64_t kc,
+                                                   double* __restrict__ out, int64_t ldo, int64_t so) {
+  __shared__ double Vs[kDT][kDK + 1];  // [m][k]
+  __shared__ double Bs[kDK][kDT + 1];  // [k][n]
+  const int64_t m0 = (int64_t)blockIdx.y * kDT, n0 = (int64_t)blockIdx.x * kDT;
+  const int64_t k_beg = (int64_t)blockIdx.z * kc;
+  const int64_t k_end = k_beg + kc < K ? k_beg + kc : K;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kDK) {
+#pragma unroll
+    for (int q = 0; q < kDT * kDK / 256; ++q) {
+      const int e = tid + 256 * q;
+      {  // V: k fastest
+        const int mm = e / kDK, kk = e % kDK;
+        const int64_t m = m0 + mm, k = k0 + kk;
+        Vs[mm][kk] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
+      }
+      if (TRANSB) {  // A[n][k]: k fastest
+        const int nn = e / kDK, kk = e % kDK;
+        const int64_t n = n0 + nn, k = k0 + kk;
+        Bs[kk][nn] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
+      } else {  // A[k][n]: n fastest
+        const int kk = e / kDT, nn = e % kDT;
+        const int64_t n = n0 + nn, k = k0 + kk;
+        Bs[kk][nn] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kDK; ks += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Vs[wm * 32 + a * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  out += (int64_t)blockIdx.z * so;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f64 16x16 output: element r of lane l is row 4 r + l / 16, column l % 16
+        const int64_t m = m0 + wm * 32 + a * 16 + 4 * r + (lane >> 4);
+        const int64_t n = n0 + wn * 32 + b * 16 + (lane & 15);
+        if (m < M && n < Nn) out[m * ldo + n] = acc[a][b][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Zero-panel bits of the Gram operand: bit g of nz[t * nzw + g / 64] is set when
-// rows [256 t, 256 t + 256) of X (the hi plane) hold a nonzero in columns
-// [32 g, 32 g + 32).  Workgroup (word, tile): 256 threads each scan 8 columns of
-// every row of the tile; four threads make a 32-column stage.
+// rows [256 t, 256 t + 256) of X (the hi plane, stage-blocked) hold a nonzero in
+// columns [32 g, 32 g + 32).  Workgroup (word, tile): each of the 4 waves scans
+// 16 of the word's 64 stage blocks, one 16 KB block at a time.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_nz_bits(const __bf16* __restrict__ hi, int64_t Npt, int64_t nzw,
                                                  uint64_t* __restrict__ nz) {
   __shared__ uint32_t part[4];
   const int64_t wd = blockIdx.x, t = blockIdx.y;
-  const int64_t col = wd * 2048 + 8 * (int64_t)threadIdx.x;
-  uint32_t any = 0;
-  if (col < Npt) {
-    const __bf16* p = hi + t * 256 * Npt + col;
-    for (int r = 0; r < 256; ++r) {
-      const uint4 v = *reinterpret_cast<const uint4*>(p + (int64_t)r * Npt);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t bits = 0;
+  for (int i = 0; i < 16; ++i) {
+    const int64_t g = wd * 64 + w * 16 + i;
+    if (g * 32 >= Npt) break;
+    const uint4* p = reinterpret_cast<const uint4*>(hi + gram_at(t * 256, g * 32, Npt));
+    uint32_t any = 0;
+    for (int j = 0; j < 16; ++j) {
+      const uint4 v = p[lane + 64 * j];
       any |= (v.x | v.y | v.z | v.w) & 0x7fff7fffu;
     }
+    if (__ballot(any != 0)) bits |= 1u << i;
   }
-  uint32_t f = any != 0 ? 1u : 0u;
-  f |= __shfl_xor(f, 1);
-  f |= __shfl_xor(f, 2);
-  const uint64_t bal = __ballot(f != 0 && (threadIdx.x & 3) == 0);
-  uint32_t bits = 0;
-  for (int i = 0; i < 16; ++i) bits |= (uint32_t)((bal >> (4 * i)) & 1u) << i;
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = bits;
+  if (lane == 0) part[w] = bits;
   __syncthreads();
   if (threadIdx.x == 0)
     nz[t * nzw + wd] = (uint64_t)part[0] | ((uint64_t)part[1] << 16) | ((uint64_t)part[2] << 32) |
@@ -1482,7 +1564,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_cptr = take(PA * L.nrb * (L.C + 1) * 8);
   L.off_crow = take((size_t)L.cap_nnz * 2);
   L.off_cval = take((size_t)L.cap_nnz * 8);
-  L.off_pd = take(L.rg > 1 ? (size_t)P * L.ncb * NA * 8 : 0);
+  L.off_pd = take(shared ? (size_t)P * std::max<int64_t>(L.ncb, kDenseChunks) * NA * 8 : 0);
   L.off_tiles = take(NA * 5 * 8);
   L.off_perm = take(NA * 4);
   L.total = o;
@@ -1493,6 +1575,8 @@ struct Ctx {
   SolveLayout L;
   bool sparse = false;
   const int32_t* perm = nullptr;  // orbit order of the Gram operand's columns (null: the rows' order)
+  bool dense_rhs = false;          // shared matrix: FP64 passes as dense MFMA products over all right-hand sides
+  int dcs = 1, drd = 1;            // dense passes: K chunks of the column sums (orbits) and of the row dots
   int64_t nnz = 0;
   char* ws;
   hipStream_t st;
@@ -1529,6 +1613,19 @@ static void colsum_rhs(const Ctx& X, const TV* v) {
 
 template <typename TV>
 static hipError_t colsum(const Ctx& X, const TV* v) {
+  if (X.dense_rhs) {
+    // chunk z of the orbits writes slab z of the partials (X.dcs chunks)
+    const int64_t n_a = X.L.NA, kc = (n_a + X.dcs - 1) / X.dcs;
+    const dim3 grid((unsigned)((X.L.C + kDT - 1) / kDT), (unsigned)((X.L.P + kDT - 1) / kDT), (unsigned)X.dcs);
+    if (X.dtype == SW_F32)
+      hipLaunchKernelGGL((k_dgemm_rhs<TV, float, false>), grid, dim3(256), 0, X.st, (int64_t)X.L.P, X.L.C, n_a, v,
+                         n_a, (const float*)X.A, X.L.C, kc, X.p<double>(X.L.off_part), (int64_t)kSlabs * X.L.C, X.L.C);
+    else
+      hipLaunchKernelGGL((k_dgemm_rhs<TV, double, false>), grid, dim3(256), 0, X.st, (int64_t)X.L.P, X.L.C, n_a, v,
+                         n_a, (const double*)X.A, X.L.C, kc, X.p<double>(X.L.off_part), (int64_t)kSlabs * X.L.C,
+                         X.L.C);
+    return hipGetLastError();
+  }
   if (X.sparse && X.L.rg > 1) {
     if (X.dtype == SW_F32) colsum_rhs<float, TV>(X, v);
     else colsum_rhs<double, TV>(X, v);
@@ -1564,7 +1661,7 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
 
 static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
   hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
-                     X.p<double>(X.L.off_part), X.sparse ? (X.L.rg > 1 ? X.L.nrb_a : 1) : kSlabs, X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
+                     X.p<double>(X.L.off_part), X.dense_rhs ? X.dcs : (X.sparse ? (X.L.rg > 1 ? X.L.nrb_a : 1) : kSlabs), X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
                      outd, acc);
   return hipGetLastError();
 }
@@ -1590,6 +1687,17 @@ static void launch_rowdot_rhs(const Ctx& X, const RowArgs& R) {
 template <typename TA>
 static void launch_rowdot(const Ctx& X, const RowArgs& R) {
   const double* sc = X.p<double>(X.L.off_sc);
+  if (X.dense_rhs) {
+    const int64_t n_a = X.L.NA, kc = ((X.L.C + X.drd - 1) / X.drd + kDK - 1) / kDK * kDK;
+    const int nz = (int)((X.L.C + kc - 1) / kc);
+    double* pd = X.p<double>(X.L.off_pd);
+    const dim3 grid((unsigned)((n_a + kDT - 1) / kDT), (unsigned)((X.L.P + kDT - 1) / kDT), (unsigned)nz);
+    hipLaunchKernelGGL((k_dgemm_rhs<double, TA, true>), grid, dim3(256), 0, X.st, (int64_t)X.L.P, n_a, X.L.C, sc, X.L.Cp,
+                       (const TA*)X.A, X.L.C, kc, pd, (int64_t)nz * n_a, n_a);
+    hipLaunchKernelGGL(k_rowdot_fin, dim3(blocks_for(n_a), (unsigned)X.L.P), dim3(256), 0, X.st, nz, (const double*)pd,
+                       R);
+    return;
+  }
   if (X.sparse && X.L.rg > 1) {
     if (X.L.rg == 2) launch_rowdot_rhs<TA, 2>(X, R);
     else if (X.L.rg == 4) launch_rowdot_rhs<TA, 4>(X, R);
@@ -1867,6 +1975,18 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   if (!(opt->flags & SW_SOLVE_DENSE)) {
     const int rs = dtype == SW_F32 ? build_sparse<float>(X) : build_sparse<double>(X);
     if (rs != SW_OK) return rs;
+  }
+  if (shared && P >= 2 && g_multi_dense != 2) {
+    // right-hand sides of one matrix: the passes as dense FP64 MFMA products read A
+    // once for all of them (2 P C N flop at ~30 TFLOP/s); the compressed passes read
+    // it once per group of rg (6 B per stored entry at ~3 TB/s)
+    const double dense_t = 2.0 * P * (double)L.C * (double)L.NA / 30e12;
+    const double comp_t = X.sparse ? (double)((P + L.rg - 1) / L.rg) * 6.0 * (double)X.nnz / 3e12 : 1e300;
+    X.dense_rhs = g_multi_dense == 1 || dense_t < comp_t;
+    const int64_t pt = (P + kDT - 1) / kDT;
+    const int64_t ct = (L.C + kDT - 1) / kDT * pt, rt = (L.NA + kDT - 1) / kDT * pt;
+    X.dcs = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSlabs, 2048 / ct, L.NA / 256}));
+    X.drd = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kDenseChunks, 2048 / rt, L.C / 128}));
   }
   {
     dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
@@ -2209,7 +2329,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     R[b].objective = obj[b];
     R[b].converged = kkt[b] <= tol_kkt ? 1 : 0;
     R[b].n_active = support[b];
-    R[b].nnz = X.sparse ? (double)X.nnz : 0.0;
+    R[b].nnz = X.sparse && !X.dense_rhs ? (double)X.nnz : 0.0;
     all_conv &= R[b].converged;
   }
   hipLaunchKernelGGL(k_scale_out, dim3(blocks_for(L.N)), dim3(256), 0, X.st, zd, L.N, X.off_d, P, X.par, w);

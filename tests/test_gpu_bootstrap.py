@@ -55,11 +55,24 @@ def test_bootstrap_data_bit_exact(gpu):
     assert np.array_equal(out.cpu().numpy(), BS.bootstrap_data(d, sig, eps, cb, C))
 
 
-def test_multi_rhs_matches_oracle_per_realisation(gpu):
-    """Six realisations on one sparse log-normal matrix with a ragged orbit count."""
+@pytest.fixture(params=[1, 2], ids=["dense_mfma_passes", "compressed_passes"])
+def multi_dense(request):
+    """The passes of the shared-matrix solve as dense FP64 MFMA products over all
+    data vectors, or as compressed passes per group of vectors."""
+    P = lib()
+    old = P.get_tuning("multi_dense")
+    P.set_tuning("multi_dense", request.param)
+    yield request.param
+    P.set_tuning("multi_dense", old)
+
+
+@pytest.mark.parametrize("density", [0.1, 0.5])
+def test_multi_rhs_matches_oracle_per_realisation(gpu, multi_dense, density):
+    """Six realisations on one sparse log-normal matrix with a ragged orbit count,
+    at 10% and 50% density, with either kind of pass."""
     n, c, cb = 1501, 600, 200
     blocks = [(0, cb), (cb, c)]
-    A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=6)
+    A = W.sparse_lognormal_matrix(n, blocks, density=density, seed=6)
     d, sig, wt = mock_problem(A, blocks, 4, 0.02, 0.02)
     D = BS.bootstrap_data(d, sig, W.bootstrap_eps(6, c, seed=1), cb, c)
     w_g, status, reps = multi_solve(A, D, sig, wt)

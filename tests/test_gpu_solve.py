@@ -387,3 +387,4 @@ def test_two_pass_iterations_match_four(gpu, flags):
         assert status == 0, passes
         assert np.abs(w - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL, passes
     assert np.abs(out[2][0] - out[4][0]).sum() <= 1e-4 * np.abs(out[4][0]).sum()
+
