@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate", "paper"])
     ap.add_argument("--bs23-steps", type=int, default=0, help="paper: accepted BS23 steps (0: the paper's 5,000)")
+    ap.add_argument("--bs23-precision", default="f32", choices=["f32", "f64"],
+                    help="paper: arithmetic of the BS23 integration (the drift check is FP64 either way)")
     ap.add_argument("--n-train", type=int, default=20000, help="surrogate: training builds")
     ap.add_argument("--mcmc-steps", type=int, default=200, help="surrogate: DA-MCMC steps per walker")
     ap.add_argument("--gram", default="bf16x3", choices=["bf16", "bf16x3", "f32"])
@@ -642,6 +644,10 @@ def bench_walkers(args):
 # FSAL, the stage combinations and the error norm, 6 x 27 + 30)
 FLOP_PER_FORCE_F64 = 63 + 14 + 32 * 28 + 12 + 22 + 27
 FLOP_PER_BS23_STEP = 3 * FLOP_PER_FORCE_F64 + 6 * 27 + 30
+# the single-precision force: the 16-node rule (Ferrers 537 as counted for the
+# leapfrog integrator, MN 22, NFW_q 27)
+FLOP_PER_FORCE_F32 = 537 + 22 + 27
+FLOP_PER_BS23_STEP_F32 = 3 * FLOP_PER_FORCE_F32 + 6 * 27 + 30
 
 
 def paper_maps(raw, cfg, n_ap, kin0, surf0):
@@ -737,7 +743,7 @@ def paper_oracle_leg(cfg, run, n_bundles=16):
         mom_o, ic_o = O.jeans_ics(pot, pos, eps, cfg["h_R"], cfg["h_z"], cfg["jeans_b"])
         ics_o = OI.dither(ic_o, mom_o[4], u, cfg["dx"], cfg["fv"])
         h0 = np.full(ics_o.shape[1], cfg["h0"])
-        A_o, _, _, _ = O.integrate_bs23_and_bin(pot, ob, ics_o, h0, S, cfg["rtol"], cfg["atol"], nthreads=threads)
+        A_o, _, dr_o, _ = O.integrate_bs23_and_bin(pot, ob, ics_o, h0, S, cfg["rtol"], cfg["atol"], nthreads=threads)
         Ab_o = OI.bundle_rows(A_o, nd)
         # the sample's own mock (the same recipe: a 10% subset with Exp(1) weights)
         w_s = W.mock_draw(n_bundles, cfg["mock"]["seed"])
@@ -772,11 +778,16 @@ def paper_oracle_leg(cfg, run, n_bundles=16):
     fl = torch.empty(n, dtype=torch.uint8, device=dev)
     ws = torch.empty(P.integrate_bs23_workspace_bytes(n, S), dtype=torch.uint8, device=dev)
     P.integrate_bs23_and_bin(run["pot"], torch.from_numpy(ics_o).to(dev), torch.from_numpy(h0).to(dev), S,
-                             cfg["rtol"], cfg["atol"], run["obs"], A, ov, dr, fl, ws)
+                             cfg["rtol"], cfg["atol"], run["obs"], A, ov, dr, fl, ws, precision=run["prec"])
     torch.cuda.synchronize()
-    l1 = np.abs(A.cpu().numpy() - A_o).sum(1) / 2
-    errors["bs23_rows"] = {"orbits": n, "row_l1_median": float(np.median(l1)), "row_l1_p90": float(np.percentile(l1, 90)),
-                           "rows_above_1e-6": float(np.mean(l1 > 1e-6))}
+    Ag = A.cpu().numpy()
+    l1 = np.abs(Ag - A_o).sum(1) / 2
+    drg = dr.cpu().numpy()
+    errors["bs23_rows"] = {"orbits": n, "precision": "f32" if run["prec"] == P.SW_F32 else "f64",
+                           "row_l1_median": float(np.median(l1)), "row_l1_p90": float(np.percentile(l1, 90)),
+                           "rows_above_1e-6": float(np.mean(l1 > 1e-6)),
+                           "summed_maps_l1": float(np.abs(Ag.sum(0) - A_o.sum(0)).sum() / np.abs(A_o.sum(0)).sum()),
+                           "drift_median": float(np.median(drg)), "drift_median_oracle": float(np.median(dr_o))}
     # the fit matrix from the oracle's bundle rows
     Ab = torch.from_numpy(Ab_o).to(dev)
     F = torch.empty(F_o.shape, dtype=torch.float64, device=dev)
@@ -856,6 +867,9 @@ def bench_paper(args):
     B = cfg["n_boot"]
     opts = P._lib.SolveOpts()
     opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
+    if args.rho is not None:
+        opts.rho = -args.rho
+    prec = P.SW_F32 if args.bs23_precision == "f32" else P.SW_F64
 
     def build():
         """The orbit library's part of a model: returns the stage events."""
@@ -864,7 +878,8 @@ def bench_paper(args):
         P.jeans_ics(pot, pos_t, eps_t, cfg["h_R"], cfg["h_z"], cfg["jeans_b"], mom, ic1)
         P.dither_ics(ic1, mom[4].contiguous(), u_t, cfg["dx"], cfg["fv"], ics)
         ev[1].record()
-        P.integrate_bs23_and_bin(pot, ics, h0, S, cfg["rtol"], cfg["atol"], obs, A, ov, dr, fl, bws)
+        P.integrate_bs23_and_bin(pot, ics, h0, S, cfg["rtol"], cfg["atol"], obs, A, ov, dr, fl, bws,
+                                 precision=prec)
         ev[2].record()
         P.bundle_rows(A, nd, A_b)
         P.cell_masses(pot, obs, cfg["stellar_mask"], cfg["n_sub"], m_star)
@@ -916,16 +931,21 @@ def bench_paper(args):
     ms = 1e3 * el / args.steps
     st_ms = {k: float(np.mean([r["ms"][k] for r in res])) for k in res[0]["ms"]}
     t_b = st_ms["bs23"]
-    work = FLOP_PER_BS23_STEP * n * S
-    roof = {"kernel": "k_bs23 + k_hist_w", "bound": "alu", "unit": "TFLOP/s", "peak": PEAK_F64_VALU / 1e12,
+    f32 = args.bs23_precision == "f32"
+    per = FLOP_PER_BS23_STEP_F32 if f32 else FLOP_PER_BS23_STEP
+    work = per * n * S
+    roof = {"kernel": "k_bs23 + k_hist_w", "bound": "alu", "unit": "TFLOP/s",
+            "peak": (PEAK_F32_VALU if f32 else PEAK_F64_VALU) / 1e12,
             "work": float(work), "ms": t_b, "achieved": round(work / (t_b * 1e-3) / 1e12, 3),
-            "work_rule": f"{FLOP_PER_BS23_STEP} FP64 flop per accepted step (three force evaluations) x orbit-steps",
+            "work_rule": f"{per} {'FP32' if f32 else 'FP64'} flop per accepted step (three force evaluations) "
+                         f"x orbit-steps",
             "traffic": None, "stage": "bs23"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     out = {"metric": METRIC, "value": n * S * args.steps / el, "unit": "orbit-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": cfg["name"] if S == cfg["n_steps"] else cfg["name"].replace("5k", f"{S}"),
+           "scaling": "weak", "vs_baseline": None, "dtype": args.bs23_precision, "data": "synthetic",
+           "config": {"workload": (cfg["name"] if S == cfg["n_steps"] else cfg["name"].replace("5k", f"{S}")).replace(
+                          "_f64", "_" + args.bs23_precision),
                       "n_orbits": n, "n_bundles": n_ic, "n_steps": S, "rtol": cfg["rtol"], "n_apertures": n_ap,
                       "n_binned_constraints": nc, "n_fit_constraints": nf, "n_bootstraps": B},
            "model_builds_per_s": 1e3 / ms, "stage_ms": {k: round(v, 2) for k, v in st_ms.items()},
@@ -933,7 +953,7 @@ def bench_paper(args):
            "context": "the paper quotes about 1.3 s per model (build + 100 bootstrap solves + chi^2) on one A100"}
     if not args.no_cpu_baseline:
         run = dict(P=P, torch=torch, dev=dev, S=S, pos=pos, eps=eps, u=W.dither_deviates(nd, n_ic, seed=cfg["ic_seed"]),
-                   pmap=pmap, n_ap=n_ap, n_mass=n_mass, kin0=kin0, surf0=surf0, pot=pot, obs=obs)
+                   pmap=pmap, n_ap=n_ap, n_mass=n_mass, kin0=kin0, surf0=surf0, pot=pot, obs=obs, prec=prec)
         out["cpu_baseline"], out["errors_vs_oracle"] = paper_oracle_leg(cfg, run)
     print(json.dumps(out))
 

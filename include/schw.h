@@ -401,7 +401,11 @@ int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, i
 
 /* ---------------------------------------------------------------------------
  * integrate_bs23_and_bin (Sec. 2.2.2, Sec. 2.2.4): the orbit library by
- * adaptive Bogacki-Shampine 3(2) steps in FP64 instead of the leapfrog: n_steps
+ * adaptive Bogacki-Shampine 3(2) steps instead of the leapfrog, with the state,
+ * the stages and the step control in `precision` (SW_F64, or SW_F32 with the
+ * leapfrog integrator's single-precision force: the bar's 16-node rule and
+ * hardware reciprocals; the total time is summed and the Jacobi drift
+ * evaluated in FP64 either way): n_steps
  * accepted steps per orbit from the trial step h0[i]; error of a step
  * max_i |y3_i - y2_i| / (atol + rtol max(|y_i|, |y3_i|)) over the six
  * coordinates, accepted when <= 1, next step h min(5, max(0.2, 0.9 err^(-1/3))).
@@ -418,9 +422,9 @@ int bundle_rows(const void* A, int32_t dtype, int64_t n_bundle, int64_t n_con, i
  *   workspace of integrate_bs23_workspace_bytes(n_orb, n_steps) bytes
  *   (24 B per orbit-step: packed cells of both blocks and the step). */
 int integrate_bs23_and_bin(const sw_potential* pot, const double* ics, const double* h0, int64_t n_orb,
-                           int32_t n_steps, double rtol, double atol, const sw_obs_spec* obs, double* A,
-                           double* overflow, double* drift, uint8_t* flags, void* workspace, size_t ws_bytes,
-                           void* stream);
+                           int32_t n_steps, double rtol, double atol, int32_t precision, const sw_obs_spec* obs,
+                           double* A, double* overflow, double* drift, uint8_t* flags, void* workspace,
+                           size_t ws_bytes, void* stream);
 size_t integrate_bs23_workspace_bytes(int64_t n_orb, int32_t n_steps);
 
 /* ---------------------------------------------------------------------------

@@ -120,7 +120,7 @@ def load():
     L.jeans_ics.argtypes = [C.POINTER(Potential), vp, vp, i64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
     L.dither_ics.argtypes = [vp, vp, vp, i64, i32, C.c_double, C.c_double, vp, vp]
     L.bundle_rows.argtypes = [vp, i32, i64, i64, i32, vp, vp]
-    L.integrate_bs23_and_bin.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, C.c_double, C.c_double,
+    L.integrate_bs23_and_bin.argtypes = [C.POINTER(Potential), vp, vp, i64, i32, C.c_double, C.c_double, i32,
                                          C.POINTER(ObsSpec), vp, vp, vp, vp, vp, sz, vp]
     L.integrate_bs23_workspace_bytes.argtypes = [i64, i32]
     L.integrate_bs23_workspace_bytes.restype = sz
@@ -392,11 +392,14 @@ def integrate_bs23_workspace_bytes(n_orb, n_steps):
     return load().integrate_bs23_workspace_bytes(int(n_orb), int(n_steps))
 
 
-def integrate_bs23_and_bin(pot, ics, h0, n_steps, rtol, atol, obs, A, overflow, drift, flags, workspace):
-    """Adaptive BS23 orbits with time-weighted binning (FP64 tensors)."""
+def integrate_bs23_and_bin(pot, ics, h0, n_steps, rtol, atol, obs, A, overflow, drift, flags, workspace,
+                           precision=SW_F64):
+    """Adaptive BS23 orbits with time-weighted binning (FP64 tensors; the
+    integration in `precision`, SW_F64 or SW_F32)."""
     _check(load().integrate_bs23_and_bin(C.byref(pot), _ptr(ics), _ptr(h0), ics.shape[1], int(n_steps), float(rtol),
-                                         float(atol), C.byref(obs), _ptr(A), _ptr(overflow), _ptr(drift), _ptr(flags),
-                                         _ptr(workspace), workspace.numel() * workspace.element_size(), _stream()))
+                                         float(atol), int(precision), C.byref(obs), _ptr(A), _ptr(overflow),
+                                         _ptr(drift), _ptr(flags), _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(), _stream()))
 
 
 def integrate_orbits(pot, ics, dt, n_steps, out):

@@ -3,7 +3,10 @@
 // after accepted step k weighs dt_k / t_total), in FP64.
 //
 // Two kernels:
-//  1. k_bs23: one orbit per lane.  Equations of motion in the bar frame for
+//  1. k_bs23: one orbit per lane, in double or in single precision (the
+//     single-precision force is the leapfrog integrator's: the bar's 16-node
+//     rule, hardware reciprocals); the total time is summed and the Jacobi
+//     drift evaluated in double either way.  Equations of motion in the bar frame for
 //     (x, p), p the inertial velocity on the rotating axes:
 //       dx/dt = p + Omega (y, -x, 0),  dp/dt = -grad Phi + Omega (p_y, -p_x, 0).
 //     Per attempt: stages k2 = f(y + h/2 k1), k3 = f(y + 3h/4 k2), the third-order
@@ -48,7 +51,44 @@ __device__ __forceinline__ void bs_rhs(const PotK& P, const double* y, double* f
   f[5] = g[2];
 }
 
-template <bool NB, bool CYL>
+// single precision: the bar's 16-node rule with hardware reciprocals, lam warm
+// started from the previous evaluation (as the leapfrog integrator does)
+template <bool NB>
+__device__ __forceinline__ void bs_rhs(const PotK& P, const float* y, float* f, float& lamw) {
+  float g[3], gb[3];
+  accel_f32<1, NB>(P, y[0], y[1], y[2], g[0], g[1], g[2], gb, lamw, 0);
+  const float W = (float)P.omega;
+  f[0] = y[3] + W * y[1];
+  f[1] = y[4] - W * y[0];
+  f[2] = y[5];
+  f[3] = (g[0] + gb[0]) + W * y[4];
+  f[4] = (g[1] + gb[1]) - W * y[3];
+  f[5] = g[2] + gb[2];
+}
+
+template <bool NB>
+__device__ __forceinline__ void bs_rhs(const PotK& P, const double* y, double* f, float&) {
+  bs_rhs<NB>(P, y, f);
+}
+
+template <bool NB>
+__device__ __forceinline__ double bs_jacobi(const PotK& P, const double* y, float) {
+  return jacobi_f64<NB>(P, y);
+}
+
+template <bool NB>
+__device__ __forceinline__ double bs_jacobi(const PotK& P, const float* y, float lamw) {
+  double yd[6];
+  for (int i = 0; i < 6; ++i) yd[i] = (double)y[i];
+  return jacobi_f64_drift<NB>(P, yd, lamw);
+}
+
+__device__ __forceinline__ double bs_pow(double e) { return pow(e, -1.0 / 3.0); }
+__device__ __forceinline__ float bs_pow(float e) { return powf(e, -1.0f / 3.0f); }
+
+// T: the arithmetic of the state, the stages and the step control (the total
+// time is summed in double, the Jacobi drift evaluated in double)
+template <typename T, bool NB, bool CYL>
 __global__ __launch_bounds__(64) void k_bs23(PotK P, ObsK O, const double* __restrict__ ics,
                                               const double* __restrict__ h0, int64_t n, int32_t S, double rtol,
                                               double atol, uint64_t* __restrict__ ev_m, uint64_t* __restrict__ ev_k,
@@ -57,34 +97,38 @@ __global__ __launch_bounds__(64) void k_bs23(PotK P, ObsK O, const double* __res
 #pragma clang fp contract(off)
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= n) return;
-  double y[6], k1[6];
-  for (int i = 0; i < 6; ++i) y[i] = ics[(int64_t)i * n + o];
-  double h = h0[o], tt = 0.0, dmax = 0.0;
-  const double E0 = jacobi_f64<NB>(P, y);
+  T y[6], k1[6];
+  for (int i = 0; i < 6; ++i) y[i] = (T)ics[(int64_t)i * n + o];
+  const T rt = (T)rtol, at = (T)atol;
+  T h = (T)h0[o];
+  double tt = 0.0, dmax = 0.0;
+  float lamw = -1.0f;
   bool bad = false;
-  bs_rhs<NB>(P, y, k1);
+  bs_rhs<NB>(P, y, k1, lamw);
+  const double E0 = bs_jacobi<NB>(P, y, lamw);
   for (int s = 0; s < S; ++s) {
-    double dt = 0.0;
+    T dt = (T)0;
     for (int tries = 0; tries < 100; ++tries) {
-      const double hh = h;
-      double t[6], k2[6], k3[6], y3[6], k4[6];
-      for (int i = 0; i < 6; ++i) t[i] = y[i] + 0.5 * hh * k1[i];
-      bs_rhs<NB>(P, t, k2);
-      for (int i = 0; i < 6; ++i) t[i] = y[i] + 0.75 * hh * k2[i];
-      bs_rhs<NB>(P, t, k3);
+      const T hh = h;
+      T t[6], k2[6], k3[6], y3[6], k4[6];
+      for (int i = 0; i < 6; ++i) t[i] = y[i] + (T)0.5 * hh * k1[i];
+      bs_rhs<NB>(P, t, k2, lamw);
+      for (int i = 0; i < 6; ++i) t[i] = y[i] + (T)0.75 * hh * k2[i];
+      bs_rhs<NB>(P, t, k3, lamw);
       for (int i = 0; i < 6; ++i)
-        y3[i] = y[i] + hh * (2.0 / 9.0 * k1[i] + 1.0 / 3.0 * k2[i] + 4.0 / 9.0 * k3[i]);
-      bs_rhs<NB>(P, y3, k4);
-      double err = 0.0;
+        y3[i] = y[i] + hh * ((T)(2.0 / 9.0) * k1[i] + (T)(1.0 / 3.0) * k2[i] + (T)(4.0 / 9.0) * k3[i]);
+      bs_rhs<NB>(P, y3, k4, lamw);
+      T err = (T)0;
       for (int i = 0; i < 6; ++i) {
-        const double y2 = y[i] + hh * (7.0 / 24.0 * k1[i] + 0.25 * k2[i] + 1.0 / 3.0 * k3[i] + 0.125 * k4[i]);
-        const double sc = atol + rtol * fmax(fabs(y[i]), fabs(y3[i]));
+        const T y2 = y[i] + hh * ((T)(7.0 / 24.0) * k1[i] + (T)0.25 * k2[i] + (T)(1.0 / 3.0) * k3[i] +
+                                  (T)0.125 * k4[i]);
+        const T sc = at + rt * fmax(fabs(y[i]), fabs(y3[i]));
         err = fmax(err, fabs(y3[i] - y2) / sc);
       }
-      double fac = err > 0.0 ? 0.9 * pow(err, -1.0 / 3.0) : 5.0;
-      fac = fmin(5.0, fmax(0.2, fac));
+      T fac = err > (T)0 ? (T)0.9 * bs_pow(err) : (T)5;
+      fac = fmin((T)5, fmax((T)0.2, fac));
       h = hh * fac;
-      if (err <= 1.0) {
+      if (err <= (T)1) {
         for (int i = 0; i < 6; ++i) {
           y[i] = y3[i];
           k1[i] = k4[i];
@@ -93,12 +137,12 @@ __global__ __launch_bounds__(64) void k_bs23(PotK P, ObsK O, const double* __res
         break;
       }
     }
-    if (dt == 0.0) bad = true;
+    if (dt == (T)0) bad = true;
     for (int i = 0; i < 6; ++i)
       if (!isfinite(y[i])) bad = true;
-    tt += dt;
+    tt += (double)dt;
     int mc[4], kc[4];
-    cells4<double, CYL>(P, O, y, mc, kc);
+    cells4<T, CYL>(P, O, y, mc, kc);
     uint64_t vm = 0, vk = 0;
     for (int c = 0; c < 4; ++c) {
       vm |= (uint64_t)(uint16_t)(mc[c] < 0 ? 0xFFFF : mc[c]) << (16 * c);
@@ -107,9 +151,9 @@ __global__ __launch_bounds__(64) void k_bs23(PotK P, ObsK O, const double* __res
     const int64_t e = o * S + s;
     ev_m[e] = vm;
     ev_k[e] = vk;
-    wts[e] = dt;
+    wts[e] = (double)dt;
     if (O.drift_every > 0 && (s + 1) % O.drift_every == 0) {
-      const double d = fabs(jacobi_f64<NB>(P, y) / E0 - 1.0);
+      const double d = fabs(bs_jacobi<NB>(P, y, lamw) / E0 - 1.0);
       if (!(d <= dmax)) dmax = d;
     }
   }
@@ -181,10 +225,11 @@ extern "C" size_t integrate_bs23_workspace_bytes(int64_t n_orb, int32_t n_steps)
 }
 
 extern "C" int integrate_bs23_and_bin(const sw_potential* pot, const double* ics, const double* h0, int64_t n_orb,
-                                      int32_t n_steps, double rtol, double atol, const sw_obs_spec* obs, double* A,
-                                      double* overflow, double* drift, uint8_t* flags, void* workspace,
-                                      size_t ws_bytes, void* stream) {
+                                      int32_t n_steps, double rtol, double atol, int32_t precision,
+                                      const sw_obs_spec* obs, double* A, double* overflow, double* drift,
+                                      uint8_t* flags, void* workspace, size_t ws_bytes, void* stream) {
   SW_CHECK(pot && obs, "integrate_bs23_and_bin: null argument");
+  SW_CHECK(precision == SW_F32 || precision == SW_F64, "integrate_bs23_and_bin: precision must be SW_F32 or SW_F64");
   SW_CHECK(n_orb >= 0 && n_orb <= 0x7fffffffLL && n_steps >= 1,
            "integrate_bs23_and_bin: need n_orb >= 0 and n_steps >= 1");
   SW_CHECK(std::isfinite(rtol) && rtol > 0.0 && std::isfinite(atol) && atol > 0.0,
@@ -206,21 +251,27 @@ extern "C" int integrate_bs23_and_bin(const sw_potential* pot, const double* ics
   double* ttot = (double*)(ws + 3 * per);
   hipStream_t st = (hipStream_t)stream;
   const dim3 grid((unsigned)((n_orb + 63) / 64)), block(64);
-  if (O.cyl) {
-    if (nb)
-      hipLaunchKernelGGL((k_bs23<true, true>), grid, block, 0, st, P, O, ics, h0, n_orb, n_steps, rtol, atol, ev_m,
-                         ev_k, wts, ttot, drift, flags);
-    else
-      hipLaunchKernelGGL((k_bs23<false, true>), grid, block, 0, st, P, O, ics, h0, n_orb, n_steps, rtol, atol, ev_m,
-                         ev_k, wts, ttot, drift, flags);
+#define SW_BS23_LAUNCH(T, NB, CYL)                                                                                \
+  hipLaunchKernelGGL((k_bs23<T, NB, CYL>), grid, block, 0, st, P, O, ics, h0, n_orb, n_steps, rtol, atol, ev_m, ev_k, \
+                     wts, ttot, drift, flags)
+  if (precision == SW_F32) {
+    if (O.cyl) {
+      if (nb) SW_BS23_LAUNCH(float, true, true);
+      else SW_BS23_LAUNCH(float, false, true);
+    } else {
+      if (nb) SW_BS23_LAUNCH(float, true, false);
+      else SW_BS23_LAUNCH(float, false, false);
+    }
   } else {
-    if (nb)
-      hipLaunchKernelGGL((k_bs23<true, false>), grid, block, 0, st, P, O, ics, h0, n_orb, n_steps, rtol, atol, ev_m,
-                         ev_k, wts, ttot, drift, flags);
-    else
-      hipLaunchKernelGGL((k_bs23<false, false>), grid, block, 0, st, P, O, ics, h0, n_orb, n_steps, rtol, atol, ev_m,
-                         ev_k, wts, ttot, drift, flags);
+    if (O.cyl) {
+      if (nb) SW_BS23_LAUNCH(double, true, true);
+      else SW_BS23_LAUNCH(double, false, true);
+    } else {
+      if (nb) SW_BS23_LAUNCH(double, true, false);
+      else SW_BS23_LAUNCH(double, false, false);
+    }
   }
+#undef SW_BS23_LAUNCH
   SW_HIP(hipGetLastError());
   const int64_t n_con = (int64_t)O.n_mass + O.n_kin + (O.surface ? O.n_ap : 0);
   int rc = hist_w(ev_m, wts, ttot, n_orb, n_steps, O.ncopy, O.n_mass, n_con, 0, A, overflow, 0, st);

@@ -64,9 +64,15 @@ hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb, 
 // The same for P right-hand sides of one S (r, tmp, s: [P] vectors at stride
 // sv): from kTrmmMinRhs of them on, two MFMA passes that read each half of S
 // once for all of them (every right-hand side is computed, act is not read);
-// below that, one matrix-vector pass per right-hand side.
+// below that, one matrix-vector pass per right-hand side.  The MFMA passes split
+// each tile's column range into trmm_parts(n, P) parts when the tiles alone give
+// fewer than kTrmmWorkgroups workgroups; part: trmm_parts(n, P) * P * sv floats
+// for their partial sums (unused when that is 1).
 constexpr int kTrmmMinRhs = 8;
+constexpr int kTrmmWorkgroups = 512;
+constexpr int kTrmmMaxParts = 32;
+int trmm_parts(int64_t n, int P);
 hipError_t inv_apply_rhs(const float* S, int64_t n, int64_t ld, int P, const float* r, float* tmp, float* s,
-                         int64_t sv, const double* act, int act_stride, hipStream_t st);
+                         int64_t sv, const double* act, int act_stride, float* part, hipStream_t st);
 
 }  // namespace sw

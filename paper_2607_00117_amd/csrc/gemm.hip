@@ -742,14 +742,17 @@ __global__ __launch_bounds__(kThreads) void k_trmv(const float* __restrict__ S, 
 // b < P, T = the lower (j <= i) or upper (j >= i) half of S, as an fp32 MFMA
 // product.  A workgroup owns a pair of 128-row tiles of T, tm and ntm-1-tm, so
 // every workgroup streams the same number of entries (the two halves of the
-// triangle it covers add up to ntm + 1 tiles of 128 columns), and an RHS tile of
-// 128 (blockIdx.y).  Entries of the diagonal tiles outside the half are zeroed as
-// they are staged.  4 waves as 2 x 2 blocks of 64 x 64 (MFMA 32x32x2 f32).
+// triangle it covers add up to ntm + 1 tiles of 128 columns), an RHS tile of
+// 128 (blockIdx.y) and part z of nzc (blockIdx.z) of each tile's column range
+// (split in whole 32-column steps), so that small matrices still give enough
+// workgroups; part z of the sums goes to Y + z * sz (nzc == 1: the result).
+// Entries of the diagonal tiles outside the half are zeroed as they are staged.
+// 4 waves as 2 x 2 blocks of 64 x 64 (MFMA 32x32x2 f32).
 // ---------------------------------------------------------------------------
 template <bool LOWER>
 __global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__ S, int64_t n, int64_t ld,
                                                        const float* __restrict__ X, float* __restrict__ Y,
-                                                       int64_t sv, int P) {
+                                                       int64_t sv, int P, int nzc, int64_t sz) {
   __shared__ float Ts[kT][kPadF];
   __shared__ float Xs[kT][kPadF];
   const int64_t ntm = n / kT;
@@ -766,7 +769,10 @@ __global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[a][c][i] = 0.0f;
-    const int64_t kbeg = LOWER ? 0 : tm * kT, kend = LOWER ? (tm + 1) * kT : n;
+    const int64_t k_lo = LOWER ? 0 : tm * kT, k_hi = LOWER ? (tm + 1) * kT : n;
+    const int64_t steps = (k_hi - k_lo) / kBKf, per = (steps + nzc - 1) / nzc;
+    const int64_t kbeg = std::min(k_hi, k_lo + (int64_t)blockIdx.z * per * kBKf);
+    const int64_t kend = std::min(k_hi, kbeg + per * kBKf);
     const float* Tb = S + tm * kT * ld;
     float4 ra[4], rb[4];
     auto gload = [&](int64_t k0) {
@@ -779,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__
                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       }
     };
-    gload(kbeg);
+    if (kbeg < kend) gload(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += kBKf) {
       const bool diag = k0 >= tm * kT && k0 < (tm + 1) * kT;
 #pragma unroll
@@ -825,9 +831,19 @@ __global__ __launch_bounds__(kThreads) void k_trmm_rhs(const float* __restrict__
         for (int i = 0; i < 16; ++i) {
           const int64_t row = tm * kT + wm * 64 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
           const int64_t b = b0 + wn * 64 + c * 32 + (lane & 31);
-          if (b < P) Y[b * sv + row] = acc[a][c][i];
+          if (b < P) Y[blockIdx.z * sz + b * sv + row] = acc[a][c][i];
         }
   }
+}
+
+// Y[b][i] = sum over z < nzc of part[z][b][i], in order (vectors at stride sv).
+__global__ __launch_bounds__(256) void k_trmm_sum(const float* __restrict__ part, int nzc, int64_t sz, int64_t n,
+                                                  int64_t sv, float* __restrict__ Y) {
+  const int64_t b = blockIdx.y, i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float t = 0.0f;
+  for (int z = 0; z < nzc; ++z) t += part[z * sz + b * sv + i];
+  Y[b * sv + i] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,12 +1064,27 @@ hipError_t spd_inverse_factor(float* S, int64_t n, int64_t ld, int64_t sK, float
   return invert_factor(S, n, ld, sK, dinv, sD, nb, tmp, sT, st);
 }
 
+int trmm_parts(int64_t n, int P) {
+  const int64_t wg = (n / kT + 1) / 2 * ((P + kT - 1) / kT);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kTrmmMaxParts, (kTrmmWorkgroups + wg - 1) / wg));
+}
+
 hipError_t inv_apply_rhs(const float* S, int64_t n, int64_t ld, int P, const float* r, float* tmp, float* s,
-                         int64_t sv, const double* act, int act_stride, hipStream_t st) {
+                         int64_t sv, const double* act, int act_stride, float* part, hipStream_t st) {
   if (P < kTrmmMinRhs) return inv_apply(S, n, ld, 0, P, r, tmp, s, sv, act, act_stride, st);
-  const dim3 grid((unsigned)((n / kT + 1) / 2), (unsigned)((P + kT - 1) / kT));
-  hipLaunchKernelGGL(k_trmm_rhs<true>, grid, dim3(kThreads), 0, st, S, n, ld, r, tmp, sv, P);
-  hipLaunchKernelGGL(k_trmm_rhs<false>, grid, dim3(kThreads), 0, st, S, n, ld, tmp, s, sv, P);
+  const int nzc = trmm_parts(n, P);
+  const dim3 grid((unsigned)((n / kT + 1) / 2), (unsigned)((P + kT - 1) / kT), (unsigned)nzc);
+  const int64_t sz = (int64_t)P * sv;
+  if (nzc == 1) {
+    hipLaunchKernelGGL(k_trmm_rhs<true>, grid, dim3(kThreads), 0, st, S, n, ld, r, tmp, sv, P, 1, sz);
+    hipLaunchKernelGGL(k_trmm_rhs<false>, grid, dim3(kThreads), 0, st, S, n, ld, tmp, s, sv, P, 1, sz);
+    return hipGetLastError();
+  }
+  const dim3 sgrid((unsigned)((n + 255) / 256), (unsigned)P);
+  hipLaunchKernelGGL(k_trmm_rhs<true>, grid, dim3(kThreads), 0, st, S, n, ld, r, part, sv, P, nzc, sz);
+  hipLaunchKernelGGL(k_trmm_sum, sgrid, dim3(256), 0, st, (const float*)part, nzc, sz, n, sv, tmp);
+  hipLaunchKernelGGL(k_trmm_rhs<false>, grid, dim3(kThreads), 0, st, S, n, ld, tmp, part, sv, P, nzc, sz);
+  hipLaunchKernelGGL(k_trmm_sum, sgrid, dim3(256), 0, st, (const float*)part, nzc, sz, n, sv, s);
   return hipGetLastError();
 }
 

@@ -136,72 +136,103 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
 // Used when the matrix is dense enough that streaming it once per pass for all
 // right-hand sides beats the compressed passes, which read it once per group of
 // a few (the fit matrices with Gauss-Hermite blocks).  A 256-thread workgroup
-// owns a 64 x 64 output tile (four waves of 32 x 32 = 2 x 2 MFMA blocks) and one
-// chunk of K, staged through LDS 32 at a time; the chunks' partials are summed
-// in order by the reductions of the compressed passes.
+// owns a 128 x 64 output tile (vectors x outputs; four waves of 64 x 32 = 4 x 2
+// MFMA blocks of 16 x 16, so the matrix is read once per pass for up to 128
+// vectors) and one chunk of K.  Both operands are staged through LDS 16 at a
+// time, k-major (rows padded by 128 bytes so that the two halves of a wave's
+// operand read fall in different banks), double-buffered: the next k-step is
+// loaded into registers while the current one is multiplied, one barrier per
+// step.  The chunks' partials are summed in order by the reductions of the
+// compressed passes.
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kDT = 64, kDK = 32;
+constexpr int kDM = 128, kDN = 64, kDK = 16;
+constexpr int kDMP = kDM + 16, kDNP = kDN + 16;
 
 template <typename TV, typename TA, bool TRANSB>
 __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_t K, const TV* __restrict__ V,
                                                    int64_t ldv, const TA* __restrict__ A, int64_t lda, int64_t kc,
                                                    double* __restrict__ out, int64_t ldo, int64_t so) {
-  __shared__ double Vs[kDT][kDK + 1];  // [m][k]
-  __shared__ double Bs[kDK][kDT + 1];  // [k][n]
-  const int64_t m0 = (int64_t)blockIdx.y * kDT, n0 = (int64_t)blockIdx.x * kDT;
+  __shared__ double Vs[2][kDK][kDMP];  // [k][m]
+  __shared__ double Bs[2][kDK][kDNP];  // [k][n]
+  const int64_t m0 = (int64_t)blockIdx.y * kDM, n0 = (int64_t)blockIdx.x * kDN;
   const int64_t k_beg = (int64_t)blockIdx.z * kc;
   const int64_t k_end = k_beg + kc < K ? k_beg + kc : K;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  f64x4 acc[2][2];
+  f64x4 acc[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += kDK) {
+  // staging: V row vm = tid / 2, k offsets vk .. vk + 7; B: TRANSB row (n) bn =
+  // tid / 4, k offsets bk .. bk + 3, else k row tid / 16, n offsets 4 (tid % 16) ..
+  const int vm = tid >> 1, vk = (tid & 1) * 8;
+  const int bq = TRANSB ? (tid >> 2) : (tid >> 4), bo = TRANSB ? (tid & 3) * 4 : (tid & 15) * 4;
+  double rv[8], rb[4];
+  auto gload = [&](int64_t k0) {
+    const int64_t m = m0 + vm;
 #pragma unroll
-    for (int q = 0; q < kDT * kDK / 256; ++q) {
-      const int e = tid + 256 * q;
-      {  // V: k fastest
-        const int mm = e / kDK, kk = e % kDK;
-        const int64_t m = m0 + mm, k = k0 + kk;
-        Vs[mm][kk] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
-      }
-      if (TRANSB) {  // A[n][k]: k fastest
-        const int nn = e / kDK, kk = e % kDK;
-        const int64_t n = n0 + nn, k = k0 + kk;
-        Bs[kk][nn] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
-      } else {  // A[k][n]: n fastest
-        const int kk = e / kDT, nn = e % kDT;
-        const int64_t n = n0 + nn, k = k0 + kk;
-        Bs[kk][nn] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = k0 + vk + j;
+      rv[j] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (TRANSB) {  // A[n][k]
+        const int64_t n = n0 + bq, k = k0 + bo + j;
+        rb[j] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
+      } else {  // A[k][n]
+        const int64_t k = k0 + bq, n = n0 + bo + j;
+        rb[j] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
       }
     }
-    __syncthreads();
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Vs[buf][vk + j][vm] = rv[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (TRANSB) Bs[buf][bo + j][bq] = rb[j];
+      else Bs[buf][bq][bo + j] = rb[j];
+    }
+  };
+  int buf = 0;
+  if (k_beg < k_end) {
+    gload(k_beg);
+    stage(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kDK) {
+    const bool more = k0 + kDK < k_end;
+    if (more) gload(k0 + kDK);
 #pragma unroll
     for (int ks = 0; ks < kDK; ks += 4) {
-      double av[2], bv[2];
+      const int kr = ks + (lane >> 4);
+      double av[4], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Vs[wm * 32 + a * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int a = 0; a < 4; ++a) av[a] = Vs[buf][kr][wm * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr][wn * 32 + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   out += (int64_t)blockIdx.z * so;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // f64 16x16 output: element r of lane l is row 4 r + l / 16, column l % 16
-        const int64_t m = m0 + wm * 32 + a * 16 + 4 * r + (lane >> 4);
+        const int64_t m = m0 + wm * 64 + a * 16 + 4 * r + (lane >> 4);
         const int64_t n = n0 + wn * 32 + b * 16 + (lane & 15);
         if (m < M && n < Nn) out[m * ldo + n] = acc[a][b][r];
       }
@@ -1318,17 +1349,19 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAArgs a, int plain) {
   if (a.par[b * kPar + 5] == 0.0) return;
   const int64_t nb = a.off[b + 1] - a.off[b];
   const int nbx = (int)((nb + kAAChunk - 1) / kAAChunk);
-  __shared__ double ts[kAADots];
-  // the block partials: lane l sums blocks l, l + 64, ..., then a fixed-order wave sum
-  for (int k = 0; k < kAADots; ++k) {
-    double v = 0.0;
-    for (int bx = threadIdx.x; bx < nbx; bx += 64) v += a.part[((int64_t)b * a.nbx + bx) * kAADots + k];
-    v = wave_sum(v);
-    if (threadIdx.x == 0) ts[k] = v;
-  }
-  if (threadIdx.x != 0) return;
+  // the block partials: lane l sums blocks l, l + 64, ..., then a fixed-order
+  // wave sum (all loads issued before the first sum waits on them)
   double t[kAADots];
-  for (int k = 0; k < kAADots; ++k) t[k] = ts[k];
+#pragma unroll
+  for (int k = 0; k < kAADots; ++k) t[k] = 0.0;
+  for (int bx = threadIdx.x; bx < nbx; bx += 64) {
+    const double* pb = a.part + ((int64_t)b * a.nbx + bx) * kAADots;
+#pragma unroll
+    for (int k = 0; k < kAADots; ++k) t[k] += pb[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kAADots; ++k) t[k] = wave_sum(t[k]);
+  if (threadIdx.x != 0) return;
   double* G = a.G + (int64_t)b * kAAMem * kAAMem;
   double* gam = a.gam + (int64_t)b * kAAMem;
   const int64_t it = (int64_t)a.st[b * 4 + 0];
@@ -1459,6 +1492,7 @@ struct SolveLayout {
   size_t off_qd, off_xd, off_zd, off_ud, off_vd, off_rd, off_hd;
   size_t off_kyf, off_r, off_tmp, off_s, off_sc, off_td, off_ys;
   size_t off_par, off_acc, off_idx, off_bad, off_ftmp;
+  size_t off_tpart;  // shared matrix: partial sums of the split multi-vector inverse products
   // Anderson acceleration of the FP64 stage (aa = history length, 0 = off)
   int aa, aa_nbx;
   size_t off_aw, off_awp, off_afp, off_adf, off_ay, off_ag, off_agam, off_ast, off_apart;
@@ -1521,6 +1555,10 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_idx = take((size_t)(P + 1) * 8 * 5);
   L.off_bad = take(64);
   L.off_ftmp = take(PA * inverse_factor_scratch(L.Cp, L.PA) * 4);
+  {
+    const int parts = shared && P >= kTrmmMinRhs ? trmm_parts(L.Cp, P) : 1;
+    L.off_tpart = take(parts > 1 ? (size_t)parts * VP * 4 : 0);
+  }
   {
     int64_t nmax = 1;
     for (int b = 0; b < P; ++b) nmax = std::max<int64_t>(nmax, off[b + 1] - off[b]);
@@ -1616,7 +1654,7 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
   if (X.dense_rhs) {
     // chunk z of the orbits writes slab z of the partials (X.dcs chunks)
     const int64_t n_a = X.L.NA, kc = (n_a + X.dcs - 1) / X.dcs;
-    const dim3 grid((unsigned)((X.L.C + kDT - 1) / kDT), (unsigned)((X.L.P + kDT - 1) / kDT), (unsigned)X.dcs);
+    const dim3 grid((unsigned)((X.L.C + kDN - 1) / kDN), (unsigned)((X.L.P + kDM - 1) / kDM), (unsigned)X.dcs);
     if (X.dtype == SW_F32)
       hipLaunchKernelGGL((k_dgemm_rhs<TV, float, false>), grid, dim3(256), 0, X.st, (int64_t)X.L.P, X.L.C, n_a, v,
                          n_a, (const float*)X.A, X.L.C, kc, X.p<double>(X.L.off_part), (int64_t)kSlabs * X.L.C, X.L.C);
@@ -1691,7 +1729,7 @@ static void launch_rowdot(const Ctx& X, const RowArgs& R) {
     const int64_t n_a = X.L.NA, kc = ((X.L.C + X.drd - 1) / X.drd + kDK - 1) / kDK * kDK;
     const int nz = (int)((X.L.C + kc - 1) / kc);
     double* pd = X.p<double>(X.L.off_pd);
-    const dim3 grid((unsigned)((n_a + kDT - 1) / kDT), (unsigned)((X.L.P + kDT - 1) / kDT), (unsigned)nz);
+    const dim3 grid((unsigned)((n_a + kDN - 1) / kDN), (unsigned)((X.L.P + kDM - 1) / kDM), (unsigned)nz);
     hipLaunchKernelGGL((k_dgemm_rhs<double, TA, true>), grid, dim3(256), 0, X.st, (int64_t)X.L.P, n_a, X.L.C, sc, X.L.Cp,
                        (const TA*)X.A, X.L.C, kc, pd, (int64_t)nz * n_a, n_a);
     hipLaunchKernelGGL(k_rowdot_fin, dim3(blocks_for(n_a), (unsigned)X.L.P), dim3(256), 0, X.st, nz, (const double*)pd,
@@ -1983,8 +2021,8 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     const double dense_t = 2.0 * P * (double)L.C * (double)L.NA / 30e12;
     const double comp_t = X.sparse ? (double)((P + L.rg - 1) / L.rg) * 6.0 * (double)X.nnz / 3e12 : 1e300;
     X.dense_rhs = g_multi_dense == 1 || dense_t < comp_t;
-    const int64_t pt = (P + kDT - 1) / kDT;
-    const int64_t ct = (L.C + kDT - 1) / kDT * pt, rt = (L.NA + kDT - 1) / kDT * pt;
+    const int64_t pt = (P + kDM - 1) / kDM;
+    const int64_t ct = (L.C + kDN - 1) / kDN * pt, rt = (L.NA + kDN - 1) / kDN * pt;
     X.dcs = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSlabs, 2048 / ct, L.NA / 256}));
     X.drd = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kDenseChunks, 2048 / rt, L.C / 128}));
   }
@@ -2015,7 +2053,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   // (rho' I + K)^-1 applied to r for every problem: one S for all right-hand sides, or one per problem
   auto apply_inverse = [&]() -> hipError_t {
     return shared ? inv_apply_rhs(K, L.Cp, L.Cp, P, X.p<float>(L.off_r), X.p<float>(L.off_tmp),
-                                  X.p<float>(L.off_s), L.Cp, X.par + 5, kPar, X.st)
+                                  X.p<float>(L.off_s), L.Cp, X.par + 5, kPar, X.p<float>(L.off_tpart), X.st)
                   : inv_apply(K, L.Cp, L.Cp, sK, P, X.p<float>(L.off_r), X.p<float>(L.off_tmp), X.p<float>(L.off_s),
                               L.Cp, X.par + 5, kPar, X.st);
   };

@@ -175,13 +175,14 @@ def test_multi_rhs_compressed_blocks(gpu):
         assert st == 0 and l1 < 1e-3
 
 
-def test_bootstrap_chi2_model_small_build(gpu):
+def test_bootstrap_chi2_model_small_build(gpu, multi_dense):
     """Small model build (FP64 integration, 2,000 orbits): 16 bootstrap
-    realisations of the kinematic maps solved on the GPU; the chi^2 of the
-    first four realisations' weights against the observed data, and their
-    marginalised chi2_model, against the oracle's solves of the same
-    realisations (an oracle solve of this size takes several seconds); all 16
-    converge and their chi2_model lies in its bounds."""
+    realisations of the kinematic maps solved on the GPU (the multi-vector
+    inverse products split over the columns of the factor), with either kind of
+    pass over the matrix; the chi^2 of the first four realisations' weights
+    against the observed data, and their marginalised chi2_model, against the
+    oracle's solves of the same realisations (an oracle solve of this size takes
+    several seconds); all 16 converge and their chi2_model lies in its bounds."""
     import torch
     import oracle as O
     P = lib()

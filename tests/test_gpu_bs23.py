@@ -25,7 +25,7 @@ from tests.gpu_common import lib
 pytestmark = pytest.mark.gpu
 
 
-def gpu_bs23(cfg, obs, ics, h0, n_steps, rtol, atol):
+def gpu_bs23(cfg, obs, ics, h0, n_steps, rtol, atol, precision=2):
     import torch
     P = lib()
     dev = torch.device("cuda:0")
@@ -41,7 +41,7 @@ def gpu_bs23(cfg, obs, ics, h0, n_steps, rtol, atol):
     h_t = torch.from_numpy(np.ascontiguousarray(h0)).to(dev)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    P.integrate_bs23_and_bin(pot, ic_t, h_t, n_steps, rtol, atol, o, A, ov, dr, fl, ws)
+    P.integrate_bs23_and_bin(pot, ic_t, h_t, n_steps, rtol, atol, o, A, ov, dr, fl, ws, precision=precision)
     t1.record()
     torch.cuda.synchronize()
     print(f"{n} orbits x {n_steps} accepted steps: {t0.elapsed_time(t1):.1f} ms")
@@ -138,3 +138,33 @@ def test_paper_tolerance_barred_model(gpu):
     assert np.median(np.abs(dr - dr_o)) <= 1e-6
     assert np.median(l1) <= 1e-3
     assert np.allclose(A[:, :18000].sum(1) + ov[:, 0], 1.0, rtol=0, atol=1e-11)
+
+
+def test_single_precision_small_model(gpu):
+    """The single-precision integration (state, stages and step control in FP32,
+    the total time and the Jacobi drift in FP64) at the paper's settings, rtol
+    1e-4 and 5,000 accepted steps, on the small model's 2,000 orbits, against the
+    FP64 oracle.  FP32 rounding (6e-8 relative) sits far below the tolerance, but
+    the step control turns it into different, equally valid step sequences (a
+    state change of u moves the next step by ~u / rtol = 6e-4), so rows differ
+    by the integration error of rtol 1e-4 itself, not by rounding.  Bar: flags
+    equal, the median and the largest Jacobi drift within a factor 2 of the
+    oracle's (the drift measures the tolerance's integration error, which FP32
+    must not inflate), the median row L1 below 5e-2, the summed matrix (the
+    model's maps for equal weights) within 1e-2 in L1, and every row's blocks
+    normalised."""
+    cfg = W.SMALL
+    obs = dict(cfg["obs"], surface=1, upsilon=1.0)
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=5000)
+    A, ov, dr, fl = gpu_bs23(cfg, obs, ics, dt, 5000, 1e-4, 1e-6, precision=1)
+    A_o, ov_o, dr_o, fl_o = oracle_bs23(cfg, obs, ics, dt, 5000, 1e-4, 1e-6)
+    l1 = np.abs(A - A_o).sum(1)
+    tot = np.abs(A.sum(0) - A_o.sum(0)).sum() / np.abs(A_o.sum(0)).sum()
+    print(f"row L1 median {np.median(l1):.3g} p90 {np.percentile(l1, 90):.3g} max {l1.max():.3g}; summed maps L1 "
+          f"{tot:.3g}; drift median {np.median(dr):.3g} (oracle {np.median(dr_o):.3g}) max {dr.max():.3g} (oracle "
+          f"{dr_o.max():.3g})")
+    assert np.array_equal(fl, fl_o)
+    assert 0.5 <= np.median(dr) / np.median(dr_o) <= 2.0 and dr.max() <= 2.0 * dr_o.max()
+    assert np.median(l1) <= 5e-2 and tot <= 1e-2
+    assert np.allclose(A[:, :1000].sum(1) + ov[:, 0], 1.0, rtol=0, atol=1e-11)
+    assert np.allclose(A[:, 1000:1750].sum(1) + ov[:, 1], 1.0, rtol=0, atol=1e-11)
