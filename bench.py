@@ -243,6 +243,8 @@ def main():
                          "and report chi2_model")
     ap.add_argument("--refine-passes", type=int, choices=[2, 4], default=None,
                     help="passes over A per FP64 iteration (2: U^T U x carried, 4: residual from A)")
+    ap.add_argument("--factor-gemm-tile", type=int, choices=[128, 256], default=None,
+                    help="output tile of the factorisation's split-bf16 products (default: the library's)")
     ap.add_argument("--factor-gemm", type=int, choices=[0, 1], default=None,
                     help="factorisation products on fp32 MFMA (0) or bf16x3 MFMA (1); default: the library's")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -260,6 +262,8 @@ def main():
         P.set_tuning("factor_gemm", args.factor_gemm)
     if args.refine_passes is not None:
         P.set_tuning("refine_passes", args.refine_passes)
+    if args.factor_gemm_tile is not None:
+        P.set_tuning("factor_gemm_tile", args.factor_gemm_tile)
     if args.workload == "walkers":
         return bench_walkers(args)
     if args.workload == "paper":
@@ -377,6 +381,7 @@ def main():
     # `achieved`), over the stage's HIP-event time on the solve stream; the work the
     # kernels issue (extra MFMA passes of the bf16x3 split, the explicit inverse,
     # residual-correction passes, Anderson mixing) is reported beside it as `issued`
+    t_prep = float(np.mean([r["t_prep_ms"] for r in reps]))
     t_gram = float(np.mean([r["t_gram_ms"] for r in reps]))
     t_factor = float(np.mean([r["t_factor_ms"] for r in reps]))
     t_admm = float(np.mean([r["t_admm_ms"] for r in reps]))
@@ -387,8 +392,8 @@ def main():
     nnz = float(reps[-1]["nnz"])
     C, N = float(nc), float(n)
     passes = {"bf16": 1, "bf16x3": 3, "f32": 1}[args.gram]
-    stages = {"integrate_and_bin": t_i, "gram": t_gram, "factorise": t_factor, "admm_fp32": t_admm,
-              "refine_fp64": t_ref}
+    stages = {"integrate_and_bin": t_i, "solve_prep": t_prep, "gram": t_gram, "factorise": t_factor,
+              "admm_fp32": t_admm, "refine_fp64": t_ref}
     # |U|: one pass over the orbit matrix as stored for the iterations (fp32 value + 16-bit
     # index per nonzero, or the dense matrix); |L|: one triangle of the fp32 inverse factor
     u_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
@@ -867,8 +872,7 @@ def bench_paper(args):
     B = cfg["n_boot"]
     opts = P._lib.SolveOpts()
     opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
-    if args.rho is not None:
-        opts.rho = -args.rho
+    opts.rho = -(args.rho if args.rho is not None else cfg["rho"])
     prec = P.SW_F32 if args.bs23_precision == "f32" else P.SW_F64
 
     def build():
@@ -947,7 +951,8 @@ def bench_paper(args):
            "config": {"workload": (cfg["name"] if S == cfg["n_steps"] else cfg["name"].replace("5k", f"{S}")).replace(
                           "_f64", "_" + args.bs23_precision),
                       "n_orbits": n, "n_bundles": n_ic, "n_steps": S, "rtol": cfg["rtol"], "n_apertures": n_ap,
-                      "n_binned_constraints": nc, "n_fit_constraints": nf, "n_bootstraps": B},
+                      "n_binned_constraints": nc, "n_fit_constraints": nf, "n_bootstraps": B,
+                      "admm_penalty": f"{-opts.rho} x trace(U U^T)/N"},
            "model_builds_per_s": 1e3 / ms, "stage_ms": {k: round(v, 2) for k, v in st_ms.items()},
            "dominant_stage": max(st_ms, key=st_ms.get), "last": res[-1], "roofline": roof,
            "context": "the paper quotes about 1.3 s per model (build + 100 bootstrap solves + chi^2) on one A100"}
@@ -1020,11 +1025,10 @@ def bench_surrogate(args):
         adapt = args.mcmc_steps // 2
 
         def refit(th_b, chi_b):
-            # the chains' neighbourhood: every full build so far, weighted like the whole training set
-            rep = max(1, n_tr // max(1, len(chi_b)))
-            sur.fit(np.concatenate([thetas[:n_tr], np.repeat(th_b, rep, axis=0)]),
-                    np.concatenate([chi[:n_tr], np.repeat(chi_b, rep)]), epochs=8, batch=512, keep_scaling=True,
-                    seed=len(chi_b))
+            # the chains' neighbourhood only: the full builds of the chains so far, with the target
+            # standardised over them, so that the network resolves chi^2 differences of a few dchi2
+            # there instead of the range of the whole prior box
+            sur.fit(th_b, chi_b, epochs=60, batch=256, seed=len(chi_b))
 
         res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log,
                            refit=refit, refit_every=max(10, adapt // 5), adapt_steps=adapt)

@@ -49,6 +49,7 @@ constexpr int kSlabs = 256;       // orbit slabs per problem in the column-sum r
 constexpr int kPar = 8;           // per-problem scalars: wt, rho, rho', mu, alpha, active
 constexpr int kAcc = 16;          // per-problem accumulators
 constexpr double kMaxDensity = 0.30;  // largest fill of A stored compressed
+constexpr int kScanBlock = 1024;     // device prefix sums: elements per workgroup (256 threads x 4)
 constexpr int kAAMem = 10;          // Anderson acceleration: iterations kept in the history
 constexpr int kAAThreads = 256, kAAPer = 4, kAAChunk = kAAThreads * kAAPer;  // AA passes: orbits per workgroup
 constexpr int kAADots = 2 * kAAMem + 1;
@@ -167,45 +168,42 @@ __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   // staging: V row vm = tid / 2, k offsets vk .. vk + 7; B: TRANSB row (n) bn =
   // tid / 4, k offsets bk .. bk + 3, else k row tid / 16, n offsets 4 (tid % 16) ..
+  // Two register sets: while k-step t is multiplied from LDS, step t + 1 waits
+  // in one set (to be staged after the multiply) and step t + 2 loads into the
+  // other, so a load has two steps of MFMA work to arrive.
   const int vm = tid >> 1, vk = (tid & 1) * 8;
   const int bq = TRANSB ? (tid >> 2) : (tid >> 4), bo = TRANSB ? (tid & 3) * 4 : (tid & 15) * 4;
-  double rv[8], rb[4];
-  auto gload = [&](int64_t k0) {
+  double rv[2][8], rb[2][4];
+  auto gload = [&](auto SET, int64_t k0) {
+    constexpr int q = decltype(SET)::value;
     const int64_t m = m0 + vm;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int64_t k = k0 + vk + j;
-      rv[j] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
+      rv[q][j] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (TRANSB) {  // A[n][k]
         const int64_t n = n0 + bq, k = k0 + bo + j;
-        rb[j] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
+        rb[q][j] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
       } else {  // A[k][n]
         const int64_t k = k0 + bq, n = n0 + bo + j;
-        rb[j] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
+        rb[q][j] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
       }
     }
   };
-  auto stage = [&](int buf) {
+  auto stage = [&](auto SET, int buf) {
+    constexpr int q = decltype(SET)::value;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Vs[buf][vk + j][vm] = rv[j];
+    for (int j = 0; j < 8; ++j) Vs[buf][vk + j][vm] = rv[q][j];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (TRANSB) Bs[buf][bo + j][bq] = rb[j];
-      else Bs[buf][bq][bo + j] = rb[j];
+      if (TRANSB) Bs[buf][bo + j][bq] = rb[q][j];
+      else Bs[buf][bq][bo + j] = rb[q][j];
     }
   };
-  int buf = 0;
-  if (k_beg < k_end) {
-    gload(k_beg);
-    stage(0);
-  }
-  __syncthreads();
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += kDK) {
-    const bool more = k0 + kDK < k_end;
-    if (more) gload(k0 + kDK);
+  auto multiply = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < kDK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -219,10 +217,29 @@ __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  if (k_beg < k_end) {
+    gload(S0{}, k_beg);
+    stage(S0{}, 0);
+  }
+  if (k_beg + kDK < k_end) gload(S1{}, k_beg + kDK);
+  __syncthreads();
+  // step t (k0 = k_beg + t kDK) multiplies LDS buffer t % 2; set (t + 1) % 2 holds step t + 1
+  auto step = [&](auto PAR, int64_t k0) {
+    constexpr int t2 = decltype(PAR)::value;
+    using Cur = std::integral_constant<int, t2>;
+    using Nxt = std::integral_constant<int, 1 - t2>;
+    if (k0 + 2 * kDK < k_end) gload(Cur{}, k0 + 2 * kDK);
+    multiply(t2);
     // the other buffer was last read before the previous barrier
-    if (more) stage(buf ^ 1);
+    if (k0 + kDK < k_end) stage(Nxt{}, 1 - t2);
     __syncthreads();
-    buf ^= 1;
+  };
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += 2 * kDK) {
+    step(S0{}, k0);
+    if (k0 + kDK < k_end) step(S1{}, k0 + kDK);
   }
   out += (int64_t)blockIdx.z * so;
 #pragma unroll
@@ -1362,6 +1379,8 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAArgs a, int plain) {
 #pragma unroll
   for (int k = 0; k < kAADots; ++k) t[k] = wave_sum(t[k]);
   if (threadIdx.x != 0) return;
+  // (every array below is indexed by compile-time constants only, the history
+  // slots reached through computed addresses, so that nothing lives in scratch)
   double* G = a.G + (int64_t)b * kAAMem * kAAMem;
   double* gam = a.gam + (int64_t)b * kAAMem;
   const int64_t it = (int64_t)a.st[b * 4 + 0];
@@ -1370,7 +1389,8 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAArgs a, int plain) {
   const int m = kAAMem;
   const int s = it >= 1 ? (int)((it - 1) % m) : 0;
   if (it >= 1) {
-    for (int k = 0; k < m; ++k) {
+#pragma unroll
+    for (int k = 0; k < kAAMem; ++k) {
       G[s * kAAMem + k] = t[k];
       G[k * kAAMem + s] = t[k];
     }
@@ -1383,46 +1403,76 @@ __global__ __launch_bounds__(64) void k_aa_solve(AAArgs a, int plain) {
   } else {
     fmin = fn < fmin ? fn : fmin;
   }
+#pragma unroll
   for (int k = 0; k < kAAMem; ++k) gam[k] = 0.0;
   if (!plain && cnt > 0) {
-    // slots newest first; M = G restricted to them, Cholesky in place
+    // slots newest first (slot of entry i: (s - i) mod m); M = G restricted to
+    // them, Cholesky in place; entries i >= cnt are left out
     double M[kAAMem][kAAMem], r[kAAMem];
     int sl[kAAMem];
     double tr = 0.0;
-    for (int i = 0; i < cnt; ++i) {
+#pragma unroll
+    for (int i = 0; i < kAAMem; ++i) {
       sl[i] = (s - i + m) % m;
-      tr += G[sl[i] * kAAMem + sl[i]];
+      if (i < cnt) tr += G[sl[i] * kAAMem + sl[i]];
     }
-    for (int i = 0; i < cnt; ++i) {
-      for (int j = 0; j < cnt; ++j) M[i][j] = G[sl[i] * kAAMem + sl[j]];
+#pragma unroll
+    for (int i = 0; i < kAAMem; ++i) {
+#pragma unroll
+      for (int j = 0; j < kAAMem; ++j) M[i][j] = (i < cnt && j < cnt) ? G[sl[i] * kAAMem + sl[j]] : 0.0;
       M[i][i] += 1e-10 * tr + 1e-300;
-      r[i] = t[kAAMem + sl[i]];
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < kAAMem; ++k) v = k == sl[i] ? t[kAAMem + k] : v;
+      r[i] = v;
     }
     bool ok = true;
-    for (int j = 0; j < cnt && ok; ++j) {
-      double dj = M[j][j];
-      for (int k = 0; k < j; ++k) dj -= M[j][k] * M[j][k];
-      if (!(dj > 0.0)) { ok = false; break; }
-      dj = sqrt(dj);
-      M[j][j] = dj;
-      for (int i = j + 1; i < cnt; ++i) {
-        double v = M[i][j];
-        for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
-        M[i][j] = v / dj;
+#pragma unroll
+    for (int j = 0; j < kAAMem; ++j) {
+      if (j < cnt && ok) {
+        double dj = M[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dj -= M[j][k] * M[j][k];
+        if (!(dj > 0.0)) {
+          ok = false;
+        } else {
+          dj = sqrt(dj);
+          M[j][j] = dj;
+#pragma unroll
+          for (int i = j + 1; i < kAAMem; ++i) {
+            if (i < cnt) {
+              double v = M[i][j];
+#pragma unroll
+              for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
+              M[i][j] = v / dj;
+            }
+          }
+        }
       }
     }
     if (ok) {
-      for (int i = 0; i < cnt; ++i) {  // L y = r, then L^T gamma = y
-        double v = r[i];
-        for (int k = 0; k < i; ++k) v -= M[i][k] * r[k];
-        r[i] = v / M[i][i];
+#pragma unroll
+      for (int i = 0; i < kAAMem; ++i) {  // L y = r, then L^T gamma = y
+        if (i < cnt) {
+          double v = r[i];
+#pragma unroll
+          for (int k = 0; k < i; ++k) v -= M[i][k] * r[k];
+          r[i] = v / M[i][i];
+        }
       }
-      for (int i = cnt - 1; i >= 0; --i) {
-        double v = r[i];
-        for (int k = i + 1; k < cnt; ++k) v -= M[k][i] * r[k];
-        r[i] = v / M[i][i];
+#pragma unroll
+      for (int i = kAAMem - 1; i >= 0; --i) {
+        if (i < cnt) {
+          double v = r[i];
+#pragma unroll
+          for (int k = i + 1; k < kAAMem; ++k)
+            if (k < cnt) v -= M[k][i] * r[k];
+          r[i] = v / M[i][i];
+        }
       }
-      for (int i = 0; i < cnt; ++i) gam[sl[i]] = r[i];
+#pragma unroll
+      for (int i = 0; i < kAAMem; ++i)
+        if (i < cnt) gam[sl[i]] = r[i];
     } else {
       cnt = 0;
     }
@@ -1508,6 +1558,7 @@ struct SolveLayout {
   int64_t nzw;    // 64-bit words of zero-panel bits per 256-row tile of X
   size_t off_nz;  // zero-panel bits of the Gram operand [Cx / 256][nzw]
   size_t off_tiles, off_perm;  // per orbit: footprint (count + bitmap of nonzero 256-constraint tiles); X's orbit order
+  size_t off_scan, off_clen, off_cpos;  // device prefix sums of the compressed copies' segment lengths
   size_t total;
 };
 
@@ -1605,6 +1656,13 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_pd = take(shared ? (size_t)P * std::max<int64_t>(L.ncb, kDenseChunks) * NA * 8 : 0);
   L.off_tiles = take(NA * 5 * 8);
   L.off_perm = take(NA * 4);
+  {  // device prefix sums of the segment lengths: block sums, totals, column segments
+    const size_t nr = NA * L.ncb, nq = PA * L.nrb * L.C;
+    const size_t nbr = (nr + kScanBlock - 1) / kScanBlock, nbc = (nq + kScanBlock - 1) / kScanBlock;
+    L.off_scan = take((2 * nbr + 2 * nbc + 4) * 8);
+    L.off_clen = take(nq * 8);
+    L.off_cpos = take(nq * 8);
+  }
   L.total = o;
   return L;
 }
@@ -1774,6 +1832,142 @@ static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Segment pointers of the compressed copies on the device.  Segments are
+// padded to whole quads, so a pointer is the exclusive prefix sum of the
+// quad-rounded lengths.  Three passes: block sums (kScanBlock elements per
+// workgroup), one workgroup scanning the block sums, then each block's own
+// scan from its offset.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t quad_len(int64_t v) { return (v + 3) & ~(int64_t)3; }
+
+// inclusive scan of one value per thread over the 256 threads (LDS, Hillis-Steele)
+__device__ __forceinline__ int64_t block_scan256(int64_t v, int64_t* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  return sh[threadIdx.x];
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void k_scan_sums(const TI* __restrict__ in, int64_t n, int64_t* __restrict__ bq,
+                                                   int64_t* __restrict__ braw) {
+  __shared__ int64_t sh[256];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int64_t q = 0, r = 0;
+  for (int j = 0; j < 4; ++j)
+    if (i0 + j < n) {
+      const int64_t v = (int64_t)in[i0 + j];
+      q += quad_len(v);
+      r += v;
+    }
+  const int64_t tq = block_scan256(q, sh);
+  __syncthreads();
+  const int64_t tr = block_scan256(r, sh);
+  if (threadIdx.x == 255) {
+    bq[blockIdx.x] = tq;
+    braw[blockIdx.x] = tr;
+  }
+}
+
+// exclusive scan of the nb block sums in place; tot[0] = sum of the quad-rounded
+// lengths, tot[1] = sum of the lengths
+__global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ bq, const int64_t* __restrict__ braw,
+                                                  int64_t nb, int64_t* __restrict__ tot) {
+  __shared__ int64_t sh[256];
+  const int64_t per = (nb + 255) / 256, j0 = threadIdx.x * per, j1 = j0 + per < nb ? j0 + per : nb;
+  int64_t q = 0, r = 0;
+  for (int64_t j = j0; j < j1; ++j) {
+    q += bq[j];
+    r += braw[j];
+  }
+  const int64_t incl = block_scan256(q, sh);
+  __syncthreads();
+  const int64_t rsum = block_scan256(r, sh);
+  int64_t run = incl - q;
+  for (int64_t j = j0; j < j1; ++j) {
+    const int64_t v = bq[j];
+    bq[j] = run;
+    run += v;
+  }
+  if (threadIdx.x == 255) {
+    tot[0] = incl;
+    tot[1] = rsum;
+  }
+}
+
+// out[i] = boff[i / kScanBlock] + sum over i' < i of the block of quad(in[i'])
+template <typename TI>
+__global__ __launch_bounds__(256) void k_scan_apply(const TI* __restrict__ in, int64_t n,
+                                                    const int64_t* __restrict__ boff, int64_t* __restrict__ out) {
+  __shared__ int64_t sh[256];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int64_t l[4], q = 0;
+  for (int j = 0; j < 4; ++j) {
+    l[j] = i0 + j < n ? quad_len((int64_t)in[i0 + j]) : 0;
+    q += l[j];
+  }
+  int64_t run = boff[blockIdx.x] + block_scan256(q, sh) - q;
+  for (int j = 0; j < 4; ++j)
+    if (i0 + j < n) {
+      out[i0 + j] = run;
+      run += l[j];
+    }
+}
+
+// per segment q = (b nrb + rb) C + c of the compressed columns: the entries of
+// column c in the slabs of row block rb of problem b
+__global__ __launch_bounds__(256) void k_col_len(const int32_t* __restrict__ cpart, int64_t C, int nrb,
+                                                 const int64_t* __restrict__ rps, int64_t blk, int64_t nq,
+                                                 int64_t* __restrict__ len) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t c = q % C, br = q / C, rb = br % nrb, b = br / nrb;
+  const int64_t spb = slabs_per_block(rps[b], blk);
+  const int64_t s0 = rb * spb < kSlabs ? rb * spb : kSlabs, s1 = (rb + 1) * spb < kSlabs ? (rb + 1) * spb : kSlabs;
+  int64_t t = 0;
+  for (int64_t s = s0; s < s1; ++s) t += cpart[(b * kSlabs + s) * C + c];
+  len[q] = t;
+}
+
+// column pointers and the first position of every slab's entries in each column
+__global__ __launch_bounds__(256) void k_col_ptrs(const int32_t* __restrict__ cpart, int64_t C, int nrb,
+                                                  const int64_t* __restrict__ rps, int64_t blk, int64_t nq,
+                                                  const int64_t* __restrict__ pos, const int64_t* __restrict__ len,
+                                                  int64_t* __restrict__ cptr, int64_t* __restrict__ slab_at) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t c = q % C, br = q / C, rb = br % nrb, b = br / nrb;
+  const int64_t spb = slabs_per_block(rps[b], blk);
+  const int64_t s0 = rb * spb < kSlabs ? rb * spb : kSlabs, s1 = (rb + 1) * spb < kSlabs ? (rb + 1) * spb : kSlabs;
+  int64_t run = pos[q];
+  cptr[br * (C + 1) + c] = run;
+  if (c == C - 1) cptr[br * (C + 1) + C] = run + quad_len(len[q]);
+  for (int64_t s = s0; s < s1; ++s) {
+    const int64_t k = (b * kSlabs + s) * C + c;
+    slab_at[k] = run;
+    run += cpart[k];
+  }
+}
+
+// exclusive quad-rounded prefix of n counts into out (out[n] = total when
+// with_total); tot[0..1] = sums of the rounded and of the raw counts
+template <typename TI>
+static hipError_t scan_quads(const TI* in, int64_t n, int64_t* out, bool with_total, int64_t* bq, int64_t* braw,
+                             int64_t* tot, hipStream_t st) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_sums<TI>, dim3((unsigned)nb), dim3(256), 0, st, in, n, bq, braw);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, bq, (const int64_t*)braw, nb, tot);
+  hipLaunchKernelGGL(k_scan_apply<TI>, dim3((unsigned)nb), dim3(256), 0, st, in, n, (const int64_t*)bq, out);
+  if (with_total) return hipMemcpyAsync(out + n, tot, 8, hipMemcpyDeviceToDevice, st);
+  return hipGetLastError();
+}
+
 // Builds the compressed copies of A when they fit; sets X.sparse.
 template <typename TA>
 static int build_sparse(Ctx& X) {
@@ -1792,20 +1986,55 @@ static int build_sparse(Ctx& X) {
   hipLaunchKernelGGL(k_col_nnz<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
                      dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, cpart);
   SW_HIP(hipGetLastError());
-  std::vector<int64_t> hr((size_t)NA * ncb);
-  std::vector<int32_t> hc((size_t)P * kSlabs * L.C);
-  SW_HIP(hipMemcpyAsync(hr.data(), rcnt, hr.size() * 8, hipMemcpyDeviceToHost, X.st));
-  SW_HIP(hipMemcpyAsync(hc.data(), cpart, hc.size() * 4, hipMemcpyDeviceToHost, X.st));
-  std::vector<uint64_t> hf((size_t)NA * 5);
-  SW_HIP(hipMemcpyAsync(hf.data(), foot, hf.size() * 8, hipMemcpyDeviceToHost, X.st));
+  // segment pointers on the device: rows, then the column segments (b, rb, c)
+  // with the first position of every slab's entries in each column
+  const int64_t nr = NA * ncb, nq = (int64_t)P * nrb * L.C;
+  const int64_t nbr = (nr + kScanBlock - 1) / kScanBlock, nbc = (nq + kScanBlock - 1) / kScanBlock;
+  int64_t* sq = X.p<int64_t>(L.off_scan);
+  int64_t *bqr = sq, *brr = sq + nbr, *bqc = sq + 2 * nbr, *brc = bqc + nbc, *tot = brc + nbc;
+  int64_t* clen = X.p<int64_t>(L.off_clen);
+  int64_t* cpos = X.p<int64_t>(L.off_cpos);
+  SW_HIP(scan_quads(rcnt, nr, X.p<int64_t>(L.off_rptr), true, bqr, brr, tot, X.st));
+  hipLaunchKernelGGL(k_col_len, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, X.st, (const int32_t*)cpart, L.C, nrb,
+                     X.rps_d, L.blk, nq, clen);
+  SW_HIP(scan_quads(clen, nq, cpos, false, bqc, brc, tot + 2, X.st));
+  hipLaunchKernelGGL(k_col_ptrs, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, X.st, (const int32_t*)cpart, L.C,
+                     nrb, X.rps_d, L.blk, nq, (const int64_t*)cpos, (const int64_t*)clen, X.p<int64_t>(L.off_cptr),
+                     X.p<int64_t>(L.off_slab));
+  SW_HIP(hipGetLastError());
+  int64_t htot[4] = {0, 0, 0, 0};
+  SW_HIP(hipMemcpyAsync(htot, tot, sizeof htot, hipMemcpyDeviceToHost, X.st));
+  std::vector<uint64_t> hf(g_gram_dense ? 0 : (size_t)NA * 5);
+  if (!hf.empty()) SW_HIP(hipMemcpyAsync(hf.data(), foot, hf.size() * 8, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipStreamSynchronize(X.st));
+  const int64_t at = htot[0], nnz = htot[1], pos = htot[2];
+  // a compressed entry costs 6 bytes per pass against 4 (fp32) dense: the
+  // compressed passes pay off well below 2/3 density; copies are kept up to
+  // kMaxDensity and the capacity of the workspace
+  const bool fits = at <= L.cap_nnz && pos <= L.cap_nnz && (double)nnz <= kMaxDensity * (double)NA * (double)L.C;
+  if (fits) {
+    hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
+                       X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
+    // column padding: clear the compressed columns, then fill the entries
+    const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words,
+                       0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words,
+                       0);
+    hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs,
+                                            (unsigned)P),
+                       dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab), L.blk,
+                       X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
+    SW_HIP(hipGetLastError());
+  }
   if (!g_gram_dense) {
     // The Gram is a sum over orbits, so its operand may take the orbits in any
     // order.  Ordered by footprint (the number of nonzero 256-constraint tiles,
     // then the bitmap of those tiles, lexicographically, within each matrix)
     // the orbits of one 32-orbit stage cover the same parts of the grid and the
     // sky, and more stages of a panel are all zero.  perm[aoff_b + j] = row
-    // (within matrix b) of column j.
+    // (within matrix b) of column j.  The host sorts while the device fills
+    // the compressed copies.
     std::vector<int32_t> perm((size_t)NA);
     for (int b = 0; b < P; ++b) {
       const int64_t a0 = L.aoff[b], a1 = L.aoff[b + 1];
@@ -1824,56 +2053,7 @@ static int build_sparse(Ctx& X) {
     SW_HIP(hipStreamSynchronize(X.st));  // perm's host copy is freed on return
     X.perm = X.p<int32_t>(L.off_perm);
   }
-  // segments are padded to whole quads (4 entries)
-  auto quad = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
-  int64_t nnz = 0, at = 0;
-  std::vector<int64_t> rptr((size_t)NA * ncb + 1);
-  for (size_t k = 0; k < hr.size(); ++k) {
-    rptr[k] = at;
-    nnz += hr[k];
-    at += quad(hr[k]);
-  }
-  rptr[hr.size()] = at;
-  // a compressed entry costs 6 bytes per pass against 4 (fp32) dense: the
-  // compressed passes pay off well below 2/3 density; copies are kept up to kMaxDensity
-  if (at > L.cap_nnz || (double)nnz > kMaxDensity * (double)NA * (double)L.C) return SW_OK;
-  // columns: segment (b, rb, c) = the slabs of row block rb; slab_at[b][s][c]
-  // = absolute position of slab s's first entry of column c
-  std::vector<int64_t> cptr((size_t)P * nrb * (L.C + 1), 0), slab_at((size_t)P * kSlabs * L.C);
-  int64_t pos = 0;
-  for (int b = 0; b < P; ++b) {
-    const int64_t spb = slabs_per_block(L.rps[b], L.blk);
-    for (int rb = 0; rb < nrb; ++rb) {
-      int64_t* cp = &cptr[((size_t)b * nrb + rb) * (L.C + 1)];
-      const int s0 = (int)std::min<int64_t>(kSlabs, rb * spb), s1 = (int)std::min<int64_t>(kSlabs, (rb + 1) * spb);
-      for (int64_t c = 0; c < L.C; ++c) {
-        cp[c] = pos;
-        int64_t run = pos;
-        for (int s = s0; s < s1; ++s) {
-          const size_t k = ((size_t)b * kSlabs + s) * L.C + c;
-          slab_at[k] = run;
-          run += hc[k];
-        }
-        pos += quad(run - pos);
-      }
-      cp[L.C] = pos;
-    }
-  }
-  if (pos > L.cap_nnz) return SW_OK;
-  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_rptr), rptr.data(), rptr.size() * 8, hipMemcpyHostToDevice, X.st));
-  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_cptr), cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, X.st));
-  SW_HIP(hipMemcpyAsync(X.p<int64_t>(L.off_slab), slab_at.data(), slab_at.size() * 8, hipMemcpyHostToDevice, X.st));
-  hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
-                     X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
-  // column padding: clear the compressed columns, then fill the entries
-  const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words, 0);
-  hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P),
-                     dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab), L.blk,
-                     X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
-  SW_HIP(hipGetLastError());
-  // the host vectors must outlive the copies
+  if (!fits) return SW_OK;
   SW_HIP(hipStreamSynchronize(X.st));
   X.sparse = true;
   X.nnz = nnz;

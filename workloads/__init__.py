@@ -233,11 +233,12 @@ def blocks(obs):
 # Jeans initial conditions x 4 dithers, BS23 (rtol 1e-4) for 5,000 accepted
 # steps, a 600-cell cylindrical density grid, ~600 irregular apertures of a
 # 60 x 40 pixel grid with 30 velocity bins, the surface-density block, and
-# 100 bootstrap realisations of the maps.
+# 100 bootstrap realisations of the maps.  rho: the ADMM penalty of the weight
+# solves as a multiple of trace(U U^T)/N.
 PAPER = dict(
     name="paper_pipeline_barred_7500x4_bs23_5k_steps_f64",
     n_ic=7500, n_dither=4, n_steps=5000, rtol=1e-4, atol=1e-6, h0=2e-3, dx=0.1, fv=0.05, h_R=3.5, h_z=1.2,
-    jeans_b=1.0, n_boot=100, n_gh=4, dh=0.02, stellar_mask=0b011, n_sub=4,
+    jeans_b=1.0, n_boot=100, n_gh=4, dh=0.02, stellar_mask=0b011, n_sub=4, rho=0.5,
     obs=dict(nx=10, ny=6, nz=10, lo=(0.0, -math.pi, -3.0), hi=(10.0, math.pi, 3.0), grid="cylindrical",
              npx=60, npy=40, plo=(-10.0, -20.0 / 3.0), phi=(10.0, 20.0 / 3.0),
              nv=30, vlo=-450.0, vhi=450.0, symmetrize=1, drift_every=1, surface=1, upsilon=1.0),
