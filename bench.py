@@ -243,8 +243,6 @@ def main():
                          "and report chi2_model")
     ap.add_argument("--refine-passes", type=int, choices=[2, 4], default=None,
                     help="passes over A per FP64 iteration (2: U^T U x carried, 4: residual from A)")
-    ap.add_argument("--factor-gemm-tile", type=int, choices=[128, 256], default=None,
-                    help="output tile of the factorisation's split-bf16 products (default: the library's)")
     ap.add_argument("--factor-gemm", type=int, choices=[0, 1], default=None,
                     help="factorisation products on fp32 MFMA (0) or bf16x3 MFMA (1); default: the library's")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -262,8 +260,6 @@ def main():
         P.set_tuning("factor_gemm", args.factor_gemm)
     if args.refine_passes is not None:
         P.set_tuning("refine_passes", args.refine_passes)
-    if args.factor_gemm_tile is not None:
-        P.set_tuning("factor_gemm_tile", args.factor_gemm_tile)
     if args.workload == "walkers":
         return bench_walkers(args)
     if args.workload == "paper":

@@ -73,8 +73,6 @@ bool obs_to_k(const sw_obs_spec* o, ObsK* k);
 //  g_rhs_group     right-hand sides of one shared matrix per workgroup (1, 2, 4, 8)
 //  g_factor_x3     1: the factorisation's large products on bf16x3 MFMA, 0: fp32 MFMA
 extern int g_factor_x3;
-//  g_gemm_wide     1: split-bf16 products with both dimensions >= 512 on 256 x 256 tiles, 0: 128 x 128
-extern int g_gemm_wide;
 //  g_gram_dense    1: the Gram streams every 32-orbit stage (no zero-panel skipping)
 //  g_refine_two    1: two passes over A per FP64 iteration (U^T U x carried), 0: four
 extern int g_gram_dense;

@@ -490,155 +490,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K,
       }
 }
 
-// ---------------------------------------------------------------------------
-// The split-bf16 product on 256 x 256 tiles: 8 waves as 2 x 4 blocks of
-// 128 x 64 (4 x 2 MFMA 32x32x16 outputs each, as the Gram), the fp32 operands
-// split into bf16 pairs as they are staged into two LDS buffers (one barrier
-// per 32-deep stage; the next stage is fetched into registers meanwhile).  A
-// tile reads 2 x 256 rows per 256 x 256 outputs, half the operand traffic per
-// output of the 128-tile kernel.  Same results as k_gemm_nt_x3 up to the fp32
-// summation order, and the same semantics at 128-tile granularity: `lower`
-// writes only the 128-tiles on or below the diagonal, `a_lower` reads row r of
-// A only for k < 128 (r / 128 + 1), split-K chunk z writes C + z sPart and a
-// chunk past a row tile's inner range writes nothing.  M and N are multiples
-// of 128; the halves of edge tiles past them are neither read nor written.
-// ---------------------------------------------------------------------------
-constexpr int kWT = 256, kWThreads = 512;
-constexpr int64_t kWideMin = 512;  // both output dimensions at least this: 256-tile kernel
-
-__global__ __launch_bounds__(kWThreads) void k_gemm_nt_x3w(int64_t M, int64_t N, int64_t ntn, int64_t K, float alpha,
-                                                           const float* __restrict__ A, int64_t lda, int64_t sA,
-                                                           const float* __restrict__ B, int64_t ldb, int64_t sB,
-                                                           float beta, float* __restrict__ C, int64_t ldc, int64_t sC,
-                                                           int lower, int a_lower, int64_t n_tiles, int64_t kc,
-                                                           int64_t sPart) {
-  A += blockIdx.y * sA;
-  B += blockIdx.y * sB;
-  C += blockIdx.y * sC;
-  __shared__ __attribute__((aligned(16))) __bf16 sm[2][4][kWT][kGPad];  // A hi, B hi, A lo, B lo
-  int64_t tm, tn;
-  if (!gemm_tile(ntn, lower, a_lower, n_tiles, tm, tn)) return;
-  const int64_t m0 = tm * kWT, n0 = tn * kWT;
-  int64_t Kend = (a_lower && m0 + kWT < K) ? m0 + kWT : K;
-  int64_t kbeg = 0;
-  if (kc > 0) {
-    kbeg = (int64_t)blockIdx.z * kc;
-    if (kbeg >= Kend) return;
-    Kend = kbeg + kc < Kend ? kbeg + kc : Kend;
-    C += (int64_t)blockIdx.z * sPart;
-  }
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 2, wn = w & 3;  // wave block: rows wm*128.., cols wn*64..
-  floatx16 acc[4][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
-  // a stage is 256 rows x 32 k of each operand: element group q = tid + 512 i
-  // (i < 4) is row q / 8, k offset 4 (q % 8), one float4 per operand
-  float4 ra[4], rb[4];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + kWThreads * i;
-      const int r = q >> 3, c = (q & 7) * 4;
-      const int64_t ra_row = m0 + r, rb_row = n0 + r;
-      float4 va = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vb = va;
-      if (ra_row < M) {
-        va = *reinterpret_cast<const float4*>(A + ra_row * lda + k0 + c);
-        if (a_lower) {  // row ra_row holds k < 128 (ra_row / 128 + 1) only
-          const int64_t kmax = (ra_row / 128 + 1) * 128 - (k0 + c);
-          if (kmax <= 0) va.x = 0.0f;
-          if (kmax <= 1) va.y = 0.0f;
-          if (kmax <= 2) va.z = 0.0f;
-          if (kmax <= 3) va.w = 0.0f;
-        }
-      }
-      if (rb_row < N) vb = *reinterpret_cast<const float4*>(B + rb_row * ldb + k0 + c);
-      ra[i] = va;
-      rb[i] = vb;
-    }
-  };
-  auto split4 = [](const float4 v, __bf16* hi, __bf16* lo) {
-    const float x[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const __bf16 h = (__bf16)x[j];
-      hi[j] = h;
-      lo[j] = (__bf16)(x[j] - (float)h);
-    }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + kWThreads * i;
-      const int r = q >> 3, c = (q & 7) * 4;
-      __bf16 h[4], l[4];
-      split4(ra[i], h, l);
-      *reinterpret_cast<uint2*>(&sm[buf][0][r][c]) = *reinterpret_cast<const uint2*>(h);
-      *reinterpret_cast<uint2*>(&sm[buf][2][r][c]) = *reinterpret_cast<const uint2*>(l);
-      split4(rb[i], h, l);
-      *reinterpret_cast<uint2*>(&sm[buf][1][r][c]) = *reinterpret_cast<const uint2*>(h);
-      *reinterpret_cast<uint2*>(&sm[buf][3][r][c]) = *reinterpret_cast<const uint2*>(l);
-    }
-  };
-  int buf = 0;
-  gload(kbeg);
-  stage(0);
-  __syncthreads();
-  for (int64_t k0 = kbeg; k0 < Kend; k0 += kBKf) {
-    const bool more = k0 + kBKf < Kend;
-    if (more) gload(k0 + kBKf);
-#pragma unroll
-    for (int ks = 0; ks < kBKf / 16; ++ks) {
-      const int kcol = ks * 16 + 8 * (lane >> 5);
-      bf16x8 bh[2], bl[2], ah[4], al[4];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        bh[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][1][wn * 64 + b * 32 + (lane & 31)][kcol]);
-        bl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][3][wn * 64 + b * 32 + (lane & 31)][kcol]);
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        ah[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][0][wm * 128 + a * 32 + (lane & 31)][kcol]);
-        al[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][2][wm * 128 + a * 32 + (lane & 31)][kcol]);
-      }
-      // sweeps over the 8 accumulators: no MFMA waits for the one before it
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-    }
-    // the other buffer was last read before the previous barrier
-    if (more) stage(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t row = m0 + wm * 128 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int64_t col = n0 + wn * 64 + b * 32 + (lane & 31);
-        if (row >= M || col >= N || (lower && row / 128 < col / 128)) continue;
-        float* cp = C + row * ldc + col;
-        const float v = alpha * acc[a][b][i];
-        *cp = (beta == 0.0f) ? v : beta * (*cp) + v;
-      }
-}
-
 // Sum of the split-K partials of an M x N product (partials compact, ld N)
 // whose row tile tm has min((tm + 1) 128, K) inner terms (a lower-triangular
 // left operand): out (ld ldo) = sum over the chunks that tile has, in chunk
@@ -1022,21 +873,10 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
 }
 
 int g_factor_x3 = 1;
-int g_gemm_wide = 0;
 
 hipError_t gemm_nt_f32(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, int64_t sA,
                        const float* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
                        bool lower, int nb, hipStream_t st, bool a_lower, bool x3) {
-  if (x3 && g_gemm_wide && M >= kWideMin && N >= kWideMin) {
-    const int64_t ntm = (M + kWT - 1) / kWT, ntn = (N + kWT - 1) / kWT;
-    const int64_t n_tiles = lower ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    const int64_t grid = (a_lower && !lower) ? kXcd * ((ntm + kXcd - 1) / kXcd) * ntn
-                                             : ((n_tiles + kXcd - 1) / kXcd) * kXcd;
-    hipLaunchKernelGGL(k_gemm_nt_x3w, dim3((unsigned)grid, (unsigned)nb), dim3(kWThreads), 0, st, M, N, ntn, K, alpha,
-                       A, lda, sA, B, ldb, sB, beta, C, ldc, sC, lower ? 1 : 0, a_lower ? 1 : 0, n_tiles, (int64_t)0,
-                       (int64_t)0);
-    return hipGetLastError();
-  }
   const int64_t ntm = M / kT, ntn = N / kT;
   const int64_t n_tiles = lower ? ntm * (ntm + 1) / 2 : ntm * ntn;
   if (n_tiles == 0) return hipSuccess;
@@ -1074,19 +914,11 @@ static hipError_t gemm_lower_split(int64_t M, int64_t N, const float* W, int64_t
   const int64_t kc = split_kc(M, ntn, nb);
   const bool x3 = g_factor_x3 != 0;
   if (kc >= M) return gemm_nt_f32(M, N, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, X, ldx, sX, false, nb, st, true, x3);
-  const int64_t nchunk = (M + kc - 1) / kc;
-  if (x3 && g_gemm_wide && M >= kWideMin && N >= kWideMin) {
-    const int64_t ntm = (M + kWT - 1) / kWT, ntw = (N + kWT - 1) / kWT, n_tiles = ntm * ntw;
-    const int64_t grid = kXcd * ((ntm + kXcd - 1) / kXcd) * ntw;
-    hipLaunchKernelGGL(k_gemm_nt_x3w, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk), dim3(kWThreads), 0, st, M,
-                       N, ntw, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles, kc, M * N);
-  } else {
-    const int64_t ntm = M / kT, n_tiles = ntm * ntn;
-    const int64_t grid = kXcd * ((ntm + kXcd - 1) / kXcd) * ntn;
-    hipLaunchKernelGGL(x3 ? k_gemm_nt_x3 : k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk),
-                       dim3(kThreads), 0, st, ntn, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1,
-                       n_tiles, kc, M * N);
-  }
+  const int64_t ntm = M / kT, n_tiles = ntm * ntn, nchunk = (M + kc - 1) / kc;
+  const int64_t grid = kXcd * ((ntm + kXcd - 1) / kXcd) * ntn;
+  hipLaunchKernelGGL(x3 ? k_gemm_nt_x3 : k_gemm_nt_f32, dim3((unsigned)grid, (unsigned)nb, (unsigned)nchunk),
+                     dim3(kThreads), 0, st, ntn, M, 1.0f, W, ldw, sW, Pt, ldp, sPt, 0.0f, parts, N, sParts, 0, 1, n_tiles,
+                     kc, M * N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nq = M * (N / 4);

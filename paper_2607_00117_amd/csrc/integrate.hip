@@ -140,11 +140,6 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_multi_dense = value;
     return SW_OK;
   }
-  if (k == "factor_gemm_tile") {
-    SW_CHECK(value == 128 || value == 256, "sw_set_tuning: factor_gemm_tile: 128 or 256");
-    g_gemm_wide = value == 256 ? 1 : 0;
-    return SW_OK;
-  }
   if (k == "refine_passes") {
     SW_CHECK(value == 2 || value == 4, "sw_set_tuning: refine_passes: 2 (h carried) or 4 (residual from A)");
     g_refine_two = value == 2 ? 1 : 0;
@@ -183,7 +178,6 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "gram_skip") return g_gram_dense ? 0 : 1;
   if (k == "refine_passes") return g_refine_two ? 2 : 4;
   if (k == "multi_dense") return g_multi_dense;
-  if (k == "factor_gemm_tile") return g_gemm_wide ? 256 : 128;
   return -1;
 }
 

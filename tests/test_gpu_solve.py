@@ -388,31 +388,3 @@ def test_two_pass_iterations_match_four(gpu, flags):
         assert np.abs(w - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL, passes
     assert np.abs(out[2][0] - out[4][0]).sum() <= 1e-4 * np.abs(out[4][0]).sum()
 
-
-def test_factor_tiles_agree(gpu):
-    """The factorisation's split-bf16 products on 256 x 256 tiles and on
-    128 x 128 tiles, at a size where the Cholesky has trailing updates and the
-    inversion split products whose edge tiles are half outside the matrix
-    (2,944 constraints = 23 blocks of 128): both solves converge to the KKT
-    tolerance, in iteration counts within 20% of each other (the factor only
-    preconditions the FP64 iteration, so a wrong product would show as a slower
-    or failed iteration), to the same weights within 1e-4 (L1)."""
-    P = lib()
-    n, c = 6000, 2944
-    blocks = [(0, 400), (400, c)]
-    A = W.sparse_lognormal_matrix(n, blocks, density=0.05, seed=12)
-    d, sig, wt = mock_problem(A, blocks, 8, 0.02, 0.02)
-    out = {}
-    old = P.get_tuning("factor_gemm_tile")
-    try:
-        for tile in (128, 256):
-            P.set_tuning("factor_gemm_tile", tile)
-            w, status, rep, _ = gpu_solve(A, d, sig, wt, 1e-2, 1)
-            out[tile] = (w, status, rep.refine_iters, rep.kkt)
-    finally:
-        P.set_tuning("factor_gemm_tile", old)
-    print({k: v[1:] for k, v in out.items()})
-    for tile, (w, status, _, kkt) in out.items():
-        assert status == 0 and kkt <= 1e-7, tile
-    assert abs(out[256][2] - out[128][2]) <= 0.2 * out[128][2] + 10
-    assert np.abs(out[256][0] - out[128][0]).sum() <= 1e-4 * np.abs(out[128][0]).sum()
