@@ -19,6 +19,7 @@ oracle's whole build of a seeded orbit subsample, and `errors_vs_oracle` the
 GPU's errors against the oracle on that subsample and on the headline solve.
 """
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -226,6 +227,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate", "paper"])
     ap.add_argument("--bs23-steps", type=int, default=0, help="paper: accepted BS23 steps (0: the paper's 5,000)")
+    ap.add_argument("--warm-bootstraps", action="store_true",
+                    help="paper: fit the observed maps first and start the bootstrap solves from those weights")
     ap.add_argument("--bs23-precision", default="f32", choices=["f32", "f64"],
                     help="paper: arithmetic of the BS23 integration (the drift check is FP64 either way)")
     ap.add_argument("--n-train", type=int, default=20000, help="surrogate: training builds")
@@ -898,6 +901,14 @@ def bench_paper(args):
     Wb = torch.empty((B, n_ic), dtype=torch.float64, device=dev)
     sws = torch.empty(P.solve_multi_workspace_bytes(n_ic, nf, B, opts), dtype=torch.uint8, device=dev)
     cws = torch.empty(P.chi2_workspace_bytes(nf), dtype=torch.uint8, device=dev)
+    # with --warm-bootstraps: the observed maps' own fit, whose weights start the bootstrap solves
+    warm = args.warm_bootstraps
+    w_obs = torch.empty(n_ic, dtype=torch.float64, device=dev)
+    ows = torch.empty(P.solve_workspace_bytes(n_ic, nf, opts) if warm else 1, dtype=torch.uint8, device=dev)
+    mopts = P._lib.SolveOpts()
+    ctypes.memmove(ctypes.addressof(mopts), ctypes.addressof(opts), ctypes.sizeof(opts))
+    if warm:
+        mopts.w0, mopts.w0_shared = w_obs.data_ptr(), 1
     res = []
 
     def step():
@@ -907,7 +918,11 @@ def bench_paper(args):
                             n_gh=n_gh)
             P.bootstrap_data(d_t, s_t, e_t, n_mass, nf, D_t)
             ev[4].record()
-            st, reps = P.solve_weights_multi(F, D_t, s_t, w_tilde, -1.0, opts, Wb, sws)
+            it_obs = 0
+            if warm:
+                st_o, rep_o = P.solve_weights(F, d_t, s_t, w_tilde, -1.0, opts, w_obs, ows)
+                it_obs = rep_o.refine_iters
+            st, reps = P.solve_weights_multi(F, D_t, s_t, w_tilde, -1.0, mopts, Wb, sws)
             chis = [P.chi2(F, Wb[b], d_t, s_t, n_mass, nf, cws) for b in range(B)]
             xm = P.chi2_model(chis)
             ev[5].record()
@@ -915,7 +930,7 @@ def bench_paper(args):
         res.append({"ms": {"ics": ev[0].elapsed_time(ev[1]), "bs23": ev[1].elapsed_time(ev[2]),
                            "bundle_cellmass": ev[2].elapsed_time(ev[3]), "fit_matrix": ev[3].elapsed_time(ev[4]),
                            "bootstrap_solve_chi2": ev[4].elapsed_time(ev[5])},
-                    "status": st, "iters_max": max(r.refine_iters for r in reps),
+                    "status": st, "iters_max": max(r.refine_iters for r in reps), "iters_observed_fit": it_obs,
                     "kkt_max": max(r.kkt for r in reps), "chi2_range": [min(chis), max(chis)], "chi2_model": xm,
                     "flagged_orbits": int((fl != 0).sum().item())})
 
@@ -1024,10 +1039,10 @@ def bench_surrogate(args):
             # the chains' neighbourhood only: the full builds of the chains so far, with the target
             # standardised over them, so that the network resolves chi^2 differences of a few dchi2
             # there instead of the range of the whole prior box
-            sur.fit(th_b, chi_b, epochs=60, batch=256, seed=len(chi_b))
+            sur.fit(th_b, chi_b, epochs=150, batch=256, seed=len(chi_b))
 
         res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log,
-                           refit=refit, refit_every=max(10, adapt // 5), adapt_steps=adapt)
+                           refit=refit, refit_every=max(10, adapt // 10), adapt_steps=adapt)
         res_mh = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=False, log=log,
                            adapt_steps=adapt)
         # the screen's error where the chains walk: full builds made after adaptation

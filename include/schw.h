@@ -228,6 +228,15 @@ typedef struct {
   double tol_kkt;      /* target relative KKT residual of the FP64 stage (<= 0: 1e-7) */
   double nu;           /* relative regularisation used when lambda < 0 */
   const uint8_t* mask; /* device [n_orb], nonzero = orbit excluded (e.g. flags); may be NULL */
+  const double* w0;    /* device: initial weights (warm start) in the layout of w, or NULL (cold
+                          start).  The FP64 stage then starts from x = z = w0 / w~ with the dual
+                          u = -(U^T (U x - y) + mu x) / rho, which makes that point stationary for
+                          its own data; the solution does not depend on w0 (a convex problem),
+                          only the iteration count does.  Bootstrap realisations started from the
+                          observed data's weights need fewer iterations. */
+  int32_t w0_shared;   /* 1: w0 holds one problem's weights [n_orb], used for every problem (the
+                          data vectors of solve_weights_multi) */
+  int32_t reserved;
 } sw_solve_opts;
 
 typedef struct {

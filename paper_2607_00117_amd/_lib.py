@@ -53,7 +53,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("gram", C.c_int32), ("max_iter", C.c_int32), ("refine_iter", C.c_int32),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("flags", C.c_int32),
                 ("rho", C.c_double), ("tol", C.c_double),
-                ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p)]
+                ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p), ("w0", C.c_void_p),
+                ("w0_shared", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveReport(C.Structure):

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_f32(int64_t ntn, int64_t K
 // C = beta C + alpha (A_hi B_hi^T + A_hi B_lo^T + A_lo B_hi^T) on bf16 MFMA
 // (32x32x16) with fp32 accumulation: the dropped terms are ~2^-16 of each
 // product.  Same tiles, schedule and split-K as k_gemm_nt_f32; operands are
-// staged as hi/lo planes in LDS (rows padded to 80 bytes).
+// staged as hi/lo planes in two LDS buffers (rows padded to 80 bytes).
 // ---------------------------------------------------------------------------
 constexpr int kX3Pad = kBKf + 8;
 
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K,
   A += blockIdx.y * sA;
   B += blockIdx.y * sB;
   C += blockIdx.y * sC;
-  __shared__ __attribute__((aligned(16))) __bf16 sm[4][kT][kX3Pad];  // A hi, B hi, A lo, B lo
+  __shared__ __attribute__((aligned(16))) __bf16 sm[2][4][kT][kX3Pad];  // [buffer] A hi, B hi, A lo, B lo
   int64_t tm, tn;
   if (!gemm_tile(ntn, lower, a_lower, n_tiles, tm, tn)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -429,36 +429,43 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K,
     Kend = kbeg + kc < Kend ? kbeg + kc : Kend;
     C += (int64_t)blockIdx.z * sPart;
   }
-  gload(kbeg);
-  for (int64_t k0 = kbeg; k0 < Kend; k0 += kBKf) {
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + kThreads * i;
       const int r = idx >> 3, c = (idx & 7) * 4;
       __bf16 h[4], l[4];
       split4(ra[i], h, l);
-      *reinterpret_cast<uint2*>(&sm[0][r][c]) = *reinterpret_cast<const uint2*>(h);
-      *reinterpret_cast<uint2*>(&sm[2][r][c]) = *reinterpret_cast<const uint2*>(l);
+      *reinterpret_cast<uint2*>(&sm[buf][0][r][c]) = *reinterpret_cast<const uint2*>(h);
+      *reinterpret_cast<uint2*>(&sm[buf][2][r][c]) = *reinterpret_cast<const uint2*>(l);
       split4(rb[i], h, l);
-      *reinterpret_cast<uint2*>(&sm[1][r][c]) = *reinterpret_cast<const uint2*>(h);
-      *reinterpret_cast<uint2*>(&sm[3][r][c]) = *reinterpret_cast<const uint2*>(l);
+      *reinterpret_cast<uint2*>(&sm[buf][1][r][c]) = *reinterpret_cast<const uint2*>(h);
+      *reinterpret_cast<uint2*>(&sm[buf][3][r][c]) = *reinterpret_cast<const uint2*>(l);
     }
-    __syncthreads();
-    if (k0 + kBKf < Kend) gload(k0 + kBKf);
+  };
+  // two stage buffers: while one is multiplied the next stage is fetched into
+  // registers and then written to the other, one barrier per stage
+  int buf = 0;
+  gload(kbeg);
+  stage(0);
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < Kend; k0 += kBKf) {
+    const bool more = k0 + kBKf < Kend;
+    if (more) gload(k0 + kBKf);
 #pragma unroll
     for (int ks = 0; ks < kBKf / 16; ++ks) {
       const int kcol = ks * 16 + 8 * (lane >> 5);
       bf16x8 bh[2], bl[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        bh[b] = *reinterpret_cast<const bf16x8*>(&sm[1][wn * 64 + b * 32 + (lane & 31)][kcol]);
-        bl[b] = *reinterpret_cast<const bf16x8*>(&sm[3][wn * 64 + b * 32 + (lane & 31)][kcol]);
+        bh[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][1][wn * 64 + b * 32 + (lane & 31)][kcol]);
+        bl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][3][wn * 64 + b * 32 + (lane & 31)][kcol]);
       }
       bf16x8 ah[2], al[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        ah[a] = *reinterpret_cast<const bf16x8*>(&sm[0][wm * 64 + a * 32 + (lane & 31)][kcol]);
-        al[a] = *reinterpret_cast<const bf16x8*>(&sm[2][wm * 64 + a * 32 + (lane & 31)][kcol]);
+        ah[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][0][wm * 64 + a * 32 + (lane & 31)][kcol]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][2][wm * 64 + a * 32 + (lane & 31)][kcol]);
       }
       // sweeps over the 4 accumulators: no MFMA waits for the one before it
 #pragma unroll
@@ -474,7 +481,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt_x3(int64_t ntn, int64_t K,
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)

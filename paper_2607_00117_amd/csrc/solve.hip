@@ -128,6 +128,43 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
   }
 }
 
+// The same operand for the bf16 modes, one 256 x 32 stage block per workgroup:
+// thread t owns row n0 + t of the block (a constraint) and its 32 orbit
+// columns, so the reads of each orbit are 1 KB runs of A's row and the block is
+// written as 64 contiguous bytes per thread (16 KB per plane, front to back).
+template <typename TA, bool X3>
+__global__ __launch_bounds__(256) void k_prep_xb(const TA* __restrict__ A, int64_t C, int64_t Npt,
+                                                 const int64_t* __restrict__ off, const int64_t* __restrict__ xoff,
+                                                 int nprob, const double* __restrict__ sigma,
+                                                 const double* __restrict__ par, const uint8_t* __restrict__ mask,
+                                                 __bf16* __restrict__ hi, __bf16* __restrict__ lo,
+                                                 const int32_t* __restrict__ perm) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;  // row of X (constraint)
+  const int64_t c0 = (int64_t)blockIdx.y * 32;                 // first column of the stage
+  const int b = find_problem(xoff, nprob, c0);                   // stages never straddle problems
+  const int64_t nb = off[b + 1] - off[b];
+  const double sc = n < C ? par[b * kPar + 0] / sigma[(int64_t)b * C + n] : 0.0;
+  __bf16 h[32], l[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int64_t jj = c0 - xoff[b] + j;
+    float v = 0.0f;
+    if (jj < nb && n < C) {
+      const int64_t i = off[b] + (perm ? perm[off[b] + jj] : jj);
+      if (!(mask && mask[i])) v = (float)((double)A[i * C + n] * sc);
+    }
+    h[j] = (__bf16)v;
+    if constexpr (X3) l[j] = (__bf16)(v - (float)h[j]);
+  }
+  __bf16* ph = hi + gram_at(n, c0, Npt);
+  __bf16* pl = lo + gram_at(n, c0, Npt);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    *reinterpret_cast<uint4*>(ph + 8 * q) = *reinterpret_cast<const uint4*>(h + 8 * q);
+    if constexpr (X3) *reinterpret_cast<uint4*>(pl + 8 * q) = *reinterpret_cast<const uint4*>(l + 8 * q);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense passes of one shared matrix over all right-hand sides on FP64 MFMA
 // (v_mfma_f64_16x16x4): out[m][z][n] = sum over k in chunk z of V[m][k] B(k, n),
@@ -1228,6 +1265,39 @@ __global__ void k_scale_out(const double* __restrict__ z, int64_t N, const int64
   if (i < N) w[i] = par[find_problem(off, nprob, i) * kPar + 0] * z[i];
 }
 
+// Warm start of the FP64 stage: x = z = w0 / w~_b (zero for masked orbits), u = 0,
+// v = z; w0 in the layout of w, or (one) a single problem's vector for all;
+// the mask is indexed by the orbit within the matrix when it is shared.
+__global__ void k_warm_start(const double* __restrict__ w0, int one, int shared, int64_t N,
+                             const int64_t* __restrict__ off, int nprob, const double* __restrict__ par,
+                             const uint8_t* __restrict__ mask, double* __restrict__ x, double* __restrict__ z,
+                             double* __restrict__ u, double* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int b = find_problem(off, nprob, i);
+  const bool masked = mask && mask[shared ? i - off[b] : i];
+  const double val = masked ? 0.0 : w0[one ? i - off[b] : i] / par[b * kPar + 0];
+  x[i] = val;
+  z[i] = val;
+  u[i] = 0.0;
+  v[i] = val;
+}
+
+// the dual that makes (x, z = x) stationary: u = -(h - q + mu x) / rho, h = U^T U x; v = z - u
+__global__ void k_warm_dual(int64_t N, const int64_t* __restrict__ off, int nprob, const double* __restrict__ par,
+                            const uint8_t* __restrict__ mask, int shared, const double* __restrict__ h,
+                            const double* __restrict__ q, const double* __restrict__ x, const double* __restrict__ z,
+                            double* __restrict__ u, double* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int b = find_problem(off, nprob, i);
+  const bool masked = mask && mask[shared ? i - off[b] : i];
+  const double rho = par[b * kPar + 1], mu = par[b * kPar + 3];
+  const double uu = masked ? 0.0 : -(h[i] - q[i] + mu * x[i]) / rho;
+  u[i] = uu;
+  v[i] = masked ? 0.0 : z[i] - uu;
+}
+
 // chi^2 over [cb, ce): one block, fixed summation order.
 __global__ void k_chi2_final(const double* __restrict__ m, const double* __restrict__ d,
                              const double* __restrict__ sigma, int64_t cb, int64_t ce, double* __restrict__ out) {
@@ -2119,6 +2189,10 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     SW_CHECK(std::isfinite(w_tilde[b]) && w_tilde[b] > 0.0, "solve_weights: w_tilde must be finite and > 0");
   }
   SW_CHECK(std::isfinite(lambda), "solve_weights: lambda must be finite");
+  if (opt->w0 && opt->w0_shared)
+    for (int b = 0; b < n_prob; ++b)
+      SW_CHECK(orbit_offsets[b + 1] - orbit_offsets[b] == orbit_offsets[1],
+               "solve_weights: w0_shared needs every problem to have the orbits of the first");
   SW_CHECK(lambda >= 0.0 || (std::isfinite(opt->nu) && opt->nu > 0.0),
            "solve_weights: lambda < 0 needs opt->nu > 0");
   SW_CHECK(opt->gram == SW_GRAM_BF16 || opt->gram == SW_GRAM_BF16X3 || opt->gram == SW_GRAM_F32,
@@ -2206,7 +2280,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     X.dcs = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSlabs, 2048 / ct, L.NA / 256}));
     X.drd = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kDenseChunks, 2048 / rt, L.C / 128}));
   }
-  {
+  if (opt->gram == SW_GRAM_F32) {
     dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
     if (dtype == SW_F32)
       hipLaunchKernelGGL(k_prep_x<float>, grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d, X.xoff_d,
@@ -2216,6 +2290,26 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
       hipLaunchKernelGGL(k_prep_x<double>, grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt, X.aoff_d,
                          X.xoff_d, PA, sigma, X.par, mask, opt->gram, X.p<__bf16>(L.off_hi), X.p<__bf16>(L.off_lo),
                          X.p<float>(L.off_xf), X.perm);
+    SW_TRY(hipGetLastError());
+  } else {
+    const dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 256), (unsigned)(L.Npt / 32));
+    __bf16 *hp = X.p<__bf16>(L.off_hi), *lp = X.p<__bf16>(L.off_lo);
+    const bool x3 = opt->gram == SW_GRAM_BF16X3;
+    if (dtype == SW_F32) {
+      if (x3)
+        hipLaunchKernelGGL((k_prep_xb<float, true>), grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d,
+                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+      else
+        hipLaunchKernelGGL((k_prep_xb<float, false>), grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d,
+                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+    } else {
+      if (x3)
+        hipLaunchKernelGGL((k_prep_xb<double, true>), grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt,
+                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+      else
+        hipLaunchKernelGGL((k_prep_xb<double, false>), grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt,
+                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+    }
     SW_TRY(hipGetLastError());
   }
   const uint64_t* nzbits = nullptr;
@@ -2513,6 +2607,24 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     }
     return hipSuccess;
   };
+  if (opt->w0) {
+    // warm start: x = z = w0 / w~, then its dual from h = U^T U x (two passes over A)
+    hipLaunchKernelGGL(k_warm_start, dim3(blocks_for(L.N)), dim3(256), 0, X.st, opt->w0, opt->w0_shared ? 1 : 0,
+                       shared ? 1 : 0, L.N, X.off_d, P, X.par, mask, xd, zd, ud, vd);
+    SW_TRY(hipGetLastError());
+    SW_TRY(colsum<double>(X, xd));
+    SW_TRY(colreduce(X, COL_PLAIN, nullptr, nullptr, td, nullptr));
+    SW_TRY(colscale<double>(X, td));
+    RowArgs Rw = RA;
+    Rw.op = ROW_H;
+    Rw.acc = nullptr;
+    Rw.hd = hd;
+    SW_TRY(rowdot(X, Rw));
+    hipLaunchKernelGGL(k_warm_dual, dim3(blocks_for(L.N)), dim3(256), 0, X.st, L.N, X.off_d, P, X.par, mask,
+                       shared ? 1 : 0, (const double*)hd, (const double*)qd, (const double*)xd, (const double*)zd, ud,
+                       vd);
+    SW_TRY(hipGetLastError());
+  }
   if (two) SW_TRY(refresh());  // h of the iterate entering the stage, before the history takes it
   if (aa) {
     hipLaunchKernelGGL(k_aa_init, dim3(blocks_for(std::max<int64_t>(L.N, P))), dim3(256), 0, X.st, AA);
