@@ -591,6 +591,8 @@ def bench_walkers(args):
     opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
     opts.mask = fl.data_ptr()
     opts.refine_iter = 5000  # the hardest walkers need up to ~2,500 accelerated iterations
+    if args.rho is not None:
+        opts.rho = -args.rho
     if args.no_accel:
         opts.flags |= P.SW_SOLVE_NO_ACCEL
     w = torch.empty(n_tot, dtype=torch.float64, device=dev)

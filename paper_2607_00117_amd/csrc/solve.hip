@@ -34,7 +34,6 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
-#include <type_traits>
 #include <vector>
 
 #include "gemm.h"
@@ -177,22 +176,25 @@ __global__ __launch_bounds__(256) void k_prep_xb(const TA* __restrict__ A, int64
 // owns a 128 x 64 output tile (vectors x outputs; four waves of 64 x 32 = 4 x 2
 // MFMA blocks of 16 x 16, so the matrix is read once per pass for up to 128
 // vectors) and one chunk of K.  Both operands are staged through LDS 16 at a
-// time, k-major (rows padded by 128 bytes so that the two halves of a wave's
-// operand read fall in different banks), double-buffered: the next k-step is
+// time as [row][k] tiles whose rows are padded to 17 doubles, so that the
+// MFMA operand reads (16 rows at one k per quarter-wave) and the staging
+// writes fall in distinct banks; consecutive lanes load consecutive addresses
+// of A and of the vectors (a wave's load touches 4 rows, or one, of 128 bytes
+// or more), whichever way A is walked.  Double-buffered: the next k-step is
 // loaded into registers while the current one is multiplied, one barrier per
 // step.  The chunks' partials are summed in order by the reductions of the
 // compressed passes.
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kDM = 128, kDN = 64, kDK = 16;
-constexpr int kDMP = kDM + 16, kDNP = kDN + 16;
+constexpr int kDKP = kDK + 1;
 
 template <typename TV, typename TA, bool TRANSB>
 __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_t K, const TV* __restrict__ V,
                                                    int64_t ldv, const TA* __restrict__ A, int64_t lda, int64_t kc,
                                                    double* __restrict__ out, int64_t ldo, int64_t so) {
-  __shared__ double Vs[2][kDK][kDMP];  // [k][m]
-  __shared__ double Bs[2][kDK][kDNP];  // [k][n]
+  __shared__ double Vs[2][kDM][kDKP];  // [m][k]
+  __shared__ double Bs[2][kDN][kDKP];  // [n][k]
   const int64_t m0 = (int64_t)blockIdx.y * kDM, n0 = (int64_t)blockIdx.x * kDN;
   const int64_t k_beg = (int64_t)blockIdx.z * kc;
   const int64_t k_end = k_beg + kc < K ? k_beg + kc : K;
@@ -203,80 +205,65 @@ __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // staging: V row vm = tid / 2, k offsets vk .. vk + 7; B: TRANSB row (n) bn =
-  // tid / 4, k offsets bk .. bk + 3, else k row tid / 16, n offsets 4 (tid % 16) ..
-  // Two register sets: while k-step t is multiplied from LDS, step t + 1 waits
-  // in one set (to be staged after the multiply) and step t + 2 loads into the
-  // other, so a load has two steps of MFMA work to arrive.
-  const int vm = tid >> 1, vk = (tid & 1) * 8;
-  const int bq = TRANSB ? (tid >> 2) : (tid >> 4), bo = TRANSB ? (tid & 3) * 4 : (tid & 15) * 4;
-  double rv[2][8], rb[2][4];
-  auto gload = [&](auto SET, int64_t k0) {
-    constexpr int q = decltype(SET)::value;
-    const int64_t m = m0 + vm;
+  // staging: element e = tid + 256 q of the V tile is row e / 16, k e % 16; of the
+  // A tile, TRANSB (A[n][k]) row n = e / 16, k e % 16, else (A[k][n]) k = e / 64,
+  // n = e % 64: consecutive lanes read consecutive addresses
+  const int64_t vrow = m0 + (tid >> 4), vcol = tid & 15;
+  const TV* __restrict__ Vp = V + vrow * ldv + vcol;
+  double rv[8], rb[4];
+  auto gload = [&](int64_t k0) {
+    const bool kin = k0 + vcol < k_end;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t k = k0 + vk + j;
-      rv[q][j] = (m < M && k < k_end) ? (double)V[m * ldv + k] : 0.0;
-    }
+    for (int j = 0; j < 8; ++j)
+      rv[j] = (kin && vrow + 16 * j < M) ? (double)Vp[16 * j * ldv + k0] : 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
       if (TRANSB) {  // A[n][k]
-        const int64_t n = n0 + bq, k = k0 + bo + j;
-        rb[q][j] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
+        const int64_t n = n0 + (e >> 4), k = k0 + (e & 15);
+        rb[j] = (n < Nn && k < k_end) ? (double)A[n * lda + k] : 0.0;
       } else {  // A[k][n]
-        const int64_t k = k0 + bq, n = n0 + bo + j;
-        rb[q][j] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
+        const int64_t k = k0 + (e >> 6), n = n0 + (e & 63);
+        rb[j] = (n < Nn && k < k_end) ? (double)A[k * lda + n] : 0.0;
       }
     }
   };
-  auto stage = [&](auto SET, int buf) {
-    constexpr int q = decltype(SET)::value;
+  auto stage = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Vs[buf][vk + j][vm] = rv[q][j];
+    for (int j = 0; j < 8; ++j) Vs[buf][(tid >> 4) + 16 * j][vcol] = rv[j];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (TRANSB) Bs[buf][bo + j][bq] = rb[q][j];
-      else Bs[buf][bq][bo + j] = rb[q][j];
+      const int e = tid + 256 * j;
+      if (TRANSB) Bs[buf][e >> 4][e & 15] = rb[j];
+      else Bs[buf][e & 63][e >> 6] = rb[j];
     }
   };
-  auto multiply = [&](int buf) {
+  int buf = 0;
+  if (k_beg < k_end) {
+    gload(k_beg);
+    stage(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += kDK) {
+    const bool more = k0 + kDK < k_end;
+    if (more) gload(k0 + kDK);
 #pragma unroll
     for (int ks = 0; ks < kDK; ks += 4) {
       const int kr = ks + (lane >> 4);
       double av[4], bv[2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = Vs[buf][kr][wm * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 4; ++a) av[a] = Vs[buf][wm * 64 + a * 16 + (lane & 15)][kr];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kr][wn * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][wn * 32 + b * 16 + (lane & 15)][kr];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
-  };
-  using S0 = std::integral_constant<int, 0>;
-  using S1 = std::integral_constant<int, 1>;
-  if (k_beg < k_end) {
-    gload(S0{}, k_beg);
-    stage(S0{}, 0);
-  }
-  if (k_beg + kDK < k_end) gload(S1{}, k_beg + kDK);
-  __syncthreads();
-  // step t (k0 = k_beg + t kDK) multiplies LDS buffer t % 2; set (t + 1) % 2 holds step t + 1
-  auto step = [&](auto PAR, int64_t k0) {
-    constexpr int t2 = decltype(PAR)::value;
-    using Cur = std::integral_constant<int, t2>;
-    using Nxt = std::integral_constant<int, 1 - t2>;
-    if (k0 + 2 * kDK < k_end) gload(Cur{}, k0 + 2 * kDK);
-    multiply(t2);
     // the other buffer was last read before the previous barrier
-    if (k0 + kDK < k_end) stage(Nxt{}, 1 - t2);
+    if (more) stage(buf ^ 1);
     __syncthreads();
-  };
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += 2 * kDK) {
-    step(S0{}, k0);
-    if (k0 + kDK < k_end) step(S1{}, k0 + kDK);
+    buf ^= 1;
   }
   out += (int64_t)blockIdx.z * so;
 #pragma unroll
