@@ -626,7 +626,8 @@ def bench_walkers(args):
         kkts = np.array([r.kkt for r in reps])
         log(f"step {i}: integrate {t_int[-1]:.1f} ms, solve+chi2 {t_solve[-1]:.1f} ms, "
             f"iters max {its.max()}+{rits.max()} median {int(np.median(its))}+{int(np.median(rits))}, "
-            f"converged {sum(r.converged for r in reps)}/{len(reps)}, kkt max {kkts.max():.2e}, nnz {reps[0].nnz:.3g}")
+            f"converged {sum(r.converged for r in reps)}/{len(reps)}, kkt max {kkts.max():.2e}, nnz {reps[0].nnz:.3g}, "
+            f"fp64 passes per iteration {reps[0].passes}")
         slow = np.argsort(-(its + 2 * rits))[:4]
         log("slowest walkers: " + "; ".join(f"#{k} n={offs[k + 1] - offs[k]} it={its[k]}+{rits[k]} kkt={kkts[k]:.1e} "
                                             f"chi2={chis[-1][k]:.4g}" for k in slow))
@@ -639,7 +640,7 @@ def bench_walkers(args):
            "orbit_steps_per_s": n_tot * n_steps * args.steps / el,
            "integrate_ms": float(np.mean(t_int)), "solve_chi2_ms": float(np.mean(t_solve)),
            "chi2_range": [float(np.min(chis[-1])), float(np.max(chis[-1]))],
-           "converged": f"{min(n_conv)}/{n_w}",
+           "converged": f"{min(n_conv)}/{n_w}", "fp64_passes_per_iteration": int(reps[0].passes),
            "converged_builds_per_s": min(n_conv) * args.steps / el}
     print(json.dumps(out))
 

@@ -254,6 +254,10 @@ typedef struct {
   double t_prep_ms, t_gram_ms, t_factor_ms, t_admm_ms, t_refine_ms;
   double nnz; /* nonzeros of A when the ADMM passes used the compressed copies, else 0
                  (dense passes over A, among them the FP64 MFMA passes of a shared matrix) */
+  int32_t passes;   /* passes over A per FP64 iteration at return: 2 (U^T U x carried with the
+                       iterate) or 4 (the residual from A; the solve falls back to it when a
+                       problem's KKT residual rebounds to 10x its smallest value) */
+  int32_t reserved;
 } sw_solve_report;
 
 int solve_weights(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, const double* d,
@@ -548,8 +552,12 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             alongside the iterate (updated by each correction,
  *                             mixed with it by the Anderson step, recomputed from
  *                             the matrix at the start of every batch of
- *                             iterations between convergence checks), or 4 (the
- *                             residual recomputed from the matrix every iteration)
+ *                             iterations between convergence checks; falling back
+ *                             to 4 when a problem's KKT residual rebounds to 10x
+ *                             its smallest value), or 4 (the residual recomputed
+ *                             from the matrix every iteration)
+ *   "refine_rebound"          the factor of that fall-back (default 10; 0 falls
+ *                             back at the second check, for tests)
  *   "gram_skip"               weight solve: 1 (default) skips the 32-orbit
  *                             stages of the Gram whose row or column panel of
  *                             the scaled matrix is zero (the result is the same

@@ -62,7 +62,8 @@ class SolveReport(C.Structure):
                 ("n_active", C.c_int32), ("mu", C.c_double), ("rho", C.c_double), ("kkt", C.c_double),
                 ("objective", C.c_double), ("primal_res", C.c_double), ("dual_res", C.c_double),
                 ("t_prep_ms", C.c_double), ("t_gram_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_admm_ms", C.c_double), ("t_refine_ms", C.c_double), ("nnz", C.c_double)]
+                ("t_admm_ms", C.c_double), ("t_refine_ms", C.c_double), ("nnz", C.c_double),
+                ("passes", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -140,6 +140,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_multi_dense = value;
     return SW_OK;
   }
+  if (k == "refine_rebound") {
+    SW_CHECK(value >= 0, "sw_set_tuning: refine_rebound: a factor >= 0");
+    g_refine_rebound = value;
+    return SW_OK;
+  }
   if (k == "refine_passes") {
     SW_CHECK(value == 2 || value == 4, "sw_set_tuning: refine_passes: 2 (h carried) or 4 (residual from A)");
     g_refine_two = value == 2 ? 1 : 0;
@@ -178,6 +183,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "gram_skip") return g_gram_dense ? 0 : 1;
   if (k == "refine_passes") return g_refine_two ? 2 : 4;
   if (k == "multi_dense") return g_multi_dense;
+  if (k == "refine_rebound") return g_refine_rebound;
   return -1;
 }
 

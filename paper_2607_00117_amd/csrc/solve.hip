@@ -61,6 +61,7 @@ constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChe
 int g_sparse_rows = 0;
 int g_gram_dense = 0;
 int g_refine_two = 1;
+int g_refine_rebound = 10;
 int g_multi_dense = 0;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
@@ -2498,7 +2499,13 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(L.N)), dim3(256), 0, X.st, vf, vd, L.N);
   SW_TRY(hipGetLastError());
   AAArgs AA;
-  const bool two = g_refine_two != 0;  // two passes over A per FP64 iteration, h carried
+  // two passes over A per FP64 iteration with h carried; the solve falls back to
+  // four (the residual from A every iteration) when a problem's KKT residual
+  // rebounds to 10x its smallest value: h drifts by U^T e / rho' per correction, e
+  // the fp32 inverse's residual, which the ten iterations between refreshes can
+  // let grow on badly conditioned problems
+  bool two = g_refine_two != 0;
+  const double rebound_factor = (double)g_refine_rebound;
   double* hd = X.p<double>(L.off_hd);
   AA.x = xd; AA.z = zd; AA.u = ud; AA.v = vd;
   AA.h = two ? hd : nullptr; AA.r = rd; AA.q = qd; AA.mask = mask; AA.shared = shared ? 1 : 0;
@@ -2619,6 +2626,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   }
   if (use_graph && n_active > 0) SW_TRY(capture([&]() { return refine_batch(check_every); }, 1, &g2.e));
   std::vector<int> rit(P, 0);
+  std::vector<double> kmin(P, HUGE_VAL);
   int k_done = 0;
   while (k_done < refine_iter && n_active > 0) {
     const int run = std::min(check_every, refine_iter - k_done);
@@ -2632,12 +2640,33 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
       if (active[b]) rit[b] = k_done;
     rc = kkt_eval();
     if (rc != SW_OK) return rc;
+    bool rebound = false;
+    for (int b = 0; b < P; ++b) {
+      if (!active[b]) continue;
+      if (kmin[b] < HUGE_VAL && kkt[b] > rebound_factor * kmin[b]) rebound = true;
+      kmin[b] = std::min(kmin[b], kkt[b]);
+    }
     for (int b = 0; b < P; ++b)
       if (active[b] && kkt[b] <= tol_kkt) {
         active[b] = 0;
         --n_active;
       }
     SW_TRY(set_active(active));
+    if (two && rebound && n_active > 0) {
+      // fall back to four passes for the rest of the solve: a new fixed-point map,
+      // so the Anderson history restarts from the current iterate
+      two = false;
+      AA.h = nullptr;
+      if (aa) {
+        hipLaunchKernelGGL(k_aa_init, dim3(blocks_for(std::max<int64_t>(L.N, P))), dim3(256), 0, X.st, AA);
+        SW_TRY(hipGetLastError());
+      }
+      if (g2.e) {
+        SW_TRY(hipGraphExecDestroy(g2.e));
+        g2.e = nullptr;
+        SW_TRY(capture([&]() { return refine_batch(check_every); }, 1, &g2.e));
+      }
+    }
   }
   int all_conv = 1;
   for (int b = 0; b < P; ++b) {
@@ -2647,6 +2676,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     R[b].converged = kkt[b] <= tol_kkt ? 1 : 0;
     R[b].n_active = support[b];
     R[b].nnz = X.sparse && !X.dense_rhs ? (double)X.nnz : 0.0;
+    R[b].passes = two ? 2 : 4;
     all_conv &= R[b].converged;
   }
   hipLaunchKernelGGL(k_scale_out, dim3(blocks_for(L.N)), dim3(256), 0, X.st, zd, L.N, X.off_d, P, X.par, w);

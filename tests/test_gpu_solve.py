@@ -388,3 +388,50 @@ def test_two_pass_iterations_match_four(gpu, flags):
         assert np.abs(w - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL, passes
     assert np.abs(out[2][0] - out[4][0]).sum() <= 1e-4 * np.abs(out[4][0]).sum()
 
+
+def test_two_pass_fallback_to_four(gpu):
+    """The two-pass FP64 stage falls back to four passes when a problem's KKT
+    residual rebounds; forced at the second check (rebound factor 0), the batched
+    solve still converges, reports four passes, and reaches the weights of the
+    plain four-pass solve within 1e-4 (L1) and the oracle's within the parity
+    bar."""
+    import torch
+    P = lib()
+    c = 500
+    blocks = [(0, 150), (150, c)]
+    sizes = [700, 1201]
+    mats, ds, sigs, wts = [], [], [], []
+    for k, n in enumerate(sizes):
+        A = W.sparse_lognormal_matrix(n, blocks, density=0.1, seed=40 + k)
+        d, sig, wt = mock_problem(A, blocks, 50 + k, 0.02, 0.02)
+        mats.append(A); ds.append(d); sigs.append(sig); wts.append(wt)
+    A = np.concatenate(mats)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A).to(dev)
+    dt = torch.from_numpy(np.stack(ds)).to(dev)
+    st = torch.from_numpy(np.stack(sigs)).to(dev)
+    opts = P._lib.SolveOpts()
+    opts.gram, opts.nu = 1, 1e-2
+    ws = torch.empty(P.solve_batched_workspace_bytes(off, c, opts), dtype=torch.uint8, device=dev)
+    out = {}
+    old_p, old_r = P.get_tuning("refine_passes"), P.get_tuning("refine_rebound")
+    try:
+        for name, passes, rebound in (("fallback", 2, 0), ("four", 4, 10)):
+            P.set_tuning("refine_passes", passes)
+            P.set_tuning("refine_rebound", rebound)
+            w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
+            status, reps = P.solve_weights_batched(At, off, dt, st, wts, -1.0, opts, w, ws)
+            out[name] = (w.cpu().numpy(), status, [r.passes for r in reps], [r.refine_iters for r in reps])
+    finally:
+        P.set_tuning("refine_passes", old_p)
+        P.set_tuning("refine_rebound", old_r)
+    print({k: v[1:] for k, v in out.items()})
+    assert out["fallback"][1] == 0 and out["four"][1] == 0
+    assert out["fallback"][2] == [4, 4]
+    wf, w4 = out["fallback"][0], out["four"][0]
+    assert np.abs(wf - w4).sum() <= 1e-4 * np.abs(w4).sum()
+    for k in range(2):
+        w_o, _ = oracle_solve(mats[k], ds[k], sigs[k], wts[k], 1e-2)
+        wk = wf[off[k]:off[k + 1]]
+        assert np.abs(wk - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
