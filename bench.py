@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate", "paper"])
     ap.add_argument("--bs23-steps", type=int, default=0, help="paper: accepted BS23 steps (0: the paper's 5,000)")
+    ap.add_argument("--no-quantum", action="store_true",
+                    help="store the compressed copies of a count matrix as fp32 values, not as counts")
     ap.add_argument("--warm-bootstraps", action="store_true",
                     help="paper: fit the observed maps first and start the bootstrap solves from those weights")
     ap.add_argument("--bs23-precision", default="f32", choices=["f32", "f64"],
@@ -311,6 +313,8 @@ def main():
     opts.gram = {"bf16": P.SW_GRAM_BF16, "bf16x3": P.SW_GRAM_BF16X3, "f32": P.SW_GRAM_F32}[args.gram]
     opts.nu = 1e-2
     opts.mask = mask.data_ptr()
+    if not args.no_quantum:
+        opts.quantum = P.count_quantum(obs, n_steps)  # the compressed copies hold counts
     if args.rho is not None:
         opts.rho = -args.rho
     w = torch.empty(n, dtype=torch.float64, device=dev)
@@ -590,6 +594,8 @@ def bench_walkers(args):
     opts = P._lib.SolveOpts()
     opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
     opts.mask = fl.data_ptr()
+    if not args.no_quantum:
+        opts.quantum = P.count_quantum(obs, n_steps)
     opts.refine_iter = 5000  # the hardest walkers need up to ~2,500 accelerated iterations
     if args.rho is not None:
         opts.rho = -args.rho

@@ -237,6 +237,13 @@ typedef struct {
   int32_t w0_shared;   /* 1: w0 holds one problem's weights [n_orb], used for every problem (the
                           data vectors of solve_weights_multi) */
   int32_t reserved;
+  double quantum;      /* > 0: every nonzero entry of A is the rounding to A's dtype of k * quantum,
+                          k an integer in 1..65535 (a histogram of counts, e.g. integrate_and_bin's
+                          leapfrog output, whose quantum is 1 / (ncopy n_steps) when there are no
+                          surface-density columns).  The compressed copies then store k (2 bytes
+                          instead of 4), and every pass over them computes with k * quantum exactly
+                          (so the FP64 stage solves for the exact multiples that A rounds).  An
+                          entry that is no such multiple fails the solve with SW_EINVAL.  0: off. */
 } sw_solve_opts;
 
 typedef struct {

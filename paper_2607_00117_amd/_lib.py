@@ -54,7 +54,7 @@ class SolveOpts(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32), ("flags", C.c_int32),
                 ("rho", C.c_double), ("tol", C.c_double),
                 ("tol_kkt", C.c_double), ("nu", C.c_double), ("mask", C.c_void_p), ("w0", C.c_void_p),
-                ("w0_shared", C.c_int32), ("reserved", C.c_int32)]
+                ("w0_shared", C.c_int32), ("reserved", C.c_int32), ("quantum", C.c_double)]
 
 
 class SolveReport(C.Structure):
@@ -186,6 +186,17 @@ def build_potential(components, omega=0.0, euler=(0.0, 0.0, 0.0)):
     out = Potential()
     _check(load().build_potential(C.byref(d), C.byref(out)))
     return out
+
+
+def count_quantum(obs, n_steps):
+    """opts.quantum for integrate_and_bin's output: its entries are counts of
+    1 / (ncopy n_steps), ncopy = 4 with the mirror copies, else 1; 0 (off) with
+    surface-density columns (divided by the mass-to-light ratio) or counts
+    that may exceed 65535."""
+    ncopy = 4 if obs.symmetrize else 1
+    if obs.surface or ncopy * int(n_steps) > 65535:
+        return 0.0
+    return 1.0 / (ncopy * int(n_steps))
 
 
 def obs_spec(spec, pix2ap=None):

@@ -438,12 +438,27 @@ __global__ __launch_bounds__(kColThreads) void k_col_nnz(const TA* __restrict__ 
   }
 }
 
+// The value stored for a nonzero entry a of A: a itself, or (TS = uint16_t,
+// a matrix of counts) the integer k with a the rounding of k q to A's type,
+// k in 1..65535; an entry that is no such multiple sets *bad.
+template <typename TA, typename TS>
+__device__ __forceinline__ TS store_val(TA a, double inv_quant, double quant, int* bad) {
+  if constexpr (sizeof(TS) == 2) {
+    const double k = rint((double)a * inv_quant);
+    const double tol = (sizeof(TA) == 4 ? 0x1p-22 : 0x1p-50) * fabs((double)a);
+    if (!(k >= 1.0 && k <= 65535.0 && fabs((double)a - k * quant) <= tol)) atomicOr(bad, 1);
+    return (TS)(k >= 1.0 && k <= 65535.0 ? k : 0.0);
+  } else {
+    return a;
+  }
+}
+
 // compressed rows: one wave per orbit; ballot + prefix count keeps column
 // order; each segment's padding is written as zero entries
-template <typename TA>
+template <typename TA, typename TS>
 __global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int64_t N, int64_t C, int ncb, int64_t blk,
                                                   const int64_t* __restrict__ ptr, uint16_t* __restrict__ col,
-                                                  TA* __restrict__ val) {
+                                                  TS* __restrict__ val, double inv_quant, double quant, int* bad) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
@@ -459,25 +474,26 @@ __global__ __launch_bounds__(256) void k_fill_csr(const TA* __restrict__ A, int6
       if (v != TA(0)) {
         const int64_t at = pos + __popcll(m & ((1ull << lane) - 1ull));
         col[at] = (uint16_t)(c - cbeg);
-        val[at] = v;
+        val[at] = store_val<TA, TS>(v, inv_quant, quant, bad);
       }
       pos += __popcll(m);
     }
     if (pos + lane < ptr[i * ncb + cb + 1]) {
       col[pos + lane] = 0;
-      val[pos + lane] = TA(0);
+      val[pos + lane] = TS(0);
     }
   }
 }
 
 // compressed columns: slab s of problem b writes its entries of column c
 // from the absolute position slab_at[b][s][c] on (padding is pre-cleared)
-template <typename TA>
+template <typename TA, typename TS>
 __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__ A, int64_t C,
                                                           const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ rps,
                                                           const int64_t* __restrict__ slab_at, int64_t blk,
-                                                          uint16_t* __restrict__ rowi, TA* __restrict__ val) {
+                                                          uint16_t* __restrict__ rowi, TS* __restrict__ val,
+                                                          double inv_quant, double quant, int* bad) {
   const int b = blockIdx.z;
   const int64_t c0 = (int64_t)blockIdx.x * kColTile, s = blockIdx.y;
   const int64_t i_beg = off[b] + s * rps[b];
@@ -500,7 +516,7 @@ __global__ __launch_bounds__(kColThreads) void k_fill_csc(const TA* __restrict__
         const TA v = A[i * C + c];
         if (v != TA(0)) {
           rowi[pos[q]] = (uint16_t)(i - blk0);
-          val[pos[q]] = v;
+          val[pos[q]] = store_val<TA, TS>(v, inv_quant, quant, bad);
           ++pos[q];
         }
       }
@@ -523,6 +539,10 @@ __device__ __forceinline__ void quad_val(const double* p, double v[4]) {
   const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
   const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
   v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+}
+__device__ __forceinline__ void quad_val(const uint16_t* p, double v[4]) {
+  const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
 }
 __device__ __forceinline__ void quad_idx(const uint16_t* p, uint32_t c[4]) {
   const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
@@ -658,7 +678,10 @@ __device__ __forceinline__ void rhs_load(const TA* __restrict__ val, const uint1
     const int64_t k = base + 4 * sl + (int64_t)i * 4 * LPR;
     ch.ok[i] = k < end;
     const int64_t kk = ch.ok[i] ? k : 0;
-    if constexpr (sizeof(TA) == 4) {
+    if constexpr (sizeof(TA) == 2) {
+      const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(val + kk));
+      ch.v[i][0] = q[0]; ch.v[i][1] = q[1]; ch.v[i][2] = q[2]; ch.v[i][3] = q[3];
+    } else if constexpr (sizeof(TA) == 4) {
       const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(val + kk));
       ch.v[i][0] = q[0]; ch.v[i][1] = q[1]; ch.v[i][2] = q[2]; ch.v[i][3] = q[3];
     } else {
@@ -689,7 +712,7 @@ __device__ __forceinline__ void rhs_use(const RhsChunk<LPR, R, Q, TA>& ch, const
 template <int LPR, int R, typename TA, typename SegF, typename OutF>
 __device__ __forceinline__ void seg_stream_rhs(const TA* __restrict__ val, const uint16_t* __restrict__ idx,
                                                const double* xs, int sl, int n_pass, SegF seg, OutF out) {
-  constexpr int Q = sizeof(TA) == 4 ? 4 : 2;  // quads per lane loaded at once
+  constexpr int Q = sizeof(TA) <= 4 ? 4 : 2;  // quads per lane loaded at once
   constexpr int64_t CH = (int64_t)Q * 4 * LPR;  // entries of the group per chunk
   int64_t b0, e0, b1, e1;
   seg(0, b0, e0);
@@ -842,7 +865,7 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
                                                    const double* __restrict__ par,
                                                    int op, const float* __restrict__ kyf, const double* __restrict__ y,
                                                    float* __restrict__ outf, double* __restrict__ outd,
-                                                   double* __restrict__ acc) {
+                                                   double* __restrict__ acc, double vscale) {
   const int b = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double wt = par[b * kPar + 0], rho = par[b * kPar + 1];
@@ -853,6 +876,7 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
     if (n < C) {
       const double* pb = part + (int64_t)b * kSlabs * C;
       for (int64_t s = 0; s < nslab; ++s) t += pb[s * C + n];
+      t *= vscale;  // compressed counts: the quantum
       if (op != COL_OBS) t *= wt / sigma[b * sS + n];
     }
     switch (op) {
@@ -924,6 +948,7 @@ struct RowArgs {
   const int64_t* csr_ptr;
   const void* csr_col;  // uint16_t column index within the column block
   const void* csr_val;
+  double vscale;        // the dots are multiplied by this (compressed counts: the quantum, else 1)
 };
 
 
@@ -940,6 +965,7 @@ constexpr int kRowSums = 9;
 
 // The update of orbit row i of problem b once its dot with sc is known.
 __device__ __forceinline__ void row_update(const RowArgs& R, int64_t i, int b, double dot, double* a) {
+  dot *= R.vscale;
   const double* P = R.par + b * kPar;
   const bool masked = R.mask && R.mask[R.shared ? i - R.off[b] : i];
   const double rho = P[1], rhop = P[2], mu = P[3], alpha = P[4];
@@ -1717,7 +1743,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   {  // device prefix sums of the segment lengths: block sums, totals, column segments
     const size_t nr = NA * L.ncb, nq = PA * L.nrb * L.C;
     const size_t nbr = (nr + kScanBlock - 1) / kScanBlock, nbc = (nq + kScanBlock - 1) / kScanBlock;
-    L.off_scan = take((2 * nbr + 2 * nbc + 4) * 8);
+    L.off_scan = take((2 * nbr + 2 * nbc + 5) * 8);  // block sums, 4 totals, the quantum check flag
     L.off_clen = take(nq * 8);
     L.off_cpos = take(nq * 8);
   }
@@ -1737,6 +1763,8 @@ struct Ctx {
   const void* A;
   int dtype;
   const double* sigma;
+  double quantum = 0.0;  // > 0: A holds roundings of integer multiples of it (compressed as counts)
+  bool quant = false;    // the compressed copies hold the counts (uint16), the passes scale by quantum
   int64_t sS;  // sigma of problem b at sigma + b * sS
   const int64_t *off_d, *xoff_d, *xlen_d, *rps_d, *aoff_d;
   double* par;
@@ -1781,7 +1809,8 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
     return hipGetLastError();
   }
   if (X.sparse && X.L.rg > 1) {
-    if (X.dtype == SW_F32) colsum_rhs<float, TV>(X, v);
+    if (X.quant) colsum_rhs<uint16_t, TV>(X, v);
+    else if (X.dtype == SW_F32) colsum_rhs<float, TV>(X, v);
     else colsum_rhs<double, TV>(X, v);
     return hipGetLastError();
   }
@@ -1793,7 +1822,11 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
     if (X.L.C * X.L.P < 64 * 256) cpw = std::max<int64_t>(kSpWaves, (X.L.C * X.L.P + 255) / 256 / kSpWaves * kSpWaves);
     if (g_sparse_cols > 0) cpw = g_sparse_cols;
     dim3 grid((unsigned)((X.L.C + cpw - 1) / cpw), (unsigned)X.L.P);
-    if (X.dtype == SW_F32)
+    if (X.quant)
+      hipLaunchKernelGGL((k_csc_colsum<uint16_t, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d,
+                         X.rps_d, X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow),
+                         X.p<uint16_t>(X.L.off_cval), v, X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
+    else if (X.dtype == SW_F32)
       hipLaunchKernelGGL((k_csc_colsum<float, TV>), grid, dim3(kSpThreads), 0, X.st, X.L.C, (int)cpw, X.off_d, X.rps_d,
                          X.L.nrb, X.p<int64_t>(X.L.off_cptr), X.p<uint16_t>(X.L.off_crow), X.p<float>(X.L.off_cval), v,
                          X.par, X.L.shared ? 1 : 0, X.p<double>(X.L.off_part));
@@ -1816,7 +1849,7 @@ static hipError_t colsum(const Ctx& X, const TV* v) {
 static hipError_t colreduce(const Ctx& X, int op, const float* kyf, float* outf, double* outd, double* acc) {
   hipLaunchKernelGGL(k_colreduce, dim3(blocks_for(X.L.Cp), (unsigned)X.L.P), dim3(256), 0, X.st,
                      X.p<double>(X.L.off_part), X.dense_rhs ? X.dcs : (X.sparse ? (X.L.rg > 1 ? X.L.nrb_a : 1) : kSlabs), X.L.C, X.L.Cp, X.sigma, X.sS, X.par, op, kyf, X.p<double>(X.L.off_ys), outf,
-                     outd, acc);
+                     outd, acc, X.quant && X.sparse && !X.dense_rhs ? X.quantum : 1.0);
   return hipGetLastError();
 }
 
@@ -1838,6 +1871,33 @@ static void launch_rowdot_rhs(const Ctx& X, const RowArgs& R) {
                      (const double*)pd, R);
 }
 
+// the compressed row dots, TS the stored value type
+template <typename TS>
+static void launch_rowdot_sparse(const Ctx& X, const RowArgs& R) {
+  const double* sc = X.p<double>(X.L.off_sc);
+  if (X.L.rg > 1) {
+    if (X.L.rg == 2) launch_rowdot_rhs<TS, 2>(X, R);
+    else if (X.L.rg == 4) launch_rowdot_rhs<TS, 4>(X, R);
+    else launch_rowdot_rhs<TS, 8>(X, R);
+    return;
+  }
+  int64_t nmax = 1;
+  for (int b = 0; b < X.L.P; ++b) nmax = std::max<int64_t>(nmax, X.L.off[b + 1] - X.L.off[b]);
+  // one 128 KB workgroup per CU: rows per workgroup chosen so that a single
+  // problem fills the 256 CUs in one round (no tail round), at most 512
+  int64_t per = (nmax + 255) / 256;
+  per = std::min<int64_t>(kMaxRowsWG, std::max<int64_t>(kSpWaves, (per + kSpWaves - 1) / kSpWaves * kSpWaves));
+  if (g_sparse_rows > 0) per = g_sparse_rows;
+  // rows with short segments (mean below 512 entries per column block) are
+  // taken by 16 lanes each, four rows per wave
+  const dim3 grid((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P);
+  const bool short_rows = g_sparse_lanes > 0 ? g_sparse_lanes == 16 : X.nnz < 512 * X.L.NA * X.L.ncb;
+  if (short_rows)
+    hipLaunchKernelGGL((k_rowdot_csr<TS, 16>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
+  else
+    hipLaunchKernelGGL((k_rowdot_csr<TS, 64>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
+}
+
 template <typename TA>
 static void launch_rowdot(const Ctx& X, const RowArgs& R) {
   const double* sc = X.p<double>(X.L.off_sc);
@@ -1852,28 +1912,8 @@ static void launch_rowdot(const Ctx& X, const RowArgs& R) {
                        R);
     return;
   }
-  if (X.sparse && X.L.rg > 1) {
-    if (X.L.rg == 2) launch_rowdot_rhs<TA, 2>(X, R);
-    else if (X.L.rg == 4) launch_rowdot_rhs<TA, 4>(X, R);
-    else launch_rowdot_rhs<TA, 8>(X, R);
-    return;
-  }
   if (X.sparse) {
-    int64_t nmax = 1;
-    for (int b = 0; b < X.L.P; ++b) nmax = std::max<int64_t>(nmax, X.L.off[b + 1] - X.L.off[b]);
-    // one 128 KB workgroup per CU: rows per workgroup chosen so that a single
-    // problem fills the 256 CUs in one round (no tail round), at most 512
-    int64_t per = (nmax + 255) / 256;
-    per = std::min<int64_t>(kMaxRowsWG, std::max<int64_t>(kSpWaves, (per + kSpWaves - 1) / kSpWaves * kSpWaves));
-    if (g_sparse_rows > 0) per = g_sparse_rows;
-    // rows with short segments (mean below 512 entries per column block) are
-    // taken by 16 lanes each, four rows per wave
-    const dim3 grid((unsigned)((nmax + per - 1) / per), (unsigned)X.L.P);
-    const bool short_rows = g_sparse_lanes > 0 ? g_sparse_lanes == 16 : X.nnz < 512 * X.L.NA * X.L.ncb;
-    if (short_rows)
-      hipLaunchKernelGGL((k_rowdot_csr<TA, 16>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
-    else
-      hipLaunchKernelGGL((k_rowdot_csr<TA, 64>), grid, dim3(kSpThreads), 0, X.st, X.L.C, X.L.ncb, (int)per, sc, R);
+    launch_rowdot_sparse<TA>(X, R);
   } else {
     hipLaunchKernelGGL(k_rowdot<TA>, dim3((unsigned)((X.L.N + 3) / 4)), dim3(kRowsBlock), 0, X.st, (const TA*)X.A,
                        X.L.N, X.L.C, sc, R);
@@ -1885,7 +1925,10 @@ static hipError_t rowdot(const Ctx& X, const RowArgs& R0) {
   R.csr_ptr = X.p<int64_t>(X.L.off_rptr);
   R.csr_col = X.p<void>(X.L.off_rcol);
   R.csr_val = X.p<void>(X.L.off_rval);
-  if (X.dtype == SW_F32) launch_rowdot<float>(X, R);
+  const bool counts = X.quant && X.sparse && !X.dense_rhs;
+  R.vscale = counts ? X.quantum : 1.0;
+  if (counts) launch_rowdot_sparse<uint16_t>(X, R);
+  else if (X.dtype == SW_F32) launch_rowdot<float>(X, R);
   else launch_rowdot<double>(X, R);
   return hipGetLastError();
 }
@@ -2070,19 +2113,34 @@ static int build_sparse(Ctx& X) {
   // compressed passes pay off well below 2/3 density; copies are kept up to
   // kMaxDensity and the capacity of the workspace
   const bool fits = at <= L.cap_nnz && pos <= L.cap_nnz && (double)nnz <= kMaxDensity * (double)NA * (double)L.C;
+  int* bad = reinterpret_cast<int*>(tot + 4);
   if (fits) {
-    hipLaunchKernelGGL(k_fill_csr<TA>, dim3((unsigned)((NA + 3) / 4)), dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
-                       X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval));
+    // values: A's own, or with a quantum the integer counts (checked entry by entry)
+    X.quant = X.quantum > 0.0;
+    const double q = X.quantum, inv_q = X.quant ? 1.0 / X.quantum : 0.0;
+    const dim3 gr((unsigned)((NA + 3) / 4)), gc((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs, (unsigned)P);
+    const int64_t idx_words = (pos + 1) / 2;
+    const int64_t val_words = X.quant ? (pos + 1) / 2 : pos * (int64_t)(sizeof(TA) / 4);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, X.st, bad, (int64_t)1, 0);
+    if (X.quant)
+      hipLaunchKernelGGL((k_fill_csr<TA, uint16_t>), gr, dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
+                         X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<uint16_t>(L.off_rval), inv_q, q, bad);
+    else
+      hipLaunchKernelGGL((k_fill_csr<TA, TA>), gr, dim3(256), 0, X.st, A, NA, L.C, ncb, L.blk,
+                         X.p<int64_t>(L.off_rptr), X.p<uint16_t>(L.off_rcol), X.p<TA>(L.off_rval), inv_q, q, bad);
     // column padding: clear the compressed columns, then fill the entries
-    const int64_t idx_words = (pos + 1) / 2, val_words = pos * (int64_t)(sizeof(TA) / 4);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(idx_words)), dim3(256), 0, X.st, X.p<int>(L.off_crow), idx_words,
                        0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(val_words)), dim3(256), 0, X.st, X.p<int>(L.off_cval), val_words,
                        0);
-    hipLaunchKernelGGL(k_fill_csc<TA>, dim3((unsigned)((L.C + kColTile - 1) / kColTile), (unsigned)kSlabs,
-                                            (unsigned)P),
-                       dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d, X.p<int64_t>(L.off_slab), L.blk,
-                       X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval));
+    if (X.quant)
+      hipLaunchKernelGGL((k_fill_csc<TA, uint16_t>), gc, dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d,
+                         X.p<int64_t>(L.off_slab), L.blk, X.p<uint16_t>(L.off_crow), X.p<uint16_t>(L.off_cval), inv_q,
+                         q, bad);
+    else
+      hipLaunchKernelGGL((k_fill_csc<TA, TA>), gc, dim3(kColThreads), 0, X.st, A, L.C, X.aoff_d, X.rps_d,
+                         X.p<int64_t>(L.off_slab), L.blk, X.p<uint16_t>(L.off_crow), X.p<TA>(L.off_cval), inv_q, q,
+                         bad);
     SW_HIP(hipGetLastError());
   }
   if (!g_gram_dense) {
@@ -2112,7 +2170,16 @@ static int build_sparse(Ctx& X) {
     X.perm = X.p<int32_t>(L.off_perm);
   }
   if (!fits) return SW_OK;
+  int hbad = 0;
+  if (X.quant) SW_HIP(hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, X.st));
   SW_HIP(hipStreamSynchronize(X.st));
+  if (hbad) {
+    X.quant = false;
+    set_error("solve_weights: opts.quantum = %.17g, but an entry of A is not the rounding of an integer multiple "
+              "of it in 1..65535",
+              X.quantum);
+    return SW_EINVAL;
+  }
   X.sparse = true;
   X.nnz = nnz;
   return SW_OK;
@@ -2183,6 +2250,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
                "solve_weights: w0_shared needs every problem to have the orbits of the first");
   SW_CHECK(lambda >= 0.0 || (std::isfinite(opt->nu) && opt->nu > 0.0),
            "solve_weights: lambda < 0 needs opt->nu > 0");
+  SW_CHECK(opt->quantum >= 0.0 && std::isfinite(opt->quantum), "solve_weights: opts.quantum must be >= 0 and finite");
   SW_CHECK(opt->gram == SW_GRAM_BF16 || opt->gram == SW_GRAM_BF16X3 || opt->gram == SW_GRAM_F32,
            "solve_weights: unknown gram mode %d", opt->gram);
   SW_CHECK(A && d && sigma && w, "solve_weights: null device buffer");
@@ -2211,6 +2279,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   X.A = A;
   X.dtype = dtype;
   X.sigma = sigma;
+  X.quantum = opt->quantum;
   X.sS = shared ? 0 : n_con;
   X.par = X.p<double>(L.off_par);
   int64_t* idx = X.p<int64_t>(L.off_idx);
@@ -2261,7 +2330,8 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     // once for all of them (2 P C N flop at ~30 TFLOP/s); the compressed passes read
     // it once per group of rg (6 B per stored entry at ~3 TB/s)
     const double dense_t = 2.0 * P * (double)L.C * (double)L.NA / 30e12;
-    const double comp_t = X.sparse ? (double)((P + L.rg - 1) / L.rg) * 6.0 * (double)X.nnz / 3e12 : 1e300;
+    const double comp_t =
+        X.sparse ? (double)((P + L.rg - 1) / L.rg) * (X.quant ? 4.0 : 6.0) * (double)X.nnz / 3e12 : 1e300;
     X.dense_rhs = g_multi_dense == 1 || dense_t < comp_t;
     const int64_t pt = (P + kDM - 1) / kDM;
     const int64_t ct = (L.C + kDN - 1) / kDN * pt, rt = (L.NA + kDN - 1) / kDN * pt;

@@ -24,6 +24,7 @@ def multi_solve(A, D, sig, wt, nu=1e-2, gram=1, **kw):
     opts = P._lib.SolveOpts()
     opts.gram, opts.nu = gram, nu
     opts.flags = kw.get("flags", 0)
+    opts.quantum = kw.get("quantum", 0.0)
     w0 = None
     if kw.get("w0") is not None:  # warm start from one weight vector for every realisation
         w0 = torch.from_numpy(np.ascontiguousarray(kw["w0"])).to(dev)
@@ -293,3 +294,47 @@ def test_warm_start_at_the_solution_converges_at_once(gpu):
     opts.w0_shared = 1
     with pytest.raises(P.SchwError):
         P.solve_weights_batched(At, off, dt, st, wts, -1.0, opts, w2, ws)
+
+
+def test_multi_rhs_count_quantum(gpu):
+    """Bootstrap realisations on a count matrix (the oracle's time fractions of
+    the small model, 1,000 steps) with the compressed passes per group of data
+    vectors: with the quantum 1 / (ncopy n_steps) the copies hold the counts,
+    and every realisation's weights meet the KKT tolerance by the oracle's
+    residual (Eq. 4), chi^2 agrees with the value copies' weights, and the first
+    realisation's weights match the oracle's within the parity bar."""
+    import torch
+    import oracle as O
+    P = lib()
+    dev = torch.device("cuda:0")
+    cfg = W.SMALL
+    n_steps = 1000
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=n_steps)
+    opot = O.make_pot(cfg["components"], cfg["omega"])
+    oobs = O.make_obs(cfg["obs"], O.euler_matrix(*cfg["euler"]))
+    c_o, _, _, _ = O.integrate_and_bin(opot, oobs, ics, dt, n_steps)
+    A = O.time_fractions(c_o, n_steps)
+    n, c = A.shape
+    blocks = W.blocks(cfg["obs"])
+    kin0 = blocks[1][0]
+    d = A.T @ W.mock_draw(n, cfg["mock"]["seed"])
+    sig = N.sigma_from_data(d, blocks, 0.01)
+    wt = N.w_tilde_from_data(d, blocks[0], n)
+    B = 12
+    D_o = BS.bootstrap_data(d, sig, W.bootstrap_eps(B, c, seed=8), kin0, c)
+    q = P.count_quantum(P.obs_spec(cfg["obs"]), n_steps)
+    old = P.get_tuning("multi_dense")
+    try:
+        P.set_tuning("multi_dense", 2)
+        w_v, st_v, reps_v = multi_solve(A, D_o, sig, wt)
+        w_q, st_q, reps_q = multi_solve(A, D_o, sig, wt, quantum=q)
+    finally:
+        P.set_tuning("multi_dense", old)
+    print("iters", [r.refine_iters for r in reps_v], [r.refine_iters for r in reps_q])
+    assert _converged(st_v, reps_v) and _converged(st_q, reps_q)
+    for b in range(B):
+        kkt = N.kkt_residual_orbit_matrix(A, D_o[b], sig, wt, reps_q[b].mu, w_q[b])
+        x_q, x_v = (N.chi2(A, w_[b], D_o[b], sig, kin0, c) for w_ in (w_q, w_v))
+        assert kkt <= 1.5e-7 and abs(x_q / x_v - 1) < 1e-6, (b, kkt, x_q, x_v)
+    w_o, _ = oracle_solve(A, D_o[0], sig, wt, 1e-2)
+    assert np.abs(w_q[0] - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL

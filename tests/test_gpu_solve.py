@@ -50,6 +50,7 @@ def gpu_solve(A, d, sig, wt, nu, gram, **kw):
     opts.tol = kw.get("tol", 0.0)
     opts.tol_kkt = kw.get("tol_kkt", 0.0)
     opts.flags = kw.get("flags", 0)
+    opts.quantum = kw.get("quantum", 0.0)
     w = torch.empty(A.shape[0], dtype=torch.float64, device=dev)
     ws = torch.empty(P.solve_workspace_bytes(A.shape[0], A.shape[1], opts), dtype=torch.uint8, device=dev)
     if "fill" in kw:  # byte pattern written over the whole workspace first
@@ -435,3 +436,48 @@ def test_two_pass_fallback_to_four(gpu):
         w_o, _ = oracle_solve(mats[k], ds[k], sigs[k], wts[k], 1e-2)
         wk = wf[off[k]:off[k + 1]]
         assert np.abs(wk - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_count_quantum_compressed_copies(gpu, dtype):
+    """A leapfrog orbit matrix is a histogram of counts of q = 1 / (ncopy
+    n_steps).  With that quantum the compressed copies hold the counts and every
+    pass computes with the exact multiples k q: the weights then meet the KKT
+    tolerance on the exact matrix (checked by the oracle's residual, Eq. 4), as
+    the value copies' weights do on A itself, and chi^2 agrees; the FP64 matrix
+    also matches the oracle's weights and chi^2.  A quantum of which the entries
+    are not multiples fails with SW_EINVAL."""
+    import oracle as O
+    from tests.gpu_common import oracle_integrate
+    P = lib()
+    cfg = W.SMALL
+    n_steps = cfg["n_steps"]
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=n_steps)
+    A, *_ = gpu_integrate(cfg, ics, dt, n_steps, dtype)
+    c_o, *_ = oracle_integrate(cfg, ics, dt, n_steps)
+    A_o = O.time_fractions(c_o, n_steps)
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A_o, blocks, cfg["mock"]["seed"], 0.02, cfg["mock"]["tol"])
+    q = P.count_quantum(P.obs_spec(cfg["obs"]), n_steps)
+    assert q > 0
+    A64 = A.astype(np.float64)
+    A_k = np.rint(A64 / q) * q  # the exact multiples A rounds
+    out = {}
+    for quantum, A_ref in ((0.0, A64), (q, A_k)):
+        w, status, rep, h = gpu_solve(A, d, sig, wt, 1e-2, 1, quantum=quantum)
+        assert status == 0, quantum
+        assert rep.nnz > 0  # the compressed copies were used
+        kkt = N.kkt_residual_orbit_matrix(A_ref, d, sig, wt, rep.mu, w)
+        x = N.chi2(A_ref, w, d, sig, blocks[1][0], blocks[1][1])
+        out[quantum] = (w, x, kkt, rep.kkt, rep.refine_iters)
+        print(quantum, "chi2", x, "kkt", kkt, rep.kkt, "iterations", rep.refine_iters)
+        assert kkt <= 1.5e-7
+    assert abs(out[q][1] / out[0.0][1] - 1) < 1e-6
+    if dtype == "f64":
+        w_o, _ = oracle_solve(A_o, d, sig, wt, 1e-2)
+        assert np.abs(out[q][0] - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
+        x_o = N.chi2(A_o, w_o, d, sig, blocks[1][0], blocks[1][1])
+        assert abs(out[q][1] / x_o - 1) < CHI2_TOL
+    with pytest.raises(P.SchwError) as e:
+        gpu_solve(A, d, sig, wt, 1e-2, 1, quantum=1.5 * q)
+    assert e.value.status == -1 and "quantum" in str(e.value)
