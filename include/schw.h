@@ -563,6 +563,9 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             to 4 when a problem's KKT residual rebounds to 10x
  *                             its smallest value), or 4 (the residual recomputed
  *                             from the matrix every iteration)
+ *   "trmv_rows"               rows per wave of the passes over the inverse factor's
+ *                             triangles: 16 (default; one load of the vector serves
+ *                             16 rows) or 2
  *   "refine_rebound"          the factor of that fall-back (default 10; 0 falls
  *                             back at the second check, for tests)
  *   "gram_skip"               weight solve: 1 (default) skips the 32-orbit

@@ -77,6 +77,8 @@ extern int g_factor_x3;
 //  g_refine_two    1: two passes over A per FP64 iteration (U^T U x carried), 0: four
 extern int g_gram_dense;
 extern int g_refine_two;
+//  g_trmv_rows     rows per wave of the inverse factor's triangle passes: 16 (row-blocked) or 2
+extern int g_trmv_rows;
 //  g_refine_rebound  two-pass FP64 stage: falls back to four passes when a KKT residual exceeds this times its minimum
 extern int g_refine_rebound;
 //  g_multi_dense   shared-matrix solves: 0 picks dense MFMA or compressed passes by cost, 1 dense, 2 compressed

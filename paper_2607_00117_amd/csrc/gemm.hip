@@ -747,6 +747,79 @@ __global__ __launch_bounds__(kThreads) void k_trmv(const float* __restrict__ S, 
   }
 }
 
+// y = T x, T the lower (j <= i) or upper (j >= i) half of the row-major S
+// (leading dimension ld), n a multiple of 16.  Wave g owns rows 8g .. 8g+7
+// and their mirror rows n-8-8g .. n-1-8g (8 (n + 1) entries of the half for
+// every wave) and streams their columns 256 at a time, four per lane: one load
+// of x serves up to 16 rows.  A chunk that straddles the diagonal of a group
+// of rows is masked entry by entry; a chunk outside a group's half is skipped.
+template <bool LOWER>
+__global__ __launch_bounds__(kThreads) void k_trmv16(const float* __restrict__ S, int64_t n, int64_t ld, int64_t sK,
+                                                     const float* __restrict__ x, float* __restrict__ y, int64_t sv,
+                                                     const double* __restrict__ act, int act_stride) {
+  const int64_t b = blockIdx.y;
+  if (act && act[b * act_stride] == 0.0) return;
+  S += b * sK;
+  x += b * sv;
+  y += b * sv;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (g >= n / 16) return;
+  const int64_t R[2] = {8 * g, n - 8 - 8 * g};  // first rows of the two groups
+  // the columns that a row of either group holds
+  const int64_t lo = LOWER ? 0 : R[0] & ~(int64_t)255, hi = LOWER ? R[1] + 8 : n;
+  float acc[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[h][r] = 0.0f;
+  for (int64_t jb = lo; jb < hi; jb += 256) {
+    const int64_t j = jb + 4 * lane;
+    const bool in = j < n;
+    bool use[2], full[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      use[h] = LOWER ? jb <= R[h] + 7 : jb + 255 >= R[h];
+      full[h] = LOWER ? jb + 255 <= R[h] : jb >= R[h] + 7;
+    }
+    f32x4 sr[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        sr[h][r] = use[h] && in ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(S + (R[h] + r) * ld + j))
+                                : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const f32x4 xv = in ? *reinterpret_cast<const f32x4*>(x + j) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!use[h]) continue;
+      if (full[h]) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          acc[h][r] += sr[h][r][0] * xv[0] + sr[h][r][1] * xv[1] + sr[h][r][2] * xv[2] + sr[h][r][3] * xv[3];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int64_t row = R[h] + r;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool ok = LOWER ? j + q <= row : j + q >= row;
+            acc[h][r] += ok ? sr[h][r][q] * xv[q] : 0.0f;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      float v = acc[h][r];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) y[R[h] + r] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Many right-hand sides against one S: Y[b][i] = sum_j T[i][j] X[b][j] for
 // b < P, T = the lower (j <= i) or upper (j >= i) half of S, as an fp32 MFMA
@@ -1100,6 +1173,14 @@ hipError_t inv_apply_rhs(const float* S, int64_t n, int64_t ld, int P, const flo
 
 hipError_t inv_apply(const float* S, int64_t n, int64_t ld, int64_t sK, int nb_prob, const float* r, float* tmp,
                      float* s, int64_t sv, const double* act, int act_stride, hipStream_t st) {
+  if (n % 16 == 0 && g_trmv_rows == 16) {
+    const unsigned g = (unsigned)((n / 16 + kThreads / 64 - 1) / (kThreads / 64));
+    hipLaunchKernelGGL(k_trmv16<true>, dim3(g, (unsigned)nb_prob), dim3(kThreads), 0, st, S, n, ld, sK, r, tmp, sv,
+                       act, act_stride);
+    hipLaunchKernelGGL(k_trmv16<false>, dim3(g, (unsigned)nb_prob), dim3(kThreads), 0, st, S, n, ld, sK, tmp, s, sv,
+                       act, act_stride);
+    return hipGetLastError();
+  }
   const unsigned g = (unsigned)((n / 2 + kThreads / 64 - 1) / (kThreads / 64));
   hipLaunchKernelGGL(k_trmv<true>, dim3(g, (unsigned)nb_prob), dim3(kThreads), 0, st, S, n, ld, sK, r, tmp, sv, act,
                      act_stride);

@@ -140,6 +140,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_multi_dense = value;
     return SW_OK;
   }
+  if (k == "trmv_rows") {
+    SW_CHECK(value == 2 || value == 16, "sw_set_tuning: trmv_rows is 2 or 16");
+    g_trmv_rows = value;
+    return SW_OK;
+  }
   if (k == "refine_rebound") {
     SW_CHECK(value >= 0, "sw_set_tuning: refine_rebound: a factor >= 0");
     g_refine_rebound = value;
@@ -184,6 +189,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "refine_passes") return g_refine_two ? 2 : 4;
   if (k == "multi_dense") return g_multi_dense;
   if (k == "refine_rebound") return g_refine_rebound;
+  if (k == "trmv_rows") return g_trmv_rows;
   return -1;
 }
 

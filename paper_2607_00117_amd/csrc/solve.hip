@@ -61,6 +61,7 @@ constexpr double kStallRatio = 0.95;  // dropped below 0.95x its value kStallChe
 int g_sparse_rows = 0;
 int g_gram_dense = 0;
 int g_refine_two = 1;
+int g_trmv_rows = 16;
 int g_refine_rebound = 10;
 int g_multi_dense = 0;
 int g_sparse_cols = 0;

@@ -481,3 +481,35 @@ def test_count_quantum_compressed_copies(gpu, dtype):
     with pytest.raises(P.SchwError) as e:
         gpu_solve(A, d, sig, wt, 1e-2, 1, quantum=1.5 * q)
     assert e.value.status == -1 and "quantum" in str(e.value)
+
+
+def test_triangle_pass_row_blocking(gpu):
+    """The passes over the inverse factor's triangles with 16 rows per wave (one
+    load of the vector for all of them, chunks across the diagonal masked) and
+    with 2: both solves converge to the same weights (1e-4, L1), within the
+    oracle's bar."""
+    import oracle as O
+    from tests.gpu_common import oracle_integrate
+    P = lib()
+    cfg = W.SMALL
+    ics, dt = W.grid_ics(W.load_table(cfg["table"]), seed=cfg["ic_seed"], n_steps=cfg["n_steps"])
+    A, *_ = gpu_integrate(cfg, ics, dt, cfg["n_steps"], "f64")
+    c_o, *_ = oracle_integrate(cfg, ics, dt, cfg["n_steps"])
+    A_o = O.time_fractions(c_o, cfg["n_steps"])
+    blocks = W.blocks(cfg["obs"])
+    d, sig, wt = mock_problem(A_o, blocks, cfg["mock"]["seed"], 0.02, cfg["mock"]["tol"])
+    w_o, _ = oracle_solve(A_o, d, sig, wt, 1e-2)
+    out = {}
+    old = P.get_tuning("trmv_rows")
+    try:
+        for rows in (2, 16):
+            P.set_tuning("trmv_rows", rows)
+            w, status, rep, _ = gpu_solve(A, d, sig, wt, 1e-2, 1)
+            out[rows] = (w, status, rep.refine_iters, rep.kkt)
+    finally:
+        P.set_tuning("trmv_rows", old)
+    print({k: v[1:] for k, v in out.items()})
+    for rows, (w, status, _, _) in out.items():
+        assert status == 0, rows
+        assert np.abs(w - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL, rows
+    assert np.abs(out[16][0] - out[2][0]).sum() <= 1e-4 * np.abs(out[2][0]).sum()
