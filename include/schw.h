@@ -563,6 +563,10 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             to 4 when a problem's KKT residual rebounds to 10x
  *                             its smallest value), or 4 (the residual recomputed
  *                             from the matrix every iteration)
+ *   "gram_counts"             1 (default): with opts.quantum the Gram's operand is the
+ *                             counts (exact in bf16 up to 256, so the bf16x3 products
+ *                             of the low plane run only where a count exceeds it), the
+ *                             scale applied to the result; 0: the scaled values
  *   "trmv_rows"               rows per wave of the passes over the inverse factor's
  *                             triangles: 16 (default; one load of the vector serves
  *                             16 rows) or 2

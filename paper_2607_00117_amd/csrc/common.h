@@ -79,6 +79,8 @@ extern int g_gram_dense;
 extern int g_refine_two;
 //  g_trmv_rows     rows per wave of the inverse factor's triangle passes: 16 (row-blocked) or 2
 extern int g_trmv_rows;
+//  g_gram_counts   1: a matrix of counts (solve opts.quantum) enters the Gram as its counts
+extern int g_gram_counts;
 //  g_refine_rebound  two-pass FP64 stage: falls back to four passes when a KKT residual exceeds this times its minimum
 extern int g_refine_rebound;
 //  g_multi_dense   shared-matrix solves: 0 picks dense MFMA or compressed passes by cost, 1 dense, 2 compressed

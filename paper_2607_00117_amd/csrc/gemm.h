@@ -30,7 +30,8 @@ __host__ __device__ inline int64_t gram_at(int64_t m, int64_t k, int64_t ld) {
 // 32-column stages whose row or column panel is zero are skipped.
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
                 const int64_t* xlen_d, const int64_t* xoff_h, const int64_t* xlen_h, int nb, float* K, int64_t ldk,
-                int64_t sK, hipStream_t st, const uint64_t* nz = nullptr, int64_t nzw = 0);
+                int64_t sK, hipStream_t st, const uint64_t* nz = nullptr, int64_t nzw = 0,
+                const uint64_t* nzl = nullptr, const float* cs = nullptr, int64_t scs = 0);
 
 // C = beta C + alpha A B^T per problem (fp32 MFMA, fp32 accumulate).
 // M, N, K multiples of 128 (K multiple of 32).  lower: only tiles with tile_m >= tile_n.

@@ -92,6 +92,12 @@ static int64_t super_grid(int64_t nt) {
 // whether rows [256 t, 256 t + 256) of X have a nonzero in columns
 // [32 g, 32 g + 32) (global stage g); a stage whose row panel or column panel
 // is zero adds nothing and is skipped.
+// Low-plane skipping (X3): when `nzl` is given (same layout, for the lo plane),
+// a stage whose row panel has a zero lo plane needs no lo(A) hi(B) product and
+// one whose column panel has none no hi(A) lo(B) product; their lo planes are
+// then neither fetched nor staged.  For a matrix of counts the operand is the
+// counts themselves, whose lo plane is zero up to 256, and `cs` (per row of X)
+// scales the result: K[m][n] = cs[m] cs[n] sum_k X[m][k] X[n][k].
 // X has Mx rows (a multiple of 256, zero past the constraints); entries of K
 // are stored for rows and columns below M only.
 // ---------------------------------------------------------------------------
@@ -105,7 +111,9 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
                                                          const int64_t* __restrict__ xoff,
                                                          const int64_t* __restrict__ xlen, int64_t ld,
                                                          float* __restrict__ Kall, int64_t ldk, int64_t sK, int64_t M,
-                                                         int64_t nt, const uint64_t* __restrict__ nz, int64_t nzw) {
+                                                         int64_t nt, const uint64_t* __restrict__ nz, int64_t nzw,
+                                                         const uint64_t* __restrict__ nzl,
+                                                         const float* __restrict__ csall, int64_t scs) {
   constexpr int NM = X3 ? 4 : 2;  // staged panels: A hi, B hi (, A lo, B lo)
   __shared__ __attribute__((aligned(16))) __bf16 sm[2][NM][kGT][kGPad];
   const int64_t bp = blockIdx.y;
@@ -127,6 +135,11 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
   // the next stage >= g whose row and column panels both hold a nonzero (g1: none)
   const uint64_t* nzA = nz ? nz + tm * nzw : nullptr;
   const uint64_t* nzB = nz ? nz + tn * nzw : nullptr;
+  const uint64_t* nlA = nzl ? nzl + tm * nzw : nullptr;
+  const uint64_t* nlB = nzl ? nzl + tn * nzw : nullptr;
+  // whether stage g's lo plane of the row (column) panel holds a nonzero
+  auto lo_a = [&](int64_t g) -> bool { return !nlA || ((nlA[g >> 6] >> (g & 63)) & 1ull); };
+  auto lo_b = [&](int64_t g) -> bool { return !nlB || ((nlB[g >> 6] >> (g & 63)) & 1ull); };
   auto next = [&](int64_t g) -> int64_t {
     if (!nzA) return g;
     while (g < g1) {
@@ -152,7 +165,8 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
   const __bf16* pBl = lo + tn * kGT * ld + tid * 8;
   constexpr int64_t kHalf = kGThreads * 8;  // elements in half a stage block
   uint4 gAh0, gAh1, gBh0, gBh1, gAl0, gAl1, gBl0, gBl1;
-  auto gload = [&](int64_t g) {
+  // la / lb: the stage's lo planes of the row / column panel are used
+  auto gload = [&](int64_t g, bool la, bool lb) {
     const int64_t k0 = g * (kGT * kGBK);
     gAh0 = *reinterpret_cast<const uint4*>(pAh + k0);
     gAh1 = *reinterpret_cast<const uint4*>(pAh + k0 + kHalf);
@@ -161,15 +175,17 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
       gBh1 = *reinterpret_cast<const uint4*>(pBh + k0 + kHalf);
     }
     if constexpr (X3) {
-      gAl0 = *reinterpret_cast<const uint4*>(pAl + k0);
-      gAl1 = *reinterpret_cast<const uint4*>(pAl + k0 + kHalf);
-      if (!diag) {
+      if (la) {
+        gAl0 = *reinterpret_cast<const uint4*>(pAl + k0);
+        gAl1 = *reinterpret_cast<const uint4*>(pAl + k0 + kHalf);
+      }
+      if (!diag && lb) {
         gBl0 = *reinterpret_cast<const uint4*>(pBl + k0);
         gBl1 = *reinterpret_cast<const uint4*>(pBl + k0 + kHalf);
       }
     }
   };
-  auto stage = [&](int buf) {
+  auto stage = [&](int buf, bool la, bool lb) {
     *reinterpret_cast<uint4*>(&sm[buf][0][r0][cc]) = gAh0;
     *reinterpret_cast<uint4*>(&sm[buf][0][r1][cc]) = gAh1;
     if (!diag) {
@@ -177,9 +193,11 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
       *reinterpret_cast<uint4*>(&sm[buf][1][r1][cc]) = gBh1;
     }
     if constexpr (X3) {
-      *reinterpret_cast<uint4*>(&sm[buf][2][r0][cc]) = gAl0;
-      *reinterpret_cast<uint4*>(&sm[buf][2][r1][cc]) = gAl1;
-      if (!diag) {
+      if (la) {
+        *reinterpret_cast<uint4*>(&sm[buf][2][r0][cc]) = gAl0;
+        *reinterpret_cast<uint4*>(&sm[buf][2][r1][cc]) = gAl1;
+      }
+      if (!diag && lb) {
         *reinterpret_cast<uint4*>(&sm[buf][3][r0][cc]) = gBl0;
         *reinterpret_cast<uint4*>(&sm[buf][3][r1][cc]) = gBl1;
       }
@@ -188,14 +206,22 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
   const int bA = 0, bB = diag ? 0 : 1;  // LDS panels read as A and as B
   int64_t g = next(g0);
   int buf = 0;
+  bool la = false, lb = false;  // lo planes of the current stage
   if (g < g1) {
-    gload(g);
-    stage(0);
+    la = lo_a(g);
+    lb = diag ? la : lo_b(g);
+    gload(g, la, lb);
+    stage(0, la, lb);
   }
   __syncthreads();
   while (g < g1) {
     const int64_t gn = next(g + 1);
-    if (gn < g1) gload(gn);
+    bool lan = false, lbn = false;
+    if (gn < g1) {
+      lan = lo_a(gn);
+      lbn = diag ? lan : lo_b(gn);
+      gload(gn, lan, lbn);
+    }
 #pragma unroll
     for (int ks = 0; ks < kGBK / 16; ++ks) {
       const int kc = ks * 16 + 8 * (lane >> 5);
@@ -204,13 +230,13 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
       for (int b = 0; b < 2; ++b) {
         bn[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB][wn * 64 + b * 32 + (lane & 31)][kc]);
         if constexpr (X3)
-          bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
+          if (lb) bnl[b] = *reinterpret_cast<const bf16x8*>(&sm[buf][bB + 2][wn * 64 + b * 32 + (lane & 31)][kc]);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         am[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][bA][wm * 128 + a * 32 + (lane & 31)][kc]);
         if constexpr (X3)
-          aml[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
+          if (la) aml[a] = *reinterpret_cast<const bf16x8*>(&sm[buf][bA + 2][wm * 128 + a * 32 + (lane & 31)][kc]);
       }
       // each sweep issues 8 MFMAs on 8 different accumulators, so no MFMA waits
       // for the one before it
@@ -219,35 +245,44 @@ __global__ __launch_bounds__(kGThreads) void k_gram_bf16(const __bf16* __restric
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bn[b], acc[a][b], 0, 0, 0);
       if constexpr (X3) {
+        if (lb) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bnl[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 2; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[a], bnl[b], acc[a][b], 0, 0, 0);
+        }
+        if (la) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml[a], bn[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 2; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aml[a], bn[b], acc[a][b], 0, 0, 0);
+        }
       }
     }
     // the other buffer was last read before the previous barrier
-    if (gn < g1) stage(buf ^ 1);
+    if (gn < g1) stage(buf ^ 1, lan, lbn);
     __syncthreads();
     buf ^= 1;
     g = gn;
+    la = lan;
+    lb = lbn;
   }
   const bool edge = (tm + 1) * kGT > M;  // only the last tile row/column can cross M
+  const float* cs = csall ? csall + bp * scs : nullptr;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
+      const int64_t col = tn * kGT + wn * 64 + b * 32 + (lane & 31);
+      const float sn = cs && col < M ? cs[col] : 1.0f;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int64_t row = tm * kGT + wm * 128 + a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int64_t col = tn * kGT + wn * 64 + b * 32 + (lane & 31);
-        if (!edge || (row < M && col < M)) K[row * ldk + col] = acc[a][b][i];
+        if (!edge || (row < M && col < M)) K[row * ldk + col] = cs ? acc[a][b][i] * (cs[row] * sn) : acc[a][b][i];
       }
+    }
 }
 
 // Tile of a 128-tiled GEMM workgroup (false: none).  With a lower-triangular
@@ -934,7 +969,8 @@ __global__ __launch_bounds__(256) void k_trmm_sum(const float* __restrict__ part
 // ---------------------------------------------------------------------------
 hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64_t M, int64_t ld, const int64_t* xoff_d,
                 const int64_t* xlen_d, const int64_t* xoff_h, const int64_t* xlen_h, int nb, float* K, int64_t ldk,
-                int64_t sK, hipStream_t st, const uint64_t* nz, int64_t nzw) {
+                int64_t sK, hipStream_t st, const uint64_t* nz, int64_t nzw, const uint64_t* nzl, const float* cs,
+                int64_t scs) {
   if (mode == SW_GRAM_F32) {
     for (int b = 0; b < nb; ++b) {
       hipError_t e = gemm_nt_f32(M, M, xlen_h[b], 1.0f, xf + xoff_h[b], ld, 0, xf + xoff_h[b], ld, 0, 0.0f, K + b * sK,
@@ -947,10 +983,12 @@ hipError_t gram(int mode, const void* hi, const void* lo, const float* xf, int64
   const int64_t grid = super_grid(nt);
   if (mode == SW_GRAM_BF16X3) {
     hipLaunchKernelGGL(k_gram_bf16<true>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
+                       (const __bf16*)hi, (const __bf16*)lo, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw, nzl, cs,
+                       scs);
   } else {
     hipLaunchKernelGGL(k_gram_bf16<false>, dim3((unsigned)grid, (unsigned)nb), dim3(kGThreads), 0, st,
-                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw);
+                       (const __bf16*)hi, (const __bf16*)hi, xoff_d, xlen_d, ld, K, ldk, sK, M, nt, nz, nzw,
+                       (const uint64_t*)nullptr, cs, scs);
   }
   return hipGetLastError();
 }

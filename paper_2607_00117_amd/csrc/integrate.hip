@@ -140,6 +140,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_multi_dense = value;
     return SW_OK;
   }
+  if (k == "gram_counts") {
+    SW_CHECK(value == 0 || value == 1, "sw_set_tuning: gram_counts is 0 or 1");
+    g_gram_counts = value;
+    return SW_OK;
+  }
   if (k == "trmv_rows") {
     SW_CHECK(value == 2 || value == 16, "sw_set_tuning: trmv_rows is 2 or 16");
     g_trmv_rows = value;
@@ -190,6 +195,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "multi_dense") return g_multi_dense;
   if (k == "refine_rebound") return g_refine_rebound;
   if (k == "trmv_rows") return g_trmv_rows;
+  if (k == "gram_counts") return g_gram_counts;
   return -1;
 }
 

@@ -62,6 +62,7 @@ int g_sparse_rows = 0;
 int g_gram_dense = 0;
 int g_refine_two = 1;
 int g_trmv_rows = 16;
+int g_gram_counts = 1;
 int g_refine_rebound = 10;
 int g_multi_dense = 0;
 int g_sparse_cols = 0;
@@ -133,13 +134,16 @@ __global__ __launch_bounds__(256) void k_prep_x(const TA* __restrict__ A, int64_
 // thread t owns row n0 + t of the block (a constraint) and its 32 orbit
 // columns, so the reads of each orbit are 1 KB runs of A's row and the block is
 // written as 64 contiguous bytes per thread (16 KB per plane, front to back).
+// inv_q > 0 (a matrix of counts of quantum 1 / inv_q): the operand is the
+// counts themselves, hi + lo exact below 65536 and lo zero up to 256; the Gram
+// then scales its entries by the count scale of k_count_scale.
 template <typename TA, bool X3>
 __global__ __launch_bounds__(256) void k_prep_xb(const TA* __restrict__ A, int64_t C, int64_t Npt,
                                                  const int64_t* __restrict__ off, const int64_t* __restrict__ xoff,
                                                  int nprob, const double* __restrict__ sigma,
                                                  const double* __restrict__ par, const uint8_t* __restrict__ mask,
                                                  __bf16* __restrict__ hi, __bf16* __restrict__ lo,
-                                                 const int32_t* __restrict__ perm) {
+                                                 const int32_t* __restrict__ perm, double inv_q) {
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;  // row of X (constraint)
   const int64_t c0 = (int64_t)blockIdx.y * 32;                 // first column of the stage
   const int b = find_problem(xoff, nprob, c0);                   // stages never straddle problems
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(256) void k_prep_xb(const TA* __restrict__ A, int64
     float v = 0.0f;
     if (jj < nb && n < C) {
       const int64_t i = off[b] + (perm ? perm[off[b] + jj] : jj);
-      if (!(mask && mask[i])) v = (float)((double)A[i * C + n] * sc);
+      if (!(mask && mask[i])) v = inv_q > 0.0 ? (float)rint((double)A[i * C + n] * inv_q) : (float)((double)A[i * C + n] * sc);
     }
     h[j] = (__bf16)v;
     if constexpr (X3) l[j] = (__bf16)(v - (float)h[j]);
@@ -279,6 +283,16 @@ __global__ __launch_bounds__(256) void k_dgemm_rhs(int64_t M, int64_t Nn, int64_
         const int64_t n = n0 + wn * 32 + b * 16 + (lane & 15);
         if (m < M && n < Nn) out[m * ldo + n] = acc[a][b][r];
       }
+}
+
+// cs[a][n] = q w~_a / sigma_n (0 past the constraints): the scale of a count
+// matrix's Gram, K[m][n] = cs[m] cs[n] sum_i k_im k_in
+__global__ __launch_bounds__(256) void k_count_scale(const double* __restrict__ sigma, int64_t sS, int64_t C,
+                                                     int64_t Cp, const double* __restrict__ par, double q,
+                                                     float* __restrict__ cs) {
+  const int a = blockIdx.y;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n < Cp) cs[a * Cp + n] = n < C ? (float)(q * par[a * kPar + 0] / sigma[a * sS + n]) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1641,7 +1655,8 @@ struct SolveLayout {
   size_t off_pd;  // rg > 1: partial row dots [P][ncb][NA]
   size_t off_rcnt, off_cpart, off_slab, off_rptr, off_rcol, off_rval, off_cptr, off_crow, off_cval;
   int64_t nzw;    // 64-bit words of zero-panel bits per 256-row tile of X
-  size_t off_nz;  // zero-panel bits of the Gram operand [Cx / 256][nzw]
+  size_t off_nz;   // zero-panel bits of the Gram operand [Cx / 256][nzw]
+  size_t off_nzl;  // the same for its lo plane (counts)
   size_t off_tiles, off_perm;  // per orbit: footprint (count + bitmap of nonzero 256-constraint tiles); X's orbit order
   size_t off_scan, off_clen, off_cpos;  // device prefix sums of the compressed copies' segment lengths
   size_t total;
@@ -1678,6 +1693,7 @@ static SolveLayout layout(int P, const int64_t* off, int64_t C, int gram_mode, i
   L.off_xf = take(gram_mode == SW_GRAM_F32 ? xe * 4 : 0);
   L.nzw = (L.Npt + 2047) / 2048;
   L.off_nz = take(gram_mode == SW_GRAM_F32 ? 0 : (size_t)(gram_rows(gram_mode, L.Cp) / 256) * L.nzw * 8);
+  L.off_nzl = take(gram_mode == SW_GRAM_BF16X3 ? (size_t)(gram_rows(gram_mode, L.Cp) / 256) * L.nzw * 8 : 0);
   L.off_K = take(PA * L.Cp * L.Cp * 4);
   L.off_dinv = take(PA * L.Cp * kNB * 4);
   L.off_part = take((size_t)P * kSlabs * L.C * 8);
@@ -2339,6 +2355,9 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     X.dcs = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSlabs, 2048 / ct, L.NA / 256}));
     X.drd = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kDenseChunks, 2048 / rt, L.C / 128}));
   }
+  // a matrix of counts (checked entry by entry with the compressed copies): the
+  // Gram operand holds the counts, scaled afterwards
+  const bool counts_gram = X.quant && opt->gram != SW_GRAM_F32 && g_gram_counts;
   if (opt->gram == SW_GRAM_F32) {
     dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 64), (unsigned)(L.Npt / 64));
     if (dtype == SW_F32)
@@ -2354,20 +2373,21 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     const dim3 grid((unsigned)(gram_rows(opt->gram, L.Cp) / 256), (unsigned)(L.Npt / 32));
     __bf16 *hp = X.p<__bf16>(L.off_hi), *lp = X.p<__bf16>(L.off_lo);
     const bool x3 = opt->gram == SW_GRAM_BF16X3;
+    const double inv_q = counts_gram ? 1.0 / X.quantum : 0.0;
     if (dtype == SW_F32) {
       if (x3)
         hipLaunchKernelGGL((k_prep_xb<float, true>), grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d,
-                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm, inv_q);
       else
         hipLaunchKernelGGL((k_prep_xb<float, false>), grid, dim3(256), 0, X.st, (const float*)A, L.C, L.Npt, X.aoff_d,
-                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+                           X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm, inv_q);
     } else {
       if (x3)
         hipLaunchKernelGGL((k_prep_xb<double, true>), grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt,
-                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm, inv_q);
       else
         hipLaunchKernelGGL((k_prep_xb<double, false>), grid, dim3(256), 0, X.st, (const double*)A, L.C, L.Npt,
-                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm);
+                           X.aoff_d, X.xoff_d, PA, sigma, X.par, mask, hp, lp, X.perm, inv_q);
     }
     SW_TRY(hipGetLastError());
   }
@@ -2377,6 +2397,19 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
                        X.st, X.p<__bf16>(L.off_hi), L.Npt, L.nzw, X.p<uint64_t>(L.off_nz));
     SW_TRY(hipGetLastError());
     nzbits = X.p<uint64_t>(L.off_nz);
+  }
+  const uint64_t* nzlo = nullptr;
+  float* cscale = nullptr;
+  if (counts_gram) {
+    if (opt->gram == SW_GRAM_BF16X3) {
+      hipLaunchKernelGGL(k_nz_bits, dim3((unsigned)L.nzw, (unsigned)(gram_rows(opt->gram, L.Cp) / 256)), dim3(256), 0,
+                         X.st, X.p<__bf16>(L.off_lo), L.Npt, L.nzw, X.p<uint64_t>(L.off_nzl));
+      nzlo = X.p<uint64_t>(L.off_nzl);
+    }
+    cscale = X.p<float>(L.off_s);  // borrowed: the iterations' vector, free until then
+    hipLaunchKernelGGL(k_count_scale, dim3(blocks_for(L.Cp), (unsigned)PA), dim3(256), 0, X.st, sigma, X.sS, L.C, L.Cp,
+                       X.par, X.quantum, cscale);
+    SW_TRY(hipGetLastError());
   }
   SW_TRY(hipEventRecord(ev[1], X.st));
 
@@ -2391,7 +2424,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
                               L.Cp, X.par + 5, kPar, X.st);
   };
   SW_TRY(gram(opt->gram, X.ws + L.off_hi, X.ws + L.off_lo, X.p<float>(L.off_xf), L.Cp, L.Npt, X.xoff_d, X.xlen_d,
-              L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st, nzbits, L.nzw));
+              L.xoff.data(), L.xlen.data(), PA, K, L.Cp, sK, X.st, nzbits, L.nzw, nzlo, cscale, L.Cp));
   SW_TRY(hipEventRecord(ev[2], X.st));
   double* acc = X.p<double>(L.off_acc);
   SW_TRY(zero_acc(X));

@@ -335,6 +335,6 @@ def test_multi_rhs_count_quantum(gpu):
     for b in range(B):
         kkt = N.kkt_residual_orbit_matrix(A, D_o[b], sig, wt, reps_q[b].mu, w_q[b])
         x_q, x_v = (N.chi2(A, w_[b], D_o[b], sig, kin0, c) for w_ in (w_q, w_v))
-        assert kkt <= 1.5e-7 and abs(x_q / x_v - 1) < 1e-6, (b, kkt, x_q, x_v)
+        assert kkt <= 1.5e-7 and abs(x_q / x_v - 1) < 1e-5, (b, kkt, x_q, x_v)
     w_o, _ = oracle_solve(A, D_o[0], sig, wt, 1e-2)
     assert np.abs(w_q[0] - w_o).sum() / np.abs(w_o).sum() < W_L1_TOL
