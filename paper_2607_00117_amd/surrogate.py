@@ -33,10 +33,12 @@ class ModelBuilder:
     family: callable theta -> (components, omega, euler)
     ics, dt: numpy [6][n], [n] (single precision is used on the device)
     obs: observable spec dict; d, sigma: numpy [n_con] (shared mock data)
+    counts: the weight solves take the leapfrog matrices as counts of
+    1 / (ncopy n_steps) (solve opts.quantum; off with surface-density columns)
     """
 
     def __init__(self, family, ics, dt, n_steps, obs, d, sigma, w_tilde, max_batch, nu=1e-2, gram=P.SW_GRAM_BF16X3,
-                 kin_block=None, drift_mask=True, solve_opts=None):
+                 kin_block=None, drift_mask=True, solve_opts=None, counts=True):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda:0")
@@ -66,6 +68,8 @@ class ModelBuilder:
         self.opts = solve_opts or P.SolveOpts()
         self.opts.gram = gram
         self.opts.nu = nu
+        if counts:
+            self.opts.quantum = P.count_quantum(self.obs, n_steps)
         offs = [self.n * k for k in range(max_batch + 1)]
         self.sws = torch.empty(P.solve_batched_workspace_bytes(offs, self.nc, self.opts), dtype=torch.uint8,
                                device=self.dev)
