@@ -47,9 +47,11 @@ FLOP_PER_ORBIT_STEP = {"mn_ferrers_nfwq_100k_orbits_10k_steps_f32": 686.0,
 # copy) for the kernels as they stand: per build for the factorisation, per
 # iteration for the ADMM stages; stages not listed were not measured
 BARRED = "mn_ferrers_nfwq_100k_orbits_10k_steps_f32"
-TRAFFIC = {(BARRED, "factorise"): 1496 * (0.8811e9 + 0.0636e9)}
-TRAFFIC_PER_ITER = {(BARRED, "admm_fp32"): 2.852e9 + 2.796e9 + 4.787e9 + 4.614e9,
-                    (BARRED, "refine_fp64"): 2 * 2.852e9 + 2 * 2.799e9 + 4.787e9 + 4.614e9 + 0.062e9}
+TRAFFIC = {(BARRED, "factorise"): 748 * (1.257e9 + 0.1149e9) + 748 * (0.01296e9 + 0.01229e9),
+           (BARRED, "gram"): 829.8e9 + 4.633e9}
+# per FP64 iteration (two passes over the count copies, and a pair more every 10 iterations for U^T U x
+# and for the KKT check; the two triangles; the Anderson kernels)
+TRAFFIC_PER_ITER = {(BARRED, "refine_fp64"): 1.2 * (1.964e9 + 1.906e9) + 2 * 4.634e9 + 0.06e9}
 
 
 def log(*a):
@@ -394,12 +396,13 @@ def main():
     it2 = float(np.mean([r["refine_iters"] for r in reps]))
     nnz = float(reps[-1]["nnz"])
     C, N = float(nc), float(n)
-    passes = {"bf16": 1, "bf16x3": 3, "f32": 1}[args.gram]
     stages = {"integrate_and_bin": t_i, "solve_prep": t_prep, "gram": t_gram, "factorise": t_factor,
               "admm_fp32": t_admm, "refine_fp64": t_ref}
-    # |U|: one pass over the orbit matrix as stored for the iterations (fp32 value + 16-bit
-    # index per nonzero, or the dense matrix); |L|: one triangle of the fp32 inverse factor
-    u_bytes = 6.0 * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
+    # |U|: one pass over the orbit matrix as stored for the iterations (per nonzero a 16-bit
+    # index and a 16-bit count, or an fp32 value; or the dense matrix); |L|: one triangle of
+    # the fp32 inverse factor
+    counts = opts.quantum > 0
+    u_bytes = (4.0 if counts else 6.0) * nnz if nnz > 0 else N * C * (8.0 if f64 else 4.0)
     l_bytes = 4.0 * C * (C + 1) / 2.0
     per_iter = 2 * u_bytes + 2 * l_bytes
     # Anderson mixing per FP64 iteration: 91 vectors of N doubles read or written
@@ -413,18 +416,18 @@ def main():
                               "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
                               "work": FLOP_PER_ORBIT_STEP[cfg["name"]] * N * n_steps, "ms": t_i,
                               "work_rule": "flop per orbit-step counted from the formulas x orbit-steps"},
-        "gram": {"kernel": f"k_gram_bf16 ({args.gram})" if args.gram != "f32" else "k_gemm_nt_f32 (Gram)",
+        "gram": {"kernel": (f"k_gram_bf16 ({args.gram}{' of the counts' if counts else ''})" if args.gram != "f32"
+                            else "k_gemm_nt_f32 (Gram)"),
                  "bound": "mfma", "unit": "TFLOP/s",
                  "peak": (PEAK_BF16 if args.gram != "f32" else PEAK_F32_MFMA) / 1e12,
-                 "work": C * (C + 1) * N, "issued": passes * C * (C + 1) * N, "ms": t_gram,
-                 "work_rule": "SYRK C(C+1)N"},
-        "factorise": {"kernel": "k_potrf_diag + k_gemm_nt_f32 (Cholesky, inverse factor)", "bound": "mfma",
+                 "work": C * (C + 1) * N, "ms": t_gram, "work_rule": "SYRK C(C+1)N"},
+        "factorise": {"kernel": "k_potrf_diag + k_gemm_nt_x3 (split-bf16 Cholesky, inverse factor)", "bound": "mfma",
                       "unit": "TFLOP/s", "peak": PEAK_F32_MFMA / 1e12, "work": C ** 3 / 3.0,
                       "issued": 2.0 * C ** 3 / 3.0, "ms": t_factor, "work_rule": "Cholesky C^3/3"},
-        "admm_fp32": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv", "bound": "hbm", "unit": "GB/s",
+        "admm_fp32": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv16", "bound": "hbm", "unit": "GB/s",
                       "peak": PEAK_HBM / 1e9, "work": it1 * per_iter, "issued": it1 * per_iter, "ms": t_admm,
                       "work_rule": "2|U| + 2|L| per iteration"},
-        "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
+        "refine_fp64": {"kernel": "k_csc_colsum + k_rowdot_csr + k_trmv16 (+ k_aa_*)", "bound": "hbm", "unit": "GB/s",
                         "peak": PEAK_HBM / 1e9, "work": it2 * per_iter,
                         "issued": it2 * (refine_passes * u_bytes + 2 * l_bytes + aa_bytes), "ms": t_ref,
                         "work_rule": "2|U| + 2|L| per iteration"},
