@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="barred", choices=["barred", "small", "walkers", "surrogate", "paper"])
     ap.add_argument("--bs23-steps", type=int, default=0, help="paper: accepted BS23 steps (0: the paper's 5,000)")
+    ap.add_argument("--refit-epochs", type=int, default=150,
+                    help="surrogate workload: epochs of each local refit during the burn-in")
     ap.add_argument("--no-quantum", action="store_true",
                     help="store the compressed copies of a count matrix as fp32 values, not as counts")
     ap.add_argument("--warm-bootstraps", action="store_true",
@@ -410,7 +412,7 @@ def main():
     # passes over A per FP64 iteration: 2 with U^T U x carried (plus 2 per batch of
     # iterations between checks to recompute it), 4 with the residual from A
     check = 10.0
-    refine_passes = 2.0 + 2.0 / check if P.get_tuning("refine_passes") == 2 else 4.0
+    refine_passes = (2.0 + 2.0 / check if P.get_tuning("refine_passes") == 2 else 4.0) + 2.0 / check  # + the KKT pair
     rooflines = {
         "integrate_and_bin": {"kernel": "k_integrate + k_hist", "bound": "alu", "unit": "TFLOP/s",
                               "peak": (PEAK_F64_VALU if f64 else PEAK_F32_VALU) / 1e12,
@@ -1051,7 +1053,7 @@ def bench_surrogate(args):
             # the chains' neighbourhood only: the full builds of the chains so far, with the target
             # standardised over them, so that the network resolves chi^2 differences of a few dchi2
             # there instead of the range of the whole prior box
-            sur.fit(th_b, chi_b, epochs=150, batch=256, seed=len(chi_b))
+            sur.fit(th_b, chi_b, epochs=args.refit_epochs, batch=256, seed=len(chi_b))
 
         res_da = S.da_mcmc(builder, sur, theta0, lo, hi, args.mcmc_steps, dchi2, use_surrogate=True, log=log,
                            refit=refit, refit_every=max(10, adapt // 10), adapt_steps=adapt)

@@ -560,8 +560,9 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             mixed with it by the Anderson step, recomputed from
  *                             the matrix at the start of every batch of
  *                             iterations between convergence checks; falling back
- *                             to 4 when a problem's KKT residual rebounds to 10x
- *                             its smallest value), or 4 (the residual recomputed
+ *                             to 4 when a problem's KKT residual stays above 10x
+ *                             its smallest value at three consecutive checks), or 4
+ *                             (the residual recomputed
  *                             from the matrix every iteration)
  *   "gram_counts"             1 (default): with opts.quantum the Gram's operand is the
  *                             counts (exact in bf16 up to 256, so the bf16x3 products
@@ -571,7 +572,8 @@ int gh_fit_matrix(const void* A, int32_t dtype, int64_t n_orb, int64_t n_con, in
  *                             triangles: 16 (default; one load of the vector serves
  *                             16 rows) or 2
  *   "refine_rebound"          the factor of that fall-back (default 10; 0 falls
- *                             back at the second check, for tests)
+ *                             back at the fourth check, for tests)
+ *   "refine_rebound_checks"   the consecutive checks it needs (default 3)
  *   "gram_skip"               weight solve: 1 (default) skips the 32-orbit
  *                             stages of the Gram whose row or column panel of
  *                             the scaled matrix is zero (the result is the same

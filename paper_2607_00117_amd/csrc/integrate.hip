@@ -150,6 +150,11 @@ extern "C" int sw_set_tuning(const char* key, int32_t value) {
     g_trmv_rows = value;
     return SW_OK;
   }
+  if (k == "refine_rebound_checks") {
+    SW_CHECK(value >= 1, "sw_set_tuning: refine_rebound_checks >= 1");
+    g_refine_rebound_checks = value;
+    return SW_OK;
+  }
   if (k == "refine_rebound") {
     SW_CHECK(value >= 0, "sw_set_tuning: refine_rebound: a factor >= 0");
     g_refine_rebound = value;
@@ -194,6 +199,7 @@ extern "C" int32_t sw_get_tuning(const char* key) {
   if (k == "refine_passes") return g_refine_two ? 2 : 4;
   if (k == "multi_dense") return g_multi_dense;
   if (k == "refine_rebound") return g_refine_rebound;
+  if (k == "refine_rebound_checks") return g_refine_rebound_checks;
   if (k == "trmv_rows") return g_trmv_rows;
   if (k == "gram_counts") return g_gram_counts;
   return -1;

@@ -64,6 +64,7 @@ int g_refine_two = 1;
 int g_trmv_rows = 16;
 int g_gram_counts = 1;
 int g_refine_rebound = 10;
+int g_refine_rebound_checks = 3;
 int g_multi_dense = 0;
 int g_sparse_cols = 0;
 int g_sparse_lanes = 0;
@@ -2604,10 +2605,11 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   SW_TRY(hipGetLastError());
   AAArgs AA;
   // two passes over A per FP64 iteration with h carried; the solve falls back to
-  // four (the residual from A every iteration) when a problem's KKT residual
-  // rebounds to 10x its smallest value: h drifts by U^T e / rho' per correction, e
-  // the fp32 inverse's residual, which the ten iterations between refreshes can
-  // let grow on badly conditioned problems
+  // four (the residual from A every iteration) when a problem's KKT residual stays
+  // above 10x its smallest value at three consecutive checks: h drifts by U^T e /
+  // rho' per correction, e the fp32 inverse's residual, which the ten iterations
+  // between refreshes can let grow on badly conditioned problems (a shorter rebound
+  // is often the Anderson step's and recovers)
   bool two = g_refine_two != 0;
   const double rebound_factor = (double)g_refine_rebound;
   double* hd = X.p<double>(L.off_hd);
@@ -2731,6 +2733,7 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
   if (use_graph && n_active > 0) SW_TRY(capture([&]() { return refine_batch(check_every); }, 1, &g2.e));
   std::vector<int> rit(P, 0);
   std::vector<double> kmin(P, HUGE_VAL);
+  std::vector<int> nreb(P, 0);  // consecutive checks above rebound_factor x kmin
   int k_done = 0;
   while (k_done < refine_iter && n_active > 0) {
     const int run = std::min(check_every, refine_iter - k_done);
@@ -2747,7 +2750,8 @@ static int solve_core(const void* A, int32_t dtype, int32_t n_prob, const int64_
     bool rebound = false;
     for (int b = 0; b < P; ++b) {
       if (!active[b]) continue;
-      if (kmin[b] < HUGE_VAL && kkt[b] > rebound_factor * kmin[b]) rebound = true;
+      nreb[b] = kmin[b] < HUGE_VAL && kkt[b] > rebound_factor * kmin[b] ? nreb[b] + 1 : 0;
+      if (nreb[b] >= g_refine_rebound_checks) rebound = true;
       kmin[b] = std::min(kmin[b], kkt[b]);
     }
     for (int b = 0; b < P; ++b)

@@ -392,7 +392,7 @@ def test_two_pass_iterations_match_four(gpu, flags):
 
 def test_two_pass_fallback_to_four(gpu):
     """The two-pass FP64 stage falls back to four passes when a problem's KKT
-    residual rebounds; forced at the second check (rebound factor 0), the batched
+    residual rebounds; forced at the fourth check (rebound factor 0), the batched
     solve still converges, reports four passes, and reaches the weights of the
     plain four-pass solve within 1e-4 (L1) and the oracle's within the parity
     bar."""
