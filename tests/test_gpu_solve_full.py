@@ -115,7 +115,9 @@ def test_barred_build_solve_certified_by_the_oracle(gpu):
     subset with Exp(1) weights + 2% noise, computed on the host from a CSR copy of
     that matrix), the drift-flagged orbits masked, the bf16x3 solve; the oracle
     re-evaluates in FP64 the regularisation, the KKT natural residual of the
-    GPU's weights and their chi^2 (kinematic block, Eq. 5)."""
+    GPU's weights and their chi^2 (kinematic block, Eq. 5).  Solved with fp32
+    values in the compressed copies and, as the benchmark runs it, with the
+    counts (the KKT residual then on the exact multiples of the quantum)."""
     import scipy.sparse as sp
     import torch
     P = lib()
@@ -153,26 +155,33 @@ def test_barred_build_solve_certified_by_the_oracle(gpu):
     mask = fl.cpu().numpy()
     keep = np.flatnonzero(mask == 0)
     mu_o = N.relative_mu_orbit_matrix(A_csr[keep], sig, wt, 1e-2)
-    opts = P._lib.SolveOpts()
-    opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
-    opts.mask = fl.data_ptr()
-    w_t = torch.empty(n, dtype=torch.float64, device=dev)
-    ws = torch.empty(P.solve_workspace_bytes(n, nc, opts), dtype=torch.uint8, device=dev)
-    d_t, s_t = torch.from_numpy(d).to(dev), torch.from_numpy(sig).to(dev)
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        status, rep = P.solve_weights(A, d_t, s_t, wt, -1.0, opts, w_t, ws)
-        cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
-        x_g = P.chi2(A, w_t, d_t, s_t, blocks[1][0], blocks[1][1], cws)
-    torch.cuda.synchronize()
-    w = w_t.cpu().numpy()
-    assert np.all(w[mask != 0] == 0) and np.all(w >= 0)
-    kkt_o = N.kkt_residual_orbit_matrix(A_csr[keep], d, sig, wt, rep.mu, w[keep])
-    x_o = N.chi2(A_csr, w, d, sig, blocks[1][0], blocks[1][1])
-    print(f"barred build: nnz {A_csr.nnz}, masked {int((mask != 0).sum())}, status {status}, "
-          f"iterations {rep.iters}+{rep.refine_iters}, kkt {rep.kkt:.2e} (oracle {kkt_o:.2e}), mu {rep.mu:.6g} "
-          f"(oracle {mu_o:.6g}), chi2 {x_g:.10g} (oracle {x_o:.10g})")
-    assert status == 0
-    assert rep.mu == pytest.approx(mu_o, rel=1e-4)
-    assert kkt_o < 1e-6
-    assert abs(x_g / x_o - 1) < 1e-10
+    # the count copies: the solve computes with the exact multiples k q that A rounds
+    q = P.count_quantum(obs, n_steps)
+    A_k = A_csr.copy()
+    A_k.data = np.rint(A_k.data / q) * q
+    for quantum, A_ref in ((0.0, A_csr), (q, A_k)):
+        opts = P._lib.SolveOpts()
+        opts.gram, opts.nu, opts.use_graph = P.SW_GRAM_BF16X3, 1e-2, 1
+        opts.mask = fl.data_ptr()
+        opts.quantum = quantum
+        w_t = torch.empty(n, dtype=torch.float64, device=dev)
+        ws = torch.empty(P.solve_workspace_bytes(n, nc, opts), dtype=torch.uint8, device=dev)
+        d_t, s_t = torch.from_numpy(d).to(dev), torch.from_numpy(sig).to(dev)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            status, rep = P.solve_weights(A, d_t, s_t, wt, -1.0, opts, w_t, ws)
+            cws = torch.empty(P.chi2_workspace_bytes(nc), dtype=torch.uint8, device=dev)
+            x_g = P.chi2(A, w_t, d_t, s_t, blocks[1][0], blocks[1][1], cws)
+        torch.cuda.synchronize()
+        del ws
+        w = w_t.cpu().numpy()
+        assert np.all(w[mask != 0] == 0) and np.all(w >= 0)
+        kkt_o = N.kkt_residual_orbit_matrix(A_ref[keep], d, sig, wt, rep.mu, w[keep])
+        x_o = N.chi2(A_csr, w, d, sig, blocks[1][0], blocks[1][1])
+        print(f"barred build, quantum {quantum:g}: nnz {A_csr.nnz}, masked {int((mask != 0).sum())}, status {status}, "
+              f"iterations {rep.iters}+{rep.refine_iters}, kkt {rep.kkt:.2e} (oracle {kkt_o:.2e}), mu {rep.mu:.6g} "
+              f"(oracle {mu_o:.6g}), chi2 {x_g:.10g} (oracle {x_o:.10g})")
+        assert status == 0
+        assert rep.mu == pytest.approx(mu_o, rel=1e-4)
+        assert kkt_o < 1e-6
+        assert abs(x_g / x_o - 1) < 1e-10
