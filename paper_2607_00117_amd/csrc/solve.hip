@@ -547,61 +547,60 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void quad_val(const float* p, double v[4]) {
-  const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
-  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
-}
-__device__ __forceinline__ void quad_val(const double* p, double v[4]) {
-  const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
-  const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
-  v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
-}
-__device__ __forceinline__ void quad_val(const uint16_t* p, double v[4]) {
-  const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
-  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
-}
-__device__ __forceinline__ void quad_idx(const uint16_t* p, uint32_t c[4]) {
-  const u16x4 q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
-  c[0] = q[0]; c[1] = q[1]; c[2] = q[2]; c[3] = q[3];
-}
+// The values of a quad of compressed entries as loaded (converted when used).
+template <typename TA> struct QuadRaw;
+template <> struct QuadRaw<uint16_t> {
+  u16x4 q;
+  __device__ void load(const uint16_t* p) { q = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p)); }
+  __device__ double operator[](int i) const { return (double)q[i]; }
+};
+template <> struct QuadRaw<float> {
+  f32x4 q;
+  __device__ void load(const float* p) { q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p)); }
+  __device__ double operator[](int i) const { return (double)q[i]; }
+};
+template <> struct QuadRaw<double> {
+  f64x2 a, b;
+  __device__ void load(const double* p) {
+    a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+    b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+  }
+  __device__ double operator[](int i) const { return i < 2 ? a[i] : b[i - 2]; }
+};
 
 // lane-partial sum_k val[k] xs[idx[k]] over the segment [k0, k1) (multiples
 // of 4) with xs in LDS, for a group of LPR lanes (lane = index in the group):
-// lane-strided quads, four in flight per lane
+// lane-strided quads, four of them loaded at once before any is used
+// (segments are a few quads per lane, so a loop that waited for each load in
+// turn would expose the memory latency); a quad past the segment re-reads the
+// lane's first one and is weighted by zero.
 template <int LPR = 64, typename TA>
 __device__ __forceinline__ double seg_dot(const TA* __restrict__ val, const uint16_t* __restrict__ idx, int64_t k0,
                                           int64_t k1, const double* xs, int lane) {
   constexpr int S = 4 * LPR;  // entries per quad row of the group
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t k = k0 + 4 * lane;
-  for (; k + 3 * S < k1; k += 4 * S) {
-    double v0[4], v1[4], v2[4], v3[4];
-    uint32_t c0[4], c1[4], c2[4], c3[4];
-    quad_val(val + k, v0);
-    quad_idx(idx + k, c0);
-    quad_val(val + k + S, v1);
-    quad_idx(idx + k + S, c1);
-    quad_val(val + k + 2 * S, v2);
-    quad_idx(idx + k + 2 * S, c2);
-    quad_val(val + k + 3 * S, v3);
-    quad_idx(idx + k + 3 * S, c3);
+  constexpr int U = 4;        // quads in flight per lane
+  double a[U] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = k0 + 4 * lane; k < k1; k += (int64_t)U * S) {
+    QuadRaw<TA> v[U];
+    u16x4 c[U];
+    double wgt[U];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a0 += v0[q] * xs[c0[q]];
-      a1 += v1[q] * xs[c1[q]];
-      a2 += v2[q] * xs[c2[q]];
-      a3 += v3[q] * xs[c3[q]];
+    for (int u = 0; u < U; ++u) {
+      const bool ok = k + (int64_t)u * S < k1;
+      const int64_t ka = ok ? k + (int64_t)u * S : k;
+      wgt[u] = ok ? 1.0 : 0.0;
+      v[u].load(val + ka);
+      c[u] = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(idx + ka));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t += v[u][q] * xs[c[u][q]];
+      a[u] += wgt[u] * t;
     }
   }
-  for (; k < k1; k += S) {
-    double v[4];
-    uint32_t c[4];
-    quad_val(val + k, v);
-    quad_idx(idx + k, c);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a0 += v[q] * xs[c[q]];
-  }
-  return (a0 + a1) + (a2 + a3);
+  return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // sum over the aligned group of LPR lanes (result in every lane of the group)
