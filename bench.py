@@ -47,11 +47,11 @@ FLOP_PER_ORBIT_STEP = {"mn_ferrers_nfwq_100k_orbits_10k_steps_f32": 686.0,
 # copy) for the kernels as they stand: per build for the factorisation, per
 # iteration for the ADMM stages; stages not listed were not measured
 BARRED = "mn_ferrers_nfwq_100k_orbits_10k_steps_f32"
-TRAFFIC = {(BARRED, "factorise"): 748 * (1.257e9 + 0.1149e9) + 748 * (0.01296e9 + 0.01229e9),
-           (BARRED, "gram"): 829.8e9 + 4.633e9}
+TRAFFIC = {(BARRED, "factorise"): 748 * (1.256e9 + 0.1149e9) + 748 * (0.01296e9 + 0.01229e9),
+           (BARRED, "gram"): 831.3e9 + 4.633e9}
 # per FP64 iteration (two passes over the count copies, and a pair more every 10 iterations for U^T U x
 # and for the KKT check; the two triangles; the Anderson kernels)
-TRAFFIC_PER_ITER = {(BARRED, "refine_fp64"): 1.2 * (1.964e9 + 1.906e9) + 2 * 4.634e9 + 0.06e9}
+TRAFFIC_PER_ITER = {(BARRED, "refine_fp64"): 1.2 * (1.895e9 + 1.854e9) + 2 * 4.634e9 + 0.06e9}
 
 
 def log(*a):
