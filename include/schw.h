@@ -263,7 +263,8 @@ typedef struct {
                  (dense passes over A, among them the FP64 MFMA passes of a shared matrix) */
   int32_t passes;   /* passes over A per FP64 iteration at return: 2 (U^T U x carried with the
                        iterate) or 4 (the residual from A; the solve falls back to it when a
-                       problem's KKT residual rebounds to 10x its smallest value) */
+                       problem's KKT residual stays above 10x its smallest value for three
+                       consecutive checks) */
   int32_t reserved;
 } sw_solve_report;
 

@@ -83,7 +83,7 @@ extern int g_trmv_rows;
 extern int g_gram_counts;
 //  g_refine_rebound  two-pass FP64 stage: falls back to four passes when a KKT residual exceeds this times its minimum
 extern int g_refine_rebound;
-//  g_refine_rebound_checks  ... at this many consecutive checks
+//  g_refine_rebound_checks  ... at this many consecutive convergence checks
 extern int g_refine_rebound_checks;
 //  g_multi_dense   shared-matrix solves: 0 picks dense MFMA or compressed passes by cost, 1 dense, 2 compressed
 extern int g_multi_dense;
